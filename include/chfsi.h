@@ -1,0 +1,231 @@
+/*
+ * chfsi.h -- C ABI of the MI355X (gfx950) Chebyshev Filtered Subspace
+ * Iteration library (libchfsi.so).
+ *
+ * Method: Berljafa, Wortmann, Di Napoli, "An optimized and scalable
+ * eigensolver for sequences of eigenvalue problems" -- Alg. 1 (ChFSI) with
+ * Alg. 2 (the Chebyshev filter) at its core, Sec. 3.1 and 3.1.1.
+ *
+ * Conventions shared by every entry point
+ *   - Complex matrices are complex128 (two IEEE doubles, real part first),
+ *     COLUMN-MAJOR, with a leading dimension ld >= rows.  Passing a
+ *     row-major Hermitian matrix instead reads conj(A): same eigenvalues,
+ *     conjugated eigenvectors.
+ *   - Pointers documented as "device" are HIP device pointers on the
+ *     current device; "host" pointers are ordinary host memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All device
+ *     work is ordered on it.  Every entry point returns after its results
+ *     are complete (it synchronises the stream).
+ *   - The caller owns every buffer.  The library never frees caller
+ *     memory.  Inputs documented as read-only are not modified.
+ *   - Scratch memory: `work` is a caller-owned device buffer of at least
+ *     the size reported by the matching *_workspace_bytes query.  The
+ *     rocSOLVER/rocBLAS handle used for the reduced eigenproblem manages
+ *     its own device memory.
+ *   - Errors are reported by the returned status; no entry point aborts,
+ *     prints or throws.  Calls with distinct workspaces on distinct streams
+ *     are independent.
+ */
+#ifndef CHFSI_H
+#define CHFSI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define CHFSI_OK              0  /* success                                              */
+#define CHFSI_INVALID_ARG     1  /* bad size, leading dimension, pointer or workspace    */
+#define CHFSI_NOT_HPD         2  /* B (or a Gram matrix) is not Hermitian positive def.  */
+#define CHFSI_NO_CONVERGENCE  3  /* max_iter reached; outputs hold the best so far       */
+#define CHFSI_NONFINITE       4  /* NaN or Inf in an input                               */
+#define CHFSI_DEVICE_ERROR    5  /* a HIP / rocSOLVER call failed                        */
+#define CHFSI_ALLOC_ERROR     6  /* internal host allocation failed                      */
+
+/* Options of the solver.  Field meanings (paper references in brackets):
+ *   tol           residual target: a Ritz pair locks when ||H y - mu y|| <=
+ *                 tol * ||H|| with ||H|| estimated by Lanczos [Sec. 3.1.1,
+ *                 eq. resl; Sec. 4]; default 1e-10.
+ *   deg0          filter degree of the first loop [Alg. 1 input DEG]; 10.
+ *   deg_max       degree cap of the optimisation [Sec. 3.1.1]; 40.
+ *   max_iter      cap on outer loops (the paper has none); 100.
+ *   lanczos_steps steps of the upper-bound estimate [Sec. 3.1]; 20.
+ *   alpha_rule    lower end of the damped interval: 0 = largest Ritz value
+ *                 of the block, 1 = the (nev+1)-th Ritz value [Sec. 3.1].
+ *   degree_mode   0 = per-vector analytic degrees [Sec. 3.1.1], 1 = fixed
+ *                 deg0 for every vector and loop.
+ *   seed          seed of the SplitMix64 counter-based generator used for
+ *                 the Lanczos start vector and a random start block. */
+typedef struct chfsi_opts {
+  double tol;
+  int deg0;
+  int deg_max;
+  int max_iter;
+  int lanczos_steps;
+  int alpha_rule;
+  int degree_mode;
+  unsigned long long seed;
+} chfsi_opts;
+
+/* Per-solve statistics (all optional to read).
+ *   step_seconds: device time per phase, indices
+ *     0 reduction, 1 lanczos, 2 filter, 3 orthonormalisation,
+ *     4 rayleigh-ritz, 5 residuals, 6 locking/permutations, 7 back-transform */
+typedef struct chfsi_info {
+  int iters;               /* outer loops                                        */
+  int converged;           /* locked wanted pairs (== nev on success)            */
+  int filter_launches;     /* filter-step kernel launches                        */
+  int cholqr_shifted;      /* orthonormalisations that needed the shifted pass   */
+  long long matvecs;       /* column mat-vecs with H (filter + RR + Lanczos)     */
+  long long filter_matvecs;/* sum over loops of the degrees of the filtered cols */
+  double filter_flops;     /* 8 n^2 per column mat-vec of the filter             */
+  double filter_seconds;   /* device time of the filter-step launches            */
+  double total_seconds;    /* host wall time of the call                         */
+  double max_resid;        /* max ||H y - lambda y|| / ||H|| over the nev pairs  */
+  double beta;             /* Lanczos upper bound of the spectrum of H           */
+  double norm_h;           /* max(|beta|, |theta_min|), the scale of `tol`       */
+  double step_seconds[8];
+} chfsi_info;
+
+/* Fill *o with the defaults listed above.  Returns CHFSI_OK, or
+ * CHFSI_INVALID_ARG for o == NULL. */
+int chfsi_default_opts(chfsi_opts* o);
+
+/* Bytes of device workspace chfsi_solve needs for this problem
+ * (generalized != 0 when B is given).  opts may be NULL. */
+size_t chfsi_workspace_bytes(int n, int nev, int nex, int generalized, const chfsi_opts* opts);
+
+/* Solve the nev lowest eigenpairs of A x = lambda B x (B == NULL: B = I)
+ * with ChFSI, Alg. 1 of the paper:
+ *   reduction to H = L^{-1} A L^{-H}, B = L L^H [Sec. 3.1], Lanczos bound,
+ *   then loops of {Chebyshev filter (Alg. 2, per-vector degrees, columns
+ *   sorted by degree [Sec. 3.2]), orthonormalisation (CholeskyQR2 against
+ *   the locked vectors), Rayleigh-Ritz, residuals, locking, degree
+ *   optimisation} until nev pairs have converged.
+ * Arguments
+ *   n, nev, nex  problem size, wanted pairs, extra (guard) vectors; the
+ *                block has k = nev + nex columns; 1 <= nev, 1 <= nex,
+ *                k <= n.
+ *   A, lda       device, n x n Hermitian, read-only (only used as given;
+ *                both triangles are read).
+ *   B, ldb       device, n x n Hermitian positive definite, read-only, or
+ *                NULL for a standard problem.
+ *   tol          residual target (overrides opts->tol); > 0.
+ *   X0, ldx0     device, n x k start block (e.g. the previous problem's
+ *                Ritz vectors, in the coordinates of A, B), read-only, or
+ *                NULL for a seeded random block.
+ *   Lambda       HOST, k doubles: all k Ritz values, ascending; the first
+ *                nev are the converged eigenvalues.
+ *   X, ldx       device, n x k output Ritz vectors (X^H B X = I), in the
+ *                order of Lambda.  May alias X0 (same pointer and ld).
+ *   work, work_bytes  device workspace, >= chfsi_workspace_bytes(...).
+ *   opts         NULL for defaults.
+ *   stream       hipStream_t or NULL.
+ *   info         NULL or statistics out.
+ * Returns a status code; on CHFSI_NO_CONVERGENCE Lambda and X hold the
+ * current pairs. */
+int chfsi_solve(int n, int nev, int nex,
+                const void* A, int lda,
+                const void* B, int ldb,
+                double tol,
+                const void* X0, int ldx0,
+                double* Lambda,
+                void* X, int ldx,
+                void* work, size_t work_bytes,
+                const chfsi_opts* opts,
+                void* stream,
+                chfsi_info* info);
+
+/* Static, human-readable text for a status code. */
+const char* chfsi_status_string(int status);
+
+/* ------------------------------------------------------------------------
+ * Step-level entry points (each one row of the hot path), device buffers.
+ * ---------------------------------------------------------------------- */
+
+/* Workspace bytes for the step-level calls below on an n x k block
+ * (covers chfsi_filter, chfsi_orthonormalize, chfsi_rayleigh_ritz,
+ * chfsi_lanczos_bounds, chfsi_zgemm split-K). */
+size_t chfsi_step_workspace_bytes(int n, int k);
+
+/* Chebyshev filter, Alg. 2: Y <- p_{m_j}(Ht) Y_j for every column j, with
+ * Ht = (H - cI)/e, p_m(t) = C_m(t) / C_m((gamma - c)/e) and the scaled
+ * three-term recurrence of eq. (3term).
+ *   H, ldh      device n x n Hermitian, read-only.
+ *   Y, ldy      device n x k, in/out.
+ *   degrees     HOST, k ints >= 1, ascending (columns sorted by degree as in
+ *               Sec. 3.2); CHFSI_INVALID_ARG otherwise.
+ *   c, e, gamma centre and half-width of the damped interval and the
+ *               estimate of lambda_1 (e > 0, gamma != c).
+ *   flops_out   NULL or the algorithmic flops (8 n^2 per column mat-vec).
+ *   launches_out NULL or number of filter-step kernel launches. */
+int chfsi_filter(int n, int k, const void* H, int ldh, void* Y, int ldy,
+                 const int* degrees, double c, double e, double gamma,
+                 void* work, size_t work_bytes, void* stream,
+                 double* flops_out, int* launches_out);
+
+/* Orthonormalise the n x k block Y against the n x nl locked block QL
+ * (two projection passes, QL^H QL = I assumed) and then by CholeskyQR2,
+ * falling back to a shifted CholeskyQR3 when the Gram matrix is not
+ * numerically positive definite.  Implements the QR step of Alg. 1.
+ *   Y, ldy     device, in/out: on return an orthonormal basis of the
+ *              projected span (same column order).
+ *   QL, ldql   device n x nl, read-only (NULL when nl == 0).
+ *   shifted_out NULL or 1 when the shifted pass was used. */
+int chfsi_orthonormalize(int n, int k, void* Y, int ldy, int nl, const void* QL, int ldql,
+                         void* work, size_t work_bytes, void* stream, int* shifted_out);
+
+/* Rayleigh-Ritz (Alg. 1) plus residual norms (eq. resl):
+ *   Z = H Q, G = Q^H Z, G W = W diag(mu) ascending, Q <- Q W, Z <- Z W,
+ *   res_j = ||Z_j - mu_j Q_j||_2.
+ *   Q, ldq   device n x k orthonormal, in/out.
+ *   Z, ldz   device n x k out (H times the new Q).
+ *   mu, res  HOST, k doubles out each. */
+int chfsi_rayleigh_ritz(int n, int k, const void* H, int ldh, void* Q, int ldq,
+                        void* Z, int ldz, double* mu, double* res,
+                        void* work, size_t work_bytes, void* stream);
+
+/* Lanczos estimate of the spectrum of H (Sec. 3.1): `steps` steps with full
+ * reorthogonalisation from the SplitMix64 start vector of `seed` (stream
+ * 0).  Outputs (HOST): upper = theta_max + |b_steps| (the bound used for
+ * beta), theta_min, theta_max. */
+int chfsi_lanczos_bounds(int n, const void* H, int ldh, int steps, unsigned long long seed,
+                         void* work, size_t work_bytes, void* stream,
+                         double* upper, double* theta_min, double* theta_max);
+
+/* Reduction of A x = lambda B x to standard form (Sec. 3.1):
+ * B = L L^H (Cholesky), H = L^{-1} A L^{-H} (Hermitian-symmetrised).
+ *   H, ldh  device n x n out.    L, ldl  device n x n out (lower; the
+ *   strictly upper part is set to zero).  A and B are read-only.
+ * Returns CHFSI_NOT_HPD when the Cholesky factorisation breaks down. */
+size_t chfsi_reduce_workspace_bytes(int n);
+int chfsi_reduce_standard(int n, const void* A, int lda, const void* B, int ldb,
+                          void* H, int ldh, void* L, int ldl,
+                          void* work, size_t work_bytes, void* stream);
+
+/* Per-vector filter degrees of Single Optimization (Sec. 3.1.1), host only:
+ * m_j = ceil(ln(res_j / tol_abs) / ln|rho_j|) clamped to [1, deg_max], with
+ * |rho_j| from t_j = (mu_j - c)/e, c = (alpha+beta)/2, e = (beta-alpha)/2.
+ * Vectors j >= n_wanted (guards) and vectors with |t_j| <= 1 get the largest
+ * degree among the others (deg_max if there is none).
+ *   mu, res  HOST, k doubles.   deg  HOST, k ints out. */
+int chfsi_degrees(int k, const double* mu, const double* res, int n_wanted,
+                  double alpha, double beta, double tol_abs, int deg_max, int* deg);
+
+/* General complex GEMM on the library's MFMA kernels:
+ * C <- alpha op(A) op(B) + beta C with op in {'N', 'C'} (no-op or conjugate
+ * transpose); C is M x N, the inner dimension K.  alpha, beta are complex
+ * (HOST, two doubles each).  Uses split-K (and `work`) when M*N is small
+ * compared with K.  C must not overlap A or B. */
+int chfsi_zgemm(char opa, char opb, int M, int N, int K,
+                const double* alpha, const void* A, int lda, const void* B, int ldb,
+                const double* beta, void* C, int ldc,
+                void* work, size_t work_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHFSI_H */

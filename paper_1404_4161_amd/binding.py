@@ -1,0 +1,289 @@
+"""Thin ctypes binding of libchfsi.so (include/chfsi.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+Matrices are torch complex128 tensors on the GPU in COLUMN-MAJOR layout
+(stride(0) == 1); ``colmajor(t)`` makes such a copy.  Workspaces are
+allocated with torch when not given.  The functions carry the C names.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from ctypes import (POINTER, Structure, c_char, c_double, c_int, c_longlong, c_size_t,
+                    c_ulonglong, c_void_p)
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libchfsi.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "chfsi.h")
+
+CHFSI_OK, CHFSI_INVALID_ARG, CHFSI_NOT_HPD, CHFSI_NO_CONVERGENCE = 0, 1, 2, 3
+CHFSI_NONFINITE, CHFSI_DEVICE_ERROR, CHFSI_ALLOC_ERROR = 4, 5, 6
+
+
+class ChfsiOpts(Structure):
+    _fields_ = [("tol", c_double), ("deg0", c_int), ("deg_max", c_int), ("max_iter", c_int),
+                ("lanczos_steps", c_int), ("alpha_rule", c_int), ("degree_mode", c_int),
+                ("seed", c_ulonglong)]
+
+
+class ChfsiInfo(Structure):
+    _fields_ = [("iters", c_int), ("converged", c_int), ("filter_launches", c_int),
+                ("cholqr_shifted", c_int), ("matvecs", c_longlong),
+                ("filter_matvecs", c_longlong), ("filter_flops", c_double),
+                ("filter_seconds", c_double), ("total_seconds", c_double),
+                ("max_resid", c_double), ("beta", c_double), ("norm_h", c_double),
+                ("step_seconds", c_double * 8)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "step_seconds"}
+        d["step_seconds"] = list(self.step_seconds)
+        return d
+
+
+_SIGS = {
+    "chfsi_default_opts": (c_int, [POINTER(ChfsiOpts)]),
+    "chfsi_workspace_bytes": (c_size_t, [c_int, c_int, c_int, c_int, POINTER(ChfsiOpts)]),
+    "chfsi_solve": (c_int, [c_int, c_int, c_int, c_void_p, c_int, c_void_p, c_int, c_double,
+                            c_void_p, c_int, POINTER(c_double), c_void_p, c_int, c_void_p,
+                            c_size_t, POINTER(ChfsiOpts), c_void_p, POINTER(ChfsiInfo)]),
+    "chfsi_status_string": (ctypes.c_char_p, [c_int]),
+    "chfsi_step_workspace_bytes": (c_size_t, [c_int, c_int]),
+    "chfsi_filter": (c_int, [c_int, c_int, c_void_p, c_int, c_void_p, c_int, POINTER(c_int),
+                             c_double, c_double, c_double, c_void_p, c_size_t, c_void_p,
+                             POINTER(c_double), POINTER(c_int)]),
+    "chfsi_orthonormalize": (c_int, [c_int, c_int, c_void_p, c_int, c_int, c_void_p, c_int,
+                                     c_void_p, c_size_t, c_void_p, POINTER(c_int)]),
+    "chfsi_rayleigh_ritz": (c_int, [c_int, c_int, c_void_p, c_int, c_void_p, c_int, c_void_p,
+                                    c_int, POINTER(c_double), POINTER(c_double), c_void_p,
+                                    c_size_t, c_void_p]),
+    "chfsi_lanczos_bounds": (c_int, [c_int, c_void_p, c_int, c_int, c_ulonglong, c_void_p,
+                                     c_size_t, c_void_p, POINTER(c_double), POINTER(c_double),
+                                     POINTER(c_double)]),
+    "chfsi_reduce_workspace_bytes": (c_size_t, [c_int]),
+    "chfsi_reduce_standard": (c_int, [c_int, c_void_p, c_int, c_void_p, c_int, c_void_p, c_int,
+                                      c_void_p, c_int, c_void_p, c_size_t, c_void_p]),
+    "chfsi_degrees": (c_int, [c_int, POINTER(c_double), POINTER(c_double), c_int, c_double,
+                              c_double, c_double, c_int, POINTER(c_int)]),
+    "chfsi_zgemm": (c_int, [c_char, c_char, c_int, c_int, c_int, POINTER(c_double), c_void_p,
+                            c_int, c_void_p, c_int, POINTER(c_double), c_void_p, c_int, c_void_p,
+                            c_size_t, c_void_p]),
+}
+
+_lib = None
+
+
+class ChfsiError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__(f"{where}: status {status} ({chfsi_status_string(status)})")
+        self.status = status
+
+
+def lib():
+    """Load libchfsi.so (fails loudly when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1404_4161_amd.build`")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(l, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = l
+    return _lib
+
+
+def header_functions():
+    """Names of the functions include/chfsi.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(chfsi_[a-z_0-9]+)\s*\(", text)))
+
+
+# ---------------------------------------------------------------------------
+# torch helpers
+
+def _torch():
+    import torch
+    return torch
+
+
+def colmajor(t):
+    """Column-major copy (stride(0) == 1) of a 2-D tensor."""
+    return t.transpose(0, 1).contiguous().transpose(0, 1)
+
+
+def _ld(t):
+    if t.dim() == 2 and t.numel() == 0:
+        return max(t.shape[0], 1)
+    if t.dim() != 2 or (t.stride(0) != 1 and t.shape[0] > 1):
+        raise ValueError("expected a column-major 2-D tensor (stride(0) == 1)")
+    return max(t.stride(1), t.shape[0], 1)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream, device):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _work(nbytes, device, work=None):
+    torch = _torch()
+    if work is not None:
+        if work.numel() * work.element_size() < nbytes:
+            raise ValueError("workspace too small")
+        return work
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _check(status, where):
+    if status != CHFSI_OK:
+        raise ChfsiError(status, where)
+
+
+# ---------------------------------------------------------------------------
+# C ABI wrappers (same names)
+
+def chfsi_default_opts():
+    o = ChfsiOpts()
+    _check(lib().chfsi_default_opts(ctypes.byref(o)), "chfsi_default_opts")
+    return o
+
+
+def chfsi_status_string(status):
+    return lib().chfsi_status_string(int(status)).decode()
+
+
+def chfsi_workspace_bytes(n, nev, nex, generalized, opts=None):
+    return int(lib().chfsi_workspace_bytes(n, nev, nex, int(bool(generalized)),
+                                           ctypes.byref(opts) if opts is not None else None))
+
+
+def chfsi_solve(A, B, nev, nex, tol, X0=None, opts=None, X=None, work=None, stream=None,
+                raise_on_error=True):
+    """Solve A x = lambda B x (B None: standard).  Returns
+    (status, Lambda[k] numpy, X (n x k column-major tensor), info dict)."""
+    torch = _torch()
+    n = A.shape[0]
+    k = nev + nex
+    dev = A.device
+    if X is None:
+        X = colmajor(torch.empty((n, k), dtype=torch.complex128, device=dev))
+    o = opts if opts is not None else chfsi_default_opts()
+    wb = chfsi_workspace_bytes(n, nev, nex, B is not None, o)
+    w = _work(wb, dev, work)
+    lam = (c_double * k)()
+    info = ChfsiInfo()
+    st = lib().chfsi_solve(n, nev, nex, _ptr(A), _ld(A), _ptr(B), _ld(B) if B is not None else 0,
+                           float(tol), _ptr(X0), _ld(X0) if X0 is not None else 0, lam, _ptr(X),
+                           _ld(X), _ptr(w), wb, ctypes.byref(o), _stream(stream, dev),
+                           ctypes.byref(info))
+    if raise_on_error and st not in (CHFSI_OK, CHFSI_NO_CONVERGENCE):
+        raise ChfsiError(st, "chfsi_solve")
+    return st, np.array(lam[:]), X, info.as_dict()
+
+
+def chfsi_step_workspace_bytes(n, k):
+    return int(lib().chfsi_step_workspace_bytes(n, k))
+
+
+def chfsi_filter(H, Y, degrees, c, e, gamma, work=None, stream=None):
+    """Alg. 2 in place on Y; returns (flops, launches)."""
+    n, k = Y.shape
+    deg = (c_int * k)(*[int(x) for x in degrees])
+    wb = chfsi_step_workspace_bytes(n, k)
+    w = _work(wb, Y.device, work)
+    fl = c_double(0.0)
+    ln = c_int(0)
+    _check(lib().chfsi_filter(n, k, _ptr(H), _ld(H), _ptr(Y), _ld(Y), deg, c, e, gamma, _ptr(w),
+                              wb, _stream(stream, Y.device), ctypes.byref(fl), ctypes.byref(ln)),
+           "chfsi_filter")
+    return fl.value, ln.value
+
+
+def chfsi_orthonormalize(Y, QL=None, work=None, stream=None):
+    n, k = Y.shape
+    nl = 0 if QL is None else QL.shape[1]
+    wb = chfsi_step_workspace_bytes(n, max(k, nl))
+    w = _work(wb, Y.device, work)
+    sh = c_int(0)
+    _check(lib().chfsi_orthonormalize(n, k, _ptr(Y), _ld(Y), nl, _ptr(QL),
+                                      _ld(QL) if QL is not None else n, _ptr(w), wb,
+                                      _stream(stream, Y.device), ctypes.byref(sh)),
+           "chfsi_orthonormalize")
+    return sh.value
+
+
+def chfsi_rayleigh_ritz(H, Q, Z, work=None, stream=None):
+    n, k = Q.shape
+    mu = (c_double * k)()
+    res = (c_double * k)()
+    wb = chfsi_step_workspace_bytes(n, k)
+    w = _work(wb, Q.device, work)
+    _check(lib().chfsi_rayleigh_ritz(n, k, _ptr(H), _ld(H), _ptr(Q), _ld(Q), _ptr(Z), _ld(Z), mu,
+                                     res, _ptr(w), wb, _stream(stream, Q.device)),
+           "chfsi_rayleigh_ritz")
+    return np.array(mu[:]), np.array(res[:])
+
+
+def chfsi_lanczos_bounds(H, steps=20, seed=0, work=None, stream=None):
+    n = H.shape[0]
+    wb = chfsi_step_workspace_bytes(n, 1)
+    w = _work(wb, H.device, work)
+    up, lo, hi = c_double(), c_double(), c_double()
+    _check(lib().chfsi_lanczos_bounds(n, _ptr(H), _ld(H), steps, seed, _ptr(w), wb,
+                                      _stream(stream, H.device), ctypes.byref(up),
+                                      ctypes.byref(lo), ctypes.byref(hi)),
+           "chfsi_lanczos_bounds")
+    return up.value, lo.value, hi.value
+
+
+def chfsi_reduce_workspace_bytes(n):
+    return int(lib().chfsi_reduce_workspace_bytes(n))
+
+
+def chfsi_reduce_standard(A, B, H=None, L=None, work=None, stream=None):
+    torch = _torch()
+    n = A.shape[0]
+    if H is None:
+        H = colmajor(torch.empty((n, n), dtype=torch.complex128, device=A.device))
+    if L is None:
+        L = colmajor(torch.empty((n, n), dtype=torch.complex128, device=A.device))
+    wb = chfsi_reduce_workspace_bytes(n)
+    w = _work(wb, A.device, work)
+    _check(lib().chfsi_reduce_standard(n, _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(H), _ld(H),
+                                       _ptr(L), _ld(L), _ptr(w), wb, _stream(stream, A.device)),
+           "chfsi_reduce_standard")
+    return H, L
+
+
+def chfsi_degrees(mu, res, n_wanted, alpha, beta, tol_abs, deg_max=40):
+    k = len(mu)
+    m = (c_double * k)(*[float(x) for x in mu])
+    r = (c_double * k)(*[float(x) for x in res])
+    d = (c_int * k)()
+    _check(lib().chfsi_degrees(k, m, r, int(n_wanted), float(alpha), float(beta), float(tol_abs),
+                               int(deg_max), d), "chfsi_degrees")
+    return np.array(d[:], dtype=np.int64)
+
+
+def chfsi_zgemm(opa, opb, alpha, A, B, beta, C, work=None, stream=None):
+    M, N = C.shape
+    K = A.shape[1] if opa in "Nn" else A.shape[0]
+    al = (c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (c_double * 2)(complex(beta).real, complex(beta).imag)
+    wb = 16 * max(M * N * 64, 1)
+    w = _work(wb, C.device, work)
+    _check(lib().chfsi_zgemm(opa.encode(), opb.encode(), M, N, K, al, _ptr(A), _ld(A), _ptr(B),
+                             _ld(B), be, _ptr(C), _ld(C), _ptr(w), wb, _stream(stream, C.device)),
+           "chfsi_zgemm")
+    return C

@@ -1,0 +1,1013 @@
+// Host driver of the ChFSI library: the outer loop of Alg. 1 (Lanczos
+// bound, filter, orthonormalisation, Rayleigh-Ritz, residuals, locking,
+// degree optimisation) over the device kernels of zgemm.hip and blas1.hip,
+// and the C ABI declared in include/chfsi.h.
+#include "chfsi.h"
+#include "internal.h"
+
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <vector>
+
+namespace chfsi {
+namespace {
+
+constexpr int NB = 64;          // Cholesky / triangular-solve block size
+constexpr size_t ALIGN = 256;
+// A Gram-matrix pivot below this fraction of its (unit) diagonal entry is a
+// CholeskyQR breakdown: kappa(Y) near 1e6 or worse.
+constexpr double GRAM_PIVOT_TOL = 1e-12;
+
+const zc ONE = {1.0, 0.0}, ZERO = {0.0, 0.0}, MONE = {-1.0, 0.0};
+
+
+#define CK(expr)                                  \
+  do {                                            \
+    int _e = (int)(expr);                         \
+    if (_e != 0) return CHFSI_DEVICE_ERROR;       \
+  } while (0)
+
+#define CKS(expr)                                 \
+  do {                                            \
+    int _s = (expr);                              \
+    if (_s != CHFSI_OK) return _s;                \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// workspace carving
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + ALIGN - 1) / ALIGN * ALIGN;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+size_t splitk_elems(int n, int nev, int k) {
+  size_t s = 0;
+  s = std::max(s, zgemm_work_elems(k, k, n));
+  // the lower-only Gram has fewer tiles and may use more splits: bound it
+  const int tm = (k + NB - 1) / NB;
+  const int lower = tm * (tm + 1) / 2;
+  if (lower < 512 && n >= 1024) {
+    int want = (1024 + lower - 1) / lower;
+    int maxs = n / 256;
+    int sp = std::min(want, maxs);
+    s = std::max(s, (size_t)std::max(sp, 1) * (size_t)k * (size_t)k);
+  }
+  s = std::max(s, zgemm_work_elems(nev, k, n));
+  return s;
+}
+
+int gemv_splits(int n) {
+  const int rowblocks = (n + 255) / 256;
+  int sp = 1024 / std::max(rowblocks, 1);
+  sp = std::max(1, std::min(sp, std::max(1, n / 128)));
+  return sp;
+}
+
+// Device buffers of the step-level routines on an n x k block.
+struct StepBufs {
+  zc *T1, *T2, *G, *K2, *invk, *scratch, *gv_part, *V, *w, *h;
+  double *mu, *res, *nrm, *E, *alph, *bet, *dummy;
+  int *perm, *deg, *info;
+  size_t scratch_elems;
+  int lanczos_cap;
+};
+
+void carve_step(Carver& c, StepBufs& b, int n, int k, int nev, int lanczos_steps) {
+  const size_t nk = (size_t)n * k;
+  b.T1 = c.take<zc>(nk);
+  b.T2 = c.take<zc>(nk);
+  b.G = c.take<zc>((size_t)k * k);
+  b.K2 = c.take<zc>((size_t)k * k);
+  b.invk = c.take<zc>((size_t)((k + NB - 1) / NB) * NB * NB);
+  b.scratch_elems = splitk_elems(n, nev, k);
+  b.scratch = c.take<zc>(std::max<size_t>(b.scratch_elems, 1));
+  b.gv_part = c.take<zc>((size_t)n * gemv_splits(n));
+  b.lanczos_cap = std::max(1, std::min(lanczos_steps, n));
+  b.V = c.take<zc>((size_t)n * (b.lanczos_cap + 1));
+  b.w = c.take<zc>(n);
+  b.h = c.take<zc>(b.lanczos_cap + 1);
+  b.mu = c.take<double>(k);
+  b.res = c.take<double>(k);
+  b.nrm = c.take<double>(k);
+  b.E = c.take<double>(k);
+  b.alph = c.take<double>(b.lanczos_cap + 1);
+  b.bet = c.take<double>(b.lanczos_cap + 1);
+  b.dummy = c.take<double>(8);
+  b.perm = c.take<int>(k);
+  b.deg = c.take<int>(k);
+  b.info = c.take<int>(8);
+}
+
+// ---------------------------------------------------------------------------
+// rocSOLVER handle (one per device), used only for the reduced k x k
+// Hermitian eigenproblem of Rayleigh-Ritz.
+
+std::mutex g_handle_mu;
+rocblas_handle g_handles[64] = {};
+
+int get_handle(rocblas_handle* h) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return CHFSI_DEVICE_ERROR;
+  if (!g_handles[dev]) {
+    if (rocblas_create_handle(&g_handles[dev]) != rocblas_status_success) return CHFSI_DEVICE_ERROR;
+  }
+  *h = g_handles[dev];
+  return CHFSI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// event timers per phase
+
+struct Timers {
+  hipStream_t s;
+  double* acc;                 // may be null
+  struct Pending { int phase; hipEvent_t a, b; };
+  std::vector<Pending> pend;
+  std::vector<hipEvent_t> pool;
+  int open_phase = -1;
+  hipEvent_t open_ev = nullptr;
+
+  Timers(hipStream_t st, double* a) : s(st), acc(a) {}
+  ~Timers() {
+    for (auto& p : pend) { pool.push_back(p.a); pool.push_back(p.b); }
+    if (open_ev) pool.push_back(open_ev);
+    for (auto e : pool) hipEventDestroy(e);
+  }
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void begin(int phase) {
+    if (!acc) return;
+    open_ev = get();
+    open_phase = phase;
+    if (open_ev) hipEventRecord(open_ev, s);
+  }
+  void end() {
+    if (!acc || !open_ev) return;
+    hipEvent_t e = get();
+    if (e) {
+      hipEventRecord(e, s);
+      pend.push_back({open_phase, open_ev, e});
+    } else {
+      pool.push_back(open_ev);
+    }
+    open_ev = nullptr;
+  }
+  // call after the stream has been synchronised
+  void drain() {
+    for (auto& p : pend) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) acc[p.phase] += 1e-3 * ms;
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pend.clear();
+  }
+};
+
+// ---------------------------------------------------------------------------
+// host helpers
+
+// Number of eigenvalues of the symmetric tridiagonal (a, b) below x (Sturm).
+int sturm_count(const std::vector<double>& a, const std::vector<double>& b, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  const int m = (int)a.size();
+  for (int i = 0; i < m; ++i) {
+    const double bb = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+    q = (a[i] - x) - (i > 0 ? bb / q : 0.0);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// Smallest and largest eigenvalue of a symmetric tridiagonal by bisection.
+void tridiag_extremes(const std::vector<double>& a, const std::vector<double>& b, double* lo,
+                      double* hi) {
+  const int m = (int)a.size();
+  double gl = 1e300, gu = -1e300;
+  for (int i = 0; i < m; ++i) {
+    double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < m - 1 ? std::fabs(b[i]) : 0.0);
+    gl = std::min(gl, a[i] - r);
+    gu = std::max(gu, a[i] + r);
+  }
+  auto kth = [&](int k) {   // k-th smallest, 0-based
+    double l = gl, u = gu;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (l + u);
+      if (mid == l || mid == u) break;
+      if (sturm_count(a, b, mid) > k) u = mid; else l = mid;
+    }
+    return 0.5 * (l + u);
+  };
+  *lo = kth(0);
+  *hi = kth(m - 1);
+}
+
+// ---------------------------------------------------------------------------
+// device building blocks
+
+// Blocked right-looking Cholesky of the Hermitian n x n matrix G (lower).
+// invd receives the inverses of the diagonal NB-blocks (NB x NB each).
+int potrf_blocked(hipStream_t s, int n, zc* G, long ldg, zc* invd, int* info, double rel_tol) {
+  for (int jb = 0; jb < n; jb += NB) {
+    const int nb = std::min(NB, n - jb);
+    zc* inv = invd + (size_t)(jb / NB) * NB * NB;
+    CK(potrf_leaf(s, nb, G + jb + (long)jb * ldg, ldg, inv, info, jb, rel_tol));
+    const int m2 = n - jb - nb;
+    if (m2 > 0) {
+      zc* a21 = G + (jb + nb) + (long)jb * ldg;
+      // L21 = A21 inv(L11)^H  (in place: each tile owns whole rows of A21)
+      CK(zgemm(s, OP_N, OP_C, m2, nb, nb, ONE, a21, ldg, inv, nb, ZERO, a21, ldg, false, nullptr, 0));
+      // A22 -= L21 L21^H (lower triangle)
+      zc* a22 = G + (jb + nb) + (long)(jb + nb) * ldg;
+      CK(zgemm(s, OP_N, OP_C, m2, m2, nb, MONE, a21, ldg, a21, ldg, ONE, a22, ldg, true, nullptr, 0));
+    }
+  }
+  return CHFSI_OK;
+}
+
+// X <- L^{-1} X for lower-triangular L (n x n) with inverted diagonal blocks.
+int trsm_left_lower(hipStream_t s, int n, int m, const zc* L, long ldl, const zc* invd, zc* X,
+                    long ldx) {
+  for (int jb = 0; jb < n; jb += NB) {
+    const int nb = std::min(NB, n - jb);
+    const zc* inv = invd + (size_t)(jb / NB) * NB * NB;
+    // X_j = inv(L_jj) X_j  (in place: one tile row covers the whole block row)
+    CK(zgemm(s, OP_N, OP_N, nb, m, nb, ONE, inv, nb, X + jb, ldx, ZERO, X + jb, ldx, false, nullptr, 0));
+    const int m2 = n - jb - nb;
+    if (m2 > 0) {
+      CK(zgemm(s, OP_N, OP_N, m2, m, nb, MONE, L + (jb + nb) + (long)jb * ldl, ldl, X + jb, ldx,
+               ONE, X + jb + nb, ldx, false, nullptr, 0));
+    }
+  }
+  return CHFSI_OK;
+}
+
+// X <- L^{-H} X (backward substitution with the upper factor L^H).
+int trsm_left_lower_h(hipStream_t s, int n, int m, const zc* L, long ldl, const zc* invd, zc* X,
+                      long ldx) {
+  const int nblk = (n + NB - 1) / NB;
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    const int jb = bi * NB;
+    const int nb = std::min(NB, n - jb);
+    const zc* inv = invd + (size_t)bi * NB * NB;
+    CK(zgemm(s, OP_C, OP_N, nb, m, nb, ONE, inv, nb, X + jb, ldx, ZERO, X + jb, ldx, false, nullptr, 0));
+    if (jb > 0) {
+      // X[0:jb] -= (L[jb:jb+nb, 0:jb])^H X_j
+      CK(zgemm(s, OP_C, OP_N, jb, m, nb, MONE, L + jb, ldl, X + jb, ldx, ONE, X, ldx, false,
+               nullptr, 0));
+    }
+  }
+  return CHFSI_OK;
+}
+
+int read_info(hipStream_t s, const int* info_dev, int* out) {
+  CK(hipMemcpyAsync(out, info_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  return CHFSI_OK;
+}
+
+// One CholeskyQR pass: Yout = Yin R^{-1} with Yin^H Yin = R^H R, after
+// normalising the columns of Yin (in place).  shift > 0 adds shift*I to the
+// Gram matrix.  Returns CHFSI_NOT_HPD on a failed factorisation.
+int cholqr_pass(hipStream_t s, int n, int k, zc* Yin, long ldy, zc* Yout, long ldo, StepBufs& b,
+                double shift) {
+  CK(col_norms(s, n, k, Yin, ldy, b.nrm));
+  CK(scale_cols_inv(s, n, k, Yin, ldy, b.nrm));
+  CK(zgemm(s, OP_C, OP_N, k, k, n, ONE, Yin, ldy, Yin, ldy, ZERO, b.G, k, true, b.scratch,
+           b.scratch_elems));
+  CK(herm_from_lower(s, k, b.G, k));
+  if (shift > 0.0) CK(add_diag(s, k, b.G, k, shift));
+  CK(hipMemsetAsync(b.info, 0, sizeof(int), s));
+  zc* invd = b.invk;
+  CKS(potrf_blocked(s, k, b.G, k, invd, b.info, GRAM_PIVOT_TOL));
+  int info = 0;
+  CKS(read_info(s, b.info, &info));
+  if (info != 0) return CHFSI_NOT_HPD;
+  CK(set_identity(s, k, b.K2, k));
+  CKS(trsm_left_lower(s, k, k, b.G, k, invd, b.K2, k));   // K2 = L^{-1}
+  // Yout = Yin L^{-H}
+  CK(zgemm(s, OP_N, OP_C, n, k, k, ONE, Yin, ldy, b.K2, k, ZERO, Yout, ldo, false, nullptr, 0));
+  return CHFSI_OK;
+}
+
+// Orthonormalise Y (n x k) against QL (n x nl) and by CholeskyQR2; result
+// in Qout (may equal Y).  Uses b.T1 as the intermediate basis.
+int orthonormalize_dev(hipStream_t s, int n, int k, zc* Y, long ldy, int nl, const zc* QL,
+                       long ldql, zc* Qout, long ldq, StepBufs& b, int* shifted) {
+  if (k <= 0) return CHFSI_OK;
+  if (nl > 0) {
+    for (int pass = 0; pass < 2; ++pass) {
+      // C = QL^H Y (nl x k, ld nl) in T2 (n x k elements, nl < n)
+      zc* C = b.T2;
+      CK(zgemm(s, OP_C, OP_N, nl, k, n, ONE, QL, ldql, Y, ldy, ZERO, C, nl, false, b.scratch,
+               b.scratch_elems));
+      CK(zgemm(s, OP_N, OP_N, n, k, nl, MONE, QL, ldql, C, nl, ONE, Y, ldy, false, nullptr, 0));
+    }
+  }
+  zc* Q1 = b.T1;
+  int st = cholqr_pass(s, n, k, Y, ldy, Q1, n, b, 0.0);
+  if (st == CHFSI_OK) st = cholqr_pass(s, n, k, Q1, n, Qout, ldq, b, 0.0);
+  if (st != CHFSI_NOT_HPD) return st;
+  // Breakdown: shifted CholeskyQR3 (Fukaya et al., SISC 2020).  The shift is
+  // 11 (n k + k (k + 1)) u ||Y||_2^2 with ||Y||_2^2 <= ||Y||_F^2 = k after
+  // column normalisation.  An exactly rank-deficient block first gets a
+  // relative 1e-10 random perturbation (counter-based generator, stream 2).
+  const double u = std::ldexp(1.0, -53);
+  const double sh = 11.0 * ((double)n * k + (double)k * (k + 1)) * u * (double)k;
+  if (shifted) *shifted = 1;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if (attempt == 1) {
+      CK(col_norms(s, n, k, Y, ldy, b.nrm));
+      CK(scale_cols_inv(s, n, k, Y, ldy, b.nrm));
+      CK(add_random(s, n, k, Y, ldy, 0x5eedull, 2, 1e-10));
+    }
+    st = cholqr_pass(s, n, k, Y, ldy, Q1, n, b, sh);
+    if (st == CHFSI_OK) st = cholqr_pass(s, n, k, Q1, n, Y, ldy, b, 0.0);
+    if (st == CHFSI_OK) st = cholqr_pass(s, n, k, Y, ldy, Q1, n, b, 0.0);
+    if (st == CHFSI_OK) {
+      CK(copy2d(s, n, k, Q1, n, Qout, ldq));
+      return CHFSI_OK;
+    }
+    if (st != CHFSI_NOT_HPD) return st;
+  }
+  return CHFSI_NOT_HPD;
+}
+
+// Rayleigh-Ritz on the orthonormal block Q (n x k):
+// Z = H Q, G = Q^H Z, G W = W diag(mu), Qout = Q W, Zout = Z W,
+// res_j = ||Zout_j - mu_j Qout_j||.  mu_h/res_h are host outputs.  Qout and
+// Zout must not overlap Q or Z.
+int rayleigh_ritz_dev(hipStream_t s, int n, int k, const zc* H, long ldh, const zc* Q, long ldq,
+                      zc* Z, long ldz, zc* Qout, long ldqo, zc* Zout, long ldzo, StepBufs& b,
+                      double* mu_h, double* res_h) {
+  CK(zgemm(s, OP_N, OP_N, n, k, n, ONE, H, ldh, Q, ldq, ZERO, Z, ldz, false, nullptr, 0));
+  CK(zgemm(s, OP_C, OP_N, k, k, n, ONE, Q, ldq, Z, ldz, ZERO, b.G, k, true, b.scratch,
+           b.scratch_elems));
+  CK(herm_from_lower(s, k, b.G, k));
+  {
+    std::lock_guard<std::mutex> lk(g_handle_mu);
+    rocblas_handle h;
+    CKS(get_handle(&h));
+    if (rocblas_set_stream(h, s) != rocblas_status_success) return CHFSI_DEVICE_ERROR;
+    if (rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_lower, k,
+                         (rocblas_double_complex*)b.G, k, b.mu, b.E, b.info) !=
+        rocblas_status_success)
+      return CHFSI_DEVICE_ERROR;
+  }
+  CK(zgemm(s, OP_N, OP_N, n, k, k, ONE, Q, ldq, b.G, k, ZERO, Qout, ldqo, false, nullptr, 0));
+  CK(zgemm(s, OP_N, OP_N, n, k, k, ONE, Z, ldz, b.G, k, ZERO, Zout, ldzo, false, nullptr, 0));
+  CK(resid_norms(s, n, k, Qout, ldqo, Zout, ldzo, b.mu, b.res));
+  int info = 0;
+  CK(hipMemcpyAsync(mu_h, b.mu, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  CK(hipMemcpyAsync(res_h, b.res, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  CK(hipMemcpyAsync(&info, b.info, sizeof(int), hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  if (info != 0) return CHFSI_DEVICE_ERROR;
+  return CHFSI_OK;
+}
+
+// Lanczos with full reorthogonalisation; returns bounds on the host.
+int lanczos_dev(hipStream_t s, int n, const zc* H, long ldh, int steps, unsigned long long seed,
+                StepBufs& b, double* upper, double* tmin, double* tmax) {
+  const int m = std::max(1, std::min(steps, std::min(n, b.lanczos_cap)));
+  const int gs = gemv_splits(n);
+  CK(fill_counter_random(s, n, 1, b.V, n, seed, 0));
+  CK(normalize_into(s, n, b.V, b.V, b.dummy));
+  for (int j = 0; j < m; ++j) {
+    const zc* vj = b.V + (size_t)j * n;
+    CK(gemv_n(s, n, H, ldh, vj, b.w, b.gv_part, gs));
+    CK(dots_c(s, n, j + 1, b.V, n, b.w, b.h));
+    CK(lanczos_axpy(s, n, j, b.V, n, b.h, b.bet, b.w, b.alph));
+    for (int pass = 0; pass < 2; ++pass) {
+      CK(dots_c(s, n, j + 1, b.V, n, b.w, b.h));
+      CK(sub_vh(s, n, j + 1, b.V, n, b.h, b.w));
+    }
+    CK(normalize_into(s, n, b.w, b.V + (size_t)(j + 1) * n, b.bet + j));
+  }
+  std::vector<double> a(m), bb(m);
+  CK(hipMemcpyAsync(a.data(), b.alph, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+  CK(hipMemcpyAsync(bb.data(), b.bet, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  // an invariant subspace ends the recurrence early
+  double amax = 0.0;
+  for (int j = 0; j < m; ++j) amax = std::max(amax, std::fabs(a[j]));
+  int meff = m;
+  for (int j = 0; j < m - 1; ++j) {
+    if (bb[j] <= 1e-14 * std::max(amax, 1e-300)) { meff = j + 1; break; }
+  }
+  std::vector<double> aa(a.begin(), a.begin() + meff), be(bb.begin(), bb.begin() + meff);
+  double lo, hi;
+  tridiag_extremes(aa, be, &lo, &hi);
+  *tmin = lo;
+  *tmax = hi;
+  *upper = hi + std::fabs(bb[meff - 1]);
+  return CHFSI_OK;
+}
+
+// Alg. 2 on device.  P0 holds Y_0 (n x k, columns sorted by ascending
+// degree m); on return column j of P[m_j mod 2] holds Y_{m_j}.
+int filter_dev(hipStream_t s, int n, int k, const zc* H, long ldh, zc* P0, zc* P1, long ld,
+               const std::vector<int>& m, double c, double e, double gamma, double* flops,
+               int* launches) {
+  if (k <= 0) return CHFSI_OK;
+  const double sig1 = e / (gamma - c);
+  const double nn = (double)n * (double)n;
+  // Y_1 = (sigma_1 / e)(H Y_0 - c Y_0)
+  CK(cheb_step(s, n, k, H, ldh, P0, ld, nullptr, ld, P1, ld, c, sig1 / e, 0.0));
+  *flops += 8.0 * nn * k;
+  *launches += 1;
+  double sig = sig1;
+  int first = 0;
+  while (first < k && m[first] <= 1) ++first;
+  const int mmax = m[k - 1];
+  for (int i = 1; i < mmax; ++i) {
+    const double sn = 1.0 / (2.0 / sig1 - sig);
+    zc* cur = (i & 1) ? P1 : P0;
+    zc* old = (i & 1) ? P0 : P1;
+    const int cols = k - first;
+    CK(cheb_step(s, n, cols, H, ldh, cur + (size_t)first * ld, ld, old + (size_t)first * ld, ld,
+                 old + (size_t)first * ld, ld, c, 2.0 * sn / e, sn * sig));
+    *flops += 8.0 * nn * cols;
+    *launches += 1;
+    sig = sn;
+    while (first < k && m[first] <= i + 1) ++first;
+  }
+  return CHFSI_OK;
+}
+
+int upload_ints(hipStream_t s, int* dst, const std::vector<int>& v) {
+  if (v.empty()) return CHFSI_OK;
+  CK(hipMemcpyAsync(dst, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, s));
+  CK(hipStreamSynchronize(s));
+  return CHFSI_OK;
+}
+
+double elapsed(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+}  // namespace
+
+// ===========================================================================
+// ChFSI solve
+
+namespace {
+
+struct SolveBufs {
+  zc *H = nullptr, *L = nullptr, *Wr = nullptr, *invd = nullptr;
+  zc *QL, *QA, *ZA, *P0, *P1, *TMP;
+  int* flag;
+  StepBufs st;
+};
+
+size_t carve_solve(Carver& c, SolveBufs& b, int n, int nev, int nex, bool gen, int lsteps) {
+  const int k = nev + nex;
+  const size_t nn = (size_t)n * n, nk = (size_t)n * k;
+  if (gen) {
+    b.H = c.take<zc>(nn);
+    b.L = c.take<zc>(nn);
+    b.Wr = c.take<zc>(nn);
+    b.invd = c.take<zc>((size_t)((n + NB - 1) / NB) * NB * NB);
+  }
+  b.QL = c.take<zc>((size_t)n * nev);
+  b.QA = c.take<zc>(nk);
+  b.ZA = c.take<zc>(nk);
+  b.P0 = c.take<zc>(nk);
+  b.P1 = c.take<zc>(nk);
+  b.TMP = c.take<zc>(nk);
+  b.flag = c.take<int>(8);
+  carve_step(c, b.st, n, k, nev, lsteps);
+  return c.off + ALIGN;
+}
+
+int degrees_host(int k, const double* mu, const double* res, int n_wanted, double alpha,
+                 double beta, double tol_abs, int deg_max, int* deg) {
+  const double c = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
+  std::vector<char> def(k, 0);
+  int fill = 0;
+  bool any = false;
+  for (int j = 0; j < std::min(n_wanted, k); ++j) {
+    const double t = (mu[j] - c) / e;
+    if (std::fabs(t) <= 1.0) continue;
+    const double r = std::sqrt(t * t - 1.0);
+    const double rho = std::max(std::fabs(t + r), std::fabs(t - r));
+    const double ratio = std::max(res[j] / tol_abs, 1.0);
+    int m = (int)std::ceil(std::log(ratio) / std::log(rho));
+    m = std::min(std::max(m, 1), deg_max);
+    deg[j] = m;
+    def[j] = 1;
+    fill = any ? std::max(fill, m) : m;
+    any = true;
+  }
+  if (!any) fill = deg_max;
+  for (int j = 0; j < k; ++j)
+    if (!def[j]) deg[j] = fill;
+  return CHFSI_OK;
+}
+
+int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int ldb, double tol,
+               const zc* X0, int ldx0, double* Lambda, zc* X, int ldx, void* work,
+               size_t work_bytes, const chfsi_opts& o, hipStream_t s, chfsi_info* info) {
+  const auto t_start = std::chrono::steady_clock::now();
+  const int k = nev + nex;
+  const bool gen = B != nullptr;
+  SolveBufs b;
+  Carver cv(work);
+  const size_t need = carve_solve(cv, b, n, nev, nex, gen, o.lanczos_steps);
+  if (work_bytes < need) return CHFSI_INVALID_ARG;
+  StepBufs& sb = b.st;
+  double* step_acc = info ? info->step_seconds : nullptr;
+  Timers tm(s, step_acc);
+  const long ld = n;
+
+  // non-finite inputs
+  CK(hipMemsetAsync(b.flag, 0, sizeof(int), s));
+  CK(check_finite(s, n, n, A, lda, b.flag));
+  if (gen) CK(check_finite(s, n, n, B, ldb, b.flag));
+  if (X0) CK(check_finite(s, n, k, X0, ldx0, b.flag));
+  int flag = 0;
+  CKS(read_info(s, b.flag, &flag));
+  if (flag) return CHFSI_NONFINITE;
+
+  // reduction to standard form (Sec. 3.1): B = L L^H, H = L^{-1} A L^{-H}
+  const zc* H = A;
+  long ldh = lda;
+  if (gen) {
+    tm.begin(0);
+    CK(copy2d(s, n, n, B, ldb, b.L, ld));
+    CK(hipMemsetAsync(sb.info, 0, sizeof(int), s));
+    CKS(potrf_blocked(s, n, b.L, ld, b.invd, sb.info, 0.0));
+    int pinfo = 0;
+    CKS(read_info(s, sb.info, &pinfo));
+    if (pinfo != 0) return CHFSI_NOT_HPD;
+    CK(zero_upper(s, n, b.L, ld));
+    CK(copy2d(s, n, n, A, lda, b.Wr, ld));
+    CKS(trsm_left_lower(s, n, n, b.L, ld, b.invd, b.Wr, ld));     // W = L^{-1} A
+    CK(conj_transpose(s, n, b.Wr, ld, b.H, ld));                   // W^H = A L^{-H}
+    CKS(trsm_left_lower(s, n, n, b.L, ld, b.invd, b.H, ld));      // H = L^{-1} A L^{-H}
+    CK(symmetrize(s, n, b.H, ld));
+    tm.end();
+    H = b.H;
+    ldh = ld;
+  }
+
+  // start block
+  if (X0) {
+    if (gen) {
+      CK(zgemm(s, OP_C, OP_N, n, k, n, ONE, b.L, ld, X0, ldx0, ZERO, b.QA, ld, false, nullptr, 0));
+    } else {
+      CK(copy2d(s, n, k, X0, ldx0, b.QA, ld));
+    }
+  } else {
+    CK(fill_counter_random(s, n, k, b.QA, ld, o.seed, 1));
+  }
+
+  // Lanczos bound (Alg. 1 line 3)
+  tm.begin(1);
+  double beta = 0.0, tmin = 0.0, tmax = 0.0;
+  CKS(lanczos_dev(s, n, H, ldh, o.lanczos_steps, o.seed, sb, &beta, &tmin, &tmax));
+  tm.end();
+  const double norm_h = std::max(std::fabs(beta), std::fabs(tmin));
+  const double tol_abs = tol * norm_h;
+  long long matvecs = std::min(o.lanczos_steps, n);
+  int shifted = 0;
+
+  // start: QR + Rayleigh-Ritz give alpha and gamma
+  std::vector<double> mu(k), res(k);
+  tm.begin(3);
+  CK(copy2d(s, n, k, b.QA, ld, b.TMP, ld));
+  CKS(orthonormalize_dev(s, n, k, b.TMP, ld, 0, nullptr, ld, b.QA, ld, sb, &shifted));
+  tm.end();
+  tm.begin(4);
+  CKS(rayleigh_ritz_dev(s, n, k, H, ldh, b.QA, ld, b.ZA, ld, b.P0, ld, b.P1, ld, sb, mu.data(),
+                        res.data()));
+  std::swap(b.QA, b.P0);
+  std::swap(b.ZA, b.P1);
+  tm.end();
+  tm.drain();
+  matvecs += k;
+  auto alpha_of = [&](int nl_, int ka_) {
+    if (o.alpha_rule == 1) return mu[std::min(nev - nl_, ka_ - 1)];
+    return mu[ka_ - 1];
+  };
+  double alpha = alpha_of(0, k);
+  double gamma = std::min(mu[0], tmin);
+  std::vector<int> deg(k, o.deg0);
+
+  int nl = 0;
+  std::vector<double> lam_locked;
+  double max_locked_res = 0.0;
+  int it = 0;
+  int status = CHFSI_NO_CONVERGENCE;
+  double filter_flops = 0.0, filter_sec = 0.0;
+  long long filter_mv = 0;
+  int launches = 0;
+  hipEvent_t fe0 = nullptr, fe1 = nullptr;
+  CK(hipEventCreate(&fe0));
+  CK(hipEventCreate(&fe1));
+  struct EvGuard { hipEvent_t a, b; ~EvGuard() { hipEventDestroy(a); hipEventDestroy(b); } } evg{fe0, fe1};
+
+  while (it < o.max_iter) {
+    ++it;
+    const int ka = k - nl;
+    const double c = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
+    // columns sorted by ascending degree (stable)
+    std::vector<int> order(ka);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return deg[x] < deg[y]; });
+    std::vector<int> msort(ka);
+    for (int j = 0; j < ka; ++j) msort[j] = deg[order[j]];
+    tm.begin(6);
+    CKS(upload_ints(s, sb.perm, order));
+    CKS(upload_ints(s, sb.deg, msort));
+    CK(gather_cols(s, n, ka, b.QA, ld, b.P0, ld, sb.perm));
+    tm.end();
+    // Chebyshev filter (Alg. 2)
+    tm.begin(2);
+    CK(hipEventRecord(fe0, s));
+    CKS(filter_dev(s, n, ka, H, ldh, b.P0, b.P1, ld, msort, c, e, gamma, &filter_flops, &launches));
+    CK(hipEventRecord(fe1, s));
+    tm.end();
+    for (int j = 0; j < ka; ++j) filter_mv += msort[j];
+    matvecs += std::accumulate(msort.begin(), msort.end(), 0LL);
+    tm.begin(6);
+    CK(gather_parity(s, n, ka, b.P0, b.P1, ld, b.TMP, ld, sb.deg));
+    tm.end();
+    // orthonormalise against the locked vectors (Alg. 1 line 5)
+    tm.begin(3);
+    int sh = 0;
+    CKS(orthonormalize_dev(s, n, ka, b.TMP, ld, nl, b.QL, ld, b.QA, ld, sb, &sh));
+    shifted += sh;
+    tm.end();
+    // Rayleigh-Ritz (lines 6-8) and residuals
+    tm.begin(4);
+    CKS(rayleigh_ritz_dev(s, n, ka, H, ldh, b.QA, ld, b.ZA, ld, b.P0, ld, b.P1, ld, sb,
+                          mu.data(), res.data()));
+    std::swap(b.QA, b.P0);
+    std::swap(b.ZA, b.P1);
+    tm.end();
+    matvecs += ka;
+    {
+      float ms = 0.f;
+      CK(hipEventElapsedTime(&ms, fe0, fe1));
+      filter_sec += 1e-3 * ms;
+    }
+    tm.drain();
+    // locking (line 9): the lowest nev - nl active pairs are candidates
+    const int ncand = nev - nl;
+    std::vector<int> lock_idx, keep_idx;
+    for (int j = 0; j < ka; ++j) {
+      if (j < ncand && res[j] <= tol_abs) lock_idx.push_back(j);
+      else keep_idx.push_back(j);
+    }
+    if (!lock_idx.empty()) {
+      tm.begin(6);
+      CKS(upload_ints(s, sb.perm, lock_idx));
+      CK(gather_cols(s, n, (int)lock_idx.size(), b.QA, ld, b.QL + (size_t)nl * ld, ld, sb.perm));
+      CKS(upload_ints(s, sb.perm, keep_idx));
+      CK(gather_cols(s, n, (int)keep_idx.size(), b.QA, ld, b.P0, ld, sb.perm));
+      std::swap(b.QA, b.P0);
+      tm.end();
+      for (int j : lock_idx) {
+        lam_locked.push_back(mu[j]);
+        max_locked_res = std::max(max_locked_res, res[j]);
+      }
+      std::vector<double> mu2, res2;
+      for (int j : keep_idx) { mu2.push_back(mu[j]); res2.push_back(res[j]); }
+      mu.assign(k, 0.0);
+      res.assign(k, 0.0);
+      std::copy(mu2.begin(), mu2.end(), mu.begin());
+      std::copy(res2.begin(), res2.end(), res.begin());
+      nl += (int)lock_idx.size();
+    }
+    if (nl >= nev) {
+      status = CHFSI_OK;
+      break;
+    }
+    const int ka2 = k - nl;
+    alpha = alpha_of(nl, ka2);
+    gamma = std::min(gamma, mu[0]);
+    deg.assign(ka2, o.deg0);
+    if (o.degree_mode != 1) {
+      degrees_host(ka2, mu.data(), res.data(), nev - nl, alpha, beta, tol_abs, o.deg_max, deg.data());
+    }
+  }
+
+  // output: all k pairs ascending; X = L^{-H} Y for the generalized problem
+  const int ka = k - nl;
+  std::vector<double> lam_all(k);
+  std::vector<int> src(k);   // index into [QL | QA]
+  for (int j = 0; j < nl; ++j) { lam_all[j] = lam_locked[j]; src[j] = j; }
+  for (int j = 0; j < ka; ++j) { lam_all[nl + j] = mu[j]; src[nl + j] = nl + j; }
+  std::vector<int> ord(k);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return lam_all[x] < lam_all[y]; });
+  tm.begin(7);
+  // [QL | QA] side by side in P1, then one gather into X in ascending order
+  CK(copy2d(s, n, nl, b.QL, ld, b.P1, ld));
+  CK(copy2d(s, n, ka, b.QA, ld, b.P1 + (size_t)nl * ld, ld));
+  std::vector<int> gperm(k);
+  for (int j = 0; j < k; ++j) gperm[j] = src[ord[j]];
+  CKS(upload_ints(s, sb.perm, gperm));
+  CK(gather_cols(s, n, k, b.P1, ld, X, ldx, sb.perm));
+  if (gen) CKS(trsm_left_lower_h(s, n, k, b.L, ld, b.invd, X, ldx));
+  tm.end();
+  CK(hipStreamSynchronize(s));
+  tm.drain();
+  for (int j = 0; j < k; ++j) Lambda[j] = lam_all[ord[j]];
+
+  if (info) {
+    info->iters = it;
+    info->converged = std::min(nl, nev);
+    info->filter_launches = launches;
+    info->cholqr_shifted = shifted;
+    info->matvecs = matvecs;
+    info->filter_matvecs = filter_mv;
+    info->filter_flops = filter_flops;
+    info->filter_seconds = filter_sec;
+    info->beta = beta;
+    info->norm_h = norm_h;
+    info->max_resid = norm_h > 0.0 ? max_locked_res / norm_h : max_locked_res;
+  }
+  if (info) info->total_seconds = elapsed(t_start);
+  return status;
+}
+
+int check_ptr(const void* p) { return (p && aligned16(p)) ? CHFSI_OK : CHFSI_INVALID_ARG; }
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+}  // namespace
+}  // namespace chfsi
+
+using namespace chfsi;
+
+extern "C" {
+
+int chfsi_default_opts(chfsi_opts* o) {
+  if (!o) return CHFSI_INVALID_ARG;
+  o->tol = 1e-10;
+  o->deg0 = 10;
+  o->deg_max = 40;
+  o->max_iter = 100;
+  o->lanczos_steps = 20;
+  o->alpha_rule = 0;
+  o->degree_mode = 0;
+  o->seed = 0;
+  return CHFSI_OK;
+}
+
+const char* chfsi_status_string(int status) {
+  switch (status) {
+    case CHFSI_OK: return "success";
+    case CHFSI_INVALID_ARG: return "invalid argument";
+    case CHFSI_NOT_HPD: return "matrix is not Hermitian positive definite";
+    case CHFSI_NO_CONVERGENCE: return "no convergence within max_iter";
+    case CHFSI_NONFINITE: return "non-finite input";
+    case CHFSI_DEVICE_ERROR: return "device error";
+    case CHFSI_ALLOC_ERROR: return "host allocation failure";
+    default: return "unknown status";
+  }
+}
+
+size_t chfsi_workspace_bytes(int n, int nev, int nex, int generalized, const chfsi_opts* opts) {
+  if (n < 1 || nev < 1 || nex < 1 || nev + nex > n) return 0;
+  chfsi_opts o;
+  chfsi_default_opts(&o);
+  if (opts) o = *opts;
+  SolveBufs b;
+  Carver c(nullptr);
+  return carve_solve(c, b, n, nev, nex, generalized != 0, std::max(o.lanczos_steps, 1));
+}
+
+int chfsi_solve(int n, int nev, int nex, const void* A, int lda, const void* B, int ldb, double tol,
+                const void* X0, int ldx0, double* Lambda, void* X, int ldx, void* work,
+                size_t work_bytes, const chfsi_opts* opts, void* stream, chfsi_info* info) {
+  try {
+    chfsi_opts o;
+    chfsi_default_opts(&o);
+    if (opts) o = *opts;
+    o.tol = tol;
+    const int k = nev + nex;
+    if (n < 1 || nev < 1 || nex < 1 || k > n || !(tol > 0.0) || lda < n || ldx < n) return CHFSI_INVALID_ARG;
+    if (check_ptr(A) || check_ptr(X) || check_ptr(work) || !Lambda) return CHFSI_INVALID_ARG;
+    if (B && (ldb < n || !aligned16(B))) return CHFSI_INVALID_ARG;
+    if (X0 && (ldx0 < n || !aligned16(X0))) return CHFSI_INVALID_ARG;
+    if (o.deg0 < 1 || o.deg_max < 1 || o.max_iter < 1 || o.lanczos_steps < 1) return CHFSI_INVALID_ARG;
+    if (X0 == X && ldx0 != ldx) return CHFSI_INVALID_ARG;
+    if (info) std::memset(info, 0, sizeof(*info));
+    return solve_impl(n, nev, nex, (const zc*)A, lda, (const zc*)B, ldb, tol, (const zc*)X0, ldx0,
+                      Lambda, (zc*)X, ldx, work, work_bytes, o, as_stream(stream), info);
+  } catch (const std::bad_alloc&) {
+    return CHFSI_ALLOC_ERROR;
+  } catch (...) {
+    return CHFSI_DEVICE_ERROR;
+  }
+}
+
+size_t chfsi_step_workspace_bytes(int n, int k) {
+  if (n < 1 || k < 1) return 0;
+  StepBufs b;
+  Carver c(nullptr);
+  carve_step(c, b, n, k, k, 20);
+  return c.off + ALIGN;
+}
+
+int chfsi_filter(int n, int k, const void* H, int ldh, void* Y, int ldy, const int* degrees,
+                 double c, double e, double gamma, void* work, size_t work_bytes, void* stream,
+                 double* flops_out, int* launches_out) {
+  try {
+    if (n < 1 || k < 1 || ldh < n || ldy < n || !degrees || !(e > 0.0) || gamma == c)
+      return CHFSI_INVALID_ARG;
+    if (check_ptr(H) || check_ptr(Y) || check_ptr(work)) return CHFSI_INVALID_ARG;
+    for (int j = 0; j < k; ++j) {
+      if (degrees[j] < 1 || (j > 0 && degrees[j] < degrees[j - 1])) return CHFSI_INVALID_ARG;
+    }
+    if (work_bytes < chfsi_step_workspace_bytes(n, k)) return CHFSI_INVALID_ARG;
+    hipStream_t s = as_stream(stream);
+    StepBufs b;
+    Carver cv(work);
+    carve_step(cv, b, n, k, k, 20);
+    std::vector<int> m(degrees, degrees + k);
+    // P0 = a packed copy of Y, P1 = T2
+    CK(copy2d(s, n, k, (const zc*)Y, ldy, b.T1, n));
+    double fl = 0.0;
+    int ln = 0;
+    CKS(filter_dev(s, n, k, (const zc*)H, ldh, b.T1, b.T2, n, m, c, e, gamma, &fl, &ln));
+    CKS(upload_ints(s, b.deg, m));
+    CK(gather_parity(s, n, k, b.T1, b.T2, n, (zc*)Y, ldy, b.deg));
+    CK(hipStreamSynchronize(s));
+    if (flops_out) *flops_out = fl;
+    if (launches_out) *launches_out = ln;
+    return CHFSI_OK;
+  } catch (...) {
+    return CHFSI_DEVICE_ERROR;
+  }
+}
+
+int chfsi_orthonormalize(int n, int k, void* Y, int ldy, int nl, const void* QL, int ldql,
+                         void* work, size_t work_bytes, void* stream, int* shifted_out) {
+  try {
+    if (n < 1 || k < 1 || ldy < n || nl < 0 || nl + k > n) return CHFSI_INVALID_ARG;
+    if (check_ptr(Y) || check_ptr(work)) return CHFSI_INVALID_ARG;
+    if (nl > 0 && (check_ptr(QL) || ldql < n)) return CHFSI_INVALID_ARG;
+    // the projection coefficients need nl x k elements of T2 (n x k): fine
+    if (work_bytes < chfsi_step_workspace_bytes(n, std::max(k, nl))) return CHFSI_INVALID_ARG;
+    hipStream_t s = as_stream(stream);
+    StepBufs b;
+    Carver cv(work);
+    carve_step(cv, b, n, std::max(k, nl), std::max(k, nl), 20);
+    int sh = 0;
+    CKS(orthonormalize_dev(s, n, k, (zc*)Y, ldy, nl, (const zc*)QL, ldql, (zc*)Y, ldy, b, &sh));
+    CK(hipStreamSynchronize(s));
+    if (shifted_out) *shifted_out = sh;
+    return CHFSI_OK;
+  } catch (...) {
+    return CHFSI_DEVICE_ERROR;
+  }
+}
+
+int chfsi_rayleigh_ritz(int n, int k, const void* H, int ldh, void* Q, int ldq, void* Z, int ldz,
+                        double* mu, double* res, void* work, size_t work_bytes, void* stream) {
+  try {
+    if (n < 1 || k < 1 || k > n || ldh < n || ldq < n || ldz < n || !mu || !res)
+      return CHFSI_INVALID_ARG;
+    if (check_ptr(H) || check_ptr(Q) || check_ptr(Z) || check_ptr(work)) return CHFSI_INVALID_ARG;
+    if (work_bytes < chfsi_step_workspace_bytes(n, k)) return CHFSI_INVALID_ARG;
+    hipStream_t s = as_stream(stream);
+    StepBufs b;
+    Carver cv(work);
+    carve_step(cv, b, n, k, k, 20);
+    // packed copy of Q in T1, H Q in T2; the rotated basis goes to the
+    // caller's Q and Z
+    CK(copy2d(s, n, k, (const zc*)Q, ldq, b.T1, n));
+    CKS(rayleigh_ritz_dev(s, n, k, (const zc*)H, ldh, b.T1, n, b.T2, n, (zc*)Q, ldq, (zc*)Z, ldz, b,
+                          mu, res));
+    return CHFSI_OK;
+  } catch (...) {
+    return CHFSI_DEVICE_ERROR;
+  }
+}
+
+int chfsi_lanczos_bounds(int n, const void* H, int ldh, int steps, unsigned long long seed,
+                         void* work, size_t work_bytes, void* stream, double* upper,
+                         double* theta_min, double* theta_max) {
+  try {
+    if (n < 1 || ldh < n || steps < 1 || steps > 20 || !upper || !theta_min || !theta_max)
+      return CHFSI_INVALID_ARG;
+    if (check_ptr(H) || check_ptr(work)) return CHFSI_INVALID_ARG;
+    if (work_bytes < chfsi_step_workspace_bytes(n, 1)) return CHFSI_INVALID_ARG;
+    hipStream_t s = as_stream(stream);
+    StepBufs b;
+    Carver cv(work);
+    carve_step(cv, b, n, 1, 1, 20);
+    return lanczos_dev(s, n, (const zc*)H, ldh, steps, seed, b, upper, theta_min, theta_max);
+  } catch (...) {
+    return CHFSI_DEVICE_ERROR;
+  }
+}
+
+size_t chfsi_reduce_workspace_bytes(int n) {
+  if (n < 1) return 0;
+  Carver c(nullptr);
+  c.take<zc>((size_t)n * n);
+  c.take<zc>((size_t)((n + NB - 1) / NB) * NB * NB);
+  c.take<int>(8);
+  return c.off + ALIGN;
+}
+
+int chfsi_reduce_standard(int n, const void* A, int lda, const void* B, int ldb, void* H, int ldh,
+                          void* L, int ldl, void* work, size_t work_bytes, void* stream) {
+  try {
+    if (n < 1 || lda < n || ldb < n || ldh < n || ldl < n) return CHFSI_INVALID_ARG;
+    if (check_ptr(A) || check_ptr(B) || check_ptr(H) || check_ptr(L) || check_ptr(work))
+      return CHFSI_INVALID_ARG;
+    if (work_bytes < chfsi_reduce_workspace_bytes(n)) return CHFSI_INVALID_ARG;
+    hipStream_t s = as_stream(stream);
+    Carver cv(work);
+    zc* W = cv.take<zc>((size_t)n * n);
+    zc* invd = cv.take<zc>((size_t)((n + NB - 1) / NB) * NB * NB);
+    int* dinfo = cv.take<int>(8);
+    zc* Lm = (zc*)L;
+    CK(copy2d(s, n, n, (const zc*)B, ldb, Lm, ldl));
+    CK(hipMemsetAsync(dinfo, 0, sizeof(int), s));
+    CKS(potrf_blocked(s, n, Lm, ldl, invd, dinfo, 0.0));
+    int pinfo = 0;
+    CKS(read_info(s, dinfo, &pinfo));
+    if (pinfo != 0) return CHFSI_NOT_HPD;
+    CK(zero_upper(s, n, Lm, ldl));
+    CK(copy2d(s, n, n, (const zc*)A, lda, W, n));
+    CKS(trsm_left_lower(s, n, n, Lm, ldl, invd, W, n));
+    CK(conj_transpose(s, n, W, n, (zc*)H, ldh));
+    CKS(trsm_left_lower(s, n, n, Lm, ldl, invd, (zc*)H, ldh));
+    CK(symmetrize(s, n, (zc*)H, ldh));
+    CK(hipStreamSynchronize(s));
+    return CHFSI_OK;
+  } catch (...) {
+    return CHFSI_DEVICE_ERROR;
+  }
+}
+
+int chfsi_degrees(int k, const double* mu, const double* res, int n_wanted, double alpha,
+                  double beta, double tol_abs, int deg_max, int* deg) {
+  if (k < 1 || !mu || !res || !deg || !(beta > alpha) || !(tol_abs > 0.0) || deg_max < 1)
+    return CHFSI_INVALID_ARG;
+  return degrees_host(k, mu, res, n_wanted, alpha, beta, tol_abs, deg_max, deg);
+}
+
+int chfsi_zgemm(char opa, char opb, int M, int N, int K, const double* alpha, const void* A,
+                int lda, const void* B, int ldb, const double* beta, void* C, int ldc, void* work,
+                size_t work_bytes, void* stream) {
+  try {
+    if (M < 0 || N < 0 || K < 0 || !alpha || !beta) return CHFSI_INVALID_ARG;
+    const Op oa = (opa == 'N' || opa == 'n') ? OP_N : ((opa == 'C' || opa == 'c') ? OP_C : (Op)-1);
+    const Op ob = (opb == 'N' || opb == 'n') ? OP_N : ((opb == 'C' || opb == 'c') ? OP_C : (Op)-1);
+    if ((int)oa < 0 || (int)ob < 0) return CHFSI_INVALID_ARG;
+    const int arows = oa == OP_N ? M : K, brows = ob == OP_N ? K : N;
+    if (lda < std::max(1, arows) || ldb < std::max(1, brows) || ldc < std::max(1, M))
+      return CHFSI_INVALID_ARG;
+    if (M == 0 || N == 0) return CHFSI_OK;
+    if (check_ptr(C) || (K > 0 && (check_ptr(A) || check_ptr(B)))) return CHFSI_INVALID_ARG;
+    hipStream_t s = as_stream(stream);
+    const size_t need = zgemm_work_elems(M, N, K);
+    zc* w = nullptr;
+    size_t we = 0;
+    if (need > 0 && work && aligned16(work) && work_bytes >= need * sizeof(zc)) {
+      w = (zc*)work;
+      we = work_bytes / sizeof(zc);
+    }
+    CK(zgemm(s, oa, ob, M, N, K, zc{alpha[0], alpha[1]}, (const zc*)A, lda, (const zc*)B, ldb,
+             zc{beta[0], beta[1]}, (zc*)C, ldc, false, w, we));
+    CK(hipStreamSynchronize(s));
+    return CHFSI_OK;
+  } catch (...) {
+    return CHFSI_DEVICE_ERROR;
+  }
+}
+
+}  // extern "C"

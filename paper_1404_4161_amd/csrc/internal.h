@@ -1,0 +1,97 @@
+// Internal declarations shared by the HIP sources of libchfsi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace chfsi {
+
+typedef double2 zc;   // complex128: x = real, y = imaginary
+
+enum Op { OP_N = 0, OP_C = 1 };
+
+// Epilogues of the complex GEMM.
+enum Epi {
+  EPI_STORE = 0,     // C = alpha * acc + beta * C
+  EPI_CHEB = 1,      // Yout = sa * (acc - shift * Ycur) - sb * Yold  (three-term step)
+  EPI_PARTIAL = 2,   // raw partial sums of a split-K launch
+};
+
+struct GemmArgs {
+  int M, N, K;
+  const zc* A; long lda;
+  const zc* B; long ldb;
+  zc* C; long ldc;
+  zc alpha, beta;
+  // Chebyshev epilogue
+  const zc* Ycur; long ldyc;
+  const zc* Yold; long ldyo;
+  double shift, sa, sb;
+  // split-K
+  int splits;        // number of K chunks (grid dimension)
+  int kchunk;        // K elements per chunk (multiple of the K tile)
+  zc* part;          // partial buffer: split s, element (i, j) at part[s*M*N + i + j*M]
+  // tiling / scheduling
+  int tiles_m, tiles_n;
+  int lower_only;    // compute only tiles that meet the lower triangle (incl. diagonal)
+  int total_tiles;   // tiles per split (after the lower-only mask)
+};
+
+// ----- launchers (return hipError_t as int) -------------------------------
+// General complex GEMM C = alpha op(A) op(B) + beta C.  work/work_elems is
+// scratch for split-K partial sums (may be null: no split-K).
+int zgemm(hipStream_t s, Op opa, Op opb, int M, int N, int K, zc alpha,
+          const zc* A, long lda, const zc* B, long ldb, zc beta, zc* C, long ldc,
+          bool lower_only, zc* work, size_t work_elems);
+
+// Scratch elements zgemm may use for a given shape (0 if no split-K).
+size_t zgemm_work_elems(int M, int N, int K);
+
+// One step of the scaled three-term Chebyshev recurrence on columns [0, N):
+// Yout = sa * (H Ycur - shift Ycur) - sb * Yold   (Yold read only if sb != 0)
+// Yout may alias Yold (in-place update of Y_{i-1} into Y_{i+1}).
+int cheb_step(hipStream_t s, int n, int N, const zc* H, long ldh,
+              const zc* Ycur, long ldyc, const zc* Yold, long ldyo,
+              zc* Yout, long ldyout, double shift, double sa, double sb);
+
+// ----- small kernels (blas1.hip) -----
+int col_norms(hipStream_t s, int n, int k, const zc* X, long ldx, double* out);
+int resid_norms(hipStream_t s, int n, int k, const zc* Q, long ldq, const zc* Z, long ldz,
+                const double* mu, double* out);
+int scale_cols_inv(hipStream_t s, int n, int k, zc* X, long ldx, const double* nrm);
+int gather_cols(hipStream_t s, int n, int cnt, const zc* src, long lds, zc* dst, long ldd,
+                const int* perm);
+int gather_parity(hipStream_t s, int n, int k, const zc* P0, const zc* P1, long ldp,
+                  zc* dst, long ldd, const int* deg);
+int copy2d(hipStream_t s, int rows, int cols, const zc* src, long lds, zc* dst, long ldd);
+int herm_from_lower(hipStream_t s, int k, zc* G, long ldg);
+int symmetrize(hipStream_t s, int n, zc* H, long ldh);
+int conj_transpose(hipStream_t s, int n, const zc* src, long lds, zc* dst, long ldd);
+int zero_upper(hipStream_t s, int n, zc* L, long ldl);
+int set_identity(hipStream_t s, int n, zc* X, long ldx);
+int add_diag(hipStream_t s, int n, zc* G, long ldg, double v);
+int check_finite(hipStream_t s, int rows, int cols, const zc* X, long ldx, int* flag);
+int fill_counter_random(hipStream_t s, int n, int k, zc* X, long ldx,
+                        unsigned long long seed, int stream_id);
+int fill_zero(hipStream_t s, size_t count, zc* X);
+
+// Cholesky leaf: factor the nb x nb block at G (lower, in place) and write
+// inv(L_block) (nb x nb, ld nb) to inv.  info (device) receives the
+// 1-based global column of the first pivot <= rel_tol * |original diagonal|
+// (or non-positive), with col_offset added.
+int potrf_leaf(hipStream_t s, int nb, zc* G, long ldg, zc* inv, int* info, int col_offset,
+               double rel_tol);
+// X += eps * (SplitMix64 uniform in [-1/2, 1/2]^2) per entry
+int add_random(hipStream_t s, int n, int k, zc* X, long ldx, unsigned long long seed,
+               int stream_id, double eps);
+
+// Lanczos helpers
+int gemv_n(hipStream_t s, int n, const zc* H, long ldh, const zc* x, zc* y, zc* part, int splits);
+int dots_c(hipStream_t s, int n, int cnt, const zc* V, long ldv, const zc* w, zc* h);
+int sub_vh(hipStream_t s, int n, int cnt, const zc* V, long ldv, const zc* h, zc* w);
+int lanczos_axpy(hipStream_t s, int n, int j, const zc* V, long ldv, const zc* h,
+                 const double* betas, zc* w, double* alphas);
+int normalize_into(hipStream_t s, int n, const zc* w, zc* v, double* beta_out);
+
+}  // namespace chfsi

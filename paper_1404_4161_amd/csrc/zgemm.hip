@@ -1,0 +1,360 @@
+// Complex FP64 GEMM on CDNA4 matrix cores (v_mfma_f64_16x16x4_f64).
+//
+// C = op(A) op(B) is computed with the 4M real split
+//   Cr = Ar Br - Ai Bi,   Ci = Ar Bi + Ai Br
+// i.e. four real 16x16x4 MFMAs per complex 16x16x4 product, 8 real flops
+// per complex multiply-add.  This GEMM is the work of the Chebyshev filter
+// (the three-term recurrence of Alg. 2 / eq. 3term in the paper), whose
+// epilogue is fused here: the product H*Y_i is never written, the kernel
+// writes Y_{i+1} = sa (H Y_i - c Y_i) - sb Y_{i-1} directly over Y_{i-1}.
+//
+// Tiling: a 256-thread workgroup (4 wave64) owns a 64x64 complex tile of C;
+// each wave owns 32x32 (2x2 MFMA tiles, real and imaginary accumulators).
+// K advances 8 complex elements per stage through a double-buffered LDS
+// tile stored k-major ([k][m] and [k][n]) with a one-element pad so that
+// both the coalesced global->LDS transposes and the MFMA operand reads are
+// free of bank conflicts.  Operands may be plain (column-major) or
+// conjugate-transposed; the loader handles either orientation.
+//
+// Scheduling: workgroups are dispatched round-robin over the 8 XCDs.  The
+// logical tile order is remapped so that consecutive tiles (same row strip
+// of A, different column tiles of B) land on the same XCD and share the A
+// strip in that XCD's L2.
+#include "internal.h"
+
+namespace chfsi {
+
+namespace {
+
+constexpr int BM = 64, BN = 64, BK = 8, NT = 256;
+constexpr int PA = BM + 1, PB = BN + 1;   // LDS pitches in complex elements
+constexpr int NXCD = 8;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ zc cmul(zc a, zc b) {
+  return zc{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+// Global -> registers for one BK x BM stage of op(A).
+template <int OPA>
+__device__ __forceinline__ void load_a(const GemmArgs& g, int m0, int k0, int kend, zc r[2]) {
+  const int t = threadIdx.x;
+  if (OPA == OP_N) {            // (m, k) = A[m + k lda], m contiguous
+    const int m = m0 + (t & 63);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int k = k0 + (t >> 6) + 4 * i;
+      r[i] = (m < g.M && k < kend) ? g.A[m + (long)k * g.lda] : zc{0.0, 0.0};
+    }
+  } else {                      // (m, k) = conj(A[k + m lda]), k contiguous
+    const int k = k0 + (t & 7);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int m = m0 + (t >> 3) + 32 * i;
+      zc v = (m < g.M && k < kend) ? g.A[k + (long)m * g.lda] : zc{0.0, 0.0};
+      r[i] = zc{v.x, -v.y};
+    }
+  }
+}
+
+template <int OPA>
+__device__ __forceinline__ void store_a(zc (*As)[PA], const zc r[2]) {
+  const int t = threadIdx.x;
+  if (OPA == OP_N) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) As[(t >> 6) + 4 * i][t & 63] = r[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) As[t & 7][(t >> 3) + 32 * i] = r[i];
+  }
+}
+
+// Global -> registers for one BK x BN stage of op(B).
+template <int OPB>
+__device__ __forceinline__ void load_b(const GemmArgs& g, int n0, int k0, int kend, zc r[2]) {
+  const int t = threadIdx.x;
+  if (OPB == OP_N) {            // (k, n) = B[k + n ldb], k contiguous
+    const int k = k0 + (t & 7);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int n = n0 + (t >> 3) + 32 * i;
+      r[i] = (n < g.N && k < kend) ? g.B[k + (long)n * g.ldb] : zc{0.0, 0.0};
+    }
+  } else {                      // (k, n) = conj(B[n + k ldb]), n contiguous
+    const int n = n0 + (t & 63);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int k = k0 + (t >> 6) + 4 * i;
+      zc v = (n < g.N && k < kend) ? g.B[n + (long)k * g.ldb] : zc{0.0, 0.0};
+      r[i] = zc{v.x, -v.y};
+    }
+  }
+}
+
+template <int OPB>
+__device__ __forceinline__ void store_b(zc (*Bs)[PB], const zc r[2]) {
+  const int t = threadIdx.x;
+  if (OPB == OP_N) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) Bs[t & 7][(t >> 3) + 32 * i] = r[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) Bs[(t >> 6) + 4 * i][t & 63] = r[i];
+  }
+}
+
+// Lower-triangle tile enumeration: t -> (tm, tn) with tn <= tm.
+__device__ __forceinline__ void lower_tile(int t, int& tm, int& tn) {
+  int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((r + 1) * (r + 2) / 2 <= t) ++r;
+  while (r * (r + 1) / 2 > t) --r;
+  tm = r;
+  tn = t - r * (r + 1) / 2;
+}
+
+template <int OPA, int OPB, int EPI>
+__global__ void __launch_bounds__(NT) zgemm_kernel(GemmArgs g) {
+  __shared__ zc As[2][BK][PA];
+  __shared__ zc Bs[2][BK][PB];
+
+  // XCD-aware remap of the hardware workgroup id to a logical tile.
+  const int per = gridDim.x / NXCD;
+  const int logical = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+  if (logical >= g.total_tiles * g.splits) return;
+  const int split = logical / g.total_tiles;
+  const int tile = logical - split * g.total_tiles;
+  int tm, tn;
+  if (g.lower_only) {
+    lower_tile(tile, tm, tn);
+  } else {
+    tm = tile / g.tiles_n;
+    tn = tile - tm * g.tiles_n;
+  }
+  const int m0 = tm * BM, n0 = tn * BN;
+  const int kbeg = split * g.kchunk;
+  const int kend = min(g.K, kbeg + g.kchunk);
+
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  d4 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      accI[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+
+  const int nk = (kend - kbeg + BK - 1) / BK;
+  zc ra[2], rb[2];
+  if (nk > 0) {
+    load_a<OPA>(g, m0, kbeg, kend, ra);
+    load_b<OPB>(g, n0, kbeg, kend, rb);
+    store_a<OPA>(As[0], ra);
+    store_b<OPB>(Bs[0], rb);
+  }
+  __syncthreads();
+
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) {
+      const int k0 = kbeg + (kt + 1) * BK;
+      load_a<OPA>(g, m0, k0, kend, ra);
+      load_b<OPB>(g, n0, k0, kend, rb);
+    }
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      zc a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[cur][kk * 4 + lk][wm * 32 + i * 16 + lr];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[cur][kk * 4 + lk][wn * 32 + j * 16 + lr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) accR[i][j] = mfma(a[i].x, b[j].x, accR[i][j]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) accI[i][j] = mfma(a[i].x, b[j].y, accI[i][j]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) accR[i][j] = mfma(-a[i].y, b[j].y, accR[i][j]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) accI[i][j] = mfma(a[i].y, b[j].x, accI[i][j]);
+    }
+    if (more) {
+      store_a<OPA>(As[cur ^ 1], ra);
+      store_b<OPB>(Bs[cur ^ 1], rb);
+    }
+    __syncthreads();
+  }
+
+  // Epilogue.  MFMA output layout: lane l, register r holds row
+  // (l / 16) + 4 r and column l % 16 of the 16x16 tile.
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 32 + i * 16 + lk + 4 * r;
+        const int col = n0 + wn * 32 + j * 16 + lr;
+        if (row >= g.M || col >= g.N) continue;
+        const zc acc = zc{accR[i][j][r], accI[i][j][r]};
+        if (EPI == EPI_STORE) {
+          zc out = cmul(g.alpha, acc);
+          zc* cp = g.C + row + (long)col * g.ldc;
+          if (g.beta.x != 0.0 || g.beta.y != 0.0) {
+            const zc cv = *cp;
+            const zc bc = cmul(g.beta, cv);
+            out.x += bc.x;
+            out.y += bc.y;
+          }
+          *cp = out;
+        } else if (EPI == EPI_CHEB) {
+          const zc yc = g.Ycur[row + (long)col * g.ldyc];
+          zc out = zc{g.sa * (acc.x - g.shift * yc.x), g.sa * (acc.y - g.shift * yc.y)};
+          if (g.sb != 0.0) {
+            const zc yo = g.Yold[row + (long)col * g.ldyo];
+            out.x -= g.sb * yo.x;
+            out.y -= g.sb * yo.y;
+          }
+          g.C[row + (long)col * g.ldc] = out;
+        } else {
+          g.part[(long)split * g.M * g.N + row + (long)col * g.M] = acc;
+        }
+      }
+}
+
+// Sum the split-K partials in a fixed order: C = alpha sum_s P_s + beta C.
+__global__ void splitk_reduce(int M, int N, int splits, const zc* part, zc alpha, zc beta,
+                              zc* C, long ldc, int lower_only) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)M * N) return;
+  const int row = (int)(idx % M), col = (int)(idx / M);
+  if (lower_only && row / BM < col / BN) return;
+  zc s = zc{0.0, 0.0};
+  for (int p = 0; p < splits; ++p) {
+    const zc v = part[(long)p * M * N + idx];
+    s.x += v.x;
+    s.y += v.y;
+  }
+  zc out = cmul(alpha, s);
+  zc* cp = C + row + (long)col * ldc;
+  if (beta.x != 0.0 || beta.y != 0.0) {
+    const zc b = cmul(beta, *cp);
+    out.x += b.x;
+    out.y += b.y;
+  }
+  *cp = out;
+}
+
+struct Plan {
+  int tiles_m, tiles_n, total, splits, kchunk;
+};
+
+Plan make_plan(int M, int N, int K, bool lower_only, bool allow_split) {
+  Plan p;
+  p.tiles_m = (M + BM - 1) / BM;
+  p.tiles_n = (N + BN - 1) / BN;
+  p.total = lower_only ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
+  p.splits = 1;
+  p.kchunk = ((K + BK - 1) / BK) * BK;
+  if (allow_split && p.total < 512 && K >= 1024) {
+    int want = (1024 + p.total - 1) / p.total;
+    int maxs = K / 256;
+    int s = want < maxs ? want : maxs;
+    if (s > 1) {
+      int chunk = (K + s - 1) / s;
+      chunk = ((chunk + BK - 1) / BK) * BK;
+      p.kchunk = chunk;
+      p.splits = (K + chunk - 1) / chunk;
+    }
+  }
+  return p;
+}
+
+template <int OPA, int OPB, int EPI>
+int launch(hipStream_t s, GemmArgs& g) {
+  const int wg = g.total_tiles * g.splits;
+  const int grid = ((wg + NXCD - 1) / NXCD) * NXCD;
+  hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, EPI>), dim3(grid), dim3(NT), 0, s, g);
+  return (int)hipGetLastError();
+}
+
+template <int EPI>
+int dispatch(hipStream_t s, Op opa, Op opb, GemmArgs& g) {
+  if (opa == OP_N && opb == OP_N) return launch<OP_N, OP_N, EPI>(s, g);
+  if (opa == OP_N && opb == OP_C) return launch<OP_N, OP_C, EPI>(s, g);
+  if (opa == OP_C && opb == OP_N) return launch<OP_C, OP_N, EPI>(s, g);
+  return launch<OP_C, OP_C, EPI>(s, g);
+}
+
+}  // namespace
+
+size_t zgemm_work_elems(int M, int N, int K) {
+  Plan p = make_plan(M, N, K, false, true);
+  return p.splits > 1 ? (size_t)p.splits * M * N : 0;
+}
+
+int zgemm(hipStream_t s, Op opa, Op opb, int M, int N, int K, zc alpha, const zc* A, long lda,
+          const zc* B, long ldb, zc beta, zc* C, long ldc, bool lower_only, zc* work,
+          size_t work_elems) {
+  if (M <= 0 || N <= 0) return 0;
+  if (lower_only && M != N) return (int)hipErrorInvalidValue;
+  Plan p = make_plan(M, N, K, lower_only, work != nullptr);
+  if (p.splits > 1 && (size_t)p.splits * M * N > work_elems) {
+    p = make_plan(M, N, K, lower_only, false);
+  }
+  GemmArgs g = {};
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.alpha = alpha; g.beta = beta;
+  g.splits = p.splits; g.kchunk = p.kchunk; g.part = work;
+  g.tiles_m = p.tiles_m; g.tiles_n = p.tiles_n; g.lower_only = lower_only ? 1 : 0;
+  g.total_tiles = p.total;
+  if (K <= 0) {
+    // C = beta C: run a single k-empty pass through the store epilogue
+    g.splits = 1; g.kchunk = BK; g.K = 0;
+    return dispatch<EPI_STORE>(s, opa, opb, g);
+  }
+  if (p.splits == 1) return dispatch<EPI_STORE>(s, opa, opb, g);
+  int err = dispatch<EPI_PARTIAL>(s, opa, opb, g);
+  if (err) return err;
+  const long total = (long)M * N;
+  const int threads = 256;
+  hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)((total + threads - 1) / threads)),
+                     dim3(threads), 0, s, M, N, p.splits, (const zc*)work, alpha, beta, C, ldc,
+                     g.lower_only);
+  return (int)hipGetLastError();
+}
+
+int cheb_step(hipStream_t s, int n, int N, const zc* H, long ldh, const zc* Ycur, long ldyc,
+              const zc* Yold, long ldyo, zc* Yout, long ldyout, double shift, double sa,
+              double sb) {
+  if (N <= 0) return 0;
+  Plan p = make_plan(n, N, n, false, false);
+  GemmArgs g = {};
+  g.M = n; g.N = N; g.K = n;
+  g.A = H; g.lda = ldh; g.B = Ycur; g.ldb = ldyc; g.C = Yout; g.ldc = ldyout;
+  g.Ycur = Ycur; g.ldyc = ldyc; g.Yold = Yold; g.ldyo = ldyo;
+  g.shift = shift; g.sa = sa; g.sb = sb;
+  g.splits = 1; g.kchunk = p.kchunk;
+  g.tiles_m = p.tiles_m; g.tiles_n = p.tiles_n; g.total_tiles = p.total;
+  return launch<OP_N, OP_N, EPI_CHEB>(s, g);
+}
+
+}  // namespace chfsi

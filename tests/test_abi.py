@@ -1,0 +1,92 @@
+"""The C-ABI library: loads without a GPU, exports every declared symbol,
+and its host-only logic matches the oracle (no device calls here)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_1404_4161_amd as ch
+from oracle import chfsi as ochfsi
+
+
+def test_library_exports_every_declared_function():
+    lib = ch.lib()
+    names = ch.header_functions()
+    assert "chfsi_solve" in names and "chfsi_filter" in names
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_default_options_and_status_strings():
+    o = ch.chfsi_default_opts()
+    assert (o.tol, o.deg0, o.deg_max, o.max_iter, o.lanczos_steps, o.alpha_rule,
+            o.degree_mode) == (1e-10, 10, 40, 100, 20, 0, 0)
+    assert ch.chfsi_status_string(0) == "success"
+    assert "converge" in ch.chfsi_status_string(3)
+    assert ch.chfsi_status_string(99) == "unknown status"
+
+
+def test_workspace_query():
+    assert ch.chfsi_workspace_bytes(0, 1, 1, False) == 0
+    assert ch.chfsi_workspace_bytes(10, 8, 3, False) == 0           # k > n
+    small = ch.chfsi_workspace_bytes(1000, 50, 20, False)
+    gen = ch.chfsi_workspace_bytes(1000, 50, 20, True)
+    assert 6 * 1000 * 70 * 16 < small < gen
+    assert gen - small >= 3 * 1000 * 1000 * 16                      # H, L, W for the reduction
+    assert ch.chfsi_step_workspace_bytes(1000, 70) > 2 * 1000 * 70 * 16
+    assert ch.chfsi_reduce_workspace_bytes(300) >= 300 * 300 * 16
+
+
+def test_invalid_arguments_are_rejected_before_any_device_call():
+    lib = ch.lib()
+    lam = (ctypes.c_double * 4)()
+    dummy = ctypes.c_void_p(256)
+    # n < 1, nex < 1, k > n, tol <= 0, null pointers
+    assert lib.chfsi_solve(0, 1, 1, dummy, 1, None, 0, 1e-10, None, 0, lam, dummy, 1, dummy,
+                           1 << 20, None, None, None) == ch.binding.CHFSI_INVALID_ARG
+    assert lib.chfsi_solve(10, 2, 0, dummy, 10, None, 0, 1e-10, None, 0, lam, dummy, 10, dummy,
+                           1 << 20, None, None, None) == ch.binding.CHFSI_INVALID_ARG
+    assert lib.chfsi_solve(10, 8, 3, dummy, 10, None, 0, 1e-10, None, 0, lam, dummy, 10, dummy,
+                           1 << 20, None, None, None) == ch.binding.CHFSI_INVALID_ARG
+    assert lib.chfsi_solve(10, 2, 2, dummy, 10, None, 0, 0.0, None, 0, lam, dummy, 10, dummy,
+                           1 << 20, None, None, None) == ch.binding.CHFSI_INVALID_ARG
+    assert lib.chfsi_solve(10, 2, 2, None, 10, None, 0, 1e-10, None, 0, lam, dummy, 10, dummy,
+                           1 << 20, None, None, None) == ch.binding.CHFSI_INVALID_ARG
+    # lda < n
+    assert lib.chfsi_solve(10, 2, 2, dummy, 9, None, 0, 1e-10, None, 0, lam, dummy, 10, dummy,
+                           1 << 20, None, None, None) == ch.binding.CHFSI_INVALID_ARG
+    # misaligned pointer
+    assert lib.chfsi_solve(10, 2, 2, ctypes.c_void_p(8), 10, None, 0, 1e-10, None, 0, lam, dummy,
+                           10, dummy, 1 << 20, None, None, None) == ch.binding.CHFSI_INVALID_ARG
+    # workspace too small is only detectable after carving: still no device call
+    assert lib.chfsi_solve(10, 2, 2, dummy, 10, None, 0, 1e-10, None, 0, lam, dummy, 10, dummy,
+                           16, None, None, None) == ch.binding.CHFSI_INVALID_ARG
+    deg = (ctypes.c_int * 2)(3, 2)
+    assert lib.chfsi_filter(10, 2, dummy, 10, dummy, 10, deg, 0.0, 1.0, -2.0, dummy, 1 << 30,
+                            None, None, None) == ch.binding.CHFSI_INVALID_ARG
+    assert lib.chfsi_zgemm(b"X", b"N", 2, 2, 2, (ctypes.c_double * 2)(), dummy, 2, dummy, 2,
+                           (ctypes.c_double * 2)(), dummy, 2, None, 0, None) == \
+        ch.binding.CHFSI_INVALID_ARG
+
+
+def test_degree_rule_bit_exact_with_oracle():
+    g = np.random.default_rng(0)
+    for trial in range(200):
+        k = int(g.integers(1, 40))
+        alpha = float(g.uniform(-16, -14))
+        beta = float(g.uniform(30, 50))
+        mu = np.sort(g.uniform(-21, alpha, k))
+        if trial % 7 == 0:
+            mu[-1] = alpha                      # a vector on the interval edge (|t| = 1)
+        res = 10.0 ** g.uniform(-9, 0, k)
+        nw = int(g.integers(0, k + 1))
+        tol = float(10.0 ** g.uniform(-10, -7))
+        dm = int(g.integers(5, 41))
+        ref = ochfsi.degree_rule(mu, res, nw, alpha, beta, tol, dm)
+        got = ch.chfsi_degrees(mu, res, nw, alpha, beta, tol, dm)
+        assert np.array_equal(ref, got), (trial, ref, got)
+
+
+def test_degrees_rejects_bad_interval():
+    with pytest.raises(ch.ChfsiError):
+        ch.chfsi_degrees([1.0], [1.0], 1, 2.0, 1.0, 1e-9)

@@ -1,0 +1,166 @@
+"""GPU parity of the library's steps (called through the C ABI) against the
+CPU oracle, on the same seeded inputs: complex GEMM, the Chebyshev filter
+(Alg. 2), orthonormalisation, Rayleigh-Ritz + residuals, Lanczos bounds
+and the reduction to standard form.  Sizes span several 64-wide tiles and
+ragged tails."""
+import numpy as np
+import pytest
+
+import paper_1404_4161_amd as ch
+from oracle import chebyshev, chfsi as ochfsi, counter_rng, eigh
+from workloads import gen
+
+from .gpu_util import dev, host, rel_col_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _rand(m, n, seed):
+    return gen.random_block(m, n, seed)
+
+
+@pytest.mark.parametrize("opa,opb", [("N", "N"), ("N", "C"), ("C", "N"), ("C", "C")])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (17, 5, 9), (64, 64, 64), (130, 67, 71),
+                                   (200, 129, 300), (40, 36, 5000), (8, 3, 0)])
+def test_zgemm_matches_numpy(opa, opb, M, N, K):
+    a = _rand(M, K, 1) if opa == "N" else _rand(K, M, 1)
+    b = _rand(K, N, 2) if opb == "N" else _rand(N, K, 2)
+    c = _rand(M, N, 3)
+    alpha, beta = 0.7 - 0.3j, -0.4 + 1.1j
+    opA = a if opa == "N" else a.conj().T
+    opB = b if opb == "N" else b.conj().T
+    ref = alpha * (opA @ opB) + beta * c
+    cd = dev(c)
+    ch.chfsi_zgemm(opa, opb, alpha, dev(a), dev(b), beta, cd)
+    got = host(cd)
+    scale = (np.abs(opA) @ np.abs(opB)).max() + np.abs(c).max()
+    assert np.abs(got - ref).max() <= 1e-14 * max(K, 1) * scale
+
+
+def _herm_problem(n, seed):
+    lam = np.sort(np.random.default_rng(seed).uniform(-20, 40, n))
+    return lam, gen.prescribed_problem(n, lam, seed + 1)
+
+
+@pytest.mark.parametrize("n,k,degrees", [
+    (200, 5, [1, 1, 2, 3, 3]),
+    (333, 37, None),
+    (1000, 70, "cfg"),
+])
+def test_filter_matches_oracle(n, k, degrees):
+    lam, h = _herm_problem(n, 7)
+    g = np.random.default_rng(n)
+    if degrees is None:
+        degrees = np.sort(g.integers(1, 16, k)).tolist()
+    elif degrees == "cfg":
+        degrees = [10] * k
+    y0 = _rand(n, k, 11)
+    alpha, beta = -15.0, 41.0
+    c, e, gamma = 0.5 * (alpha + beta), 0.5 * (beta - alpha), -20.5
+    ref = chebyshev.chebyshev_filter(h, y0, degrees, c, e, gamma)
+    yd = dev(y0)
+    flops, launches = ch.chfsi_filter(dev(h), yd, degrees, c, e, gamma)
+    got = host(yd)
+    assert rel_col_err(got, ref).max() < 1e-11
+    assert launches == max(degrees)
+    assert flops == pytest.approx(8.0 * n * n * sum(degrees))
+
+
+def test_filter_single_column_and_all_degree_one():
+    n = 97
+    lam, h = _herm_problem(n, 3)
+    y0 = _rand(n, 1, 4)
+    ref = chebyshev.chebyshev_filter(h, y0, [6], 10.0, 30.0, -19.0)
+    yd = dev(y0)
+    ch.chfsi_filter(dev(h), yd, [6], 10.0, 30.0, -19.0)
+    assert rel_col_err(host(yd), ref).max() < 1e-12
+    y1 = _rand(n, 3, 5)
+    ref1 = chebyshev.chebyshev_filter(h, y1, [1, 1, 1], 10.0, 30.0, -19.0)
+    yd1 = dev(y1)
+    ch.chfsi_filter(dev(h), yd1, [1, 1, 1], 10.0, 30.0, -19.0)
+    assert rel_col_err(host(yd1), ref1).max() < 1e-13
+
+
+def test_filter_rejects_unsorted_degrees():
+    h = dev(np.eye(8))
+    y = dev(np.ones((8, 2)))
+    with pytest.raises(ch.ChfsiError):
+        ch.chfsi_filter(h, y, [3, 1], 0.0, 1.0, -2.0)
+
+
+@pytest.mark.parametrize("n,k,nl", [(150, 20, 0), (300, 45, 30), (1000, 70, 0)])
+def test_orthonormalize_matches_oracle_span(n, k, nl):
+    y = _rand(n, k, 21)
+    ql = ochfsi.orthonormalize(_rand(n, nl, 22), np.zeros((n, 0), complex)) if nl else None
+    ref = ochfsi.orthonormalize(y, ql if nl else np.zeros((n, 0), complex))
+    yd = dev(y)
+    ch.chfsi_orthonormalize(yd, dev(ql) if nl else None)
+    q = host(yd)
+    assert np.abs(q.conj().T @ q - np.eye(k)).max() < 1e-13
+    if nl:
+        assert np.abs(ql.conj().T @ q).max() < 1e-13
+    # same span as the oracle's QR basis
+    assert np.abs(ref @ (ref.conj().T @ q) - q).max() < 1e-12
+
+
+def test_orthonormalize_ill_conditioned_block_uses_shift():
+    n, k = 400, 24
+    lam, h = _herm_problem(n, 5)
+    y0 = _rand(n, k, 6)
+    # filtering a random block with a high degree makes it nearly rank deficient
+    y = chebyshev.chebyshev_filter(h, y0, [40] * k, 25.0, 16.0, -20.0)
+    yd = dev(y)
+    shifted = ch.chfsi_orthonormalize(yd)
+    q = host(yd)
+    assert np.abs(q.conj().T @ q - np.eye(k)).max() < 1e-12
+    assert shifted in (0, 1)
+
+
+@pytest.mark.parametrize("n,k", [(130, 17), (1000, 70)])
+def test_rayleigh_ritz_and_residuals_match_oracle(n, k):
+    lam, h = _herm_problem(n, 9)
+    q = ochfsi.orthonormalize(_rand(n, k, 3), np.zeros((n, 0), complex))
+    mu_ref, q_ref, z_ref = ochfsi.rayleigh_ritz(h, q)
+    res_ref = ochfsi.residual_norms(q_ref, z_ref, mu_ref)
+    qd = dev(q)
+    zd = dev(np.zeros((n, k), complex))
+    mu, res = ch.chfsi_rayleigh_ritz(dev(h), qd, zd)
+    assert np.abs(mu - mu_ref).max() <= 1e-12 * np.abs(lam).max()
+    assert np.abs(res - res_ref).max() <= 1e-11 * np.abs(lam).max()
+    qg, zg = host(qd), host(zd)
+    assert np.abs(zg - h @ qg).max() < 1e-11 * np.abs(lam).max()
+    assert np.abs(qg.conj().T @ qg - np.eye(k)).max() < 1e-12
+
+
+@pytest.mark.parametrize("n", [5, 300, 1000])
+def test_lanczos_bounds_match_oracle(n):
+    lam, h = _herm_problem(n, 13)
+    v0 = counter_rng.complex_block(3, counter_rng.STREAM_LANCZOS, n, 1)
+    ref = ochfsi.lanczos_bounds(h, 20, v0)
+    got = ch.chfsi_lanczos_bounds(dev(h), 20, 3)
+    assert abs(got[0] - ref[0]) <= 1e-9 * abs(ref[0])
+    assert abs(got[1] - ref[1]) <= 1e-9 * max(abs(ref[1]), 1.0)
+    assert abs(got[2] - ref[2]) <= 1e-9 * abs(ref[2])
+    assert got[0] >= lam[-1] - 1e-9
+
+
+@pytest.mark.parametrize("n", [64, 300, 700])
+def test_reduce_standard_matches_oracle(n):
+    a = gen.prescribed_problem(n, np.linspace(-20, 40, n), 2)
+    b = gen.random_hpd(n, 3)
+    h_ref, l_ref = ochfsi.reduce_to_standard(a, b)
+    hd, ld = ch.chfsi_reduce_standard(dev(a), dev(b))
+    h, l = host(hd), host(ld)
+    assert np.abs(l - l_ref).max() < 1e-13
+    assert np.abs(h - h_ref).max() < 1e-12 * np.abs(h_ref).max()
+    assert np.abs(h - h.conj().T).max() == 0.0
+
+
+def test_reduce_standard_detects_non_hpd():
+    n = 70
+    a = gen.random_hermitian_unit(n, 1)
+    b = np.eye(n, dtype=complex)
+    b[66, 66] = -1.0
+    with pytest.raises(ch.ChfsiError) as ei:
+        ch.chfsi_reduce_standard(dev(a), dev(b))
+    assert ei.value.status == ch.binding.CHFSI_NOT_HPD
