@@ -1,0 +1,193 @@
+"""Benchmark: ChFSI on a sequence of dense generalized Hermitian eigenproblems.
+
+One step = one call of chfsi_solve on the next problem of the sequence
+(reduction to standard form, Lanczos bound, filter/QR/Rayleigh-Ritz/
+residual/locking loops until nev pairs reach residual 1e-10, back-
+transform), warm-started from the previous problem's Ritz vectors.
+
+Default workload: generalized complex Hermitian A x = lambda B x,
+n = 8000, nev = 400, nex = 80, B = I + 0.05 G (G random HPD of unit norm),
+a 10-problem sequence with perturbations 1e-2 * 0.5^l.  The first problem
+(random start) is the warm-up; the timed steps are warm-started problems.
+All matrices are generated on the GPU from seeded host draws and are
+resident in HBM before timing starts.
+
+Printed (one JSON line): filter TFLOP/s (algorithmic 8 n^2 flops per
+column mat-vec / device time of the filter-step kernels) as `value`, the
+wall time per sequence step as `ms_per_step`, the roofline of the
+filter-step kernel and the CPU oracle's filter rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(a_host: np.ndarray, k: int, degree: int, seed: int = 0):
+    """Time the CPU oracle's Chebyshev filter (Alg. 2) on a bounded sample:
+    the n x n matrix of the workload and k columns at one degree."""
+    from oracle import chebyshev
+    try:
+        import threadpoolctl
+        info = threadpoolctl.threadpool_info()
+        threads = max([i.get("num_threads", 1) for i in info if i.get("user_api") == "blas"] or [1])
+    except Exception:   # pragma: no cover
+        threads = os.cpu_count() or 1
+    n = a_host.shape[0]
+    g = np.random.default_rng(seed)
+    y0 = (g.standard_normal((n, k)) + 1j * g.standard_normal((n, k))) * np.sqrt(0.5)
+    t = time.perf_counter()
+    chebyshev.chebyshev_filter(a_host, y0, [degree] * k, 12.5, 27.5, -20.0)
+    dt = time.perf_counter() - t
+    flops = 8.0 * n * n * k * degree
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"oracle Chebyshev filter (Alg. 2), n={n}, {k} columns, degree {degree}, "
+                      f"{dt:.1f} s on the host"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=9)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="gen-n8000", choices=["gen-n8000", "std-n1000"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-degree", type=int, default=6)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
+                                   "part of this build", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_1404_4161_amd as ch
+    from workloads import gen
+
+    ch.lib()   # fail loudly if the HIP library is missing
+    conf = gen.CONFIGS[args.workload]
+    total = args.warmup + args.steps
+    if total > conf.length:
+        log(f"warmup + steps = {total} exceeds the sequence length {conf.length}; "
+            f"the sequence is extended with the same perturbation schedule")
+        conf = gen.SequenceConfig(conf.name, conf.cfg, conf.n, conf.nev, conf.nex,
+                                  conf.generalized, total, conf.delta, conf.b_weight, conf.tol,
+                                  conf.deg0)
+    dev = "cuda:0"
+    t0 = time.perf_counter()
+    seq = gen.Sequence(conf, kind="torch", device=dev)
+    problems = []
+    for l, a in seq.problems():
+        problems.append(a)
+        if l >= total:
+            break
+    B = seq.B
+    torch.cuda.synchronize()
+    log(f"generated {len(problems)} problems (n={conf.n}) in {time.perf_counter() - t0:.1f}s")
+    a1_host = problems[0].cpu().numpy() if not args.no_cpu_baseline else None
+
+    n, nev, nex, k = conf.n, conf.nev, conf.nex, conf.k
+    opts = ch.chfsi_default_opts()
+    wb = ch.chfsi_workspace_bytes(n, nev, nex, B is not None, opts)
+    work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    X = ch.colmajor(torch.empty((n, k), dtype=torch.complex128, device=dev))
+    x_prev = None
+    stream = torch.cuda.current_stream(dev)
+
+    def solve(a, x0):
+        st, lam, x, info = ch.chfsi_solve(a, B, nev, nex, conf.tol, X0=x0, opts=opts, X=X,
+                                          work=work, stream=stream)
+        if st != 0:
+            raise RuntimeError(f"chfsi_solve status {st}")
+        return lam, info
+
+    for w in range(args.warmup):
+        lam, info = solve(problems[w], x_prev)
+        x_prev = X
+        log(f"warmup problem {w + 1}: iters {info['iters']} filter "
+            f"{info['filter_flops'] / max(info['filter_seconds'], 1e-12) / 1e12:.2f} TFLOP/s "
+            f"total {info['total_seconds']:.3f}s")
+
+    torch.cuda.synchronize()
+    infos, walls = [], []
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        ts = time.perf_counter()
+        lam, info = solve(problems[args.warmup + s], x_prev)
+        x_prev = X
+        walls.append(time.perf_counter() - ts)
+        infos.append(info)
+        log(f"problem {args.warmup + s + 1}: iters {info['iters']} launches "
+            f"{info['filter_launches']} filter {info['filter_seconds'] * 1e3:.1f} ms "
+            f"step {walls[-1] * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+
+    flops = sum(i["filter_flops"] for i in infos)
+    fsec = sum(i["filter_seconds"] for i in infos)
+    launches = sum(i["filter_launches"] for i in infos)
+    tflops = flops / fsec / 1e12
+    avg_launch = fsec / launches
+    phases = np.sum([i["step_seconds"] for i in infos], axis=0) / args.steps
+    out = {
+        "metric": "filter TFLOP/s + s/sequence-step at 1e-10 residual, FP64 vs mixed+learned",
+        "value": round(tflops, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{conf.name}: {'generalized' if B is not None else 'standard'} complex "
+                         f"Hermitian sequence, n={n}, nev={nev}, nex={nex}, tol={conf.tol}, "
+                         f"FP64 filter (complex, 4M split on MFMA)"),
+            "n": n, "nev": nev, "nex": nex, "problems_timed": args.steps,
+        },
+        "s_per_sequence_step_median": round(statistics.median(walls), 4),
+        "filter_tflops_over_wall": round(flops / elapsed / 1e12, 3),
+        "filter_share_of_step": round(fsec / elapsed, 3),
+        "phase_seconds_per_step": {name: round(float(v), 4) for name, v in zip(
+            ["reduction", "lanczos", "filter", "orthonormalize", "rayleigh_ritz", "residuals",
+             "locking", "back_transform"], phases)},
+        "iters_per_step": [i["iters"] for i in infos],
+        "roofline": {
+            "kernel": "zgemm_kernel<OP_N, OP_N, EPI_CHEB> (Chebyshev filter step)",
+            "bound": "mfma",
+            "achieved": round(tflops, 3),
+            "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(tflops / PEAK_FP64_TFLOPS, 4),
+            "traffic": None,
+            "avg_launch_us": round(avg_launch * 1e6, 2),
+            "launches": launches,
+        },
+    }
+    if not args.no_cpu_baseline:
+        del problems
+        torch.cuda.empty_cache()
+        log("timing the CPU oracle's filter on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(a1_host, k, args.cpu_degree)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
