@@ -169,6 +169,7 @@ def main():
             ["reduction", "lanczos", "filter", "orthonormalize", "rayleigh_ritz", "residuals",
              "locking", "back_transform"], phases)},
         "iters_per_step": [i["iters"] for i in infos],
+        "b_factor_reused_per_step": [i["b_factor_reused"] for i in infos],
         "roofline": {
             "kernel": "zgemm_kernel<OP_N, OP_N, EPI_CHEB> (Chebyshev filter step)",
             "bound": "mfma",

@@ -56,6 +56,12 @@ extern "C" {
  *                 of the block, 1 = the (nev+1)-th Ritz value [Sec. 3.1].
  *   degree_mode   0 = per-vector analytic degrees [Sec. 3.1.1], 1 = fixed
  *                 deg0 for every vector and loop.
+ *   reuse_b_factor  1 (default): keep the Cholesky factor of B and its
+ *                 inverse in the workspace and reuse them on the next call
+ *                 with the same workspace when B is bitwise unchanged (a
+ *                 64-bit fingerprint of B is checked on every call); 0:
+ *                 always factor B.  For sequences whose B is fixed the
+ *                 factor is then computed once per sequence.
  *   seed          seed of the SplitMix64 counter-based generator used for
  *                 the Lanczos start vector and a random start block. */
 typedef struct chfsi_opts {
@@ -66,6 +72,8 @@ typedef struct chfsi_opts {
   int lanczos_steps;
   int alpha_rule;
   int degree_mode;
+  int reuse_b_factor;
+  int reserved;
   unsigned long long seed;
 } chfsi_opts;
 
@@ -78,6 +86,8 @@ typedef struct chfsi_info {
   int converged;           /* locked wanted pairs (== nev on success)            */
   int filter_launches;     /* filter-step kernel launches                        */
   int cholqr_shifted;      /* orthonormalisations that needed the shifted pass   */
+  int b_factor_reused;     /* 1 when B's factor came from the workspace          */
+  int reserved;
   long long matvecs;       /* column mat-vecs with H (filter + RR + Lanczos)     */
   long long filter_matvecs;/* sum over loops of the degrees of the filtered cols */
   double filter_flops;     /* 8 n^2 per column mat-vec of the filter             */
@@ -94,7 +104,9 @@ typedef struct chfsi_info {
 int chfsi_default_opts(chfsi_opts* o);
 
 /* Bytes of device workspace chfsi_solve needs for this problem
- * (generalized != 0 when B is given).  opts may be NULL. */
+ * (generalized != 0 when B is given).  opts may be NULL.  For a generalized
+ * problem the workspace starts with B's factor (see reuse_b_factor); keep
+ * passing the same workspace along a sequence to reuse it. */
 size_t chfsi_workspace_bytes(int n, int nev, int nex, int generalized, const chfsi_opts* opts);
 
 /* Solve the nev lowest eigenpairs of A x = lambda B x (B == NULL: B = I)

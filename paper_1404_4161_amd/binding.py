@@ -26,19 +26,20 @@ CHFSI_NONFINITE, CHFSI_DEVICE_ERROR, CHFSI_ALLOC_ERROR = 4, 5, 6
 class ChfsiOpts(Structure):
     _fields_ = [("tol", c_double), ("deg0", c_int), ("deg_max", c_int), ("max_iter", c_int),
                 ("lanczos_steps", c_int), ("alpha_rule", c_int), ("degree_mode", c_int),
-                ("seed", c_ulonglong)]
+                ("reuse_b_factor", c_int), ("reserved", c_int), ("seed", c_ulonglong)]
 
 
 class ChfsiInfo(Structure):
     _fields_ = [("iters", c_int), ("converged", c_int), ("filter_launches", c_int),
-                ("cholqr_shifted", c_int), ("matvecs", c_longlong),
+                ("cholqr_shifted", c_int), ("b_factor_reused", c_int), ("reserved", c_int),
+                ("matvecs", c_longlong),
                 ("filter_matvecs", c_longlong), ("filter_flops", c_double),
                 ("filter_seconds", c_double), ("total_seconds", c_double),
                 ("max_resid", c_double), ("beta", c_double), ("norm_h", c_double),
                 ("step_seconds", c_double * 8)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "step_seconds"}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("step_seconds", "reserved")}
         d["step_seconds"] = list(self.step_seconds)
         return d
 

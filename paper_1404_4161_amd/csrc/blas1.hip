@@ -223,13 +223,48 @@ __global__ void k_add_random(int n, zc* X, long ldx, unsigned long long base, do
   *x = v;
 }
 
+// Order-independent 64-bit fingerprint of a matrix: the wrapping sum over
+// entries of SplitMix64-mixed (bits, position) words.  Integer addition is
+// associative, so the value does not depend on the reduction order.
+__device__ __forceinline__ unsigned long long entry_hash(zc v, unsigned long long p) {
+  const unsigned long long re = (unsigned long long)__double_as_longlong(v.x);
+  const unsigned long long im = (unsigned long long)__double_as_longlong(v.y);
+  return splitmix_mix(re ^ splitmix_mix(2 * p + 1)) + splitmix_mix(im ^ splitmix_mix(2 * p + 2));
+}
+
+__global__ void k_hash_part(int rows, int cols, const zc* X, long ldx, unsigned long long* part) {
+  __shared__ unsigned long long red[NT];
+  unsigned long long h = 0;
+  const long total = (long)rows * cols;
+  for (long i = (long)blockIdx.x * NT + threadIdx.x; i < total; i += (long)gridDim.x * NT) {
+    const int r = (int)(i % rows), c = (int)(i / rows);
+    h += entry_hash(X[r + (long)c * ldx], (unsigned long long)i);
+  }
+  red[threadIdx.x] = h;
+  __syncthreads();
+  for (int off = NT / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_hash_sum(int nparts, const unsigned long long* part, unsigned long long* out) {
+  if (threadIdx.x == 0) {
+    unsigned long long h = 0;
+    for (int i = 0; i < nparts; ++i) h += part[i];
+    out[0] = h;
+  }
+}
+
 __global__ void k_fill_zero(size_t count, zc* X) {
   const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
   if (i < count) X[i] = zc{0.0, 0.0};
 }
 
 // Cholesky of one nb x nb (nb <= 64) diagonal block in LDS, right-looking,
-// plus the inverse of the factor by column-parallel forward substitution.
+// plus the inverse of the factor by right-looking forward substitution.
+// Thread t owns row t % 64 and the columns (t / 64) + 4 q, q = 0..15.
 // A pivot d_j <= rel_tol * (original diagonal entry j) counts as a breakdown.
 __global__ void __launch_bounds__(NT) k_potrf_leaf(int nb, zc* G, long ldg, zc* inv, int* info,
                                                    int col_offset, double rel_tol) {
@@ -238,11 +273,16 @@ __global__ void __launch_bounds__(NT) k_potrf_leaf(int nb, zc* G, long ldg, zc* 
   __shared__ double D0[64];
   __shared__ int bad;
   const int t = threadIdx.x;
+  const int r = t & 63, cg = t >> 6;
   if (t == 0) bad = 0;
-  for (int idx = t; idx < nb * nb; idx += NT) {
-    const int r = idx % nb, c = idx / nb;
-    S[c][r] = (r >= c) ? G[r + (long)c * ldg] : zc{0.0, 0.0};
-    if (r == c) D0[r] = fabs(G[r + (long)c * ldg].x);
+#pragma unroll 4
+  for (int q = 0; q < 16; ++q) {
+    const int c = cg + 4 * q;
+    if (r < nb && c < nb) {
+      const zc v = (r >= c) ? G[r + (long)c * ldg] : zc{0.0, 0.0};
+      S[c][r] = v;
+      if (r == c) D0[r] = fabs(v.x);
+    }
   }
   __syncthreads();
   for (int j = 0; j < nb; ++j) {
@@ -254,47 +294,65 @@ __global__ void __launch_bounds__(NT) k_potrf_leaf(int nb, zc* G, long ldg, zc* 
     const double ljj = sqrt(d);
     const double inv_l = 1.0 / ljj;
     __syncthreads();
-    for (int i = j + 1 + t; i < nb; i += NT) {
-      zc v = S[j][i];
-      v.x *= inv_l;
-      v.y *= inv_l;
-      S[j][i] = v;
+    if (cg == 0 && r > j && r < nb) {
+      zc v = S[j][r];
+      S[j][r] = zc{v.x * inv_l, v.y * inv_l};
     }
     if (t == 0) S[j][j] = zc{ljj, 0.0};
     __syncthreads();
-    const int m = nb - j - 1;
-    for (int idx = t; idx < m * m; idx += NT) {
-      const int i = j + 1 + idx % m, p = j + 1 + idx / m;
-      if (i < p) continue;
-      const zc a = S[j][i], b = S[j][p];    // S(i,p) -= L(i,j) conj(L(p,j))
-      zc v = S[p][i];
-      v.x -= a.x * b.x + a.y * b.y;
-      v.y -= a.y * b.x - a.x * b.y;
-      S[p][i] = v;
+    if (r > j && r < nb) {
+      const zc a = S[j][r];      // L(r, j)
+#pragma unroll 4
+      for (int q = 0; q < 16; ++q) {
+        const int p = cg + 4 * q;
+        if (p > j && p <= r) {   // S(r, p) -= L(r, j) conj(L(p, j))
+          const zc b = S[j][p];
+          zc v = S[p][r];
+          v.x -= a.x * b.x + a.y * b.y;
+          v.y -= a.y * b.x - a.x * b.y;
+          S[p][r] = v;
+        }
+      }
     }
     __syncthreads();
   }
-  // inverse of the lower-triangular factor, one column per thread
-  if (t < nb) {
-    const int c = t;
-    for (int i = 0; i < c; ++i) X[c][i] = zc{0.0, 0.0};
-    X[c][c] = zc{1.0 / S[c][c].x, 0.0};
-    for (int i = c + 1; i < nb; ++i) {
-      zc s = zc{0.0, 0.0};
-      for (int p = c; p < i; ++p) {
-        const zc l = S[p][i], x = X[c][p];
-        s.x += l.x * x.x - l.y * x.y;
-        s.y += l.x * x.y + l.y * x.x;
-      }
-      const double f = -1.0 / S[i][i].x;
-      X[c][i] = zc{s.x * f, s.y * f};
-    }
+  // inverse: L X = I, one row of X finished per step
+#pragma unroll 4
+  for (int q = 0; q < 16; ++q) {
+    const int c = cg + 4 * q;
+    if (r < nb && c < nb) X[c][r] = zc{r == c ? 1.0 : 0.0, 0.0};
   }
   __syncthreads();
-  for (int idx = t; idx < nb * nb; idx += NT) {
-    const int r = idx % nb, c = idx / nb;
-    G[r + (long)c * ldg] = S[c][r];
-    inv[r + (long)c * nb] = X[c][r];
+  for (int i = 0; i < nb; ++i) {
+    if (cg == 0 && r <= i) {
+      const double f = 1.0 / S[i][i].x;
+      const zc v = X[r][i];
+      X[r][i] = zc{v.x * f, v.y * f};
+    }
+    __syncthreads();
+    if (r > i && r < nb) {
+      const zc l = S[i][r];      // L(r, i)
+#pragma unroll 4
+      for (int q = 0; q < 16; ++q) {
+        const int c = cg + 4 * q;
+        if (c <= i) {            // X(r, c) -= L(r, i) X(i, c)
+          const zc x = X[c][i];
+          zc v = X[c][r];
+          v.x -= l.x * x.x - l.y * x.y;
+          v.y -= l.x * x.y + l.y * x.x;
+          X[c][r] = v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll 4
+  for (int q = 0; q < 16; ++q) {
+    const int c = cg + 4 * q;
+    if (r < nb && c < nb) {
+      G[r + (long)c * ldg] = S[c][r];
+      inv[r + (long)c * nb] = X[c][r];
+    }
   }
   if (t == 0 && bad != 0 && *info == 0) *info = col_offset + bad;
 }
@@ -502,6 +560,16 @@ int fill_counter_random(hipStream_t s, int n, int k, zc* X, long ldx, unsigned l
   if (n <= 0 || k <= 0) return 0;
   const unsigned long long base = seed + ((unsigned long long)stream_id << 48);
   hipLaunchKernelGGL(k_fill_random, grid_rows(n, k), dim3(NT), 0, s, n, X, ldx, base);
+  return last();
+}
+
+int matrix_hash(hipStream_t s, int rows, int cols, const zc* X, long ldx,
+                unsigned long long* part, unsigned long long* out) {
+  hipLaunchKernelGGL(k_hash_part, dim3(HASH_PARTS), dim3(NT), 0, s, rows, cols, X, ldx, part);
+  int e = last();
+  if (e) return e;
+  hipLaunchKernelGGL(k_hash_sum, dim3(1), dim3(64), 0, s, HASH_PARTS, (const unsigned long long*)part,
+                     out);
   return last();
 }
 

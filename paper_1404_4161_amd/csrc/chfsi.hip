@@ -82,7 +82,8 @@ int gemv_splits(int n) {
 
 // Device buffers of the step-level routines on an n x k block.
 struct StepBufs {
-  zc *T1, *T2, *G, *K2, *invk, *scratch, *gv_part, *V, *w, *h;
+  zc *T1, *T2, *G, *K2, *invk, *scratch, *gv_part, *V, *w, *h, *fpart;
+  size_t fpart_elems;
   double *mu, *res, *nrm, *E, *alph, *bet, *dummy;
   int *perm, *deg, *info;
   size_t scratch_elems;
@@ -93,6 +94,8 @@ void carve_step(Carver& c, StepBufs& b, int n, int k, int nev, int lanczos_steps
   const size_t nk = (size_t)n * k;
   b.T1 = c.take<zc>(nk);
   b.T2 = c.take<zc>(nk);
+  b.fpart_elems = (size_t)CHEB_MAX_SPLITS * nk;
+  b.fpart = c.take<zc>(b.fpart_elems);
   b.G = c.take<zc>((size_t)k * k);
   b.K2 = c.take<zc>((size_t)k * k);
   b.invk = c.take<zc>((size_t)((k + NB - 1) / NB) * NB * NB);
@@ -177,6 +180,7 @@ struct Timers {
   void drain() {
     for (auto& p : pend) {
       float ms = 0.f;
+      hipEventSynchronize(p.b);
       if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) acc[p.phase] += 1e-3 * ms;
       pool.push_back(p.a);
       pool.push_back(p.b);
@@ -249,37 +253,38 @@ int potrf_blocked(hipStream_t s, int n, zc* G, long ldg, zc* invd, int* info, do
 }
 
 // X <- L^{-1} X for lower-triangular L (n x n) with inverted diagonal blocks.
+// lower_rhs: X is lower triangular (e.g. the identity), so block row j only
+// has non-zero columns [0, jb + nb) and the products skip the rest.
 int trsm_left_lower(hipStream_t s, int n, int m, const zc* L, long ldl, const zc* invd, zc* X,
-                    long ldx) {
+                    long ldx, bool lower_rhs = false) {
   for (int jb = 0; jb < n; jb += NB) {
     const int nb = std::min(NB, n - jb);
     const zc* inv = invd + (size_t)(jb / NB) * NB * NB;
+    const int cols = lower_rhs ? std::min(m, jb + nb) : m;
     // X_j = inv(L_jj) X_j  (in place: one tile row covers the whole block row)
-    CK(zgemm(s, OP_N, OP_N, nb, m, nb, ONE, inv, nb, X + jb, ldx, ZERO, X + jb, ldx, false, nullptr, 0));
+    CK(zgemm(s, OP_N, OP_N, nb, cols, nb, ONE, inv, nb, X + jb, ldx, ZERO, X + jb, ldx, false,
+             nullptr, 0));
     const int m2 = n - jb - nb;
     if (m2 > 0) {
-      CK(zgemm(s, OP_N, OP_N, m2, m, nb, MONE, L + (jb + nb) + (long)jb * ldl, ldl, X + jb, ldx,
-               ONE, X + jb + nb, ldx, false, nullptr, 0));
+      CK(zgemm(s, OP_N, OP_N, m2, cols, nb, MONE, L + (jb + nb) + (long)jb * ldl, ldl, X + jb,
+               ldx, ONE, X + jb + nb, ldx, false, nullptr, 0));
     }
   }
   return CHFSI_OK;
 }
 
-// X <- L^{-H} X (backward substitution with the upper factor L^H).
-int trsm_left_lower_h(hipStream_t s, int n, int m, const zc* L, long ldl, const zc* invd, zc* X,
-                      long ldx) {
-  const int nblk = (n + NB - 1) / NB;
-  for (int bi = nblk - 1; bi >= 0; --bi) {
-    const int jb = bi * NB;
-    const int nb = std::min(NB, n - jb);
-    const zc* inv = invd + (size_t)bi * NB * NB;
-    CK(zgemm(s, OP_C, OP_N, nb, m, nb, ONE, inv, nb, X + jb, ldx, ZERO, X + jb, ldx, false, nullptr, 0));
-    if (jb > 0) {
-      // X[0:jb] -= (L[jb:jb+nb, 0:jb])^H X_j
-      CK(zgemm(s, OP_C, OP_N, jb, m, nb, MONE, L + jb, ldl, X + jb, ldx, ONE, X, ldx, false,
-               nullptr, 0));
-    }
-  }
+// Reduction to standard form (Sec. 3.1) given Linv = L^{-1} for B = L L^H
+// (lower, strictly upper part zero): W = Linv A (lower-triangular operand:
+// the K range of each tile row stops at its diagonal), H = W Linv^H on the
+// lower tiles only (upper-triangular operand), completed by Hermitian
+// symmetry.
+int reduce_with_inverse(hipStream_t s, int n, const zc* A, long lda, const zc* Linv, zc* W,
+                        zc* H, long ld) {
+  CK(zgemm(s, OP_N, OP_N, n, n, n, ONE, Linv, ld, A, lda, ZERO, W, ld, false, nullptr, 0,
+           KTRI_A_LOWER));
+  CK(zgemm(s, OP_N, OP_C, n, n, n, ONE, W, ld, Linv, ld, ZERO, H, ld, true, nullptr, 0,
+           KTRI_B_UPPER));
+  CK(herm_from_lower(s, n, H, ld));
   return CHFSI_OK;
 }
 
@@ -307,9 +312,10 @@ int cholqr_pass(hipStream_t s, int n, int k, zc* Yin, long ldy, zc* Yout, long l
   CKS(read_info(s, b.info, &info));
   if (info != 0) return CHFSI_NOT_HPD;
   CK(set_identity(s, k, b.K2, k));
-  CKS(trsm_left_lower(s, k, k, b.G, k, invd, b.K2, k));   // K2 = L^{-1}
-  // Yout = Yin L^{-H}
-  CK(zgemm(s, OP_N, OP_C, n, k, k, ONE, Yin, ldy, b.K2, k, ZERO, Yout, ldo, false, nullptr, 0));
+  CKS(trsm_left_lower(s, k, k, b.G, k, invd, b.K2, k, true));   // K2 = L^{-1}
+  // Yout = Yin L^{-H} (upper-triangular right operand)
+  CK(zgemm(s, OP_N, OP_C, n, k, k, ONE, Yin, ldy, b.K2, k, ZERO, Yout, ldo, false, nullptr, 0,
+           KTRI_B_UPPER));
   return CHFSI_OK;
 }
 
@@ -430,13 +436,13 @@ int lanczos_dev(hipStream_t s, int n, const zc* H, long ldh, int steps, unsigned
 // Alg. 2 on device.  P0 holds Y_0 (n x k, columns sorted by ascending
 // degree m); on return column j of P[m_j mod 2] holds Y_{m_j}.
 int filter_dev(hipStream_t s, int n, int k, const zc* H, long ldh, zc* P0, zc* P1, long ld,
-               const std::vector<int>& m, double c, double e, double gamma, double* flops,
-               int* launches) {
+               const std::vector<int>& m, double c, double e, double gamma, zc* part,
+               size_t part_elems, double* flops, int* launches) {
   if (k <= 0) return CHFSI_OK;
   const double sig1 = e / (gamma - c);
   const double nn = (double)n * (double)n;
   // Y_1 = (sigma_1 / e)(H Y_0 - c Y_0)
-  CK(cheb_step(s, n, k, H, ldh, P0, ld, nullptr, ld, P1, ld, c, sig1 / e, 0.0));
+  CK(cheb_step(s, n, k, H, ldh, P0, ld, nullptr, ld, P1, ld, c, sig1 / e, 0.0, part, part_elems));
   *flops += 8.0 * nn * k;
   *launches += 1;
   double sig = sig1;
@@ -449,7 +455,7 @@ int filter_dev(hipStream_t s, int n, int k, const zc* H, long ldh, zc* P0, zc* P
     zc* old = (i & 1) ? P0 : P1;
     const int cols = k - first;
     CK(cheb_step(s, n, cols, H, ldh, cur + (size_t)first * ld, ld, old + (size_t)first * ld, ld,
-                 old + (size_t)first * ld, ld, c, 2.0 * sn / e, sn * sig));
+                 old + (size_t)first * ld, ld, c, 2.0 * sn / e, sn * sig, part, part_elems));
     *flops += 8.0 * nn * cols;
     *launches += 1;
     sig = sn;
@@ -478,8 +484,16 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 namespace {
 
+// Header of the persistent B-factor region at the start of the workspace.
+constexpr unsigned long long FACTOR_MAGIC = 0xC4F5100BFAC70001ull;
+struct FactorHeader {
+  unsigned long long magic, n, hash, pad;
+};
+
 struct SolveBufs {
-  zc *H = nullptr, *L = nullptr, *Wr = nullptr, *invd = nullptr;
+  unsigned long long* header = nullptr;   // FactorHeader (device)
+  unsigned long long* hpart = nullptr;    // hash partials + new hash
+  zc *H = nullptr, *L = nullptr, *Linv = nullptr, *W = nullptr, *invd = nullptr;
   zc *QL, *QA, *ZA, *P0, *P1, *TMP;
   int* flag;
   StepBufs st;
@@ -489,9 +503,13 @@ size_t carve_solve(Carver& c, SolveBufs& b, int n, int nev, int nex, bool gen, i
   const int k = nev + nex;
   const size_t nn = (size_t)n * n, nk = (size_t)n * k;
   if (gen) {
-    b.H = c.take<zc>(nn);
+    // persistent factor region first, so its offset does not depend on k
+    b.header = c.take<unsigned long long>(4);
     b.L = c.take<zc>(nn);
-    b.Wr = c.take<zc>(nn);
+    b.Linv = c.take<zc>(nn);
+    b.hpart = c.take<unsigned long long>(HASH_PARTS + 1);
+    b.H = c.take<zc>(nn);
+    b.W = c.take<zc>(nn);
     b.invd = c.take<zc>((size_t)((n + NB - 1) / NB) * NB * NB);
   }
   b.QL = c.take<zc>((size_t)n * nev);
@@ -554,38 +572,50 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
   CKS(read_info(s, b.flag, &flag));
   if (flag) return CHFSI_NONFINITE;
 
-  // reduction to standard form (Sec. 3.1): B = L L^H, H = L^{-1} A L^{-H}
+  // reduction to standard form (Sec. 3.1): B = L L^H, H = L^{-1} A L^{-H};
+  // the start block in the new coordinates is Y0 = L^H X0
   const zc* H = A;
   long ldh = lda;
   if (gen) {
     tm.begin(0);
-    CK(copy2d(s, n, n, B, ldb, b.L, ld));
-    CK(hipMemsetAsync(sb.info, 0, sizeof(int), s));
-    CKS(potrf_blocked(s, n, b.L, ld, b.invd, sb.info, 0.0));
-    int pinfo = 0;
-    CKS(read_info(s, sb.info, &pinfo));
-    if (pinfo != 0) return CHFSI_NOT_HPD;
-    CK(zero_upper(s, n, b.L, ld));
-    CK(copy2d(s, n, n, A, lda, b.Wr, ld));
-    CKS(trsm_left_lower(s, n, n, b.L, ld, b.invd, b.Wr, ld));     // W = L^{-1} A
-    CK(conj_transpose(s, n, b.Wr, ld, b.H, ld));                   // W^H = A L^{-H}
-    CKS(trsm_left_lower(s, n, n, b.L, ld, b.invd, b.H, ld));      // H = L^{-1} A L^{-H}
-    CK(symmetrize(s, n, b.H, ld));
+    // reuse the factor of B when the workspace holds the factor of this B
+    FactorHeader hdr = {};
+    unsigned long long hnew = 0;
+    CK(matrix_hash(s, n, n, B, ldb, b.hpart, b.hpart + HASH_PARTS));
+    CK(hipMemcpyAsync(&hdr, b.header, sizeof(hdr), hipMemcpyDeviceToHost, s));
+    CK(hipMemcpyAsync(&hnew, b.hpart + HASH_PARTS, sizeof(hnew), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    const bool reuse = o.reuse_b_factor && hdr.magic == FACTOR_MAGIC &&
+                       hdr.n == (unsigned long long)n && hdr.hash == hnew;
+    if (info) info->b_factor_reused = reuse ? 1 : 0;
+    if (!reuse) {
+      FactorHeader inval = {0, 0, 0, 0};
+      CK(hipMemcpyAsync(b.header, &inval, sizeof(inval), hipMemcpyHostToDevice, s));
+      CK(copy2d(s, n, n, B, ldb, b.L, ld));
+      CK(hipMemsetAsync(sb.info, 0, sizeof(int), s));
+      CKS(potrf_blocked(s, n, b.L, ld, b.invd, sb.info, 0.0));
+      int pinfo = 0;
+      CKS(read_info(s, sb.info, &pinfo));
+      if (pinfo != 0) return CHFSI_NOT_HPD;
+      CK(zero_upper(s, n, b.L, ld));
+      CK(set_identity(s, n, b.Linv, ld));
+      CKS(trsm_left_lower(s, n, n, b.L, ld, b.invd, b.Linv, ld, true));
+      FactorHeader valid = {FACTOR_MAGIC, (unsigned long long)n, hnew, 0};
+      CK(hipMemcpyAsync(b.header, &valid, sizeof(valid), hipMemcpyHostToDevice, s));
+      CK(hipStreamSynchronize(s));
+    }
+    if (X0) {
+      CK(zgemm(s, OP_C, OP_N, n, k, n, ONE, b.L, ld, X0, ldx0, ZERO, b.QA, ld, false, nullptr, 0,
+               KTRI_A_UPPER));
+    }
+    CKS(reduce_with_inverse(s, n, A, lda, b.Linv, b.W, b.H, ld));
     tm.end();
     H = b.H;
     ldh = ld;
+  } else if (X0) {
+    CK(copy2d(s, n, k, X0, ldx0, b.QA, ld));
   }
-
-  // start block
-  if (X0) {
-    if (gen) {
-      CK(zgemm(s, OP_C, OP_N, n, k, n, ONE, b.L, ld, X0, ldx0, ZERO, b.QA, ld, false, nullptr, 0));
-    } else {
-      CK(copy2d(s, n, k, X0, ldx0, b.QA, ld));
-    }
-  } else {
-    CK(fill_counter_random(s, n, k, b.QA, ld, o.seed, 1));
-  }
+  if (!X0) CK(fill_counter_random(s, n, k, b.QA, ld, o.seed, 1));
 
   // Lanczos bound (Alg. 1 line 3)
   tm.begin(1);
@@ -650,7 +680,8 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
     // Chebyshev filter (Alg. 2)
     tm.begin(2);
     CK(hipEventRecord(fe0, s));
-    CKS(filter_dev(s, n, ka, H, ldh, b.P0, b.P1, ld, msort, c, e, gamma, &filter_flops, &launches));
+    CKS(filter_dev(s, n, ka, H, ldh, b.P0, b.P1, ld, msort, c, e, gamma, sb.fpart, sb.fpart_elems,
+                   &filter_flops, &launches));
     CK(hipEventRecord(fe1, s));
     tm.end();
     for (int j = 0; j < ka; ++j) filter_mv += msort[j];
@@ -734,8 +765,14 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
   std::vector<int> gperm(k);
   for (int j = 0; j < k; ++j) gperm[j] = src[ord[j]];
   CKS(upload_ints(s, sb.perm, gperm));
-  CK(gather_cols(s, n, k, b.P1, ld, X, ldx, sb.perm));
-  if (gen) CKS(trsm_left_lower_h(s, n, k, b.L, ld, b.invd, X, ldx));
+  if (gen) {
+    // X = L^{-H} Y (upper-triangular operand)
+    CK(gather_cols(s, n, k, b.P1, ld, b.TMP, ld, sb.perm));
+    CK(zgemm(s, OP_C, OP_N, n, k, n, ONE, b.Linv, ld, b.TMP, ld, ZERO, X, ldx, false, nullptr, 0,
+             KTRI_A_UPPER));
+  } else {
+    CK(gather_cols(s, n, k, b.P1, ld, X, ldx, sb.perm));
+  }
   tm.end();
   CK(hipStreamSynchronize(s));
   tm.drain();
@@ -778,6 +815,8 @@ int chfsi_default_opts(chfsi_opts* o) {
   o->lanczos_steps = 20;
   o->alpha_rule = 0;
   o->degree_mode = 0;
+  o->reuse_b_factor = 1;
+  o->reserved = 0;
   o->seed = 0;
   return CHFSI_OK;
 }
@@ -858,7 +897,8 @@ int chfsi_filter(int n, int k, const void* H, int ldh, void* Y, int ldy, const i
     CK(copy2d(s, n, k, (const zc*)Y, ldy, b.T1, n));
     double fl = 0.0;
     int ln = 0;
-    CKS(filter_dev(s, n, k, (const zc*)H, ldh, b.T1, b.T2, n, m, c, e, gamma, &fl, &ln));
+    CKS(filter_dev(s, n, k, (const zc*)H, ldh, b.T1, b.T2, n, m, c, e, gamma, b.fpart,
+                   b.fpart_elems, &fl, &ln));
     CKS(upload_ints(s, b.deg, m));
     CK(gather_parity(s, n, k, b.T1, b.T2, n, (zc*)Y, ldy, b.deg));
     CK(hipStreamSynchronize(s));
@@ -936,6 +976,8 @@ size_t chfsi_reduce_workspace_bytes(int n) {
   if (n < 1) return 0;
   Carver c(nullptr);
   c.take<zc>((size_t)n * n);
+  c.take<zc>((size_t)n * n);
+  c.take<zc>((size_t)n * n);
   c.take<zc>((size_t)((n + NB - 1) / NB) * NB * NB);
   c.take<int>(8);
   return c.off + ALIGN;
@@ -950,7 +992,9 @@ int chfsi_reduce_standard(int n, const void* A, int lda, const void* B, int ldb,
     if (work_bytes < chfsi_reduce_workspace_bytes(n)) return CHFSI_INVALID_ARG;
     hipStream_t s = as_stream(stream);
     Carver cv(work);
+    zc* Linv = cv.take<zc>((size_t)n * n);
     zc* W = cv.take<zc>((size_t)n * n);
+    zc* Hp = cv.take<zc>((size_t)n * n);
     zc* invd = cv.take<zc>((size_t)((n + NB - 1) / NB) * NB * NB);
     int* dinfo = cv.take<int>(8);
     zc* Lm = (zc*)L;
@@ -961,11 +1005,10 @@ int chfsi_reduce_standard(int n, const void* A, int lda, const void* B, int ldb,
     CKS(read_info(s, dinfo, &pinfo));
     if (pinfo != 0) return CHFSI_NOT_HPD;
     CK(zero_upper(s, n, Lm, ldl));
-    CK(copy2d(s, n, n, (const zc*)A, lda, W, n));
-    CKS(trsm_left_lower(s, n, n, Lm, ldl, invd, W, n));
-    CK(conj_transpose(s, n, W, n, (zc*)H, ldh));
-    CKS(trsm_left_lower(s, n, n, Lm, ldl, invd, (zc*)H, ldh));
-    CK(symmetrize(s, n, (zc*)H, ldh));
+    CK(set_identity(s, n, Linv, n));
+    CKS(trsm_left_lower(s, n, n, Lm, ldl, invd, Linv, n, true));
+    CKS(reduce_with_inverse(s, n, (const zc*)A, lda, Linv, W, Hp, n));
+    CK(copy2d(s, n, n, Hp, n, (zc*)H, ldh));
     CK(hipStreamSynchronize(s));
     return CHFSI_OK;
   } catch (...) {

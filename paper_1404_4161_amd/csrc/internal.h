@@ -36,14 +36,21 @@ struct GemmArgs {
   int tiles_m, tiles_n;
   int lower_only;    // compute only tiles that meet the lower triangle (incl. diagonal)
   int total_tiles;   // tiles per split (after the lower-only mask)
+  int rows_desc;     // visit tile rows in descending order (set by the launcher)
+  int ktri;          // triangular operand: 0 none, 1 op(A) lower (k < m0 + BM),
+                     // 2 op(B) upper (k < n0 + BN), 3 op(A) upper (k >= m0)
 };
+
+enum KTri { KTRI_NONE = 0, KTRI_A_LOWER = 1, KTRI_B_UPPER = 2, KTRI_A_UPPER = 3 };
 
 // ----- launchers (return hipError_t as int) -------------------------------
 // General complex GEMM C = alpha op(A) op(B) + beta C.  work/work_elems is
 // scratch for split-K partial sums (may be null: no split-K).
+// ktri skips the K range where a triangular operand is zero (the memory
+// there must hold zeros or is not read at all).
 int zgemm(hipStream_t s, Op opa, Op opb, int M, int N, int K, zc alpha,
           const zc* A, long lda, const zc* B, long ldb, zc beta, zc* C, long ldc,
-          bool lower_only, zc* work, size_t work_elems);
+          bool lower_only, zc* work, size_t work_elems, int ktri = KTRI_NONE);
 
 // Scratch elements zgemm may use for a given shape (0 if no split-K).
 size_t zgemm_work_elems(int M, int N, int K);
@@ -51,9 +58,15 @@ size_t zgemm_work_elems(int M, int N, int K);
 // One step of the scaled three-term Chebyshev recurrence on columns [0, N):
 // Yout = sa * (H Ycur - shift Ycur) - sb * Yold   (Yold read only if sb != 0)
 // Yout may alias Yold (in-place update of Y_{i-1} into Y_{i+1}).
+// With part != null (part_elems complex elements of scratch) the step may
+// split K over several workgroups per tile to fill the resident slots
+// evenly; the partial sums are then combined, with the same epilogue, by a
+// second kernel.
+constexpr int CHEB_MAX_SPLITS = 4;
 int cheb_step(hipStream_t s, int n, int N, const zc* H, long ldh,
               const zc* Ycur, long ldyc, const zc* Yold, long ldyo,
-              zc* Yout, long ldyout, double shift, double sa, double sb);
+              zc* Yout, long ldyout, double shift, double sa, double sb,
+              zc* part, size_t part_elems);
 
 // ----- small kernels (blas1.hip) -----
 int col_norms(hipStream_t s, int n, int k, const zc* X, long ldx, double* out);
@@ -75,6 +88,11 @@ int check_finite(hipStream_t s, int rows, int cols, const zc* X, long ldx, int* 
 int fill_counter_random(hipStream_t s, int n, int k, zc* X, long ldx,
                         unsigned long long seed, int stream_id);
 int fill_zero(hipStream_t s, size_t count, zc* X);
+// 64-bit fingerprint of a rows x cols matrix into out[0] (device); part
+// holds HASH_PARTS partial sums.
+constexpr int HASH_PARTS = 1024;
+int matrix_hash(hipStream_t s, int rows, int cols, const zc* X, long ldx,
+                unsigned long long* part, unsigned long long* out);
 
 // Cholesky leaf: factor the nb x nb block at G (lower, in place) and write
 // inv(L_block) (nb x nb, ld nb) to inv.  info (device) receives the

@@ -22,6 +22,8 @@
 // strip in that XCD's L2.
 #include "internal.h"
 
+#include <algorithm>
+
 namespace chfsi {
 
 namespace {
@@ -117,27 +119,42 @@ __device__ __forceinline__ void lower_tile(int t, int& tm, int& tn) {
   tn = t - r * (r + 1) / 2;
 }
 
+// Four resident workgroups per CU (16 waves): the kernel fits in 128
+// registers per lane without spills, with accumulators in VGPRs.
 template <int OPA, int OPB, int EPI>
-__global__ void __launch_bounds__(NT) zgemm_kernel(GemmArgs g) {
+__global__ void __launch_bounds__(NT, 4) zgemm_kernel(GemmArgs g) {
   __shared__ zc As[2][BK][PA];
   __shared__ zc Bs[2][BK][PB];
 
-  // XCD-aware remap of the hardware workgroup id to a logical tile.
-  const int per = gridDim.x / NXCD;
-  const int logical = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
-  if (logical >= g.total_tiles * g.splits) return;
-  const int split = logical / g.total_tiles;
-  const int tile = logical - split * g.total_tiles;
-  int tm, tn;
+  // Tile scheduling.  Workgroups are dispatched round-robin over the XCDs
+  // (hardware id w runs on XCD w % 8).  For rectangular tile sets XCD x owns
+  // the (virtual) tile rows v = x, x + 8, ...: all column tiles of a row stay
+  // on one XCD and share the A strip in its L2, and every XCD gets a mix of
+  // rows, which balances triangular K ranges.  A virtual row is a (split,
+  // tile row) pair.
+  int split, tm, tn;
   if (g.lower_only) {
-    lower_tile(tile, tm, tn);
+    const int logical = blockIdx.x;
+    if (logical >= g.total_tiles * g.splits) return;
+    split = logical / g.total_tiles;
+    lower_tile(logical - split * g.total_tiles, tm, tn);
   } else {
-    tm = tile / g.tiles_n;
-    tn = tile - tm * g.tiles_n;
+    const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
+    const int vrows = g.splits * g.tiles_m;
+    const int rows_x = (vrows - xcd + NXCD - 1) / NXCD;
+    const int ri = slot / g.tiles_n;
+    tn = slot - ri * g.tiles_n;
+    if (ri >= rows_x) return;
+    const int v = xcd + NXCD * (g.rows_desc ? rows_x - 1 - ri : ri);
+    split = v / g.tiles_m;
+    tm = v - split * g.tiles_m;
   }
   const int m0 = tm * BM, n0 = tn * BN;
-  const int kbeg = split * g.kchunk;
-  const int kend = min(g.K, kbeg + g.kchunk);
+  int kbeg = split * g.kchunk;
+  int kend = min(g.K, kbeg + g.kchunk);
+  if (g.ktri == KTRI_A_LOWER) kend = min(kend, m0 + BM);
+  else if (g.ktri == KTRI_B_UPPER) kend = min(kend, n0 + BN);
+  else if (g.ktri == KTRI_A_UPPER) kbeg = max(kbeg, m0);
 
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -262,6 +279,65 @@ __global__ void splitk_reduce(int M, int N, int splits, const zc* part, zc alpha
   *cp = out;
 }
 
+// Split-K Chebyshev step: Yout = sa (sum_s P_s - shift Ycur) - sb Yold.
+__global__ void cheb_reduce(int M, int N, int splits, const zc* part, const zc* Ycur, long ldyc,
+                            const zc* Yold, long ldyo, zc* Yout, long ldyout, double shift,
+                            double sa, double sb) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)M * N) return;
+  const int row = (int)(idx % M), col = (int)(idx / M);
+  zc s = zc{0.0, 0.0};
+  for (int p = 0; p < splits; ++p) {
+    const zc v = part[(long)p * M * N + idx];
+    s.x += v.x;
+    s.y += v.y;
+  }
+  const zc yc = Ycur[row + (long)col * ldyc];
+  zc out = zc{sa * (s.x - shift * yc.x), sa * (s.y - shift * yc.y)};
+  if (sb != 0.0) {
+    const zc yo = Yold[row + (long)col * ldyo];
+    out.x -= sb * yo.x;
+    out.y -= sb * yo.y;
+  }
+  Yout[row + (long)col * ldyout] = out;
+}
+
+// Resident workgroup slots of the device (CUs x 4), cached per device.
+int device_slots() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
+  if (cache[dev] == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    cache[dev] = 4 * cus;
+  }
+  return cache[dev];
+}
+
+// Split count for a launch of `tiles` output tiles with inner size K: the
+// smallest split (<= max_splits, chunks >= 1024) whose workgroup count fills
+// the resident slots to at least 90%, else the best one.
+int wave_splits(int tiles, int K, int max_splits) {
+  const int slots = device_slots();
+  int best = 1;
+  double best_u = 0.0;
+  for (int s = 1; s <= max_splits; ++s) {
+    if (s > 1 && K / s < 1024) break;
+    const long wg = (long)tiles * s;
+    const long waves = (wg + slots - 1) / slots;
+    const double u = (double)wg / (double)(waves * slots);
+    if (u >= 0.9) return s;
+    if (u > best_u + 1e-9) {
+      best_u = u;
+      best = s;
+    }
+  }
+  return best;
+}
+
 struct Plan {
   int tiles_m, tiles_n, total, splits, kchunk;
 };
@@ -289,8 +365,16 @@ Plan make_plan(int M, int N, int K, bool lower_only, bool allow_split) {
 
 template <int OPA, int OPB, int EPI>
 int launch(hipStream_t s, GemmArgs& g) {
-  const int wg = g.total_tiles * g.splits;
-  const int grid = ((wg + NXCD - 1) / NXCD) * NXCD;
+  int grid;
+  if (g.lower_only) {
+    grid = g.total_tiles * g.splits;
+  } else {
+    const int vrows = g.splits * g.tiles_m;
+    grid = ((vrows + NXCD - 1) / NXCD) * g.tiles_n * NXCD;
+  }
+  // rows whose K range is longest first (triangular A with the long rows at
+  // the bottom), so the tail of the launch is made of short tiles
+  g.rows_desc = (g.ktri == KTRI_A_LOWER) ? 1 : 0;
   hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, EPI>), dim3(grid), dim3(NT), 0, s, g);
   return (int)hipGetLastError();
 }
@@ -312,7 +396,7 @@ size_t zgemm_work_elems(int M, int N, int K) {
 
 int zgemm(hipStream_t s, Op opa, Op opb, int M, int N, int K, zc alpha, const zc* A, long lda,
           const zc* B, long ldb, zc beta, zc* C, long ldc, bool lower_only, zc* work,
-          size_t work_elems) {
+          size_t work_elems, int ktri) {
   if (M <= 0 || N <= 0) return 0;
   if (lower_only && M != N) return (int)hipErrorInvalidValue;
   Plan p = make_plan(M, N, K, lower_only, work != nullptr);
@@ -326,6 +410,7 @@ int zgemm(hipStream_t s, Op opa, Op opb, int M, int N, int K, zc alpha, const zc
   g.splits = p.splits; g.kchunk = p.kchunk; g.part = work;
   g.tiles_m = p.tiles_m; g.tiles_n = p.tiles_n; g.lower_only = lower_only ? 1 : 0;
   g.total_tiles = p.total;
+  g.ktri = ktri;
   if (K <= 0) {
     // C = beta C: run a single k-empty pass through the store epilogue
     g.splits = 1; g.kchunk = BK; g.K = 0;
@@ -344,7 +429,7 @@ int zgemm(hipStream_t s, Op opa, Op opb, int M, int N, int K, zc alpha, const zc
 
 int cheb_step(hipStream_t s, int n, int N, const zc* H, long ldh, const zc* Ycur, long ldyc,
               const zc* Yold, long ldyo, zc* Yout, long ldyout, double shift, double sa,
-              double sb) {
+              double sb, zc* part, size_t part_elems) {
   if (N <= 0) return 0;
   Plan p = make_plan(n, N, n, false, false);
   GemmArgs g = {};
@@ -352,9 +437,29 @@ int cheb_step(hipStream_t s, int n, int N, const zc* H, long ldh, const zc* Ycur
   g.A = H; g.lda = ldh; g.B = Ycur; g.ldb = ldyc; g.C = Yout; g.ldc = ldyout;
   g.Ycur = Ycur; g.ldyc = ldyc; g.Yold = Yold; g.ldyo = ldyo;
   g.shift = shift; g.sa = sa; g.sb = sb;
-  g.splits = 1; g.kchunk = p.kchunk;
   g.tiles_m = p.tiles_m; g.tiles_n = p.tiles_n; g.total_tiles = p.total;
-  return launch<OP_N, OP_N, EPI_CHEB>(s, g);
+  int splits = 1;
+  if (part != nullptr) {
+    const int max_s = (int)std::min<size_t>(CHEB_MAX_SPLITS, part_elems / ((size_t)n * N));
+    if (max_s > 1) splits = wave_splits(p.total, n, max_s);
+  }
+  if (splits == 1) {
+    g.splits = 1;
+    g.kchunk = p.kchunk;
+    return launch<OP_N, OP_N, EPI_CHEB>(s, g);
+  }
+  int chunk = (n + splits - 1) / splits;
+  chunk = ((chunk + BK - 1) / BK) * BK;
+  g.kchunk = chunk;
+  g.splits = (n + chunk - 1) / chunk;
+  g.part = part;
+  int err = launch<OP_N, OP_N, EPI_PARTIAL>(s, g);
+  if (err) return err;
+  const long total = (long)n * N;
+  hipLaunchKernelGGL(cheb_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, n, N,
+                     g.splits, (const zc*)part, Ycur, ldyc, Yold, ldyo, Yout, ldyout, shift, sa,
+                     sb);
+  return (int)hipGetLastError();
 }
 
 }  // namespace chfsi

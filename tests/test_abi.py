@@ -20,7 +20,7 @@ def test_library_exports_every_declared_function():
 def test_default_options_and_status_strings():
     o = ch.chfsi_default_opts()
     assert (o.tol, o.deg0, o.deg_max, o.max_iter, o.lanczos_steps, o.alpha_rule,
-            o.degree_mode) == (1e-10, 10, 40, 100, 20, 0, 0)
+            o.degree_mode, o.reuse_b_factor) == (1e-10, 10, 40, 100, 20, 0, 0, 1)
     assert ch.chfsi_status_string(0) == "success"
     assert "converge" in ch.chfsi_status_string(3)
     assert ch.chfsi_status_string(99) == "unknown status"

@@ -154,3 +154,32 @@ def test_solve_error_paths():
     assert st == 0
     ref = ochfsi.chfsi(a, 6, 2)
     assert np.abs(lam[:6] - ref.lam[:6]).max() <= RTOL * np.abs(ref.lam[:6]).min()
+
+
+def test_b_factor_reused_only_for_identical_b():
+    import torch
+    conf = gen.small_config("f", 300, 12, 4, True, length=2, cfg=92, delta=1e-2)
+    seq = gen.Sequence(conf)
+    probs = [a.copy() for _, a in seq.problems()]
+    bd = dev(seq.B)
+    wb = ch.chfsi_workspace_bytes(300, 12, 4, True)
+    work = torch.empty(wb, dtype=torch.uint8, device="cuda:0")
+    st, lam1, x1, info1 = ch.chfsi_solve(dev(probs[0]), bd, 12, 4, 1e-10, work=work)
+    assert st == 0 and info1["b_factor_reused"] == 0
+    st, lam2, x2, info2 = ch.chfsi_solve(dev(probs[1]), bd, 12, 4, 1e-10, X0=x1, work=work)
+    assert st == 0 and info2["b_factor_reused"] == 1
+    fresh = ch.chfsi_solve(dev(probs[1]), bd, 12, 4, 1e-10, X0=x1)
+    assert np.array_equal(lam2, fresh[1]) and fresh[3]["b_factor_reused"] == 0
+    # a one-ulp change of B must invalidate the stored factor
+    b2 = seq.B.copy()
+    b2[5, 5] = np.nextafter(b2[5, 5].real, 2.0)
+    st, lam3, x3, info3 = ch.chfsi_solve(dev(probs[1]), dev(b2), 12, 4, 1e-10, X0=x1, work=work)
+    assert st == 0 and info3["b_factor_reused"] == 0
+    h, _ = ochfsi.reduce_to_standard(probs[1], b2)
+    ref = eigh.eigvalsh(h)[:12]
+    assert np.abs(lam3[:12] - ref).max() <= RTOL * np.abs(ref).min()
+    # reuse disabled by option
+    o = _opts(reuse_b_factor=0)
+    st, lam4, _, info4 = ch.chfsi_solve(dev(probs[1]), dev(b2), 12, 4, 1e-10, X0=x1, work=work,
+                                        opts=o)
+    assert st == 0 and info4["b_factor_reused"] == 0
