@@ -33,6 +33,24 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 
+# HBM bytes of one full-width filter step (n = 8000, N = 480), from the two
+# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) calibrated on a 1 GiB
+# copy; valid only for the kernel source it was measured on.
+TRAFFIC_MEASURED = {
+    "zgemm_sha256": "a171d3bd7ee8b827a0282d158334bab2018fd744e84609e099af6c3bc72ee002",
+    "bytes_per_full_width_step": 4.724e9,
+    "algorithmic_bytes_per_full_width_step": 1.208e9,
+}
+
+
+def traffic_entry():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1404_4161_amd", "csrc", "zgemm.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if sha != TRAFFIC_MEASURED["zgemm_sha256"]:
+        return None
+    return round(TRAFFIC_MEASURED["bytes_per_full_width_step"] / 1e9, 3)
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -60,6 +78,35 @@ def cpu_baseline(a_host: np.ndarray, k: int, degree: int, seed: int = 0):
                       f"{dt:.1f} s on the host"}
 
 
+def filter_only(conf, degree):
+    """One 1 GiB device-to-device copy (counter calibration), then one
+    Chebyshev filter of the workload's n x k block at a uniform degree on a
+    random Hermitian matrix (the filter's cost does not depend on the
+    values)."""
+    import torch
+    import paper_1404_4161_amd as ch
+    dev = "cuda:0"
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)      # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    n, k = conf.n, conf.k
+    g = torch.Generator(device=dev)
+    g.manual_seed(0)
+    h = torch.randn(n, n, dtype=torch.complex128, device=dev, generator=g)
+    h = ch.colmajor(0.5 * (h + h.conj().transpose(0, 1)))
+    y = ch.colmajor(torch.randn(n, k, dtype=torch.complex128, device=dev, generator=g))
+    nrm = 1.1 * (2.0 * n) ** 0.5      # semicircle edge of this random Hermitian matrix
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    flops, launches = ch.chfsi_filter(h, y, [degree] * k, 0.0, nrm, -1.05 * nrm)
+    dt = time.perf_counter() - t
+    print(json.dumps({"mode": "filter-only", "n": n, "k": k, "degree": degree,
+                      "launches": launches, "seconds": round(dt, 6),
+                      "tflops_wall": round(flops / dt / 1e12, 3),
+                      "copy_bytes": src.numel() * 8}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +115,11 @@ def main():
     ap.add_argument("--workload", default="gen-n8000", choices=["gen-n8000", "std-n1000"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-degree", type=int, default=6)
+    ap.add_argument("--filter-only", action="store_true",
+                    help="time only the Chebyshev filter at the workload shape (n x k block, "
+                         "uniform degree) after a 1 GiB device copy used to calibrate "
+                         "hardware byte counters; for profiler runs")
+    ap.add_argument("--degree", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
@@ -80,6 +132,9 @@ def main():
 
     ch.lib()   # fail loudly if the HIP library is missing
     conf = gen.CONFIGS[args.workload]
+    if args.filter_only:
+        filter_only(conf, args.degree)
+        return
     total = args.warmup + args.steps
     if total > conf.length:
         log(f"warmup + steps = {total} exceeds the sequence length {conf.length}; "
@@ -177,7 +232,9 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(tflops / PEAK_FP64_TFLOPS, 4),
-            "traffic": None,
+            "traffic": traffic_entry(),
+            "traffic_unit": "GB per full-width step (n=8000, N=480), HBM, from FETCH_SIZE/WRITE_SIZE",
+            "algorithmic_bytes_full_width_gb": 1.208,
             "avg_launch_us": round(avg_launch * 1e6, 2),
             "launches": launches,
         },
