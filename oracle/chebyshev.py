@@ -70,19 +70,19 @@ def chebyshev_filter(h: np.ndarray, y0: np.ndarray, degrees, c: float, e: float,
     if any(x < 1 for x in m) or any(m[j] > m[j + 1] for j in range(k - 1)):
         raise ValueError("degrees must be >= 1 and sorted ascending")
     n = h.shape[0]
-    ht = (h - c * np.eye(n)) / e                       # line 1
-    sig1 = e / (gamma - c)                             # line 2
+    ht = (h - c * np.eye(n)) / e                       # shifted, scaled matrix
+    sig1 = e / (gamma - c)
     y_prev = y0.astype(np.complex128, copy=True)
-    y_cur = sig1 * (ht @ y_prev)                       # line 3
-    s = next((j for j in range(k) if m[j] != 1), k)    # line 4
+    y_cur = sig1 * (ht @ y_prev)                       # degree-1 iterate
+    s = next((j for j in range(k) if m[j] != 1), k)    # first column still active
     sig = sig1
-    for i in range(1, m[-1]):                          # line 5
-        sig_next = 1.0 / (2.0 / sig1 - sig)            # line 6
+    for i in range(1, m[-1]):
+        sig_next = 1.0 / (2.0 / sig1 - sig)
         y_next = np.empty_like(y_cur)
-        y_next[:, :s] = y_cur[:, :s]                   # line 7 (frozen)
+        y_next[:, :s] = y_cur[:, :s]                   # finished columns carried forward
         y_next[:, s:] = (2.0 * sig_next) * (ht @ y_cur[:, s:]) \
-            - (sig_next * sig) * y_prev[:, s:]         # line 8
-        s = next((j for j in range(s, k) if m[j] != i + 1), k)   # line 9
+            - (sig_next * sig) * y_prev[:, s:]         # three-term recurrence
+        s = next((j for j in range(s, k) if m[j] != i + 1), k)
         y_prev, y_cur = y_cur, y_next
         sig = sig_next
     return y_cur

@@ -196,7 +196,7 @@ def chfsi(a: np.ndarray, nev: int, nex: int, b: Optional[np.ndarray] = None,
         if l is not None:
             y = l.conj().T @ y
 
-    # Lanczos bound (Alg. 1, line 3)
+    # Lanczos bound (Alg. 1, the LANCZOS step)
     v0 = counter_rng.complex_block(o.seed, counter_rng.STREAM_LANCZOS, n, 1)
     beta, theta_min, theta_max = lanczos_bounds(h, o.lanczos_steps, v0)
     norm_h = max(abs(beta), abs(theta_min))

@@ -617,7 +617,7 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
   }
   if (!X0) CK(fill_counter_random(s, n, k, b.QA, ld, o.seed, 1));
 
-  // Lanczos bound (Alg. 1 line 3)
+  // Lanczos bound (the LANCZOS step of Alg. 1)
   tm.begin(1);
   double beta = 0.0, tmin = 0.0, tmax = 0.0;
   CKS(lanczos_dev(s, n, H, ldh, o.lanczos_steps, o.seed, sb, &beta, &tmin, &tmax));
@@ -689,13 +689,13 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
     tm.begin(6);
     CK(gather_parity(s, n, ka, b.P0, b.P1, ld, b.TMP, ld, sb.deg));
     tm.end();
-    // orthonormalise against the locked vectors (Alg. 1 line 5)
+    // orthonormalise against the locked vectors (the QR step of Alg. 1)
     tm.begin(3);
     int sh = 0;
     CKS(orthonormalize_dev(s, n, ka, b.TMP, ld, nl, b.QL, ld, b.QA, ld, sb, &sh));
     shifted += sh;
     tm.end();
-    // Rayleigh-Ritz (lines 6-8) and residuals
+    // Rayleigh-Ritz (the RAYLEIGH-RITZ steps of Alg. 1) and residuals
     tm.begin(4);
     CKS(rayleigh_ritz_dev(s, n, ka, H, ldh, b.QA, ld, b.ZA, ld, b.P0, ld, b.P1, ld, sb,
                           mu.data(), res.data()));
@@ -709,7 +709,7 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
       filter_sec += 1e-3 * ms;
     }
     tm.drain();
-    // locking (line 9): the lowest nev - nl active pairs are candidates
+    // locking (the LOCKING step): the lowest nev - nl active pairs are candidates
     const int ncand = nev - nl;
     std::vector<int> lock_idx, keep_idx;
     for (int j = 0; j < ka; ++j) {
