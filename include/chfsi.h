@@ -128,6 +128,12 @@ size_t chfsi_workspace_bytes(int n, int nev, int nex, int generalized, const chf
  *   X0, ldx0     device, n x k start block (e.g. the previous problem's
  *                Ritz vectors, in the coordinates of A, B), read-only, or
  *                NULL for a seeded random block.
+ *   Lambda0      HOST, k doubles ascending, or NULL: the Ritz values that go
+ *                with X0 (the previous problem's eigenvalues, the inputs
+ *                lambda_1 and lambda_{nev+1} of Alg. 1).  When given, the
+ *                first filter takes its interval from them and filters X0
+ *                directly; when NULL, one QR + Rayleigh-Ritz of the start
+ *                block supplies them.  Requires X0.
  *   Lambda       HOST, k doubles: all k Ritz values, ascending; the first
  *                nev are the converged eigenvalues.
  *   X, ldx       device, n x k output Ritz vectors (X^H B X = I), in the
@@ -143,6 +149,7 @@ int chfsi_solve(int n, int nev, int nex,
                 const void* B, int ldb,
                 double tol,
                 const void* X0, int ldx0,
+                const double* Lambda0,
                 double* Lambda,
                 void* X, int ldx,
                 void* work, size_t work_bytes,

@@ -23,9 +23,11 @@ Readings where the paper is silent or ambiguous (identical on the GPU):
     (nev+1)-th Ritz value.  gamma (estimate of lambda_1) is
     min(Lanczos theta_min, smallest Ritz value seen).  beta is the Lanczos
     bound theta_max + |b_s|, fixed for the problem.
-  * Before the first filter the start block gets one QR + Rayleigh-Ritz
-    with the current H, which supplies alpha and gamma; no eigenvalues of
-    the previous problem need to be passed in.
+  * With the previous problem's Ritz values (``lam0``, the inputs
+    lambda_1 and lambda_{nev+1} of Alg. 1) the first filter takes alpha and
+    gamma from them and filters the start block directly.  Without them the
+    start block first gets one QR + Rayleigh-Ritz with the current H, which
+    supplies alpha and gamma.
   * Convergence: lock when ||H q - mu q|| <= tol * N_H with
     N_H = max(|beta|, |theta_min|).  Only the lowest (nev - locked) active
     pairs are candidates; every candidate below the threshold locks.
@@ -166,7 +168,8 @@ def degree_rule(mu, res, n_wanted: int, alpha: float, beta: float, tol_abs: floa
 # Alg. 1
 
 def chfsi(a: np.ndarray, nev: int, nex: int, b: Optional[np.ndarray] = None,
-          x0: Optional[np.ndarray] = None, opts: Optional[Options] = None) -> Result:
+          x0: Optional[np.ndarray] = None, opts: Optional[Options] = None,
+          lam0: Optional[np.ndarray] = None) -> Result:
     o = opts or Options()
     a = np.asarray(a, dtype=np.complex128)
     n = a.shape[0]
@@ -203,12 +206,17 @@ def chfsi(a: np.ndarray, nev: int, nex: int, b: Optional[np.ndarray] = None,
     tol_abs = o.tol * norm_h
     matvecs = min(o.lanczos_steps, n)
 
-    # start: one QR + Rayleigh-Ritz supplies alpha and gamma
     q_locked = np.zeros((n, 0), dtype=np.complex128)
     lam_locked: List[float] = []
-    qa = orthonormalize(y, q_locked)
-    mu, qa, za = rayleigh_ritz(h, qa)
-    matvecs += k
+    if x0 is not None and lam0 is not None:
+        # Alg. 1 inputs: the previous eigenvalues bound the first filter
+        mu = np.asarray(lam0, dtype=np.float64).copy()
+        qa = y
+    else:
+        # start: one QR + Rayleigh-Ritz supplies alpha and gamma
+        qa = orthonormalize(y, q_locked)
+        mu, qa, za = rayleigh_ritz(h, qa)
+        matvecs += k
     alpha = _alpha(mu, nev, 0, o.alpha_rule)
     gamma = min(float(mu[0]), theta_min)
     deg = np.full(k, o.deg0, dtype=np.int64)
@@ -264,13 +272,16 @@ def _alpha(mu, nev, n_locked, rule):
     return float(mu[-1])
 
 
-def solve_sequence(problems, nev, nex, b=None, opts=None, warm=True):
+def solve_sequence(problems, nev, nex, b=None, opts=None, warm=True, with_lambda=False):
     """Solve A^(1), A^(2), ... warm-starting each from the previous Ritz
-    vectors (Sec. 2.2, Alg. 1 input Y^(l-1))."""
+    vectors (Sec. 2.2, Alg. 1 input Y^(l-1)) and, with ``with_lambda``, the
+    previous Ritz values."""
     out = []
     x = None
+    lam = None
     for a in problems:
-        r = chfsi(a, nev, nex, b=b, x0=x if warm else None, opts=opts)
+        r = chfsi(a, nev, nex, b=b, x0=x if warm else None, opts=opts,
+                  lam0=lam if (warm and with_lambda) else None)
         out.append(r)
-        x = r.x
+        x, lam = r.x, r.lam
     return out

@@ -48,8 +48,8 @@ _SIGS = {
     "chfsi_default_opts": (c_int, [POINTER(ChfsiOpts)]),
     "chfsi_workspace_bytes": (c_size_t, [c_int, c_int, c_int, c_int, POINTER(ChfsiOpts)]),
     "chfsi_solve": (c_int, [c_int, c_int, c_int, c_void_p, c_int, c_void_p, c_int, c_double,
-                            c_void_p, c_int, POINTER(c_double), c_void_p, c_int, c_void_p,
-                            c_size_t, POINTER(ChfsiOpts), c_void_p, POINTER(ChfsiInfo)]),
+                            c_void_p, c_int, POINTER(c_double), POINTER(c_double), c_void_p, c_int,
+                            c_void_p, c_size_t, POINTER(ChfsiOpts), c_void_p, POINTER(ChfsiInfo)]),
     "chfsi_status_string": (ctypes.c_char_p, [c_int]),
     "chfsi_step_workspace_bytes": (c_size_t, [c_int, c_int]),
     "chfsi_filter": (c_int, [c_int, c_int, c_void_p, c_int, c_void_p, c_int, POINTER(c_int),
@@ -170,9 +170,10 @@ def chfsi_workspace_bytes(n, nev, nex, generalized, opts=None):
 
 
 def chfsi_solve(A, B, nev, nex, tol, X0=None, opts=None, X=None, work=None, stream=None,
-                raise_on_error=True):
-    """Solve A x = lambda B x (B None: standard).  Returns
-    (status, Lambda[k] numpy, X (n x k column-major tensor), info dict)."""
+                raise_on_error=True, Lambda0=None):
+    """Solve A x = lambda B x (B None: standard).  Lambda0: the Ritz values
+    that go with X0 (optional).  Returns (status, Lambda[k] numpy,
+    X (n x k column-major tensor), info dict)."""
     torch = _torch()
     n = A.shape[0]
     k = nev + nex
@@ -183,9 +184,11 @@ def chfsi_solve(A, B, nev, nex, tol, X0=None, opts=None, X=None, work=None, stre
     wb = chfsi_workspace_bytes(n, nev, nex, B is not None, o)
     w = _work(wb, dev, work)
     lam = (c_double * k)()
+    lam0 = None if Lambda0 is None else (c_double * k)(*[float(v) for v in Lambda0])
     info = ChfsiInfo()
     st = lib().chfsi_solve(n, nev, nex, _ptr(A), _ld(A), _ptr(B), _ld(B) if B is not None else 0,
-                           float(tol), _ptr(X0), _ld(X0) if X0 is not None else 0, lam, _ptr(X),
+                           float(tol), _ptr(X0), _ld(X0) if X0 is not None else 0, lam0, lam,
+                           _ptr(X),
                            _ld(X), _ptr(w), wb, ctypes.byref(o), _stream(stream, dev),
                            ctypes.byref(info))
     if raise_on_error and st not in (CHFSI_OK, CHFSI_NO_CONVERGENCE):

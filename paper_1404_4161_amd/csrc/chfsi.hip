@@ -549,7 +549,8 @@ int degrees_host(int k, const double* mu, const double* res, int n_wanted, doubl
 }
 
 int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int ldb, double tol,
-               const zc* X0, int ldx0, double* Lambda, zc* X, int ldx, void* work,
+               const zc* X0, int ldx0, const double* Lambda0, double* Lambda, zc* X, int ldx,
+               void* work,
                size_t work_bytes, const chfsi_opts& o, hipStream_t s, chfsi_info* info) {
   const auto t_start = std::chrono::steady_clock::now();
   const int k = nev + nex;
@@ -627,20 +628,26 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
   long long matvecs = std::min(o.lanczos_steps, n);
   int shifted = 0;
 
-  // start: QR + Rayleigh-Ritz give alpha and gamma
+  // Start.  With the previous problem's Ritz values (Alg. 1 inputs) the
+  // first filter takes its bounds from them and filters X0 directly;
+  // otherwise one QR + Rayleigh-Ritz of the start block supplies them.
   std::vector<double> mu(k), res(k);
-  tm.begin(3);
-  CK(copy2d(s, n, k, b.QA, ld, b.TMP, ld));
-  CKS(orthonormalize_dev(s, n, k, b.TMP, ld, 0, nullptr, ld, b.QA, ld, sb, &shifted));
-  tm.end();
-  tm.begin(4);
-  CKS(rayleigh_ritz_dev(s, n, k, H, ldh, b.QA, ld, b.ZA, ld, b.P0, ld, b.P1, ld, sb, mu.data(),
-                        res.data()));
-  std::swap(b.QA, b.P0);
-  std::swap(b.ZA, b.P1);
-  tm.end();
-  tm.drain();
-  matvecs += k;
+  if (X0 && Lambda0) {
+    for (int j = 0; j < k; ++j) mu[j] = Lambda0[j];
+  } else {
+    tm.begin(3);
+    CK(copy2d(s, n, k, b.QA, ld, b.TMP, ld));
+    CKS(orthonormalize_dev(s, n, k, b.TMP, ld, 0, nullptr, ld, b.QA, ld, sb, &shifted));
+    tm.end();
+    tm.begin(4);
+    CKS(rayleigh_ritz_dev(s, n, k, H, ldh, b.QA, ld, b.ZA, ld, b.P0, ld, b.P1, ld, sb, mu.data(),
+                          res.data()));
+    std::swap(b.QA, b.P0);
+    std::swap(b.ZA, b.P1);
+    tm.end();
+    tm.drain();
+    matvecs += k;
+  }
   auto alpha_of = [&](int nl_, int ka_) {
     if (o.alpha_rule == 1) return mu[std::min(nev - nl_, ka_ - 1)];
     return mu[ka_ - 1];
@@ -845,8 +852,9 @@ size_t chfsi_workspace_bytes(int n, int nev, int nex, int generalized, const chf
 }
 
 int chfsi_solve(int n, int nev, int nex, const void* A, int lda, const void* B, int ldb, double tol,
-                const void* X0, int ldx0, double* Lambda, void* X, int ldx, void* work,
-                size_t work_bytes, const chfsi_opts* opts, void* stream, chfsi_info* info) {
+                const void* X0, int ldx0, const double* Lambda0, double* Lambda, void* X, int ldx,
+                void* work, size_t work_bytes, const chfsi_opts* opts, void* stream,
+                chfsi_info* info) {
   try {
     chfsi_opts o;
     chfsi_default_opts(&o);
@@ -859,9 +867,17 @@ int chfsi_solve(int n, int nev, int nex, const void* A, int lda, const void* B, 
     if (X0 && (ldx0 < n || !aligned16(X0))) return CHFSI_INVALID_ARG;
     if (o.deg0 < 1 || o.deg_max < 1 || o.max_iter < 1 || o.lanczos_steps < 1) return CHFSI_INVALID_ARG;
     if (X0 == X && ldx0 != ldx) return CHFSI_INVALID_ARG;
+    if (Lambda0) {
+      if (!X0) return CHFSI_INVALID_ARG;
+      for (int j = 0; j < k; ++j) {
+        if (!std::isfinite(Lambda0[j])) return CHFSI_NONFINITE;
+        if (j > 0 && Lambda0[j] < Lambda0[j - 1]) return CHFSI_INVALID_ARG;
+      }
+      if (!(Lambda0[k - 1] > Lambda0[0])) return CHFSI_INVALID_ARG;
+    }
     if (info) std::memset(info, 0, sizeof(*info));
     return solve_impl(n, nev, nex, (const zc*)A, lda, (const zc*)B, ldb, tol, (const zc*)X0, ldx0,
-                      Lambda, (zc*)X, ldx, work, work_bytes, o, as_stream(stream), info);
+                      Lambda0, Lambda, (zc*)X, ldx, work, work_bytes, o, as_stream(stream), info);
   } catch (const std::bad_alloc&) {
     return CHFSI_ALLOC_ERROR;
   } catch (...) {

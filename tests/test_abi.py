@@ -42,24 +42,31 @@ def test_invalid_arguments_are_rejected_before_any_device_call():
     lam = (ctypes.c_double * 4)()
     dummy = ctypes.c_void_p(256)
     # n < 1, nex < 1, k > n, tol <= 0, null pointers
-    assert lib.chfsi_solve(0, 1, 1, dummy, 1, None, 0, 1e-10, None, 0, lam, dummy, 1, dummy,
+    assert lib.chfsi_solve(0, 1, 1, dummy, 1, None, 0, 1e-10, None, 0, None, lam, dummy, 1, dummy,
                            1 << 20, None, None, None) == ch.binding.CHFSI_INVALID_ARG
-    assert lib.chfsi_solve(10, 2, 0, dummy, 10, None, 0, 1e-10, None, 0, lam, dummy, 10, dummy,
+    assert lib.chfsi_solve(10, 2, 0, dummy, 10, None, 0, 1e-10, None, 0, None, lam, dummy, 10, dummy,
                            1 << 20, None, None, None) == ch.binding.CHFSI_INVALID_ARG
-    assert lib.chfsi_solve(10, 8, 3, dummy, 10, None, 0, 1e-10, None, 0, lam, dummy, 10, dummy,
+    assert lib.chfsi_solve(10, 8, 3, dummy, 10, None, 0, 1e-10, None, 0, None, lam, dummy, 10, dummy,
                            1 << 20, None, None, None) == ch.binding.CHFSI_INVALID_ARG
-    assert lib.chfsi_solve(10, 2, 2, dummy, 10, None, 0, 0.0, None, 0, lam, dummy, 10, dummy,
+    assert lib.chfsi_solve(10, 2, 2, dummy, 10, None, 0, 0.0, None, 0, None, lam, dummy, 10, dummy,
                            1 << 20, None, None, None) == ch.binding.CHFSI_INVALID_ARG
-    assert lib.chfsi_solve(10, 2, 2, None, 10, None, 0, 1e-10, None, 0, lam, dummy, 10, dummy,
+    assert lib.chfsi_solve(10, 2, 2, None, 10, None, 0, 1e-10, None, 0, None, lam, dummy, 10, dummy,
                            1 << 20, None, None, None) == ch.binding.CHFSI_INVALID_ARG
     # lda < n
-    assert lib.chfsi_solve(10, 2, 2, dummy, 9, None, 0, 1e-10, None, 0, lam, dummy, 10, dummy,
+    assert lib.chfsi_solve(10, 2, 2, dummy, 9, None, 0, 1e-10, None, 0, None, lam, dummy, 10, dummy,
                            1 << 20, None, None, None) == ch.binding.CHFSI_INVALID_ARG
     # misaligned pointer
-    assert lib.chfsi_solve(10, 2, 2, ctypes.c_void_p(8), 10, None, 0, 1e-10, None, 0, lam, dummy,
+    assert lib.chfsi_solve(10, 2, 2, ctypes.c_void_p(8), 10, None, 0, 1e-10, None, 0, None, lam, dummy,
                            10, dummy, 1 << 20, None, None, None) == ch.binding.CHFSI_INVALID_ARG
+    # Lambda0 without X0, or not ascending
+    lam0 = (ctypes.c_double * 4)(1.0, 2.0, 3.0, 4.0)
+    assert lib.chfsi_solve(10, 2, 2, dummy, 10, None, 0, 1e-10, None, 0, lam0, lam, dummy, 10,
+                           dummy, 1 << 30, None, None, None) == ch.binding.CHFSI_INVALID_ARG
+    bad0 = (ctypes.c_double * 4)(1.0, 3.0, 2.0, 4.0)
+    assert lib.chfsi_solve(10, 2, 2, dummy, 10, None, 0, 1e-10, dummy, 10, bad0, lam, dummy, 10,
+                           dummy, 1 << 30, None, None, None) == ch.binding.CHFSI_INVALID_ARG
     # workspace too small is only detectable after carving: still no device call
-    assert lib.chfsi_solve(10, 2, 2, dummy, 10, None, 0, 1e-10, None, 0, lam, dummy, 10, dummy,
+    assert lib.chfsi_solve(10, 2, 2, dummy, 10, None, 0, 1e-10, None, 0, None, lam, dummy, 10, dummy,
                            16, None, None, None) == ch.binding.CHFSI_INVALID_ARG
     deg = (ctypes.c_int * 2)(3, 2)
     assert lib.chfsi_filter(10, 2, dummy, 10, dummy, 10, deg, 0.0, 1.0, -2.0, dummy, 1 << 30,

@@ -183,3 +183,20 @@ def test_b_factor_reused_only_for_identical_b():
     st, lam4, _, info4 = ch.chfsi_solve(dev(probs[1]), dev(b2), 12, 4, 1e-10, X0=x1, work=work,
                                         opts=o)
     assert st == 0 and info4["b_factor_reused"] == 0
+
+
+def test_solve_sequence_with_previous_eigenvalues():
+    """Warm start with X0 and Lambda0 (Alg. 1 inputs) against the oracle
+    doing the same, on the n = 1000 standard workload."""
+    conf = gen.CONFIGS["std-n1000"]
+    probs = [a.copy() for _, a in gen.Sequence(conf).problems()]
+    refs = ochfsi.solve_sequence(probs, conf.nev, conf.nex, with_lambda=True)
+    x, lam = None, None
+    for a, ref in zip(probs, refs):
+        st, lam, xd, info = ch.chfsi_solve(dev(a), None, conf.nev, conf.nex, conf.tol, X0=x,
+                                           Lambda0=lam if x is not None else None)
+        assert st == 0
+        assert np.abs(lam[:conf.nev] - ref.lam[:conf.nev]).max() <= \
+            RTOL * np.abs(ref.lam[:conf.nev]).min()
+        _check_pairs(a, None, lam, host(xd), conf.nev, conf.tol, info["norm_h"])
+        x = xd

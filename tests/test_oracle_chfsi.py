@@ -250,3 +250,17 @@ def test_std_n1000_sequence_matches_prescribed_and_dense_spectra():
     assert np.abs(rs[1].lam[:conf.nev] - ref).max() <= 1e-10 * np.abs(ref).min()
     # warm-started problems need far fewer mat-vecs than the cold first one
     assert max(r.matvecs for r in rs[1:]) < 0.5 * rs[0].matvecs
+
+
+def test_previous_eigenvalues_as_filter_bounds():
+    """Alg. 1 takes the previous problem's eigenvalues as inputs; using them
+    instead of a start Rayleigh-Ritz saves mat-vecs and gives the same
+    eigenvalues."""
+    conf = gen.small_config("s", 300, 15, 5, False, length=3)
+    probs = [a.copy() for _, a in gen.Sequence(conf).problems()]
+    plain = chfsi.solve_sequence(probs, 15, 5)
+    lam = chfsi.solve_sequence(probs, 15, 5, with_lambda=True)
+    for p, q in zip(plain[1:], lam[1:]):
+        assert q.status == chfsi.STATUS_OK
+        assert q.matvecs < p.matvecs
+        assert np.abs(p.lam[:15] - q.lam[:15]).max() < 1e-11 * np.abs(p.lam[:15]).max()
