@@ -159,43 +159,50 @@ def main():
     a1_host = problems[0].cpu().numpy() if not args.no_cpu_baseline else None
 
     n, nev, nex, k = conf.n, conf.nev, conf.nex, conf.k
-    opts = ch.chfsi_default_opts()
-    wb = ch.chfsi_workspace_bytes(n, nev, nex, B is not None, opts)
+    stream = torch.cuda.current_stream(dev)
+    opts0 = ch.chfsi_default_opts()
+    opts1 = ch.chfsi_default_opts()
+    opts1.precision = 1
+    wb = max(ch.chfsi_workspace_bytes(n, nev, nex, B is not None, o) for o in (opts0, opts1))
     work = torch.empty(wb, dtype=torch.uint8, device=dev)
     X = ch.colmajor(torch.empty((n, k), dtype=torch.complex128, device=dev))
-    x_prev = None
-    lam_prev = None
-    stream = torch.cuda.current_stream(dev)
 
-    def solve(a, x0, lam0):
-        st, lam, x, info = ch.chfsi_solve(a, B, nev, nex, conf.tol, X0=x0, opts=opts, X=X,
-                                          work=work, stream=stream,
-                                          Lambda0=None if args.no_lambda0 else lam0)
-        if st != 0:
-            raise RuntimeError(f"chfsi_solve status {st}")
-        return lam, info
+    def run_sequence(opts, label):
+        """Warm-up problem(s), then the timed steps; returns per-step infos,
+        wall times, eigenvalues and the elapsed time of the timed region."""
+        x_prev, lam_prev = None, None
 
-    for w in range(args.warmup):
-        lam_prev, info = solve(problems[w], x_prev, lam_prev)
-        x_prev = X
-        log(f"warmup problem {w + 1}: iters {info['iters']} filter "
-            f"{info['filter_flops'] / max(info['filter_seconds'], 1e-12) / 1e12:.2f} TFLOP/s "
-            f"total {info['total_seconds']:.3f}s")
+        def solve(a):
+            st, lam, x, info = ch.chfsi_solve(
+                a, B, nev, nex, conf.tol, X0=x_prev, opts=opts, X=X, work=work, stream=stream,
+                Lambda0=None if (args.no_lambda0 or x_prev is None) else lam_prev)
+            if st != 0:
+                raise RuntimeError(f"chfsi_solve status {st}")
+            return lam, info
 
-    torch.cuda.synchronize()
-    infos, walls = [], []
-    t_start = time.perf_counter()
-    for s in range(args.steps):
-        ts = time.perf_counter()
-        lam_prev, info = solve(problems[args.warmup + s], x_prev, lam_prev)
-        x_prev = X
-        walls.append(time.perf_counter() - ts)
-        infos.append(info)
-        log(f"problem {args.warmup + s + 1}: iters {info['iters']} launches "
-            f"{info['filter_launches']} filter {info['filter_seconds'] * 1e3:.1f} ms "
-            f"step {walls[-1] * 1e3:.1f} ms")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+        for w in range(args.warmup):
+            lam_prev, info = solve(problems[w])
+            x_prev = X
+            log(f"[{label}] warmup problem {w + 1}: iters {info['iters']} total "
+                f"{info['total_seconds']:.3f}s")
+        torch.cuda.synchronize()
+        infos, walls, lams = [], [], []
+        t_start = time.perf_counter()
+        for s_ in range(args.steps):
+            ts = time.perf_counter()
+            lam_prev, info = solve(problems[args.warmup + s_])
+            x_prev = X
+            walls.append(time.perf_counter() - ts)
+            infos.append(info)
+            lams.append(lam_prev[:nev].copy())
+            log(f"[{label}] problem {args.warmup + s_ + 1}: iters {info['iters']} "
+                f"(fp32 {info['filter_iters_fp32']}) filter {info['filter_seconds'] * 1e3:.1f} ms "
+                f"step {walls[-1] * 1e3:.1f} ms")
+        torch.cuda.synchronize()
+        return infos, walls, lams, time.perf_counter() - t_start
+
+    infos, walls, lams64, elapsed = run_sequence(opts0, "fp64")
+    minfos, mwalls, lams32, melapsed = run_sequence(opts1, "mixed")
 
     flops = sum(i["filter_flops"] for i in infos)
     fsec = sum(i["filter_seconds"] for i in infos)
@@ -203,6 +210,14 @@ def main():
     tflops = flops / fsec / 1e12
     avg_launch = fsec / launches
     phases = np.sum([i["step_seconds"] for i in infos], axis=0) / args.steps
+    mphases = np.sum([i["step_seconds"] for i in minfos], axis=0) / args.steps
+    phase_names = ["reduction", "lanczos", "filter", "orthonormalize", "rayleigh_ritz",
+                   "residuals", "locking", "back_transform"]
+    mflops = sum(i["filter_flops"] for i in minfos)
+    msec = sum(i["filter_seconds"] for i in minfos)
+    f32_flops = sum(i["filter_flops_fp32"] for i in minfos)
+    f32_sec = sum(i["filter_seconds_fp32"] for i in minfos)
+    eig_diff = [float(np.max(np.abs(a - b) / np.abs(a))) for a, b in zip(lams64, lams32)]
     out = {
         "metric": "filter TFLOP/s + s/sequence-step at 1e-10 residual, FP64 vs mixed+learned",
         "value": round(tflops, 3),
@@ -226,9 +241,7 @@ def main():
         "s_per_sequence_step_median": round(statistics.median(walls), 4),
         "filter_tflops_over_wall": round(flops / elapsed / 1e12, 3),
         "filter_share_of_step": round(fsec / elapsed, 3),
-        "phase_seconds_per_step": {name: round(float(v), 4) for name, v in zip(
-            ["reduction", "lanczos", "filter", "orthonormalize", "rayleigh_ritz", "residuals",
-             "locking", "back_transform"], phases)},
+        "phase_seconds_per_step": {nm: round(float(v), 4) for nm, v in zip(phase_names, phases)},
         "iters_per_step": [i["iters"] for i in infos],
         "b_factor_reused_per_step": [i["b_factor_reused"] for i in infos],
         "roofline": {
@@ -243,6 +256,19 @@ def main():
             "algorithmic_bytes_full_width_gb": 1.208,
             "avg_launch_us": round(avg_launch * 1e6, 2),
             "launches": launches,
+        },
+        "mixed": {
+            "precision": "FP32 defect filter where the residuals allow, FP64 QR/RR/residuals",
+            "ms_per_step": round(1e3 * melapsed / args.steps, 3),
+            "s_per_sequence_step_median": round(statistics.median(mwalls), 4),
+            "speedup_vs_fp64_per_step": round(elapsed / melapsed, 3),
+            "filter_effective_tflops": round(mflops / msec / 1e12, 3),
+            "fp32_gemm_tflops": round(f32_flops / f32_sec / 1e12, 3) if f32_sec > 0 else None,
+            "fp32_peak_tflops": 157.3,
+            "fp32_filter_loops_per_step": [i["filter_iters_fp32"] for i in minfos],
+            "iters_per_step": [i["iters"] for i in minfos],
+            "phase_seconds_per_step": {nm: round(float(v), 4) for nm, v in zip(phase_names, mphases)},
+            "max_rel_eig_diff_vs_fp64_per_step": eig_diff,
         },
     }
     if not args.no_cpu_baseline:

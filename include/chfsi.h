@@ -62,6 +62,14 @@ extern "C" {
  *                 64-bit fingerprint of B is checked on every call); 0:
  *                 always factor B.  For sequences whose B is fixed the
  *                 factor is then computed once per sequence.
+ *   precision     0 (default): FP64 filter.  1: mixed -- when the current
+ *                 Ritz pairs' residuals are small enough that FP32 rounding
+ *                 cannot limit the filter (checked per outer loop: the
+ *                 floor eps_fp32 * residual must be 100x below the
+ *                 residual the filter aims at), the
+ *                 filter runs in complex FP32 on the defect
+ *                 E = p(Ht) Q - Q p(mu_t) of the Ritz vectors Q; QR,
+ *                 Rayleigh-Ritz, residuals and locking stay FP64.
  *   seed          seed of the SplitMix64 counter-based generator used for
  *                 the Lanczos start vector and a random start block. */
 typedef struct chfsi_opts {
@@ -73,7 +81,7 @@ typedef struct chfsi_opts {
   int alpha_rule;
   int degree_mode;
   int reuse_b_factor;
-  int reserved;
+  int precision;
   unsigned long long seed;
 } chfsi_opts;
 
@@ -87,7 +95,7 @@ typedef struct chfsi_info {
   int filter_launches;     /* filter-step kernel launches                        */
   int cholqr_shifted;      /* orthonormalisations that needed the shifted pass   */
   int b_factor_reused;     /* 1 when B's factor came from the workspace          */
-  int reserved;
+  int filter_iters_fp32;   /* outer loops whose filter ran in FP32 defect form   */
   long long matvecs;       /* column mat-vecs with H (filter + RR + Lanczos)     */
   long long filter_matvecs;/* sum over loops of the degrees of the filtered cols */
   double filter_flops;     /* 8 n^2 per column mat-vec of the filter             */
@@ -97,6 +105,8 @@ typedef struct chfsi_info {
   double beta;             /* Lanczos upper bound of the spectrum of H           */
   double norm_h;           /* max(|beta|, |theta_min|), the scale of `tol`       */
   double step_seconds[8];
+  double filter_flops_fp32;   /* FP32 GEMM flops executed by defect filters      */
+  double filter_seconds_fp32; /* device time of the defect filters               */
 } chfsi_info;
 
 /* Fill *o with the defaults listed above.  Returns CHFSI_OK, or
@@ -184,6 +194,21 @@ int chfsi_filter(int n, int k, const void* H, int ldh, void* Y, int ldy,
                  const int* degrees, double c, double e, double gamma,
                  void* work, size_t work_bytes, void* stream,
                  double* flops_out, int* launches_out);
+
+/* Mixed-precision form of chfsi_filter (same result, FP32 GEMMs): filters
+ * the Ritz vectors Q (n x k, ascending degrees as in chfsi_filter) given
+ * Z = H Q and the Ritz values mu (HOST, k doubles), by running the
+ * recurrence on the defect p_i(Ht) Q - Q diag(p_i((mu - c)/e)) in complex
+ * FP32 (v_mfma_f32_16x16x4_f32).  The rounding error scales with the
+ * residuals ||Z_j - mu_j Q_j|| instead of ||Q_j||.  Q and Z must be packed
+ * (ldq = ldz = n); degrees <= 256; work >= chfsi_defect_workspace_bytes.
+ *   Y, ldy    device n x k out (must not overlap Q or Z).
+ *   flops_out NULL or the executed FP32 GEMM flops. */
+size_t chfsi_defect_workspace_bytes(int n, int k);
+int chfsi_filter_defect(int n, int k, const void* H, int ldh, const void* Q, int ldq,
+                        const void* Z, int ldz, const double* mu, const int* degrees, double c,
+                        double e, double gamma, void* Y, int ldy, void* work, size_t work_bytes,
+                        void* stream, double* flops_out);
 
 /* Orthonormalise the n x k block Y against the n x nl locked block QL
  * (two projection passes, QL^H QL = I assumed) and then by CholeskyQR2,

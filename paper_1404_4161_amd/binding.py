@@ -26,17 +26,19 @@ CHFSI_NONFINITE, CHFSI_DEVICE_ERROR, CHFSI_ALLOC_ERROR = 4, 5, 6
 class ChfsiOpts(Structure):
     _fields_ = [("tol", c_double), ("deg0", c_int), ("deg_max", c_int), ("max_iter", c_int),
                 ("lanczos_steps", c_int), ("alpha_rule", c_int), ("degree_mode", c_int),
-                ("reuse_b_factor", c_int), ("reserved", c_int), ("seed", c_ulonglong)]
+                ("reuse_b_factor", c_int), ("precision", c_int), ("seed", c_ulonglong)]
 
 
 class ChfsiInfo(Structure):
     _fields_ = [("iters", c_int), ("converged", c_int), ("filter_launches", c_int),
-                ("cholqr_shifted", c_int), ("b_factor_reused", c_int), ("reserved", c_int),
+                ("cholqr_shifted", c_int), ("b_factor_reused", c_int),
+                ("filter_iters_fp32", c_int),
                 ("matvecs", c_longlong),
                 ("filter_matvecs", c_longlong), ("filter_flops", c_double),
                 ("filter_seconds", c_double), ("total_seconds", c_double),
                 ("max_resid", c_double), ("beta", c_double), ("norm_h", c_double),
-                ("step_seconds", c_double * 8)]
+                ("step_seconds", c_double * 8), ("filter_flops_fp32", c_double),
+                ("filter_seconds_fp32", c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("step_seconds", "reserved")}
@@ -55,6 +57,11 @@ _SIGS = {
     "chfsi_filter": (c_int, [c_int, c_int, c_void_p, c_int, c_void_p, c_int, POINTER(c_int),
                              c_double, c_double, c_double, c_void_p, c_size_t, c_void_p,
                              POINTER(c_double), POINTER(c_int)]),
+    "chfsi_defect_workspace_bytes": (c_size_t, [c_int, c_int]),
+    "chfsi_filter_defect": (c_int, [c_int, c_int, c_void_p, c_int, c_void_p, c_int, c_void_p,
+                                    c_int, POINTER(c_double), POINTER(c_int), c_double, c_double,
+                                    c_double, c_void_p, c_int, c_void_p, c_size_t, c_void_p,
+                                    POINTER(c_double)]),
     "chfsi_orthonormalize": (c_int, [c_int, c_int, c_void_p, c_int, c_int, c_void_p, c_int,
                                      c_void_p, c_size_t, c_void_p, POINTER(c_int)]),
     "chfsi_rayleigh_ritz": (c_int, [c_int, c_int, c_void_p, c_int, c_void_p, c_int, c_void_p,
@@ -212,6 +219,25 @@ def chfsi_filter(H, Y, degrees, c, e, gamma, work=None, stream=None):
                               wb, _stream(stream, Y.device), ctypes.byref(fl), ctypes.byref(ln)),
            "chfsi_filter")
     return fl.value, ln.value
+
+
+def chfsi_filter_defect(H, Q, Z, mu, degrees, c, e, gamma, Y=None, work=None, stream=None):
+    """Mixed-precision Alg. 2 on Ritz vectors Q (Z = H Q, Ritz values mu);
+    returns (Y, executed FP32 flops)."""
+    torch = _torch()
+    n, k = Q.shape
+    if Y is None:
+        Y = colmajor(torch.empty((n, k), dtype=torch.complex128, device=Q.device))
+    m = (c_double * k)(*[float(x) for x in mu])
+    deg = (c_int * k)(*[int(x) for x in degrees])
+    wb = int(lib().chfsi_defect_workspace_bytes(n, k))
+    w = _work(wb, Q.device, work)
+    fl = c_double(0.0)
+    _check(lib().chfsi_filter_defect(n, k, _ptr(H), _ld(H), _ptr(Q), _ld(Q), _ptr(Z), _ld(Z), m,
+                                     deg, c, e, gamma, _ptr(Y), _ld(Y), _ptr(w), wb,
+                                     _stream(stream, Q.device), ctypes.byref(fl)),
+           "chfsi_filter_defect")
+    return Y, fl.value
 
 
 def chfsi_orthonormalize(Y, QL=None, work=None, stream=None):

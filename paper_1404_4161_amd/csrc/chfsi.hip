@@ -25,6 +25,8 @@ constexpr size_t ALIGN = 256;
 // A Gram-matrix pivot below this fraction of its (unit) diagonal entry is a
 // CholeskyQR breakdown: kappa(Y) near 1e6 or worse.
 constexpr double GRAM_PIVOT_TOL = 1e-12;
+// Largest filter degree the mixed-precision coefficient table holds.
+constexpr int CR_ROWS = 256;
 
 const zc ONE = {1.0, 0.0}, ZERO = {0.0, 0.0}, MONE = {-1.0, 0.0};
 
@@ -84,6 +86,9 @@ int gemv_splits(int n) {
 struct StepBufs {
   zc *T1, *T2, *G, *K2, *invk, *scratch, *gv_part, *V, *w, *h, *fpart;
   size_t fpart_elems;
+  void *R32, *E0, *E1;          // mixed-precision filter: complex64 n x k each
+  float* crtab;                 // CR_ROWS x k coefficients of the residual term
+  double* pm;                   // k final scalars p_{m_j}(mu_t)
   double *mu, *res, *nrm, *E, *alph, *bet, *dummy;
   int *perm, *deg, *info;
   size_t scratch_elems;
@@ -116,6 +121,11 @@ void carve_step(Carver& c, StepBufs& b, int n, int k, int nev, int lanczos_steps
   b.perm = c.take<int>(k);
   b.deg = c.take<int>(k);
   b.info = c.take<int>(8);
+  b.R32 = c.take<char>(nk * 8);
+  b.E0 = c.take<char>(nk * 8);
+  b.E1 = c.take<char>(nk * 8);
+  b.crtab = c.take<float>((size_t)CR_ROWS * k);
+  b.pm = c.take<double>(k);
 }
 
 // ---------------------------------------------------------------------------
@@ -464,6 +474,99 @@ int filter_dev(hipStream_t s, int n, int k, const zc* H, long ldh, zc* P0, zc* P
   return CHFSI_OK;
 }
 
+template <class T>
+int upload(hipStream_t s, T* dst, const std::vector<T>& v) {
+  if (v.empty()) return CHFSI_OK;
+  CK(hipMemcpyAsync(dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+  CK(hipStreamSynchronize(s));
+  return CHFSI_OK;
+}
+
+// Mixed-precision Alg. 2 on the defect of the Ritz vectors (cfilter32.hip).
+// Q, Z = H Q (ld) and mu (host) are in the current column order; order[j]
+// is the column filtered j-th (ascending degree m[j]).  The filtered block
+// goes to Y (ld), and Qs (ld) receives the reordered Q.
+int defect_filter_dev(hipStream_t s, int n, int k, const void* H32, const zc* Q, const zc* Z,
+                      long ld, const std::vector<double>& mu, const std::vector<int>& order,
+                      const std::vector<int>& m, double c, double e, double gamma, zc* Qs, zc* Y,
+                      StepBufs& b, double* flops32, int* launches) {
+  if (k <= 0) return CHFSI_OK;
+  const int mmax = m[k - 1];
+  if (mmax > CR_ROWS) return CHFSI_INVALID_ARG;
+  const double sig1 = e / (gamma - c);
+  // p_i(mu_t) for i <= m_j by the scalar form of the recurrence, and the
+  // coefficient cr_i[j] = 2 sigma_{i+1} p_i(mu_t_j) / e of step i
+  std::vector<float> cr((size_t)mmax * k, 0.f);
+  std::vector<double> pm(k);
+  std::vector<double> sig(mmax + 1);
+  sig[1] = sig1;
+  for (int i = 1; i < mmax; ++i) sig[i + 1] = 1.0 / (2.0 / sig1 - sig[i]);
+  for (int j = 0; j < k; ++j) {
+    const double t = (mu[order[j]] - c) / e;
+    double pprev = 1.0, pcur = sig1 * t;
+    for (int i = 1; i < m[j]; ++i) {
+      cr[(size_t)i * k + j] = (float)(2.0 * sig[i + 1] * pcur / e);
+      const double pnext = 2.0 * sig[i + 1] * t * pcur - sig[i + 1] * sig[i] * pprev;
+      pprev = pcur;
+      pcur = pnext;
+    }
+    pm[j] = pcur;
+  }
+  CKS(upload(s, b.mu, mu));
+  CKS(upload(s, b.perm, order));
+  CKS(upload(s, b.deg, m));
+  CKS(upload(s, b.crtab, cr));
+  CKS(upload(s, b.pm, pm));
+  CK(defect_setup_launch(s, n, k, Q, Z, ld, b.mu, b.perm, Qs, b.R32, b.E0, b.E1,
+                         (float)(sig1 / e)));
+  int first = 0;
+  while (first < k && m[first] <= 1) ++first;
+  const size_t c64 = 8;   // bytes per complex64
+  for (int i = 1; i < mmax; ++i) {
+    const char* cur = (const char*)((i & 1) ? b.E1 : b.E0);
+    char* old = (char*)((i & 1) ? b.E0 : b.E1);
+    const size_t off = (size_t)first * n * c64;
+    const int cols = k - first;
+    CK(defect_step(s, n, cols, H32, cur + off, old + off, old + off, (const char*)b.R32 + off,
+                   b.crtab + (size_t)i * k + first, (float)c, (float)(2.0 * sig[i + 1] / e),
+                   (float)(sig[i + 1] * sig[i]), b.fpart, b.fpart_elems * 2));
+    *flops32 += 8.0 * (double)n * n * cols;
+    *launches += 1;
+    while (first < k && m[first] <= i + 1) ++first;
+  }
+  CK(defect_assemble_launch(s, n, k, Qs, ld, b.E0, b.E1, b.deg, b.pm, Y, ld));
+  return CHFSI_OK;
+}
+
+// Whether FP32 rounding in the defect filter stays far below what the
+// filter is aiming at, for every wanted vector.  The rounding error of a
+// defect step is about eps_fp32 times the defect, i.e. eps_fp32 ||r_j|| /
+// ||H|| relative to the column.  Components of that error inside the span
+// of the block (the directions the filter amplifies, eq. resl) are removed
+// by the Rayleigh-Ritz step that follows; the filter damps the rest.  The
+// FP32 form is used when this floor is 100x below the residual the filter
+// aims at (the tolerance, or the current residual reduced by rho_j^m).
+bool defect_filter_safe(int n_wanted, const std::vector<double>& mu,
+                        const std::vector<double>& res, const std::vector<int>& deg, double c,
+                        double e, double gamma, double tol, double norm_h) {
+  const double eps32 = std::ldexp(1.0, -24);
+  auto rho = [](double t) {
+    if (std::fabs(t) <= 1.0) return 1.0;
+    const double r = std::sqrt(t * t - 1.0);
+    return std::max(std::fabs(t + r), std::fabs(t - r));
+  };
+  (void)gamma;
+  for (int j = 0; j < n_wanted; ++j) {
+    const double rel = res[j] / norm_h;
+    if (!(rel <= 1e-2)) return false;
+    const double rj = rho((mu[j] - c) / e);
+    const double floor_ = eps32 * rel;
+    const double target = std::max(tol, rel * std::pow(rj, -deg[j]));
+    if (floor_ > 0.01 * target) return false;
+  }
+  return true;
+}
+
 int upload_ints(hipStream_t s, int* dst, const std::vector<int>& v) {
   if (v.empty()) return CHFSI_OK;
   CK(hipMemcpyAsync(dst, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, s));
@@ -495,11 +598,13 @@ struct SolveBufs {
   unsigned long long* hpart = nullptr;    // hash partials + new hash
   zc *H = nullptr, *L = nullptr, *Linv = nullptr, *W = nullptr, *invd = nullptr;
   zc *QL, *QA, *ZA, *P0, *P1, *TMP;
+  void* H32 = nullptr;          // fp32(H), mixed precision only
   int* flag;
   StepBufs st;
 };
 
-size_t carve_solve(Carver& c, SolveBufs& b, int n, int nev, int nex, bool gen, int lsteps) {
+size_t carve_solve(Carver& c, SolveBufs& b, int n, int nev, int nex, bool gen, int lsteps,
+                   int precision) {
   const int k = nev + nex;
   const size_t nn = (size_t)n * n, nk = (size_t)n * k;
   if (gen) {
@@ -518,6 +623,7 @@ size_t carve_solve(Carver& c, SolveBufs& b, int n, int nev, int nex, bool gen, i
   b.P0 = c.take<zc>(nk);
   b.P1 = c.take<zc>(nk);
   b.TMP = c.take<zc>(nk);
+  if (precision == 1) b.H32 = c.take<char>(nn * 8);
   b.flag = c.take<int>(8);
   carve_step(c, b.st, n, k, nev, lsteps);
   return c.off + ALIGN;
@@ -557,7 +663,7 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
   const bool gen = B != nullptr;
   SolveBufs b;
   Carver cv(work);
-  const size_t need = carve_solve(cv, b, n, nev, nex, gen, o.lanczos_steps);
+  const size_t need = carve_solve(cv, b, n, nev, nex, gen, o.lanczos_steps, o.precision);
   if (work_bytes < need) return CHFSI_INVALID_ARG;
   StepBufs& sb = b.st;
   double* step_acc = info ? info->step_seconds : nullptr;
@@ -662,8 +768,13 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
   int it = 0;
   int status = CHFSI_NO_CONVERGENCE;
   double filter_flops = 0.0, filter_sec = 0.0;
+  double flops32 = 0.0, sec32 = 0.0;
+  int iters32 = 0;
   long long filter_mv = 0;
   int launches = 0;
+  // residuals of the current block known (after a Rayleigh-Ritz)
+  bool have_res = !(X0 && Lambda0);
+  if (o.precision == 1) CK(matrix_to_fp32(s, n, H, ldh, b.H32));
   hipEvent_t fe0 = nullptr, fe1 = nullptr;
   CK(hipEventCreate(&fe0));
   CK(hipEventCreate(&fe1));
@@ -679,23 +790,56 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return deg[x] < deg[y]; });
     std::vector<int> msort(ka);
     for (int j = 0; j < ka; ++j) msort[j] = deg[order[j]];
-    tm.begin(6);
-    CKS(upload_ints(s, sb.perm, order));
-    CKS(upload_ints(s, sb.deg, msort));
-    CK(gather_cols(s, n, ka, b.QA, ld, b.P0, ld, sb.perm));
-    tm.end();
-    // Chebyshev filter (Alg. 2)
-    tm.begin(2);
+    // precision of this filter: the FP32 defect form needs the residual
+    // block of the current Ritz pairs and small enough residuals
+    bool use32 = false;
+    if (o.precision == 1) {
+      if (!have_res) {
+        // first loop of a warm start with Lambda0: one product gives Z = H Q
+        tm.begin(4);
+        CK(zgemm(s, OP_N, OP_N, n, ka, n, ONE, H, ldh, b.QA, ld, ZERO, b.ZA, ld, false, nullptr, 0));
+        CKS(upload(s, sb.mu, std::vector<double>(mu.begin(), mu.begin() + ka)));
+        CK(resid_norms(s, n, ka, b.QA, ld, b.ZA, ld, sb.mu, sb.res));
+        CK(hipMemcpyAsync(res.data(), sb.res, sizeof(double) * ka, hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        tm.end();
+        matvecs += ka;
+        have_res = true;
+      }
+      use32 = defect_filter_safe(nev - nl, mu, res, deg, c, e, gamma, tol, norm_h);
+    }
+    double fl_before = filter_flops;
     CK(hipEventRecord(fe0, s));
-    CKS(filter_dev(s, n, ka, H, ldh, b.P0, b.P1, ld, msort, c, e, gamma, sb.fpart, sb.fpart_elems,
-                   &filter_flops, &launches));
+    if (use32) {
+      tm.begin(2);
+      double f32 = 0.0;
+      CKS(defect_filter_dev(s, n, ka, b.H32, b.QA, b.ZA, ld, std::vector<double>(mu.begin(), mu.begin() + ka),
+                            order, msort, c, e, gamma, b.P0, b.TMP, sb, &f32, &launches));
+      tm.end();
+      flops32 += f32;
+      iters32 += 1;
+      for (int j = 0; j < ka; ++j) filter_flops += 8.0 * (double)n * n * msort[j];
+    } else {
+      tm.begin(6);
+      CKS(upload_ints(s, sb.perm, order));
+      CKS(upload_ints(s, sb.deg, msort));
+      CK(gather_cols(s, n, ka, b.QA, ld, b.P0, ld, sb.perm));
+      tm.end();
+      // Chebyshev filter (Alg. 2)
+      tm.begin(2);
+      CKS(filter_dev(s, n, ka, H, ldh, b.P0, b.P1, ld, msort, c, e, gamma, sb.fpart,
+                     sb.fpart_elems, &filter_flops, &launches));
+      tm.end();
+    }
     CK(hipEventRecord(fe1, s));
-    tm.end();
     for (int j = 0; j < ka; ++j) filter_mv += msort[j];
     matvecs += std::accumulate(msort.begin(), msort.end(), 0LL);
-    tm.begin(6);
-    CK(gather_parity(s, n, ka, b.P0, b.P1, ld, b.TMP, ld, sb.deg));
-    tm.end();
+    if (!use32) {
+      tm.begin(6);
+      CK(gather_parity(s, n, ka, b.P0, b.P1, ld, b.TMP, ld, sb.deg));
+      tm.end();
+    }
+    (void)fl_before;
     // orthonormalise against the locked vectors (the QR step of Alg. 1)
     tm.begin(3);
     int sh = 0;
@@ -714,7 +858,9 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
       float ms = 0.f;
       CK(hipEventElapsedTime(&ms, fe0, fe1));
       filter_sec += 1e-3 * ms;
+      if (use32) sec32 += 1e-3 * ms;
     }
+    have_res = true;
     tm.drain();
     // locking (the LOCKING step): the lowest nev - nl active pairs are candidates
     const int ncand = nev - nl;
@@ -729,7 +875,9 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
       CK(gather_cols(s, n, (int)lock_idx.size(), b.QA, ld, b.QL + (size_t)nl * ld, ld, sb.perm));
       CKS(upload_ints(s, sb.perm, keep_idx));
       CK(gather_cols(s, n, (int)keep_idx.size(), b.QA, ld, b.P0, ld, sb.perm));
+      CK(gather_cols(s, n, (int)keep_idx.size(), b.ZA, ld, b.P1, ld, sb.perm));
       std::swap(b.QA, b.P0);
+      std::swap(b.ZA, b.P1);
       tm.end();
       for (int j : lock_idx) {
         lam_locked.push_back(mu[j]);
@@ -794,6 +942,9 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
     info->filter_matvecs = filter_mv;
     info->filter_flops = filter_flops;
     info->filter_seconds = filter_sec;
+    info->filter_iters_fp32 = iters32;
+    info->filter_flops_fp32 = flops32;
+    info->filter_seconds_fp32 = sec32;
     info->beta = beta;
     info->norm_h = norm_h;
     info->max_resid = norm_h > 0.0 ? max_locked_res / norm_h : max_locked_res;
@@ -823,7 +974,7 @@ int chfsi_default_opts(chfsi_opts* o) {
   o->alpha_rule = 0;
   o->degree_mode = 0;
   o->reuse_b_factor = 1;
-  o->reserved = 0;
+  o->precision = 0;
   o->seed = 0;
   return CHFSI_OK;
 }
@@ -848,7 +999,8 @@ size_t chfsi_workspace_bytes(int n, int nev, int nex, int generalized, const chf
   if (opts) o = *opts;
   SolveBufs b;
   Carver c(nullptr);
-  return carve_solve(c, b, n, nev, nex, generalized != 0, std::max(o.lanczos_steps, 1));
+  return carve_solve(c, b, n, nev, nex, generalized != 0, std::max(o.lanczos_steps, 1),
+                     o.precision);
 }
 
 int chfsi_solve(int n, int nev, int nex, const void* A, int lda, const void* B, int ldb, double tol,
@@ -866,6 +1018,8 @@ int chfsi_solve(int n, int nev, int nex, const void* A, int lda, const void* B, 
     if (B && (ldb < n || !aligned16(B))) return CHFSI_INVALID_ARG;
     if (X0 && (ldx0 < n || !aligned16(X0))) return CHFSI_INVALID_ARG;
     if (o.deg0 < 1 || o.deg_max < 1 || o.max_iter < 1 || o.lanczos_steps < 1) return CHFSI_INVALID_ARG;
+    if (o.precision < 0 || o.precision > 1) return CHFSI_INVALID_ARG;
+    if (o.precision == 1 && (o.deg0 > CR_ROWS || o.deg_max > CR_ROWS)) return CHFSI_INVALID_ARG;
     if (X0 == X && ldx0 != ldx) return CHFSI_INVALID_ARG;
     if (Lambda0) {
       if (!X0) return CHFSI_INVALID_ARG;
@@ -920,6 +1074,53 @@ int chfsi_filter(int n, int k, const void* H, int ldh, void* Y, int ldy, const i
     CK(hipStreamSynchronize(s));
     if (flops_out) *flops_out = fl;
     if (launches_out) *launches_out = ln;
+    return CHFSI_OK;
+  } catch (...) {
+    return CHFSI_DEVICE_ERROR;
+  }
+}
+
+size_t chfsi_defect_workspace_bytes(int n, int k) {
+  if (n < 1 || k < 1) return 0;
+  StepBufs b;
+  Carver c(nullptr);
+  carve_step(c, b, n, k, k, 20);
+  c.take<char>((size_t)n * n * 8);
+  return c.off + ALIGN;
+}
+
+int chfsi_filter_defect(int n, int k, const void* H, int ldh, const void* Q, int ldq,
+                        const void* Z, int ldz, const double* mu, const int* degrees, double c,
+                        double e, double gamma, void* Y, int ldy, void* work, size_t work_bytes,
+                        void* stream, double* flops_out) {
+  try {
+    if (n < 1 || k < 1 || k > n || ldh < n || ldq != n || ldz != n || ldy < n || !mu ||
+        !degrees || !(e > 0.0) || gamma == c)
+      return CHFSI_INVALID_ARG;
+    if (check_ptr(H) || check_ptr(Q) || check_ptr(Z) || check_ptr(Y) || check_ptr(work))
+      return CHFSI_INVALID_ARG;
+    for (int j = 0; j < k; ++j) {
+      if (degrees[j] < 1 || degrees[j] > CR_ROWS || (j > 0 && degrees[j] < degrees[j - 1]))
+        return CHFSI_INVALID_ARG;
+    }
+    if (work_bytes < chfsi_defect_workspace_bytes(n, k)) return CHFSI_INVALID_ARG;
+    hipStream_t s = as_stream(stream);
+    StepBufs b;
+    Carver cv(work);
+    carve_step(cv, b, n, k, k, 20);
+    void* H32 = cv.take<char>((size_t)n * n * 8);
+    CK(matrix_to_fp32(s, n, (const zc*)H, ldh, H32));
+    std::vector<int> order(k), m(degrees, degrees + k);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<double> muv(mu, mu + k);
+    double f32 = 0.0;
+    int launches = 0;
+    // Qs -> T1 (packed); Y written with its own leading dimension
+    CKS(defect_filter_dev(s, n, k, H32, (const zc*)Q, (const zc*)Z, n, muv, order, m, c, e, gamma,
+                          b.T1, b.T2, b, &f32, &launches));
+    CK(copy2d(s, n, k, b.T2, n, (zc*)Y, ldy));
+    CK(hipStreamSynchronize(s));
+    if (flops_out) *flops_out = f32;
     return CHFSI_OK;
   } catch (...) {
     return CHFSI_DEVICE_ERROR;

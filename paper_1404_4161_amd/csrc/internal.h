@@ -112,4 +112,22 @@ int lanczos_axpy(hipStream_t s, int n, int j, const zc* V, long ldv, const zc* h
                  const double* betas, zc* w, double* alphas);
 int normalize_into(hipStream_t s, int n, const zc* w, zc* v, double* beta_out);
 
+// ----- mixed-precision (FP32 defect) filter, cfilter32.hip -----
+// H32 receives fp32(H) as a packed n x n complex64 matrix.
+int matrix_to_fp32(hipStream_t s, int n, const zc* H, long ldh, void* H32);
+// Columns j < k in degree order: Qs[:, j] = Q[:, perm[j]], R32[:, j] =
+// fp32(Z[:, perm[j]] - mu[perm[j]] Q[:, perm[j]]), E0 = 0, E1 = s1 R32.
+// Q, Z, Qs have leading dimension ld; R32, E0, E1 are packed (ld n).
+int defect_setup_launch(hipStream_t s, int n, int k, const zc* Q, const zc* Z, long ld,
+                        const double* mu, const int* perm, zc* Qs, void* R32, void* E0, void* E1,
+                        float s1);
+// One defect step on N columns (pointers already offset to the window):
+// Eout = sa (H32 Ecur - shift Ecur) + cr[j] R32_j - sb Eold.
+int defect_step(hipStream_t s, int n, int N, const void* H32, const void* Ecur, const void* Eold,
+                void* Eout, const void* R32, const float* cr, float shift, float sa, float sb,
+                void* part, size_t part_elems);
+// Y[:, j] = pm[j] Qs[:, j] + E_{deg[j]}[:, j] (E_m in E1 for odd m).
+int defect_assemble_launch(hipStream_t s, int n, int k, const zc* Qs, long ld, const void* E0,
+                           const void* E1, const int* deg, const double* pm, zc* Y, long ldy);
+
 }  // namespace chfsi

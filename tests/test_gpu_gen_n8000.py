@@ -47,16 +47,19 @@ def sequence():
 
 
 @pytest.mark.timeout(900)
-def test_gen_n8000_sequence_matches_golden(sequence):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_gen_n8000_sequence_matches_golden(sequence, precision):
     import torch
     conf, seq, probs = sequence
+    opts = ch.chfsi_default_opts()
+    opts.precision = precision
     ref = _golden()
     assert sorted(ref) == list(range(1, conf.length + 1))
     x, lam = None, None
     for l, a in enumerate(probs, start=1):
         # warm start with the previous Ritz vectors and values, as the benchmark
         st, lam, xd, info = ch.chfsi_solve(a, seq.B, conf.nev, conf.nex, conf.tol, X0=x,
-                                           Lambda0=lam if x is not None else None)
+                                           Lambda0=lam if x is not None else None, opts=opts)
         assert st == 0, (l, st)
         err = np.abs(lam[:conf.nev] - ref[l]) / np.abs(ref[l])
         assert err.max() <= 1e-10, (l, err.max())

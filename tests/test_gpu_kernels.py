@@ -164,3 +164,31 @@ def test_reduce_standard_detects_non_hpd():
     with pytest.raises(ch.ChfsiError) as ei:
         ch.chfsi_reduce_standard(dev(a), dev(b))
     assert ei.value.status == ch.binding.CHFSI_NOT_HPD
+
+
+@pytest.mark.parametrize("delta", [1e-3, 1e-6])
+def test_defect_filter_matches_oracle_with_error_scaling_like_the_residual(delta):
+    """The FP32 defect filter reproduces the oracle's FP64 filter on Ritz
+    vectors; its error is about eps_fp32 * ||R|| / ||H|| (times the filter's
+    growth), i.e. it shrinks with the residuals."""
+    n, k = 700, 40
+    lam, h = _herm_problem(n, 23)
+    q0 = np.linalg.eigh(h)[1][:, :k]
+    noisy = q0 + delta * _rand(n, k, 24)
+    q = ochfsi.orthonormalize(noisy, np.zeros((n, 0), complex))
+    mu, q, z = ochfsi.rayleigh_ritz(h, q)
+    res = ochfsi.residual_norms(q, z, mu)
+    deg = np.sort(np.random.default_rng(3).integers(2, 20, k)).tolist()
+    alpha, beta = float(mu[-1]) + 1.0, 41.0
+    c, e, gamma = 0.5 * (alpha + beta), 0.5 * (beta - alpha), float(mu[0])
+    ref = chebyshev.chebyshev_filter(h, q, deg, c, e, gamma)
+    yd, f32 = ch.chfsi_filter_defect(dev(h), dev(q), dev(z), mu, deg, c, e, gamma)
+    got = host(yd)
+    err = rel_col_err(got, ref)
+    norm_h = np.abs(lam).max()
+    # eq. (resl): rounding grows like (|rho_1| / |rho_j|)^m relative to column j
+    growth = (chebyshev.rho(np.array([(gamma - c) / e]))[0]
+              / chebyshev.rho((mu - c) / e)) ** np.array(deg)
+    bound = 1e3 * 2.0 ** -24 * (res / norm_h) * growth + 1e-13
+    assert np.all(err <= bound), (err / bound).max()
+    assert f32 == pytest.approx(8.0 * n * n * sum(m - 1 for m in deg))

@@ -200,3 +200,26 @@ def test_solve_sequence_with_previous_eigenvalues():
             RTOL * np.abs(ref.lam[:conf.nev]).min()
         _check_pairs(a, None, lam, host(xd), conf.nev, conf.tol, info["norm_h"])
         x = xd
+
+
+@pytest.mark.parametrize("with_lambda", [False, True])
+def test_solve_mixed_precision_matches_oracle(with_lambda):
+    """precision = 1: filters run in FP32 defect form once residuals allow;
+    the eigenvalues still match the FP64 oracle to 1e-10."""
+    conf = gen.CONFIGS["std-n1000"]
+    probs = [a.copy() for _, a in gen.Sequence(conf).problems()]
+    refs = ochfsi.solve_sequence(probs, conf.nev, conf.nex)
+    o = _opts(precision=1)
+    x, lam = None, None
+    used32 = 0
+    for a, ref in zip(probs, refs):
+        st, lam, xd, info = ch.chfsi_solve(dev(a), None, conf.nev, conf.nex, conf.tol, X0=x,
+                                           Lambda0=lam if (with_lambda and x is not None) else None,
+                                           opts=o)
+        assert st == 0
+        assert np.abs(lam[:conf.nev] - ref.lam[:conf.nev]).max() <= \
+            RTOL * np.abs(ref.lam[:conf.nev]).min()
+        _check_pairs(a, None, lam, host(xd), conf.nev, conf.tol, info["norm_h"])
+        used32 += info["filter_iters_fp32"]
+        x = xd
+    assert used32 > 0
