@@ -114,12 +114,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gen-n8000", choices=["gen-n8000", "std-n1000"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-degree", type=int, default=6)
+    ap.add_argument("--cpu-degree", type=int, default=40)
     ap.add_argument("--filter-only", action="store_true",
                     help="time only the Chebyshev filter at the workload shape (n x k block, "
                          "uniform degree) after a 1 GiB device copy used to calibrate "
                          "hardware byte counters; for profiler runs")
     ap.add_argument("--degree", type=int, default=4)
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training the degree network and the learned-degree sequences")
+    ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--no-lambda0", action="store_true",
                     help="warm-start from the previous Ritz vectors only (one extra QR + "
                          "Rayleigh-Ritz per problem) instead of vectors and values")
@@ -167,6 +170,34 @@ def main():
     work = torch.empty(wb, dtype=torch.uint8, device=dev)
     X = ch.colmajor(torch.empty((n, k), dtype=torch.complex128, device=dev))
 
+    # Degree network (untimed): convergence logs of a sequence with the same
+    # recipe under another seed, then training with the library's kernels.
+    blob, train_report = None, None
+    if not args.no_learned:
+        from paper_1404_4161_amd import learned
+        t0 = time.perf_counter()
+        tconf = gen.variant(conf, conf.cfg + 100)
+        tseq = gen.Sequence(tconf, kind="torch", device=dev)
+        tprobs = [a.clone() for l, a in tseq.problems() if l <= min(tconf.length, total)]
+        buf = learned.LogBuffer(400_000)
+        tw = torch.empty(wb, dtype=torch.uint8, device=dev)
+        collect = []
+        for prec, jit in ((0, 0.0), (0, 0.3)):
+            o = ch.chfsi_default_opts()
+            o.precision, o.first_rule, o.degree_jitter, o.seed = prec, 1, jit, 7
+            its = [i["iters"] for i in learned.solve_sequence_logged(
+                tprobs, tseq.B, nev, nex, conf.tol, o, buf, work=tw)]
+            collect.append({"precision": prec, "jitter": jit, "iters": its})
+        del tprobs, tseq, tw
+        torch.cuda.empty_cache()
+        tc = time.perf_counter()
+        blob, train_report = learned.fit(buf.records(), steps=args.train_steps)
+        train_report["train_seconds"] = round(time.perf_counter() - tc, 2)
+        train_report["collect_seconds"] = round(tc - t0, 2)
+        train_report["log_runs"] = collect
+        train_report["training_sequence"] = f"{conf.name} recipe, seed namespace {tconf.cfg}"
+        log(f"degree network: {train_report}")
+
     def run_sequence(opts, label):
         """Warm-up problem(s), then the timed steps; returns per-step infos,
         wall times, eigenvalues and the elapsed time of the timed region."""
@@ -175,7 +206,8 @@ def main():
         def solve(a):
             st, lam, x, info = ch.chfsi_solve(
                 a, B, nev, nex, conf.tol, X0=x_prev, opts=opts, X=X, work=work, stream=stream,
-                Lambda0=None if (args.no_lambda0 or x_prev is None) else lam_prev)
+                Lambda0=None if (args.no_lambda0 or x_prev is None) else lam_prev,
+                mlp=blob if opts.degree_mode == 2 else None)
             if st != 0:
                 raise RuntimeError(f"chfsi_solve status {st}")
             return lam, info
@@ -203,6 +235,14 @@ def main():
 
     infos, walls, lams64, elapsed = run_sequence(opts0, "fp64")
     minfos, mwalls, lams32, melapsed = run_sequence(opts1, "mixed")
+    learned_runs = {}
+    if blob is not None:
+        # mixed: the first loop of a warm start stays at deg0 (FP32 defect
+        # form); FP64: the first loop's degrees come from X0's residuals
+        for label, prec, fr in (("mixed+learned", 1, 0), ("fp64+learned", 0, 1)):
+            o = ch.chfsi_default_opts()
+            o.precision, o.degree_mode, o.first_rule = prec, 2, fr
+            learned_runs[label] = run_sequence(o, label)
 
     flops = sum(i["filter_flops"] for i in infos)
     fsec = sum(i["filter_seconds"] for i in infos)
@@ -271,6 +311,30 @@ def main():
             "max_rel_eig_diff_vs_fp64_per_step": eig_diff,
         },
     }
+    for label, (linfos, lwalls, llams, lelapsed) in learned_runs.items():
+        lph = np.sum([i["step_seconds"] for i in linfos], axis=0) / args.steps
+        out[label] = {
+            "precision": "FP32 defect filter where the residuals allow" if label.startswith("mixed")
+                         else "FP64 filter",
+            "degrees": "learned (network trained on logs of another sequence; rule fallback)",
+            "first_loop_degrees": ("deg0" if label.startswith("mixed") else
+                                   "from the residuals of X0 (one extra product H X0)"),
+            "ms_per_step": round(1e3 * lelapsed / args.steps, 3),
+            "s_per_sequence_step_median": round(statistics.median(lwalls), 4),
+            "speedup_vs_fp64_per_step": round(elapsed / lelapsed, 3),
+            "iters_per_step": [i["iters"] for i in linfos],
+            "fp32_filter_loops_per_step": [i["filter_iters_fp32"] for i in linfos],
+            "filter_matvecs_per_step": [i["filter_matvecs"] for i in linfos],
+            "learned_cols": sum(i["learned_cols"] for i in linfos),
+            "fallback_cols": sum(i["fallback_cols"] for i in linfos),
+            "learned_raised_cols": sum(i["learned_raised"] for i in linfos),
+            "phase_seconds_per_step": {nm: round(float(v), 4) for nm, v in zip(phase_names, lph)},
+            "max_rel_eig_diff_vs_fp64_per_step": [
+                float(np.max(np.abs(a - b) / np.abs(a))) for a, b in zip(lams64, llams)],
+        }
+    out["fp64_filter_matvecs_per_step"] = [i["filter_matvecs"] for i in infos]
+    if train_report is not None:
+        out["degree_network"] = train_report
     if not args.no_cpu_baseline:
         del problems
         torch.cuda.empty_cache()

@@ -55,7 +55,12 @@ extern "C" {
  *   alpha_rule    lower end of the damped interval: 0 = largest Ritz value
  *                 of the block, 1 = the (nev+1)-th Ritz value [Sec. 3.1].
  *   degree_mode   0 = per-vector analytic degrees [Sec. 3.1.1], 1 = fixed
- *                 deg0 for every vector and loop.
+ *                 deg0 for every vector and loop, 2 = learned: a network
+ *                 predicts how fast each vector converges compared with
+ *                 the analytic model and the degree is scaled to match
+ *                 (see chfsi_degrees_learned); the analytic degree stays
+ *                 the floor of every learned degree and the fallback for
+ *                 inputs outside the network's training range.
  *   reuse_b_factor  1 (default): keep the Cholesky factor of B and its
  *                 inverse in the workspace and reuse them on the next call
  *                 with the same workspace when B is bitwise unchanged (a
@@ -71,7 +76,24 @@ extern "C" {
  *                 E = p(Ht) Q - Q p(mu_t) of the Ritz vectors Q; QR,
  *                 Rayleigh-Ritz, residuals and locking stay FP64.
  *   seed          seed of the SplitMix64 counter-based generator used for
- *                 the Lanczos start vector and a random start block. */
+ *                 the Lanczos start vector and a random start block.
+ *   degree_jitter 0 (default), or s > 0: every wanted vector's degree m is
+ *                 replaced by round(m * exp(s * u)), u uniform in [-1, 1]
+ *                 from the counter generator (stream 3, counter = loop *
+ *                 k + column), clamped to [1, deg_max].  Used to collect
+ *                 convergence logs over a range of degrees.
+ *   first_rule    0 (default): the first loop uses deg0 [Alg. 1].  1: in a
+ *                 warm start with Lambda0, the residuals of X0 are computed
+ *                 first (one product H X0) and the first loop's degrees
+ *                 come from the degree rule in force (Sec. 3.1.1 applies
+ *                 once the residuals are known).  The mixed path computes
+ *                 those residuals anyway.
+ *   log, log_capacity  HOST buffer of log_capacity records of
+ *                 CHFSI_LOG_FIELDS doubles, or NULL: one record per
+ *                 filtered wanted vector and loop (layout below).  The
+ *                 number written is info->log_records.
+ *   mlp           HOST, CHFSI_MLP_PARAMS floats: the degree network used by
+ *                 degree_mode 2 (required then; read once per call). */
 typedef struct chfsi_opts {
   double tol;
   int deg0;
@@ -83,6 +105,11 @@ typedef struct chfsi_opts {
   int reuse_b_factor;
   int precision;
   unsigned long long seed;
+  double degree_jitter;
+  int first_rule;
+  int log_capacity;
+  double* log;
+  const float* mlp;
 } chfsi_opts;
 
 /* Per-solve statistics (all optional to read).
@@ -107,7 +134,38 @@ typedef struct chfsi_info {
   double step_seconds[8];
   double filter_flops_fp32;   /* FP32 GEMM flops executed by defect filters      */
   double filter_seconds_fp32; /* device time of the defect filters               */
+  int log_records;         /* records written to opts->log                       */
+  int learned_cols;        /* wanted column degrees taken from the network       */
+  int fallback_cols;       /* wanted column degrees that fell back to the rule   */
+  int learned_raised;      /* network degrees above the rule's degree            */
 } chfsi_info;
+
+/* Convergence log record (CHFSI_LOG_FIELDS doubles), one per wanted vector
+ * j of the active block filtered in a loop:
+ *   0 loop (1-based)       1 j (position in the active block, ascending mu)
+ *   2 wanted columns left  3 active block size
+ *   4 mu_j before          5 res_j before (||H q - mu q||)
+ *   6 gap_j = distance to the nearest other Ritz value of the block
+ *   7 alpha  8 beta  9 gamma   10 norm_h   11 tol * norm_h
+ *   12 degree used         13 degree of the analytic rule
+ *   14 res at position j after the loop's Rayleigh-Ritz
+ *   15 flags: 1 FP32 defect filter, 2 degree from the network,
+ *             4 network fallback to the rule, 8 jittered, 16 capped at
+ *             the reach of one FP32 loop
+ *   16..23 the network's input features (chfsi_degree_features). */
+#define CHFSI_LOG_FIELDS 24
+
+/* Degree network: an 8 -> 64 -> 64 -> 1 perceptron with tanh activations
+ * in FP32.  Parameter blob (CHFSI_MLP_PARAMS floats):
+ *   [0, 8) feature means, [8, 16) feature scales (inputs are standardised
+ *   as (x - mean) / scale), [16, 528) W1 (64 x 8 row-major), [528, 592) b1,
+ *   [592, 4688) W2 (64 x 64 row-major), [4688, 4752) b2, [4752, 4816) w3,
+ *   [4816] b3, [4817] margin.
+ * Output: y ~ ln(observed log-reduction of the residual per degree /
+ * ln|rho_j|), the log of the vector's convergence speed relative to the
+ * analytic model of Sec. 3.1.1 (eq. resl). */
+#define CHFSI_MLP_FEATURES 8
+#define CHFSI_MLP_PARAMS 4818
 
 /* Fill *o with the defaults listed above.  Returns CHFSI_OK, or
  * CHFSI_INVALID_ARG for o == NULL. */
@@ -257,6 +315,59 @@ int chfsi_reduce_standard(int n, const void* A, int lda, const void* B, int ldb,
  *   mu, res  HOST, k doubles.   deg  HOST, k ints out. */
 int chfsi_degrees(int k, const double* mu, const double* res, int n_wanted,
                   double alpha, double beta, double tol_abs, int deg_max, int* deg);
+
+/* Input features of the degree network for wanted vector j (host only),
+ * with t = (mu_j - c)/e, c, e from alpha and beta, |rho| = |t| + sqrt(t^2-1):
+ *   f0 = ln(max(res_j, tol_abs) / tol_abs)   f1 = ln(ln|rho|)
+ *   f2 = ln(max(f0 / ln|rho|, 1/2))          f3 = ln|t|
+ *   f4 = (mu_j - gamma) / (alpha - gamma)    f5 = ln(max(gap_j / e, 1e-12))
+ *   f6 = ln(max(res_j, 1e-300) / norm_h)     f7 = min(loop - 1, 4)
+ * Writes 8 doubles to f and returns CHFSI_OK, or CHFSI_INVALID_ARG when
+ * |t| <= 1 (no analytic rate; such vectors take the guard degree). */
+int chfsi_degree_features(double mu, double res, double gap, double alpha, double beta,
+                          double gamma, double norm_h, double tol_abs, int loop, double* f);
+
+/* Learned per-vector degrees (degree_mode 2), the network run by the
+ * library's HIP kernel: for wanted vector j with features f (above) and
+ * prediction y, m_j = max(ceil(m_a * exp(margin - y)), r_j) clamped to
+ * [1, deg_max], with m_a = f0 / ln|rho| the analytic continuous degree and
+ * r_j the analytic degree (chfsi_degrees).  r_j is used alone when
+ * |t_j| <= 1, when a standardised feature lies outside [-6, 6] or when y is
+ * not finite.  The blob's margin is applied only when the loop can finish
+ * every wanted vector, i.e. every ceil(m_a * exp(-y)) (m_a for the rule's
+ * vectors) is <= deg_max; otherwise margin 0 is used.  In the solver's
+ * mixed mode a loop that must be capped to FP32's reach also uses margin 0.
+ * Guards and the vectors without a rate get the largest wanted degree.
+ *   mu, res   HOST, k doubles (ascending mu).  params HOST blob.
+ *   deg       HOST, k ints out.  pred, src: HOST k floats / ints out or NULL
+ *             (src: 0 rule fallback, 1 network, 2 guard fill).
+ *   work      device, >= chfsi_mlp_workspace_bytes(k). */
+int chfsi_degrees_learned(int k, const double* mu, const double* res, int n_wanted,
+                          double alpha, double beta, double gamma, double norm_h, double tol_abs,
+                          int loop, int deg_max, const float* params, void* work,
+                          size_t work_bytes, void* stream, int* deg, float* pred, int* src);
+
+/* Training and inference kernels of the degree network (device buffers,
+ * FP32).  X is n x 8 row-major, T and y hold n floats, params / grad / m /
+ * v hold CHFSI_MLP_PARAMS floats.
+ *   chfsi_mlp_forward:  y = net(X).
+ *   chfsi_mlp_gradient: grad = d/dparams of (1/n) sum (net(X_s) - T_s)^2
+ *     (zero for the statistics and the margin), loss (device, 1 float) =
+ *     sum of squared errors.  Sums run in a fixed order (deterministic).
+ *   chfsi_mlp_adam:     one Adam step (beta1 0.9, beta2 0.999, eps 1e-8,
+ *     bias-corrected, step number t >= 1) on the weights and biases.
+ *   chfsi_mlp_train:    `steps` full-batch Adam steps from params (in/out),
+ *     moments starting at zero; loss_out HOST (steps floats, mean squared
+ *     error before each step) or NULL.
+ * work >= chfsi_mlp_workspace_bytes(n). */
+size_t chfsi_mlp_workspace_bytes(int n);
+int chfsi_mlp_forward(int n, const float* X, const float* params, float* y, void* stream);
+int chfsi_mlp_gradient(int n, const float* X, const float* T, const float* params, float* grad,
+                       float* loss, void* work, size_t work_bytes, void* stream);
+int chfsi_mlp_adam(float* params, const float* grad, float* m, float* v, float lr, int t,
+                   void* stream);
+int chfsi_mlp_train(int n, const float* X, const float* T, float* params, int steps, float lr,
+                    void* work, size_t work_bytes, void* stream, float* loss_out);
 
 /* General complex GEMM on the library's MFMA kernels:
  * C <- alpha op(A) op(B) + beta C with op in {'N', 'C'} (no-op or conjugate

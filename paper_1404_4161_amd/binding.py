@@ -10,8 +10,8 @@ from __future__ import annotations
 import ctypes
 import os
 import re
-from ctypes import (POINTER, Structure, c_char, c_double, c_int, c_longlong, c_size_t,
-                    c_ulonglong, c_void_p)
+from ctypes import (POINTER, Structure, c_char, c_double, c_float, c_int, c_longlong,
+                    c_size_t, c_ulonglong, c_void_p)
 
 import numpy as np
 
@@ -21,12 +21,17 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "chfsi.h")
 
 CHFSI_OK, CHFSI_INVALID_ARG, CHFSI_NOT_HPD, CHFSI_NO_CONVERGENCE = 0, 1, 2, 3
 CHFSI_NONFINITE, CHFSI_DEVICE_ERROR, CHFSI_ALLOC_ERROR = 4, 5, 6
+CHFSI_LOG_FIELDS = 24
+CHFSI_MLP_FEATURES = 8
+CHFSI_MLP_PARAMS = 4818
 
 
 class ChfsiOpts(Structure):
     _fields_ = [("tol", c_double), ("deg0", c_int), ("deg_max", c_int), ("max_iter", c_int),
                 ("lanczos_steps", c_int), ("alpha_rule", c_int), ("degree_mode", c_int),
-                ("reuse_b_factor", c_int), ("precision", c_int), ("seed", c_ulonglong)]
+                ("reuse_b_factor", c_int), ("precision", c_int), ("seed", c_ulonglong),
+                ("degree_jitter", c_double), ("first_rule", c_int), ("log_capacity", c_int),
+                ("log", POINTER(c_double)), ("mlp", POINTER(c_float))]
 
 
 class ChfsiInfo(Structure):
@@ -38,10 +43,11 @@ class ChfsiInfo(Structure):
                 ("filter_seconds", c_double), ("total_seconds", c_double),
                 ("max_resid", c_double), ("beta", c_double), ("norm_h", c_double),
                 ("step_seconds", c_double * 8), ("filter_flops_fp32", c_double),
-                ("filter_seconds_fp32", c_double)]
+                ("filter_seconds_fp32", c_double), ("log_records", c_int),
+                ("learned_cols", c_int), ("fallback_cols", c_int), ("learned_raised", c_int)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("step_seconds", "reserved")}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "step_seconds"}
         d["step_seconds"] = list(self.step_seconds)
         return d
 
@@ -75,6 +81,19 @@ _SIGS = {
                                       c_void_p, c_int, c_void_p, c_size_t, c_void_p]),
     "chfsi_degrees": (c_int, [c_int, POINTER(c_double), POINTER(c_double), c_int, c_double,
                               c_double, c_double, c_int, POINTER(c_int)]),
+    "chfsi_degree_features": (c_int, [c_double, c_double, c_double, c_double, c_double, c_double,
+                                      c_double, c_double, c_int, POINTER(c_double)]),
+    "chfsi_degrees_learned": (c_int, [c_int, POINTER(c_double), POINTER(c_double), c_int, c_double,
+                                      c_double, c_double, c_double, c_double, c_int, c_int,
+                                      POINTER(c_float), c_void_p, c_size_t, c_void_p,
+                                      POINTER(c_int), POINTER(c_float), POINTER(c_int)]),
+    "chfsi_mlp_workspace_bytes": (c_size_t, [c_int]),
+    "chfsi_mlp_forward": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "chfsi_mlp_gradient": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_size_t, c_void_p]),
+    "chfsi_mlp_adam": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_int, c_void_p]),
+    "chfsi_mlp_train": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_int, c_float, c_void_p,
+                                c_size_t, c_void_p, POINTER(c_float)]),
     "chfsi_zgemm": (c_int, [c_char, c_char, c_int, c_int, c_int, POINTER(c_double), c_void_p,
                             c_int, c_void_p, c_int, POINTER(c_double), c_void_p, c_int, c_void_p,
                             c_size_t, c_void_p]),
@@ -177,17 +196,29 @@ def chfsi_workspace_bytes(n, nev, nex, generalized, opts=None):
 
 
 def chfsi_solve(A, B, nev, nex, tol, X0=None, opts=None, X=None, work=None, stream=None,
-                raise_on_error=True, Lambda0=None):
+                raise_on_error=True, Lambda0=None, log=None, mlp=None):
     """Solve A x = lambda B x (B None: standard).  Lambda0: the Ritz values
-    that go with X0 (optional).  Returns (status, Lambda[k] numpy,
-    X (n x k column-major tensor), info dict)."""
+    that go with X0 (optional).  log: float64 numpy array (cap, 24) that
+    receives convergence records (opts.log / log_capacity); mlp: float32
+    numpy blob of the degree network (opts.mlp).  Returns (status,
+    Lambda[k] numpy, X (n x k column-major tensor), info dict)."""
     torch = _torch()
     n = A.shape[0]
     k = nev + nex
     dev = A.device
     if X is None:
         X = colmajor(torch.empty((n, k), dtype=torch.complex128, device=dev))
-    o = opts if opts is not None else chfsi_default_opts()
+    o = ChfsiOpts.from_buffer_copy(opts if opts is not None else chfsi_default_opts())
+    if log is not None:
+        if log.dtype != np.float64 or not log.flags.c_contiguous or log.ndim != 2 \
+                or log.shape[1] != CHFSI_LOG_FIELDS:
+            raise ValueError("log must be a C-contiguous float64 array (cap, 24)")
+        o.log = log.ctypes.data_as(POINTER(c_double))
+        o.log_capacity = log.shape[0]
+    if mlp is not None:
+        if mlp.dtype != np.float32 or not mlp.flags.c_contiguous or mlp.size != CHFSI_MLP_PARAMS:
+            raise ValueError("mlp must be a contiguous float32 blob of CHFSI_MLP_PARAMS entries")
+        o.mlp = mlp.ctypes.data_as(POINTER(c_float))
     wb = chfsi_workspace_bytes(n, nev, nex, B is not None, o)
     w = _work(wb, dev, work)
     lam = (c_double * k)()
@@ -317,3 +348,101 @@ def chfsi_zgemm(opa, opb, alpha, A, B, beta, C, work=None, stream=None):
                              _ld(B), be, _ptr(C), _ld(C), _ptr(w), wb, _stream(stream, C.device)),
            "chfsi_zgemm")
     return C
+
+
+def chfsi_degree_features(mu, res, gap, alpha, beta, gamma, norm_h, tol_abs, loop):
+    """The 8 network inputs of one vector, or None when |t| <= 1."""
+    f = (c_double * CHFSI_MLP_FEATURES)()
+    st = lib().chfsi_degree_features(float(mu), float(res), float(gap), float(alpha), float(beta),
+                                     float(gamma), float(norm_h), float(tol_abs), int(loop), f)
+    return None if st != CHFSI_OK else np.array(f[:])
+
+
+def _f32_blob(params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    if p.size != CHFSI_MLP_PARAMS:
+        raise ValueError("parameter blob must hold CHFSI_MLP_PARAMS floats")
+    return p
+
+
+def chfsi_degrees_learned(mu, res, n_wanted, alpha, beta, gamma, norm_h, tol_abs, loop, params,
+                          deg_max=40, device="cuda", work=None, stream=None):
+    """Learned degrees; returns (deg, pred, src) numpy arrays."""
+    k = len(mu)
+    p = _f32_blob(params)
+    m = (c_double * k)(*[float(x) for x in mu])
+    r = (c_double * k)(*[float(x) for x in res])
+    d = (c_int * k)()
+    pr = (c_float * k)()
+    sr = (c_int * k)()
+    wb = int(lib().chfsi_mlp_workspace_bytes(k))
+    torch = _torch()
+    dev = torch.device(device)
+    w = _work(wb, dev, work)
+    _check(lib().chfsi_degrees_learned(k, m, r, int(n_wanted), float(alpha), float(beta),
+                                       float(gamma), float(norm_h), float(tol_abs), int(loop),
+                                       int(deg_max), p.ctypes.data_as(POINTER(c_float)), _ptr(w),
+                                       wb, _stream(stream, dev), d, pr, sr),
+           "chfsi_degrees_learned")
+    return (np.array(d[:], dtype=np.int64), np.array(pr[:], dtype=np.float32),
+            np.array(sr[:], dtype=np.int64))
+
+
+def _f32_dev(t, shape):
+    torch = _torch()
+    if t.dtype != torch.float32 or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected a contiguous float32 tensor of shape {shape}")
+    return t
+
+
+def chfsi_mlp_forward(X, params, stream=None):
+    """y = net(X) for X (n, 8) float32 on the GPU; returns y (n,)."""
+    torch = _torch()
+    n = X.shape[0]
+    _f32_dev(X, (n, CHFSI_MLP_FEATURES))
+    _f32_dev(params, (CHFSI_MLP_PARAMS,))
+    y = torch.empty(n, dtype=torch.float32, device=X.device)
+    _check(lib().chfsi_mlp_forward(n, _ptr(X), _ptr(params), _ptr(y), _stream(stream, X.device)),
+           "chfsi_mlp_forward")
+    return y
+
+
+def chfsi_mlp_gradient(X, T, params, work=None, stream=None):
+    """Gradient of the mean squared error; returns (grad tensor, sum of
+    squared errors)."""
+    torch = _torch()
+    n = X.shape[0]
+    _f32_dev(X, (n, CHFSI_MLP_FEATURES))
+    _f32_dev(T, (n,))
+    _f32_dev(params, (CHFSI_MLP_PARAMS,))
+    g = torch.empty(CHFSI_MLP_PARAMS, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    wb = int(lib().chfsi_mlp_workspace_bytes(n))
+    w = _work(wb, X.device, work)
+    _check(lib().chfsi_mlp_gradient(n, _ptr(X), _ptr(T), _ptr(params), _ptr(g), _ptr(loss),
+                                    _ptr(w), wb, _stream(stream, X.device)),
+           "chfsi_mlp_gradient")
+    return g, float(loss.item())
+
+
+def chfsi_mlp_adam(params, grad, m, v, lr, t, stream=None):
+    """One Adam step in place on params (and the moments m, v)."""
+    for x in (params, grad, m, v):
+        _f32_dev(x, (CHFSI_MLP_PARAMS,))
+    _check(lib().chfsi_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), float(lr), int(t),
+                                _stream(stream, params.device)), "chfsi_mlp_adam")
+
+
+def chfsi_mlp_train(X, T, params, steps, lr, work=None, stream=None):
+    """`steps` full-batch Adam steps in place on params; returns the mean
+    squared error before each step (numpy)."""
+    n = X.shape[0]
+    _f32_dev(X, (n, CHFSI_MLP_FEATURES))
+    _f32_dev(T, (n,))
+    _f32_dev(params, (CHFSI_MLP_PARAMS,))
+    losses = (c_float * max(int(steps), 1))()
+    wb = int(lib().chfsi_mlp_workspace_bytes(n))
+    w = _work(wb, X.device, work)
+    _check(lib().chfsi_mlp_train(n, _ptr(X), _ptr(T), _ptr(params), int(steps), float(lr), _ptr(w),
+                                 wb, _stream(stream, X.device), losses), "chfsi_mlp_train")
+    return np.array(losses[:int(steps)], dtype=np.float64)

@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -89,6 +90,7 @@ struct StepBufs {
   void *R32, *E0, *E1;          // mixed-precision filter: complex64 n x k each
   float* crtab;                 // CR_ROWS x k coefficients of the residual term
   double* pm;                   // k final scalars p_{m_j}(mu_t)
+  float *mlp_p, *mlp_x, *mlp_y;  // degree network: parameters, k x 8 inputs, k outputs
   double *mu, *res, *nrm, *E, *alph, *bet, *dummy;
   int *perm, *deg, *info;
   size_t scratch_elems;
@@ -126,6 +128,9 @@ void carve_step(Carver& c, StepBufs& b, int n, int k, int nev, int lanczos_steps
   b.E1 = c.take<char>(nk * 8);
   b.crtab = c.take<float>((size_t)CR_ROWS * k);
   b.pm = c.take<double>(k);
+  b.mlp_p = c.take<float>(MLP_PARAMS);
+  b.mlp_x = c.take<float>((size_t)MLP_IN * k);
+  b.mlp_y = c.take<float>(k);
 }
 
 // ---------------------------------------------------------------------------
@@ -567,6 +572,46 @@ bool defect_filter_safe(int n_wanted, const std::vector<double>& mu,
   return true;
 }
 
+// Mixed precision: one FP32 defect loop can reduce a residual by about
+// 1/(100 eps32) (the bound of defect_filter_safe).  When every wanted
+// vector needs at most twice that, cap its degree at one loop's reach so
+// that the loop runs in FP32 and the next one finishes; the guards take the
+// largest capped degree.  capped[j] marks the capped columns.  Returns
+// false (deg unchanged) when the cap does not apply.
+bool cap_degrees_fp32(int n_wanted, const std::vector<double>& mu, const std::vector<double>& res,
+                      std::vector<int>& deg, double c, double e, double norm_h,
+                      std::vector<char>& capped) {
+  const double reach_nats = std::log(1.0 / (100.0 * std::ldexp(1.0, -24)));
+  const int ka = (int)deg.size();
+  const int nw = std::min(n_wanted, ka);
+  std::vector<int> d = deg;
+  std::vector<char> rate(ka, 0), cap(ka, 0);
+  int fill = 0;
+  bool any = false, changed = false;
+  for (int j = 0; j < nw; ++j) {
+    if (!(res[j] / norm_h <= 1e-2)) return false;
+    const double t = (mu[j] - c) / e;
+    if (!(std::fabs(t) > 1.0)) continue;
+    const double lr = std::log(std::fabs(t) + std::sqrt(t * t - 1.0));
+    const int reach = (int)std::floor(reach_nats / lr * (1.0 - 1e-12));
+    if (reach < 1 || d[j] > 2 * reach) return false;
+    if (d[j] > reach) {
+      d[j] = reach;
+      cap[j] = 1;
+      changed = true;
+    }
+    rate[j] = 1;
+    fill = any ? std::max(fill, d[j]) : d[j];
+    any = true;
+  }
+  if (!any || !changed) return false;
+  for (int j = 0; j < ka; ++j)
+    if (!rate[j]) d[j] = fill;
+  deg.swap(d);
+  capped.swap(cap);
+  return true;
+}
+
 int upload_ints(hipStream_t s, int* dst, const std::vector<int>& v) {
   if (v.empty()) return CHFSI_OK;
   CK(hipMemcpyAsync(dst, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, s));
@@ -651,6 +696,135 @@ int degrees_host(int k, const double* mu, const double* res, int n_wanted, doubl
   if (!any) fill = deg_max;
   for (int j = 0; j < k; ++j)
     if (!def[j]) deg[j] = fill;
+  return CHFSI_OK;
+}
+
+// Input features of the degree network (the layout is documented with
+// chfsi_degree_features).  Returns false when the vector has no analytic
+// rate (|t| <= 1).
+bool degree_features(double mu, double res, double gap, double alpha, double beta, double gamma,
+                     double norm_h, double tol_abs, int loop, double* f, double* ln_rho) {
+  const double c = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
+  const double t = (mu - c) / e;
+  if (!(std::fabs(t) > 1.0)) return false;
+  const double lr = std::log(std::fabs(t) + std::sqrt(t * t - 1.0));
+  const double f0 = std::log(std::max(res, tol_abs) / tol_abs);
+  f[0] = f0;
+  f[1] = std::log(lr);
+  f[2] = std::log(std::max(f0 / lr, 0.5));
+  f[3] = std::log(std::fabs(t));
+  f[4] = (alpha != gamma) ? (mu - gamma) / (alpha - gamma) : 0.0;
+  f[5] = std::log(std::max(gap / e, 1e-12));
+  f[6] = std::log(std::max(res, 1e-300) / norm_h);
+  f[7] = (double)std::min(std::max(loop - 1, 0), 4);
+  if (ln_rho) *ln_rho = lr;
+  return true;
+}
+
+// Distance from mu[j] to the nearest other value of the ascending mu[0..k).
+double ritz_gap(int k, const double* mu, int j, double e) {
+  double g = std::numeric_limits<double>::infinity();
+  if (j > 0) g = std::min(g, mu[j] - mu[j - 1]);
+  if (j + 1 < k) g = std::min(g, mu[j + 1] - mu[j]);
+  return std::isfinite(g) ? g : e;
+}
+
+// SplitMix64 output i of stream `stream` (the generator of the start block
+// and Lanczos vector), as a double in [0, 1).
+double splitmix_host(unsigned long long seed, int stream, unsigned long long i) {
+  unsigned long long z = seed + ((unsigned long long)stream << 48) + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return (double)(z >> 11) * 0x1.0p-53;
+}
+
+constexpr int STREAM_JITTER = 3;
+constexpr double MLP_OOD = 6.0;   // standardised features beyond this use the rule
+
+// Learned degrees (the rule of chfsi_degrees_learned).  prm_host is the
+// caller's blob, prm_dev its device copy; x_dev / y_dev hold k rows.
+// src (k ints) receives 0 rule fallback, 1 network, 2 guard fill; feats
+// (k x 8, may be null) the features of the wanted vectors.
+int learned_degrees(hipStream_t s, int k, const double* mu, const double* res, int n_wanted,
+                    double alpha, double beta, double gamma, double norm_h, double tol_abs,
+                    int loop, int deg_max, const float* prm_host, const float* prm_dev,
+                    float* x_dev, float* y_dev, int* deg, float* pred, int* src, double* feats,
+                    int finishing_mode = -1, bool* finishing_out = nullptr) {
+  std::vector<int> rule(k);
+  degrees_host(k, mu, res, n_wanted, alpha, beta, tol_abs, deg_max, rule.data());
+  const double e = 0.5 * (beta - alpha);
+  const int nw = std::min(n_wanted, k);
+  std::vector<int> rows;
+  std::vector<float> X;
+  std::vector<double> lrho(k, 0.0), m_a(k, 0.0);
+  std::vector<char> ood(k, 0);
+  for (int j = 0; j < k; ++j) {
+    src[j] = 2;
+    if (pred) pred[j] = NAN;
+  }
+  for (int j = 0; j < nw; ++j) {
+    double f[MLP_IN];
+    if (!degree_features(mu[j], res[j], ritz_gap(k, mu, j, e), alpha, beta, gamma, norm_h,
+                         tol_abs, loop, f, &lrho[j]))
+      continue;
+    if (feats) std::copy(f, f + MLP_IN, feats + (size_t)j * MLP_IN);
+    m_a[j] = f[0] / lrho[j];
+    for (int i = 0; i < MLP_IN; ++i) {
+      const double sd = prm_host[MLP_STD + i] > 0.f ? prm_host[MLP_STD + i] : 1.0;
+      const double z = (f[i] - prm_host[MLP_MEAN + i]) / sd;
+      if (!(std::fabs(z) <= MLP_OOD)) ood[j] = 1;
+      X.push_back((float)f[i]);
+    }
+    rows.push_back(j);
+  }
+  std::vector<float> y(rows.size());
+  if (!rows.empty()) {
+    CK(hipMemcpyAsync(x_dev, X.data(), sizeof(float) * X.size(), hipMemcpyHostToDevice, s));
+    CK(mlp_forward(s, (int)rows.size(), x_dev, prm_dev, y_dev));
+    CK(hipMemcpyAsync(y.data(), y_dev, sizeof(float) * y.size(), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+  }
+  // A loop that can finish every wanted vector (all predicted degrees
+  // within deg_max) takes the safety margin: a miss there costs a whole
+  // extra loop.  Otherwise some vectors go on anyway and the rest take the
+  // predicted degree.
+  bool finishing = finishing_mode == 1;
+  if (finishing_mode < 0) {
+    finishing = true;
+    for (size_t r = 0; r < rows.size(); ++r) {
+      const int j = rows[r];
+      const bool net = !ood[j] && std::isfinite(y[r]);
+      const double need = net ? m_a[j] * std::exp(-(double)y[r]) : m_a[j];
+      if (!(std::ceil(need) <= (double)deg_max)) finishing = false;
+    }
+  }
+  if (finishing_out) *finishing_out = finishing;
+  const double margin = finishing ? (double)prm_host[MLP_MARGIN] : 0.0;
+  int fill = 0;
+  bool any = false;
+  for (size_t r = 0; r < rows.size(); ++r) {
+    const int j = rows[r];
+    if (pred) pred[j] = y[r];
+    int m;
+    if (ood[j] || !std::isfinite(y[r])) {
+      m = rule[j];
+      src[j] = 0;
+    } else {
+      const double mc = m_a[j] * std::exp(margin - (double)y[r]);
+      m = std::isfinite(mc) ? (int)std::min<double>(std::ceil(mc), (double)deg_max) : deg_max;
+      // the rule's degree is the floor: the network only adds degree where
+      // the analytic model is too optimistic
+      m = std::min(std::max(std::max(m, 1), rule[j]), deg_max);
+      src[j] = 1;
+    }
+    deg[j] = m;
+    fill = any ? std::max(fill, m) : m;
+    any = true;
+  }
+  if (!any) fill = deg_max;
+  for (int j = 0; j < k; ++j)
+    if (src[j] == 2) deg[j] = fill;
   return CHFSI_OK;
 }
 
@@ -761,6 +935,13 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
   double alpha = alpha_of(0, k);
   double gamma = std::min(mu[0], tmin);
   std::vector<int> deg(k, o.deg0);
+  // per position: where the degree came from (0 rule, 1 network, 2 guard,
+  // 3 fixed deg0), the rule's degree, jittered or not
+  std::vector<int> dsrc(k, 3), rule_deg(k, o.deg0);
+  std::vector<char> jittered(k, 0);
+  int learned_cols = 0, fallback_cols = 0, learned_raised = 0, log_records = 0;
+  if (o.degree_mode == 2)
+    CK(hipMemcpyAsync(sb.mlp_p, o.mlp, sizeof(float) * MLP_PARAMS, hipMemcpyHostToDevice, s));
 
   int nl = 0;
   std::vector<double> lam_locked;
@@ -780,34 +961,134 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
   CK(hipEventCreate(&fe1));
   struct EvGuard { hipEvent_t a, b; ~EvGuard() { hipEventDestroy(a); hipEventDestroy(b); } } evg{fe0, fe1};
 
+  // Degrees of the active block for loop `loop` (Sec. 3.1.1, or learned,
+  // then the optional jitter); needs the residuals of the block.
+  auto choose_degrees = [&](int ka_, int loop) -> int {
+    const int nw = std::min(nev - nl, ka_);
+    deg.assign(ka_, o.deg0);
+    dsrc.assign(ka_, 3);
+    jittered.assign(ka_, 0);
+    if (o.degree_mode == 1) return CHFSI_OK;
+    std::vector<int> rule(ka_);
+    degrees_host(ka_, mu.data(), res.data(), nev - nl, alpha, beta, tol_abs, o.deg_max, rule.data());
+    if (o.degree_mode == 2) {
+      bool finishing = false;
+      CKS(learned_degrees(s, ka_, mu.data(), res.data(), nev - nl, alpha, beta, gamma, norm_h,
+                          tol_abs, loop, o.deg_max, o.mlp, sb.mlp_p, sb.mlp_x, sb.mlp_y,
+                          deg.data(), nullptr, dsrc.data(), nullptr, -1, &finishing));
+      if (finishing && o.precision == 1) {
+        // a loop whose degrees get capped to the reach of FP32 cannot finish
+        const double cc = 0.5 * (alpha + beta), ee = 0.5 * (beta - alpha);
+        std::vector<int> d2 = deg;
+        std::vector<char> cp(ka_, 0);
+        if (!defect_filter_safe(nev - nl, mu, res, deg, cc, ee, gamma, tol, norm_h) &&
+            cap_degrees_fp32(nev - nl, mu, res, d2, cc, ee, norm_h, cp))
+          CKS(learned_degrees(s, ka_, mu.data(), res.data(), nev - nl, alpha, beta, gamma, norm_h,
+                              tol_abs, loop, o.deg_max, o.mlp, sb.mlp_p, sb.mlp_x, sb.mlp_y,
+                              deg.data(), nullptr, dsrc.data(), nullptr, 0, nullptr));
+      }
+      for (int j = 0; j < nw; ++j) {
+        if (dsrc[j] == 1) ++learned_cols;
+        if (dsrc[j] == 1 && deg[j] > rule[j]) ++learned_raised;
+        if (dsrc[j] == 0) ++fallback_cols;
+      }
+    } else {
+      deg = rule;
+      dsrc.assign(ka_, 0);
+    }
+    if (o.degree_jitter > 0.0) {
+      const double cc = 0.5 * (alpha + beta), ee = 0.5 * (beta - alpha);
+      int fill = 0;
+      bool any = false;
+      std::vector<char> rate(ka_, 0);
+      for (int j = 0; j < nw; ++j) {
+        if (!(std::fabs((mu[j] - cc) / ee) > 1.0)) continue;
+        rate[j] = 1;
+        const double u = 2.0 * splitmix_host(o.seed, STREAM_JITTER,
+                                             (unsigned long long)(loop - 1) * k + j) - 1.0;
+        int m = (int)std::lround(deg[j] * std::exp(o.degree_jitter * u));
+        deg[j] = std::min(std::max(m, 1), o.deg_max);
+        jittered[j] = 1;
+        fill = any ? std::max(fill, deg[j]) : deg[j];
+        any = true;
+      }
+      if (!any) fill = o.deg_max;
+      for (int j = 0; j < ka_; ++j)
+        if (!rate[j]) deg[j] = fill;
+    }
+    return CHFSI_OK;
+  };
+
   while (it < o.max_iter) {
     ++it;
     const int ka = k - nl;
     const double c = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
+    // A warm start with Lambda0 may take its first degrees from the rule
+    // once the residuals of X0 are known (first_rule).
+    const bool warm_rule = it == 1 && X0 && Lambda0 && o.first_rule && o.degree_mode != 1;
+    if (!have_res && (o.precision == 1 || warm_rule)) {
+      // one product gives Z = H Q and the residuals of the warm start block
+      tm.begin(4);
+      CK(zgemm(s, OP_N, OP_N, n, ka, n, ONE, H, ldh, b.QA, ld, ZERO, b.ZA, ld, false, nullptr, 0));
+      CKS(upload(s, sb.mu, std::vector<double>(mu.begin(), mu.begin() + ka)));
+      CK(resid_norms(s, n, ka, b.QA, ld, b.ZA, ld, sb.mu, sb.res));
+      CK(hipMemcpyAsync(res.data(), sb.res, sizeof(double) * ka, hipMemcpyDeviceToHost, s));
+      CK(hipStreamSynchronize(s));
+      tm.end();
+      matvecs += ka;
+      have_res = true;
+    }
+    if (warm_rule) CKS(choose_degrees(ka, 1));
+    // the rule's degrees of this loop (judge of learned degrees, log)
+    const int nw_loop = std::min(nev - nl, ka);
+    if (have_res)
+      degrees_host(ka, mu.data(), res.data(), nev - nl, alpha, beta, tol_abs, o.deg_max,
+                   rule_deg.data());
+    // precision of this filter: the FP32 defect form needs the residual
+    // block of the current Ritz pairs and small enough residuals
+    bool use32 = false;
+    std::vector<char> capped(ka, 0);
+    if (o.precision == 1) {
+      use32 = defect_filter_safe(nev - nl, mu, res, deg, c, e, gamma, tol, norm_h);
+      if (!use32) {
+        std::vector<int> d2 = deg;
+        if (cap_degrees_fp32(nev - nl, mu, res, d2, c, e, norm_h, capped) &&
+            defect_filter_safe(nev - nl, mu, res, d2, c, e, gamma, tol, norm_h)) {
+          deg.swap(d2);
+          use32 = true;
+        } else {
+          capped.assign(ka, 0);
+        }
+      }
+    }
+    const bool logging = o.log && log_records < o.log_capacity && have_res;
+    std::vector<double> pending;
+    if (logging) {
+      pending.assign((size_t)nw_loop * CHFSI_LOG_FIELDS, NAN);
+      for (int j = 0; j < nw_loop; ++j) {
+        double* r = &pending[(size_t)j * CHFSI_LOG_FIELDS];
+        const double gap = ritz_gap(ka, mu.data(), j, e);
+        r[0] = it; r[1] = j; r[2] = nev - nl; r[3] = ka;
+        r[4] = mu[j]; r[5] = res[j]; r[6] = gap;
+        r[7] = alpha; r[8] = beta; r[9] = gamma; r[10] = norm_h; r[11] = tol_abs;
+        r[12] = deg[j]; r[13] = rule_deg[j];
+        int flags = 0;
+        if (dsrc[j] == 1) flags |= 2;
+        if (dsrc[j] == 0 && o.degree_mode == 2) flags |= 4;
+        if (jittered[j]) flags |= 8;
+        if (use32) flags |= 1;
+        if (capped[j]) flags |= 16;
+        r[15] = flags;
+        degree_features(mu[j], res[j], gap, alpha, beta, gamma, norm_h, tol_abs, it, r + 16,
+                        nullptr);
+      }
+    }
     // columns sorted by ascending degree (stable)
     std::vector<int> order(ka);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return deg[x] < deg[y]; });
     std::vector<int> msort(ka);
     for (int j = 0; j < ka; ++j) msort[j] = deg[order[j]];
-    // precision of this filter: the FP32 defect form needs the residual
-    // block of the current Ritz pairs and small enough residuals
-    bool use32 = false;
-    if (o.precision == 1) {
-      if (!have_res) {
-        // first loop of a warm start with Lambda0: one product gives Z = H Q
-        tm.begin(4);
-        CK(zgemm(s, OP_N, OP_N, n, ka, n, ONE, H, ldh, b.QA, ld, ZERO, b.ZA, ld, false, nullptr, 0));
-        CKS(upload(s, sb.mu, std::vector<double>(mu.begin(), mu.begin() + ka)));
-        CK(resid_norms(s, n, ka, b.QA, ld, b.ZA, ld, sb.mu, sb.res));
-        CK(hipMemcpyAsync(res.data(), sb.res, sizeof(double) * ka, hipMemcpyDeviceToHost, s));
-        CK(hipStreamSynchronize(s));
-        tm.end();
-        matvecs += ka;
-        have_res = true;
-      }
-      use32 = defect_filter_safe(nev - nl, mu, res, deg, c, e, gamma, tol, norm_h);
-    }
     double fl_before = filter_flops;
     CK(hipEventRecord(fe0, s));
     if (use32) {
@@ -862,6 +1143,14 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
     }
     have_res = true;
     tm.drain();
+    if (logging) {
+      for (int j = 0; j < nw_loop && log_records < o.log_capacity; ++j) {
+        double* r = &pending[(size_t)j * CHFSI_LOG_FIELDS];
+        r[14] = res[j];
+        std::copy(r, r + CHFSI_LOG_FIELDS, o.log + (size_t)log_records * CHFSI_LOG_FIELDS);
+        ++log_records;
+      }
+    }
     // locking (the LOCKING step): the lowest nev - nl active pairs are candidates
     const int ncand = nev - nl;
     std::vector<int> lock_idx, keep_idx;
@@ -898,10 +1187,7 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
     const int ka2 = k - nl;
     alpha = alpha_of(nl, ka2);
     gamma = std::min(gamma, mu[0]);
-    deg.assign(ka2, o.deg0);
-    if (o.degree_mode != 1) {
-      degrees_host(ka2, mu.data(), res.data(), nev - nl, alpha, beta, tol_abs, o.deg_max, deg.data());
-    }
+    CKS(choose_degrees(ka2, it + 1));
   }
 
   // output: all k pairs ascending; X = L^{-H} Y for the generalized problem
@@ -948,6 +1234,10 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
     info->beta = beta;
     info->norm_h = norm_h;
     info->max_resid = norm_h > 0.0 ? max_locked_res / norm_h : max_locked_res;
+    info->log_records = log_records;
+    info->learned_cols = learned_cols;
+    info->fallback_cols = fallback_cols;
+    info->learned_raised = learned_raised;
   }
   if (info) info->total_seconds = elapsed(t_start);
   return status;
@@ -976,6 +1266,11 @@ int chfsi_default_opts(chfsi_opts* o) {
   o->reuse_b_factor = 1;
   o->precision = 0;
   o->seed = 0;
+  o->degree_jitter = 0.0;
+  o->first_rule = 0;
+  o->log_capacity = 0;
+  o->log = nullptr;
+  o->mlp = nullptr;
   return CHFSI_OK;
 }
 
@@ -1019,6 +1314,15 @@ int chfsi_solve(int n, int nev, int nex, const void* A, int lda, const void* B, 
     if (X0 && (ldx0 < n || !aligned16(X0))) return CHFSI_INVALID_ARG;
     if (o.deg0 < 1 || o.deg_max < 1 || o.max_iter < 1 || o.lanczos_steps < 1) return CHFSI_INVALID_ARG;
     if (o.precision < 0 || o.precision > 1) return CHFSI_INVALID_ARG;
+    if (o.degree_mode < 0 || o.degree_mode > 2 || o.first_rule < 0 || o.first_rule > 1)
+      return CHFSI_INVALID_ARG;
+    if (!(o.degree_jitter >= 0.0) || !std::isfinite(o.degree_jitter)) return CHFSI_INVALID_ARG;
+    if (o.log_capacity < 0 || (o.log_capacity > 0 && !o.log)) return CHFSI_INVALID_ARG;
+    if (o.degree_mode == 2) {
+      if (!o.mlp) return CHFSI_INVALID_ARG;
+      for (int i = 0; i < MLP_PARAMS; ++i)
+        if (!std::isfinite(o.mlp[i])) return CHFSI_NONFINITE;
+    }
     if (o.precision == 1 && (o.deg0 > CR_ROWS || o.deg_max > CR_ROWS)) return CHFSI_INVALID_ARG;
     if (X0 == X && ldx0 != ldx) return CHFSI_INVALID_ARG;
     if (Lambda0) {
@@ -1238,6 +1542,119 @@ int chfsi_degrees(int k, const double* mu, const double* res, int n_wanted, doub
   if (k < 1 || !mu || !res || !deg || !(beta > alpha) || !(tol_abs > 0.0) || deg_max < 1)
     return CHFSI_INVALID_ARG;
   return degrees_host(k, mu, res, n_wanted, alpha, beta, tol_abs, deg_max, deg);
+}
+
+int chfsi_degree_features(double mu, double res, double gap, double alpha, double beta,
+                          double gamma, double norm_h, double tol_abs, int loop, double* f) {
+  if (!f || !(beta > alpha) || !(tol_abs > 0.0) || !(norm_h > 0.0)) return CHFSI_INVALID_ARG;
+  return degree_features(mu, res, gap, alpha, beta, gamma, norm_h, tol_abs, loop, f, nullptr)
+             ? CHFSI_OK
+             : CHFSI_INVALID_ARG;
+}
+
+size_t chfsi_mlp_workspace_bytes(int n) {
+  if (n < 1) n = 1;
+  // parameters, Adam moments and gradient, inputs/outputs for inference,
+  // and the gradient scratch
+  const size_t floats =
+      3 * (size_t)MLP_PARAMS + 4096 + (size_t)n * (MLP_IN + 1) + mlp_grad_work_floats(n);
+  return floats * sizeof(float) + 8 * ALIGN;
+}
+
+int chfsi_degrees_learned(int k, const double* mu, const double* res, int n_wanted, double alpha,
+                          double beta, double gamma, double norm_h, double tol_abs, int loop,
+                          int deg_max, const float* params, void* work, size_t work_bytes,
+                          void* stream, int* deg, float* pred, int* src) {
+  try {
+    if (k < 1 || !mu || !res || !deg || !params || !(beta > alpha) || !(tol_abs > 0.0) ||
+        !(norm_h > 0.0) || deg_max < 1 || n_wanted < 0 || check_ptr(work) ||
+        work_bytes < chfsi_mlp_workspace_bytes(k))
+      return CHFSI_INVALID_ARG;
+    for (int i = 0; i < MLP_PARAMS; ++i)
+      if (!std::isfinite(params[i])) return CHFSI_NONFINITE;
+    hipStream_t s = as_stream(stream);
+    Carver cv(work);
+    float* p = cv.take<float>(MLP_PARAMS);
+    float* x = cv.take<float>((size_t)MLP_IN * k);
+    float* y = cv.take<float>(k);
+    CK(hipMemcpyAsync(p, params, sizeof(float) * MLP_PARAMS, hipMemcpyHostToDevice, s));
+    std::vector<int> sv(k);
+    CKS(learned_degrees(s, k, mu, res, n_wanted, alpha, beta, gamma, norm_h, tol_abs, loop,
+                        deg_max, params, p, x, y, deg, pred, sv.data(), nullptr));
+    if (src) std::copy(sv.begin(), sv.end(), src);
+    return CHFSI_OK;
+  } catch (const std::bad_alloc&) {
+    return CHFSI_ALLOC_ERROR;
+  } catch (...) {
+    return CHFSI_DEVICE_ERROR;
+  }
+}
+
+int chfsi_mlp_forward(int n, const float* X, const float* params, float* y, void* stream) {
+  if (n < 0 || (n > 0 && (!X || !params || !y))) return CHFSI_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  CK(mlp_forward(s, n, X, params, y));
+  CK(hipStreamSynchronize(s));
+  return CHFSI_OK;
+}
+
+int chfsi_mlp_gradient(int n, const float* X, const float* T, const float* params, float* grad,
+                       float* loss, void* work, size_t work_bytes, void* stream) {
+  if (n < 1 || !X || !T || !params || !grad || !loss || check_ptr(work) ||
+      work_bytes < chfsi_mlp_workspace_bytes(n))
+    return CHFSI_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  CK(mlp_gradient(s, n, X, T, params, grad, loss, (float*)work));
+  CK(hipStreamSynchronize(s));
+  return CHFSI_OK;
+}
+
+int chfsi_mlp_adam(float* params, const float* grad, float* m, float* v, float lr, int t,
+                   void* stream) {
+  if (!params || !grad || !m || !v || t < 1 || !(lr > 0.f)) return CHFSI_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  CK(mlp_adam(s, params, grad, m, v, lr, t));
+  CK(hipStreamSynchronize(s));
+  return CHFSI_OK;
+}
+
+int chfsi_mlp_train(int n, const float* X, const float* T, float* params, int steps, float lr,
+                    void* work, size_t work_bytes, void* stream, float* loss_out) {
+  try {
+    if (n < 1 || !X || !T || !params || steps < 0 || !(lr > 0.f) || check_ptr(work) ||
+        work_bytes < chfsi_mlp_workspace_bytes(n))
+      return CHFSI_INVALID_ARG;
+    hipStream_t s = as_stream(stream);
+    Carver cv(work);
+    float* G = cv.take<float>(MLP_PARAMS);
+    float* M = cv.take<float>(MLP_PARAMS);
+    float* V = cv.take<float>(MLP_PARAMS);
+    float* loss = cv.take<float>(4096);
+    float* scratch = cv.take<float>(mlp_grad_work_floats(n));
+    CK(hipMemsetAsync(M, 0, sizeof(float) * MLP_PARAMS, s));
+    CK(hipMemsetAsync(V, 0, sizeof(float) * MLP_PARAMS, s));
+    // the losses of up to LB steps stay on the device between copies
+    constexpr int LB = 4096;
+    std::vector<float> hl(steps);
+    int done = 0;
+    for (int t = 1; t <= steps; ++t) {
+      CK(mlp_gradient(s, n, X, T, params, G, loss + (t - 1) % LB, scratch));
+      CK(mlp_adam(s, params, G, M, V, lr, t));
+      if (loss_out && (t % LB == 0 || t == steps)) {
+        CK(hipMemcpyAsync(hl.data() + done, loss, sizeof(float) * (t - done), hipMemcpyDeviceToHost, s));
+        CK(hipStreamSynchronize(s));
+        done = t;
+      }
+    }
+    CK(hipStreamSynchronize(s));
+    if (loss_out)
+      for (int t = 0; t < steps; ++t) loss_out[t] = hl[t] / (float)n;
+    return CHFSI_OK;
+  } catch (const std::bad_alloc&) {
+    return CHFSI_ALLOC_ERROR;
+  } catch (...) {
+    return CHFSI_DEVICE_ERROR;
+  }
 }
 
 int chfsi_zgemm(char opa, char opb, int M, int N, int K, const double* alpha, const void* A,

@@ -130,4 +130,31 @@ int defect_step(hipStream_t s, int n, int N, const void* H32, const void* Ecur, 
 int defect_assemble_launch(hipStream_t s, int n, int k, const zc* Qs, long ld, const void* E0,
                            const void* E1, const int* deg, const double* pm, zc* Y, long ldy);
 
+// ----- degree network (mlp.hip) -----
+// Parameter blob layout (floats); the same layout is documented in chfsi.h.
+constexpr int MLP_IN = 8, MLP_H = 64;
+constexpr int MLP_MEAN = 0;
+constexpr int MLP_STD = MLP_MEAN + MLP_IN;
+constexpr int MLP_W1 = MLP_STD + MLP_IN;          // MLP_H x MLP_IN, row-major
+constexpr int MLP_B1 = MLP_W1 + MLP_H * MLP_IN;
+constexpr int MLP_W2 = MLP_B1 + MLP_H;            // MLP_H x MLP_H, row-major
+constexpr int MLP_B2 = MLP_W2 + MLP_H * MLP_H;
+constexpr int MLP_W3 = MLP_B2 + MLP_H;
+constexpr int MLP_B3 = MLP_W3 + MLP_H;
+constexpr int MLP_MARGIN = MLP_B3 + 1;
+constexpr int MLP_PARAMS = MLP_MARGIN + 1;
+// Samples per partial sum of the gradient reduction.
+constexpr int MLP_CHUNK = 2048;
+
+// Device floats used by mlp_gradient for n samples.
+size_t mlp_grad_work_floats(int n);
+// y[s] = net(X[s, :]) for n samples (X row-major n x MLP_IN).
+int mlp_forward(hipStream_t s, int n, const float* X, const float* prm, float* Y);
+// Gradient of (1/n) sum_s (net(X_s) - T_s)^2 with respect to every entry of
+// the blob (zero for the non-trained ones) into G; the loss into loss_dev[0].
+int mlp_gradient(hipStream_t s, int n, const float* X, const float* T, const float* prm,
+                 float* G, float* loss_dev, float* work);
+// One Adam step (t >= 1) on the trained entries.
+int mlp_adam(hipStream_t s, float* prm, const float* G, float* M, float* V, float lr, int t);
+
 }  // namespace chfsi

@@ -97,3 +97,57 @@ def test_degree_rule_bit_exact_with_oracle():
 def test_degrees_rejects_bad_interval():
     with pytest.raises(ch.ChfsiError):
         ch.chfsi_degrees([1.0], [1.0], 1, 2.0, 1.0, 1e-9)
+
+
+def test_learned_degree_options_defaults_and_validation():
+    o = ch.chfsi_default_opts()
+    assert (o.degree_jitter, o.first_rule, o.log_capacity) == (0.0, 0, 0)
+    assert not o.log and not o.mlp
+    lib = ch.lib()
+    lam = (ctypes.c_double * 4)()
+    dummy = ctypes.c_void_p(256)
+
+    def solve_with(**kw):
+        oo = ch.chfsi_default_opts()
+        for key, v in kw.items():
+            setattr(oo, key, v)
+        return lib.chfsi_solve(10, 2, 2, dummy, 10, None, 0, 1e-10, None, 0, None, lam, dummy, 10,
+                               dummy, 1 << 30, ctypes.byref(oo), None, None)
+
+    assert solve_with(degree_mode=3) == ch.binding.CHFSI_INVALID_ARG
+    assert solve_with(degree_mode=2) == ch.binding.CHFSI_INVALID_ARG        # no network
+    assert solve_with(degree_jitter=-0.1) == ch.binding.CHFSI_INVALID_ARG
+    assert solve_with(first_rule=2) == ch.binding.CHFSI_INVALID_ARG
+    assert solve_with(log_capacity=5) == ch.binding.CHFSI_INVALID_ARG       # no buffer
+    bad = (ctypes.c_float * ch.binding.CHFSI_MLP_PARAMS)()
+    bad[7] = float("inf")
+    assert solve_with(degree_mode=2, mlp=ctypes.cast(bad, ctypes.POINTER(ctypes.c_float))) == \
+        ch.binding.CHFSI_NONFINITE
+    # network entry points check their sizes before touching the device
+    assert lib.chfsi_mlp_gradient(0, dummy, dummy, dummy, dummy, dummy, dummy, 1 << 30, None) == \
+        ch.binding.CHFSI_INVALID_ARG
+    assert lib.chfsi_mlp_adam(dummy, dummy, dummy, dummy, 1e-3, 0, None) == \
+        ch.binding.CHFSI_INVALID_ARG
+    assert lib.chfsi_mlp_train(5, dummy, dummy, dummy, 3, 1e-3, dummy, 16, None, None) == \
+        ch.binding.CHFSI_INVALID_ARG
+    assert ch.lib().chfsi_mlp_workspace_bytes(1000) > 1000 * (8 + 4 * 64) * 4
+
+
+def test_degree_features_match_oracle():
+    from oracle import mlp
+    g = np.random.default_rng(11)
+    alpha, beta, gamma, norm_h, tol_abs = -9.0, 45.0, -26.0, 45.0, 4.5e-9
+    n_ok = 0
+    for _ in range(300):
+        mu = g.uniform(-40, 50)
+        res = 10.0 ** g.uniform(-12, 0)
+        gap = 10.0 ** g.uniform(-14, 1)
+        loop = int(g.integers(1, 9))
+        got = ch.chfsi_degree_features(mu, res, gap, alpha, beta, gamma, norm_h, tol_abs, loop)
+        ref = mlp.features(mu, res, gap, alpha, beta, gamma, norm_h, tol_abs, loop)
+        if ref is None:
+            assert got is None
+            continue
+        n_ok += 1
+        assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), (mu, res, gap)
+    assert n_ok > 100

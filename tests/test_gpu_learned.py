@@ -1,0 +1,79 @@
+"""What the learned degrees gain (degree_mode 2) over the paper's analytic
+rule, on sequences the network never saw.
+
+The network is trained on the GPU (the library's own kernels) from the
+convergence logs of two generalized sequences; a third sequence with the
+same recipe but other seeds is then solved with the rule and with the
+network.  The learned run must need fewer outer loops over the sequence
+(the cold first problem, where the rule's degrees from the first loop's
+residuals are far too optimistic, gains most) for about the same number of
+mat-vecs, and both runs must match the oracle's eigenvalues to 1e-10."""
+import numpy as np
+import pytest
+
+import paper_1404_4161_amd as ch
+from paper_1404_4161_amd import learned
+from oracle import chfsi as ochfsi, eigh
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+N, NEV, NEX, LENGTH = 600, 30, 8, 6
+
+
+def _conf(cfg):
+    conf = gen.small_config("lg", N, NEV, NEX, True, length=LENGTH, cfg=cfg)
+    return gen.dataclasses.replace(conf, delta=gen._decay(1e-2))
+
+
+def _problems(cfg):
+    import torch
+    seq = gen.Sequence(_conf(cfg), kind="torch", device="cuda:0")
+    probs = [a.clone() for _, a in seq.problems()]
+    torch.cuda.synchronize()
+    return seq, probs
+
+
+@pytest.fixture(scope="module")
+def network():
+    buf = learned.LogBuffer(100_000)
+    for cfg in (510, 511):
+        seq, probs = _problems(cfg)
+        for jit in (0.0, 0.3):
+            o = ch.chfsi_default_opts()
+            o.first_rule, o.degree_jitter, o.seed = 1, jit, cfg
+            learned.solve_sequence_logged(probs, seq.B, NEV, NEX, 1e-10, o, buf)
+    rec = buf.records()
+    blob, report = learned.fit(rec, steps=1500)
+    return blob, report
+
+
+@pytest.mark.timeout(600)
+def test_learned_degrees_need_fewer_loops_than_the_rule(network):
+    blob, report = network
+    # the network explains most of the spread of the observed speeds
+    assert report["holdout_mse"] < 0.3 * report["holdout_var"], report
+    seq, probs = _problems(512)
+    host_b = seq.B.cpu().numpy()
+    totals = {}
+    for mode in (0, 2):
+        o = ch.chfsi_default_opts()
+        o.first_rule, o.degree_mode = 1, mode
+        x = lam = None
+        loops = mv = 0
+        for l, a in enumerate(probs):
+            st, lam, x, info = ch.chfsi_solve(a, seq.B, NEV, NEX, 1e-10, X0=x,
+                                              Lambda0=lam if x is not None else None, opts=o,
+                                              mlp=blob if mode == 2 else None)
+            assert st == 0, (mode, l, st)
+            loops += info["iters"]
+            mv += info["matvecs"]
+            if mode == 2:
+                assert info["fallback_cols"] <= 0.1 * info["learned_cols"]
+            h, _ = ochfsi.reduce_to_standard(a.cpu().numpy(), host_b)
+            ref = eigh.eigvalsh(h)[:NEV]
+            assert np.abs(lam[:NEV] - ref).max() <= 1e-10 * np.abs(ref).min(), (mode, l)
+        totals[mode] = (loops, mv)
+    print("rule (loops, matvecs):", totals[0], "learned:", totals[2])
+    assert totals[2][0] <= 0.8 * totals[0][0], totals
+    assert totals[2][1] <= 1.15 * totals[0][1], totals

@@ -281,3 +281,8 @@ def random_hpd(n: int, seed: int, weight: float = 0.05) -> np.ndarray:
 
 def random_block(n: int, k: int, seed: int) -> np.ndarray:
     return np.asfortranarray(complex_gaussian(np.random.Generator(np.random.PCG64(seed)), n, k))
+
+
+def variant(conf: SequenceConfig, cfg: int, name: str = None) -> SequenceConfig:
+    """The same recipe under another seed namespace (e.g. training data)."""
+    return dataclasses.replace(conf, cfg=cfg, name=name or f"{conf.name}@{cfg}")
