@@ -225,6 +225,38 @@ int chfsi_solve(int n, int nev, int nex,
                 void* stream,
                 chfsi_info* info);
 
+/* Batched solve of independent problems (e.g. the k-points of one
+ * self-consistency step, Sec. 1 / Sec. 4: every k-point gives its own
+ * sequence): `count` problems, each with the arguments of chfsi_solve given
+ * by index q (arrays of count entries), run their outer loops in lockstep.
+ * Every loop's FP64 filters of all problems share one launch per recurrence
+ * step (a grouped MFMA kernel over all problems' tiles); QR, Rayleigh-Ritz
+ * and the FP32 defect filters run per problem on the same stream.  Each
+ * problem runs the same algorithm as chfsi_solve with the same arguments;
+ * only the summation order of the filter products may differ (the grouped
+ * launch does not split K).
+ *   B, X0, Lambda0 may be NULL (no problem has one) or hold NULL entries;
+ *   ldb / ldx0 are then read only for the non-NULL entries.
+ *   work[q], work_bytes[q]  per-problem workspaces (chfsi_workspace_bytes),
+ *               pairwise distinct; B's factor is reused per workspace.
+ *   batch_work  device, >= chfsi_batch_workspace_bytes(count, opts): the
+ *               launch arguments of the grouped filter.
+ *   opts        shared by all problems; log_capacity must be 0.
+ *   flags       bit 0: capture each loop's grouped filter launches as one
+ *               HIP graph and launch it (needs a non-NULL stream).
+ *   info        NULL or count statistics records.
+ *   status      HOST, count ints out: each problem's status.
+ * Returns CHFSI_OK when every problem converged, else the first error
+ * (or CHFSI_NO_CONVERGENCE). */
+size_t chfsi_batch_workspace_bytes(int count, const chfsi_opts* opts);
+int chfsi_solve_batch(int count, const int* n, const int* nev, const int* nex,
+                      const void* const* A, const int* lda, const void* const* B, const int* ldb,
+                      double tol, const void* const* X0, const int* ldx0,
+                      const double* const* Lambda0, double* const* Lambda, void* const* X,
+                      const int* ldx, void* const* work, const size_t* work_bytes,
+                      void* batch_work, size_t batch_work_bytes, const chfsi_opts* opts, int flags,
+                      void* stream, chfsi_info* info, int* status);
+
 /* Static, human-readable text for a status code. */
 const char* chfsi_status_string(int status);
 

@@ -9,5 +9,6 @@ from .binding import (ChfsiError, ChfsiInfo, ChfsiOpts, chfsi_default_opts, chfs
                       chfsi_mlp_forward, chfsi_mlp_gradient, chfsi_mlp_train,
                       chfsi_filter, chfsi_filter_defect, chfsi_lanczos_bounds, chfsi_orthonormalize,
                       chfsi_rayleigh_ritz, chfsi_reduce_standard, chfsi_reduce_workspace_bytes,
-                      chfsi_solve, chfsi_status_string, chfsi_step_workspace_bytes,
+                      chfsi_solve, chfsi_solve_batch, chfsi_batch_workspace_bytes,
+                      chfsi_status_string, chfsi_step_workspace_bytes,
                       chfsi_workspace_bytes, chfsi_zgemm, colmajor, header_functions, lib)

@@ -59,6 +59,14 @@ _SIGS = {
                             c_void_p, c_int, POINTER(c_double), POINTER(c_double), c_void_p, c_int,
                             c_void_p, c_size_t, POINTER(ChfsiOpts), c_void_p, POINTER(ChfsiInfo)]),
     "chfsi_status_string": (ctypes.c_char_p, [c_int]),
+    "chfsi_batch_workspace_bytes": (c_size_t, [c_int, POINTER(ChfsiOpts)]),
+    "chfsi_solve_batch": (c_int, [c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int),
+                                  POINTER(c_void_p), POINTER(c_int), POINTER(c_void_p),
+                                  POINTER(c_int), c_double, POINTER(c_void_p), POINTER(c_int),
+                                  POINTER(POINTER(c_double)), POINTER(POINTER(c_double)),
+                                  POINTER(c_void_p), POINTER(c_int), POINTER(c_void_p),
+                                  POINTER(c_size_t), c_void_p, c_size_t, POINTER(ChfsiOpts), c_int,
+                                  c_void_p, POINTER(ChfsiInfo), POINTER(c_int)]),
     "chfsi_step_workspace_bytes": (c_size_t, [c_int, c_int]),
     "chfsi_filter": (c_int, [c_int, c_int, c_void_p, c_int, c_void_p, c_int, POINTER(c_int),
                              c_double, c_double, c_double, c_void_p, c_size_t, c_void_p,
@@ -446,3 +454,66 @@ def chfsi_mlp_train(X, T, params, steps, lr, work=None, stream=None):
     _check(lib().chfsi_mlp_train(n, _ptr(X), _ptr(T), _ptr(params), int(steps), float(lr), _ptr(w),
                                  wb, _stream(stream, X.device), losses), "chfsi_mlp_train")
     return np.array(losses[:int(steps)], dtype=np.float64)
+
+
+def chfsi_batch_workspace_bytes(count, opts=None):
+    return int(lib().chfsi_batch_workspace_bytes(int(count), ctypes.byref(opts)
+                                                 if opts is not None else None))
+
+
+def chfsi_solve_batch(As, Bs, nevs, nexs, tol, X0s=None, opts=None, Lambda0s=None, Xs=None,
+                      works=None, stream=None, graph=False, raise_on_error=True):
+    """Solve len(As) independent problems in lockstep (grouped filter
+    launches).  Bs / X0s / Lambda0s: lists (entries may be None) or None.
+    Returns (status, [Lambda numpy], [X tensors], [info dicts], [statuses])."""
+    torch = _torch()
+    count = len(As)
+    dev = As[0].device
+    o = opts if opts is not None else chfsi_default_opts()
+    ns = [a.shape[0] for a in As]
+    ks = [nevs[q] + nexs[q] for q in range(count)]
+    if Xs is None:
+        Xs = [colmajor(torch.empty((ns[q], ks[q]), dtype=torch.complex128, device=dev))
+              for q in range(count)]
+    wbs = [chfsi_workspace_bytes(ns[q], nevs[q], nexs[q], Bs is not None and Bs[q] is not None, o)
+           for q in range(count)]
+    if works is None:
+        works = [_work(wbs[q], dev) for q in range(count)]
+    bw = chfsi_batch_workspace_bytes(count, o)
+    bwork = _work(bw, dev)
+    I = c_int * count
+    P = c_void_p * count
+    lam = [(c_double * ks[q])() for q in range(count)]
+    lam_ptrs = (POINTER(c_double) * count)(*[ctypes.cast(x, POINTER(c_double)) for x in lam])
+    lam0 = None
+    keep = []
+    if Lambda0s is not None:
+        arrs = []
+        for q in range(count):
+            if Lambda0s[q] is None:
+                arrs.append(None)
+            else:
+                a = (c_double * ks[q])(*[float(v) for v in Lambda0s[q]])
+                keep.append(a)
+                arrs.append(ctypes.cast(a, POINTER(c_double)))
+        lam0 = (POINTER(c_double) * count)(*arrs)
+    b_ptrs = b_lds = None
+    if Bs is not None:
+        b_ptrs = P(*[None if b is None else b.data_ptr() for b in Bs])
+        b_lds = I(*[0 if b is None else _ld(b) for b in Bs])
+    x0_ptrs = x0_lds = None
+    if X0s is not None:
+        x0_ptrs = P(*[None if x is None else x.data_ptr() for x in X0s])
+        x0_lds = I(*[0 if x is None else _ld(x) for x in X0s])
+    infos = (ChfsiInfo * count)()
+    sts = I()
+    st = lib().chfsi_solve_batch(
+        count, I(*ns), I(*[int(v) for v in nevs]), I(*[int(v) for v in nexs]),
+        P(*[a.data_ptr() for a in As]), I(*[_ld(a) for a in As]), b_ptrs, b_lds, float(tol),
+        x0_ptrs, x0_lds, lam0, lam_ptrs, P(*[x.data_ptr() for x in Xs]), I(*[_ld(x) for x in Xs]),
+        P(*[w.data_ptr() for w in works]), (c_size_t * count)(*wbs), _ptr(bwork), bw,
+        ctypes.byref(o), 1 if graph else 0, _stream(stream, dev), infos, sts)
+    if raise_on_error and st not in (CHFSI_OK, CHFSI_NO_CONVERGENCE):
+        raise ChfsiError(st, "chfsi_solve_batch")
+    return (st, [np.array(l[:]) for l in lam], Xs, [i.as_dict() for i in infos],
+            [int(v) for v in sts])

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -828,149 +829,201 @@ int learned_degrees(hipStream_t s, int k, const double* mu, const double* res, i
   return CHFSI_OK;
 }
 
-int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int ldb, double tol,
-               const zc* X0, int ldx0, const double* Lambda0, double* Lambda, zc* X, int ldx,
-               void* work,
-               size_t work_bytes, const chfsi_opts& o, hipStream_t s, chfsi_info* info) {
-  const auto t_start = std::chrono::steady_clock::now();
-  const int k = nev + nex;
-  const bool gen = B != nullptr;
+// One chfsi_solve call as a state machine over the phases of Alg. 1:
+// setup (input checks, reduction, Lanczos bound, start block), then loops
+// of begin_loop (degrees, precision, degree order), the filter, end_loop
+// (QR, Rayleigh-Ritz, residuals, locking, next degrees), and finish
+// (output).  A single solve runs the filter itself (filter_own); a batch of
+// solves runs its FP64 filters together in grouped launches.
+struct Solve {
+  // arguments
+  int n = 0, nev = 0, nex = 0, k = 0;
+  const zc* A = nullptr;
+  int lda = 0;
+  const zc* B = nullptr;
+  int ldb = 0;
+  double tol = 0.0;
+  const zc* X0 = nullptr;
+  int ldx0 = 0;
+  const double* Lambda0 = nullptr;
+  double* Lambda = nullptr;
+  zc* X = nullptr;
+  int ldx = 0;
+  void* work = nullptr;
+  size_t work_bytes = 0;
+  chfsi_opts o = {};
+  hipStream_t s = nullptr;
+  chfsi_info* info = nullptr;
+
+  // state across loops
+  std::chrono::steady_clock::time_point t_start;
+  bool gen = false;
   SolveBufs b;
-  Carver cv(work);
-  const size_t need = carve_solve(cv, b, n, nev, nex, gen, o.lanczos_steps, o.precision);
-  if (work_bytes < need) return CHFSI_INVALID_ARG;
-  StepBufs& sb = b.st;
-  double* step_acc = info ? info->step_seconds : nullptr;
-  Timers tm(s, step_acc);
-  const long ld = n;
-
-  // non-finite inputs
-  CK(hipMemsetAsync(b.flag, 0, sizeof(int), s));
-  CK(check_finite(s, n, n, A, lda, b.flag));
-  if (gen) CK(check_finite(s, n, n, B, ldb, b.flag));
-  if (X0) CK(check_finite(s, n, k, X0, ldx0, b.flag));
-  int flag = 0;
-  CKS(read_info(s, b.flag, &flag));
-  if (flag) return CHFSI_NONFINITE;
-
-  // reduction to standard form (Sec. 3.1): B = L L^H, H = L^{-1} A L^{-H};
-  // the start block in the new coordinates is Y0 = L^H X0
-  const zc* H = A;
-  long ldh = lda;
-  if (gen) {
-    tm.begin(0);
-    // reuse the factor of B when the workspace holds the factor of this B
-    FactorHeader hdr = {};
-    unsigned long long hnew = 0;
-    CK(matrix_hash(s, n, n, B, ldb, b.hpart, b.hpart + HASH_PARTS));
-    CK(hipMemcpyAsync(&hdr, b.header, sizeof(hdr), hipMemcpyDeviceToHost, s));
-    CK(hipMemcpyAsync(&hnew, b.hpart + HASH_PARTS, sizeof(hnew), hipMemcpyDeviceToHost, s));
-    CK(hipStreamSynchronize(s));
-    const bool reuse = o.reuse_b_factor && hdr.magic == FACTOR_MAGIC &&
-                       hdr.n == (unsigned long long)n && hdr.hash == hnew;
-    if (info) info->b_factor_reused = reuse ? 1 : 0;
-    if (!reuse) {
-      FactorHeader inval = {0, 0, 0, 0};
-      CK(hipMemcpyAsync(b.header, &inval, sizeof(inval), hipMemcpyHostToDevice, s));
-      CK(copy2d(s, n, n, B, ldb, b.L, ld));
-      CK(hipMemsetAsync(sb.info, 0, sizeof(int), s));
-      CKS(potrf_blocked(s, n, b.L, ld, b.invd, sb.info, 0.0));
-      int pinfo = 0;
-      CKS(read_info(s, sb.info, &pinfo));
-      if (pinfo != 0) return CHFSI_NOT_HPD;
-      CK(zero_upper(s, n, b.L, ld));
-      CK(set_identity(s, n, b.Linv, ld));
-      CKS(trsm_left_lower(s, n, n, b.L, ld, b.invd, b.Linv, ld, true));
-      FactorHeader valid = {FACTOR_MAGIC, (unsigned long long)n, hnew, 0};
-      CK(hipMemcpyAsync(b.header, &valid, sizeof(valid), hipMemcpyHostToDevice, s));
-      CK(hipStreamSynchronize(s));
-    }
-    if (X0) {
-      CK(zgemm(s, OP_C, OP_N, n, k, n, ONE, b.L, ld, X0, ldx0, ZERO, b.QA, ld, false, nullptr, 0,
-               KTRI_A_UPPER));
-    }
-    CKS(reduce_with_inverse(s, n, A, lda, b.Linv, b.W, b.H, ld));
-    tm.end();
-    H = b.H;
-    ldh = ld;
-  } else if (X0) {
-    CK(copy2d(s, n, k, X0, ldx0, b.QA, ld));
-  }
-  if (!X0) CK(fill_counter_random(s, n, k, b.QA, ld, o.seed, 1));
-
-  // Lanczos bound (the LANCZOS step of Alg. 1)
-  tm.begin(1);
-  double beta = 0.0, tmin = 0.0, tmax = 0.0;
-  CKS(lanczos_dev(s, n, H, ldh, o.lanczos_steps, o.seed, sb, &beta, &tmin, &tmax));
-  tm.end();
-  const double norm_h = std::max(std::fabs(beta), std::fabs(tmin));
-  const double tol_abs = tol * norm_h;
-  long long matvecs = std::min(o.lanczos_steps, n);
+  Timers tm{nullptr, nullptr};
+  long ld = 0;
+  const zc* H = nullptr;
+  long ldh = 0;
+  double beta = 0.0, tmin = 0.0, tmax = 0.0, norm_h = 0.0, tol_abs = 0.0;
+  long long matvecs = 0, filter_mv = 0;
   int shifted = 0;
-
-  // Start.  With the previous problem's Ritz values (Alg. 1 inputs) the
-  // first filter takes its bounds from them and filters X0 directly;
-  // otherwise one QR + Rayleigh-Ritz of the start block supplies them.
-  std::vector<double> mu(k), res(k);
-  if (X0 && Lambda0) {
-    for (int j = 0; j < k; ++j) mu[j] = Lambda0[j];
-  } else {
-    tm.begin(3);
-    CK(copy2d(s, n, k, b.QA, ld, b.TMP, ld));
-    CKS(orthonormalize_dev(s, n, k, b.TMP, ld, 0, nullptr, ld, b.QA, ld, sb, &shifted));
-    tm.end();
-    tm.begin(4);
-    CKS(rayleigh_ritz_dev(s, n, k, H, ldh, b.QA, ld, b.ZA, ld, b.P0, ld, b.P1, ld, sb, mu.data(),
-                          res.data()));
-    std::swap(b.QA, b.P0);
-    std::swap(b.ZA, b.P1);
-    tm.end();
-    tm.drain();
-    matvecs += k;
-  }
-  auto alpha_of = [&](int nl_, int ka_) {
-    if (o.alpha_rule == 1) return mu[std::min(nev - nl_, ka_ - 1)];
-    return mu[ka_ - 1];
-  };
-  double alpha = alpha_of(0, k);
-  double gamma = std::min(mu[0], tmin);
-  std::vector<int> deg(k, o.deg0);
-  // per position: where the degree came from (0 rule, 1 network, 2 guard,
+  std::vector<double> mu, res;
+  double alpha = 0.0, gamma = 0.0;
+  // per position: degree, where it came from (0 rule, 1 network, 2 guard,
   // 3 fixed deg0), the rule's degree, jittered or not
-  std::vector<int> dsrc(k, 3), rule_deg(k, o.deg0);
-  std::vector<char> jittered(k, 0);
+  std::vector<int> deg, dsrc, rule_deg;
+  std::vector<char> jittered;
   int learned_cols = 0, fallback_cols = 0, learned_raised = 0, log_records = 0;
-  if (o.degree_mode == 2)
-    CK(hipMemcpyAsync(sb.mlp_p, o.mlp, sizeof(float) * MLP_PARAMS, hipMemcpyHostToDevice, s));
-
   int nl = 0;
   std::vector<double> lam_locked;
   double max_locked_res = 0.0;
   int it = 0;
   int status = CHFSI_NO_CONVERGENCE;
-  double filter_flops = 0.0, filter_sec = 0.0;
-  double flops32 = 0.0, sec32 = 0.0;
-  int iters32 = 0;
-  long long filter_mv = 0;
-  int launches = 0;
-  // residuals of the current block known (after a Rayleigh-Ritz)
-  bool have_res = !(X0 && Lambda0);
-  if (o.precision == 1) CK(matrix_to_fp32(s, n, H, ldh, b.H32));
+  double filter_flops = 0.0, filter_sec = 0.0, flops32 = 0.0, sec32 = 0.0;
+  int iters32 = 0, launches = 0;
+  bool have_res = false;   // residuals of the current block known
   hipEvent_t fe0 = nullptr, fe1 = nullptr;
-  CK(hipEventCreate(&fe0));
-  CK(hipEventCreate(&fe1));
-  struct EvGuard { hipEvent_t a, b; ~EvGuard() { hipEventDestroy(a); hipEventDestroy(b); } } evg{fe0, fe1};
+  bool done = false;
+
+  // the current loop
+  int ka = 0, nw_loop = 0;
+  double c = 0.0, e = 0.0;
+  bool use32 = false, logging = false, own_filter = false;
+  std::vector<char> capped;
+  std::vector<double> pending;
+  std::vector<int> order, msort;
+
+  ~Solve() {
+    if (fe0) hipEventDestroy(fe0);
+    if (fe1) hipEventDestroy(fe1);
+  }
+
+  double alpha_of(int nl_, int ka_) const {
+    if (o.alpha_rule == 1) return mu[std::min(nev - nl_, ka_ - 1)];
+    return mu[ka_ - 1];
+  }
+
+  int setup() {
+    t_start = std::chrono::steady_clock::now();
+    k = nev + nex;
+    gen = B != nullptr;
+    Carver cv(work);
+    const size_t need = carve_solve(cv, b, n, nev, nex, gen, o.lanczos_steps, o.precision);
+    if (work_bytes < need) return CHFSI_INVALID_ARG;
+    StepBufs& sb = b.st;
+    tm.s = s;
+    tm.acc = info ? info->step_seconds : nullptr;
+    ld = n;
+
+    // non-finite inputs
+    CK(hipMemsetAsync(b.flag, 0, sizeof(int), s));
+    CK(check_finite(s, n, n, A, lda, b.flag));
+    if (gen) CK(check_finite(s, n, n, B, ldb, b.flag));
+    if (X0) CK(check_finite(s, n, k, X0, ldx0, b.flag));
+    int flag = 0;
+    CKS(read_info(s, b.flag, &flag));
+    if (flag) return CHFSI_NONFINITE;
+
+    // reduction to standard form (Sec. 3.1): B = L L^H, H = L^{-1} A L^{-H};
+    // the start block in the new coordinates is Y0 = L^H X0
+    H = A;
+    ldh = lda;
+    if (gen) {
+      tm.begin(0);
+      // reuse the factor of B when the workspace holds the factor of this B
+      FactorHeader hdr = {};
+      unsigned long long hnew = 0;
+      CK(matrix_hash(s, n, n, B, ldb, b.hpart, b.hpart + HASH_PARTS));
+      CK(hipMemcpyAsync(&hdr, b.header, sizeof(hdr), hipMemcpyDeviceToHost, s));
+      CK(hipMemcpyAsync(&hnew, b.hpart + HASH_PARTS, sizeof(hnew), hipMemcpyDeviceToHost, s));
+      CK(hipStreamSynchronize(s));
+      const bool reuse = o.reuse_b_factor && hdr.magic == FACTOR_MAGIC &&
+                         hdr.n == (unsigned long long)n && hdr.hash == hnew;
+      if (info) info->b_factor_reused = reuse ? 1 : 0;
+      if (!reuse) {
+        FactorHeader inval = {0, 0, 0, 0};
+        CK(hipMemcpyAsync(b.header, &inval, sizeof(inval), hipMemcpyHostToDevice, s));
+        CK(copy2d(s, n, n, B, ldb, b.L, ld));
+        CK(hipMemsetAsync(sb.info, 0, sizeof(int), s));
+        CKS(potrf_blocked(s, n, b.L, ld, b.invd, sb.info, 0.0));
+        int pinfo = 0;
+        CKS(read_info(s, sb.info, &pinfo));
+        if (pinfo != 0) return CHFSI_NOT_HPD;
+        CK(zero_upper(s, n, b.L, ld));
+        CK(set_identity(s, n, b.Linv, ld));
+        CKS(trsm_left_lower(s, n, n, b.L, ld, b.invd, b.Linv, ld, true));
+        FactorHeader valid = {FACTOR_MAGIC, (unsigned long long)n, hnew, 0};
+        CK(hipMemcpyAsync(b.header, &valid, sizeof(valid), hipMemcpyHostToDevice, s));
+        CK(hipStreamSynchronize(s));
+      }
+      if (X0) {
+        CK(zgemm(s, OP_C, OP_N, n, k, n, ONE, b.L, ld, X0, ldx0, ZERO, b.QA, ld, false, nullptr,
+                 0, KTRI_A_UPPER));
+      }
+      CKS(reduce_with_inverse(s, n, A, lda, b.Linv, b.W, b.H, ld));
+      tm.end();
+      H = b.H;
+      ldh = ld;
+    } else if (X0) {
+      CK(copy2d(s, n, k, X0, ldx0, b.QA, ld));
+    }
+    if (!X0) CK(fill_counter_random(s, n, k, b.QA, ld, o.seed, 1));
+
+    // Lanczos bound (the LANCZOS step of Alg. 1)
+    tm.begin(1);
+    CKS(lanczos_dev(s, n, H, ldh, o.lanczos_steps, o.seed, sb, &beta, &tmin, &tmax));
+    tm.end();
+    norm_h = std::max(std::fabs(beta), std::fabs(tmin));
+    tol_abs = tol * norm_h;
+    matvecs = std::min(o.lanczos_steps, n);
+
+    // Start.  With the previous problem's Ritz values (Alg. 1 inputs) the
+    // first filter takes its bounds from them and filters X0 directly;
+    // otherwise one QR + Rayleigh-Ritz of the start block supplies them.
+    mu.assign(k, 0.0);
+    res.assign(k, 0.0);
+    if (X0 && Lambda0) {
+      for (int j = 0; j < k; ++j) mu[j] = Lambda0[j];
+    } else {
+      tm.begin(3);
+      CK(copy2d(s, n, k, b.QA, ld, b.TMP, ld));
+      CKS(orthonormalize_dev(s, n, k, b.TMP, ld, 0, nullptr, ld, b.QA, ld, sb, &shifted));
+      tm.end();
+      tm.begin(4);
+      CKS(rayleigh_ritz_dev(s, n, k, H, ldh, b.QA, ld, b.ZA, ld, b.P0, ld, b.P1, ld, sb,
+                            mu.data(), res.data()));
+      std::swap(b.QA, b.P0);
+      std::swap(b.ZA, b.P1);
+      tm.end();
+      tm.drain();
+      matvecs += k;
+    }
+    alpha = alpha_of(0, k);
+    gamma = std::min(mu[0], tmin);
+    deg.assign(k, o.deg0);
+    dsrc.assign(k, 3);
+    rule_deg.assign(k, o.deg0);
+    jittered.assign(k, 0);
+    if (o.degree_mode == 2)
+      CK(hipMemcpyAsync(sb.mlp_p, o.mlp, sizeof(float) * MLP_PARAMS, hipMemcpyHostToDevice, s));
+    have_res = !(X0 && Lambda0);
+    if (o.precision == 1) CK(matrix_to_fp32(s, n, H, ldh, b.H32));
+    CK(hipEventCreate(&fe0));
+    CK(hipEventCreate(&fe1));
+    return CHFSI_OK;
+  }
 
   // Degrees of the active block for loop `loop` (Sec. 3.1.1, or learned,
   // then the optional jitter); needs the residuals of the block.
-  auto choose_degrees = [&](int ka_, int loop) -> int {
+  int choose_degrees(int ka_, int loop) {
+    StepBufs& sb = b.st;
     const int nw = std::min(nev - nl, ka_);
     deg.assign(ka_, o.deg0);
     dsrc.assign(ka_, 3);
     jittered.assign(ka_, 0);
     if (o.degree_mode == 1) return CHFSI_OK;
     std::vector<int> rule(ka_);
-    degrees_host(ka_, mu.data(), res.data(), nev - nl, alpha, beta, tol_abs, o.deg_max, rule.data());
+    degrees_host(ka_, mu.data(), res.data(), nev - nl, alpha, beta, tol_abs, o.deg_max,
+                 rule.data());
     if (o.degree_mode == 2) {
       bool finishing = false;
       CKS(learned_degrees(s, ka_, mu.data(), res.data(), nev - nl, alpha, beta, gamma, norm_h,
@@ -983,9 +1036,9 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
         std::vector<char> cp(ka_, 0);
         if (!defect_filter_safe(nev - nl, mu, res, deg, cc, ee, gamma, tol, norm_h) &&
             cap_degrees_fp32(nev - nl, mu, res, d2, cc, ee, norm_h, cp))
-          CKS(learned_degrees(s, ka_, mu.data(), res.data(), nev - nl, alpha, beta, gamma, norm_h,
-                              tol_abs, loop, o.deg_max, o.mlp, sb.mlp_p, sb.mlp_x, sb.mlp_y,
-                              deg.data(), nullptr, dsrc.data(), nullptr, 0, nullptr));
+          CKS(learned_degrees(s, ka_, mu.data(), res.data(), nev - nl, alpha, beta, gamma,
+                              norm_h, tol_abs, loop, o.deg_max, o.mlp, sb.mlp_p, sb.mlp_x,
+                              sb.mlp_y, deg.data(), nullptr, dsrc.data(), nullptr, 0, nullptr));
       }
       for (int j = 0; j < nw; ++j) {
         if (dsrc[j] == 1) ++learned_cols;
@@ -1017,12 +1070,22 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
         if (!rate[j]) deg[j] = fill;
     }
     return CHFSI_OK;
-  };
+  }
 
-  while (it < o.max_iter) {
+  // Start of an outer loop: degrees, precision, degree order; for an FP64
+  // filter the active block is gathered into P0 in that order.  Sets done
+  // when the loop cap is reached.
+  int begin_loop() {
+    StepBufs& sb = b.st;
+    own_filter = false;
+    if (it >= o.max_iter) {
+      done = true;
+      return CHFSI_OK;
+    }
     ++it;
-    const int ka = k - nl;
-    const double c = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
+    ka = k - nl;
+    c = 0.5 * (alpha + beta);
+    e = 0.5 * (beta - alpha);
     // A warm start with Lambda0 may take its first degrees from the rule
     // once the residuals of X0 are known (first_rule).
     const bool warm_rule = it == 1 && X0 && Lambda0 && o.first_rule && o.degree_mode != 1;
@@ -1039,15 +1102,15 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
       have_res = true;
     }
     if (warm_rule) CKS(choose_degrees(ka, 1));
-    // the rule's degrees of this loop (judge of learned degrees, log)
-    const int nw_loop = std::min(nev - nl, ka);
+    // the rule's degrees of this loop (for the log)
+    nw_loop = std::min(nev - nl, ka);
     if (have_res)
       degrees_host(ka, mu.data(), res.data(), nev - nl, alpha, beta, tol_abs, o.deg_max,
                    rule_deg.data());
     // precision of this filter: the FP32 defect form needs the residual
     // block of the current Ritz pairs and small enough residuals
-    bool use32 = false;
-    std::vector<char> capped(ka, 0);
+    use32 = false;
+    capped.assign(ka, 0);
     if (o.precision == 1) {
       use32 = defect_filter_safe(nev - nl, mu, res, deg, c, e, gamma, tol, norm_h);
       if (!use32) {
@@ -1061,8 +1124,8 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
         }
       }
     }
-    const bool logging = o.log && log_records < o.log_capacity && have_res;
-    std::vector<double> pending;
+    logging = o.log && log_records < o.log_capacity && have_res;
+    pending.clear();
     if (logging) {
       pending.assign((size_t)nw_loop * CHFSI_LOG_FIELDS, NAN);
       for (int j = 0; j < nw_loop; ++j) {
@@ -1084,28 +1147,37 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
       }
     }
     // columns sorted by ascending degree (stable)
-    std::vector<int> order(ka);
+    order.resize(ka);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return deg[x] < deg[y]; });
-    std::vector<int> msort(ka);
+    msort.resize(ka);
     for (int j = 0; j < ka; ++j) msort[j] = deg[order[j]];
-    double fl_before = filter_flops;
-    CK(hipEventRecord(fe0, s));
-    if (use32) {
-      tm.begin(2);
-      double f32 = 0.0;
-      CKS(defect_filter_dev(s, n, ka, b.H32, b.QA, b.ZA, ld, std::vector<double>(mu.begin(), mu.begin() + ka),
-                            order, msort, c, e, gamma, b.P0, b.TMP, sb, &f32, &launches));
-      tm.end();
-      flops32 += f32;
-      iters32 += 1;
-      for (int j = 0; j < ka; ++j) filter_flops += 8.0 * (double)n * n * msort[j];
-    } else {
+    if (!use32) {
       tm.begin(6);
       CKS(upload_ints(s, sb.perm, order));
       CKS(upload_ints(s, sb.deg, msort));
       CK(gather_cols(s, n, ka, b.QA, ld, b.P0, ld, sb.perm));
       tm.end();
+    }
+    return CHFSI_OK;
+  }
+
+  // The filter of this loop on this problem alone (Alg. 2, or its FP32
+  // defect form), timed with events on the stream.
+  int filter_own() {
+    StepBufs& sb = b.st;
+    CK(hipEventRecord(fe0, s));
+    if (use32) {
+      tm.begin(2);
+      double f32 = 0.0;
+      CKS(defect_filter_dev(s, n, ka, b.H32, b.QA, b.ZA, ld,
+                            std::vector<double>(mu.begin(), mu.begin() + ka), order, msort, c, e,
+                            gamma, b.P0, b.TMP, sb, &f32, &launches));
+      tm.end();
+      flops32 += f32;
+      iters32 += 1;
+      for (int j = 0; j < ka; ++j) filter_flops += 8.0 * (double)n * n * msort[j];
+    } else {
       // Chebyshev filter (Alg. 2)
       tm.begin(2);
       CKS(filter_dev(s, n, ka, H, ldh, b.P0, b.P1, ld, msort, c, e, gamma, sb.fpart,
@@ -1113,6 +1185,14 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
       tm.end();
     }
     CK(hipEventRecord(fe1, s));
+    own_filter = true;
+    return CHFSI_OK;
+  }
+
+  // End of an outer loop: QR, Rayleigh-Ritz, residuals, log, locking and
+  // the next loop's degrees.  Sets done on convergence.
+  int end_loop() {
+    StepBufs& sb = b.st;
     for (int j = 0; j < ka; ++j) filter_mv += msort[j];
     matvecs += std::accumulate(msort.begin(), msort.end(), 0LL);
     if (!use32) {
@@ -1120,7 +1200,6 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
       CK(gather_parity(s, n, ka, b.P0, b.P1, ld, b.TMP, ld, sb.deg));
       tm.end();
     }
-    (void)fl_before;
     // orthonormalise against the locked vectors (the QR step of Alg. 1)
     tm.begin(3);
     int sh = 0;
@@ -1135,7 +1214,7 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
     std::swap(b.ZA, b.P1);
     tm.end();
     matvecs += ka;
-    {
+    if (own_filter) {
       float ms = 0.f;
       CK(hipEventElapsedTime(&ms, fe0, fe1));
       filter_sec += 1e-3 * ms;
@@ -1173,7 +1252,10 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
         max_locked_res = std::max(max_locked_res, res[j]);
       }
       std::vector<double> mu2, res2;
-      for (int j : keep_idx) { mu2.push_back(mu[j]); res2.push_back(res[j]); }
+      for (int j : keep_idx) {
+        mu2.push_back(mu[j]);
+        res2.push_back(res[j]);
+      }
       mu.assign(k, 0.0);
       res.assign(k, 0.0);
       std::copy(mu2.begin(), mu2.end(), mu.begin());
@@ -1182,70 +1264,313 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
     }
     if (nl >= nev) {
       status = CHFSI_OK;
-      break;
+      done = true;
+      return CHFSI_OK;
     }
     const int ka2 = k - nl;
     alpha = alpha_of(nl, ka2);
     gamma = std::min(gamma, mu[0]);
     CKS(choose_degrees(ka2, it + 1));
+    return CHFSI_OK;
   }
 
-  // output: all k pairs ascending; X = L^{-H} Y for the generalized problem
-  const int ka = k - nl;
-  std::vector<double> lam_all(k);
-  std::vector<int> src(k);   // index into [QL | QA]
-  for (int j = 0; j < nl; ++j) { lam_all[j] = lam_locked[j]; src[j] = j; }
-  for (int j = 0; j < ka; ++j) { lam_all[nl + j] = mu[j]; src[nl + j] = nl + j; }
-  std::vector<int> ord(k);
-  std::iota(ord.begin(), ord.end(), 0);
-  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return lam_all[x] < lam_all[y]; });
-  tm.begin(7);
-  // [QL | QA] side by side in P1, then one gather into X in ascending order
-  CK(copy2d(s, n, nl, b.QL, ld, b.P1, ld));
-  CK(copy2d(s, n, ka, b.QA, ld, b.P1 + (size_t)nl * ld, ld));
-  std::vector<int> gperm(k);
-  for (int j = 0; j < k; ++j) gperm[j] = src[ord[j]];
-  CKS(upload_ints(s, sb.perm, gperm));
-  if (gen) {
-    // X = L^{-H} Y (upper-triangular operand)
-    CK(gather_cols(s, n, k, b.P1, ld, b.TMP, ld, sb.perm));
-    CK(zgemm(s, OP_C, OP_N, n, k, n, ONE, b.Linv, ld, b.TMP, ld, ZERO, X, ldx, false, nullptr, 0,
-             KTRI_A_UPPER));
-  } else {
-    CK(gather_cols(s, n, k, b.P1, ld, X, ldx, sb.perm));
+  // Output: all k pairs ascending; X = L^{-H} Y for the generalized
+  // problem.  Returns the solve's status.
+  int finish() {
+    StepBufs& sb = b.st;
+    const int kact = k - nl;
+    std::vector<double> lam_all(k);
+    std::vector<int> src(k);   // index into [QL | QA]
+    for (int j = 0; j < nl; ++j) {
+      lam_all[j] = lam_locked[j];
+      src[j] = j;
+    }
+    for (int j = 0; j < kact; ++j) {
+      lam_all[nl + j] = mu[j];
+      src[nl + j] = nl + j;
+    }
+    std::vector<int> ord(k);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return lam_all[x] < lam_all[y]; });
+    tm.begin(7);
+    // [QL | QA] side by side in P1, then one gather into X in ascending order
+    CK(copy2d(s, n, nl, b.QL, ld, b.P1, ld));
+    CK(copy2d(s, n, kact, b.QA, ld, b.P1 + (size_t)nl * ld, ld));
+    std::vector<int> gperm(k);
+    for (int j = 0; j < k; ++j) gperm[j] = src[ord[j]];
+    CKS(upload_ints(s, sb.perm, gperm));
+    if (gen) {
+      // X = L^{-H} Y (upper-triangular operand)
+      CK(gather_cols(s, n, k, b.P1, ld, b.TMP, ld, sb.perm));
+      CK(zgemm(s, OP_C, OP_N, n, k, n, ONE, b.Linv, ld, b.TMP, ld, ZERO, X, ldx, false, nullptr,
+               0, KTRI_A_UPPER));
+    } else {
+      CK(gather_cols(s, n, k, b.P1, ld, X, ldx, sb.perm));
+    }
+    tm.end();
+    CK(hipStreamSynchronize(s));
+    tm.drain();
+    for (int j = 0; j < k; ++j) Lambda[j] = lam_all[ord[j]];
+
+    if (info) {
+      info->iters = it;
+      info->converged = std::min(nl, nev);
+      info->filter_launches = launches;
+      info->cholqr_shifted = shifted;
+      info->matvecs = matvecs;
+      info->filter_matvecs = filter_mv;
+      info->filter_flops = filter_flops;
+      info->filter_seconds = filter_sec;
+      info->filter_iters_fp32 = iters32;
+      info->filter_flops_fp32 = flops32;
+      info->filter_seconds_fp32 = sec32;
+      info->beta = beta;
+      info->norm_h = norm_h;
+      info->max_resid = norm_h > 0.0 ? max_locked_res / norm_h : max_locked_res;
+      info->log_records = log_records;
+      info->learned_cols = learned_cols;
+      info->fallback_cols = fallback_cols;
+      info->learned_raised = learned_raised;
+      info->total_seconds = elapsed(t_start);
+    }
+    return status;
   }
-  tm.end();
+};
+
+int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int ldb, double tol,
+               const zc* X0, int ldx0, const double* Lambda0, double* Lambda, zc* X, int ldx,
+               void* work, size_t work_bytes, const chfsi_opts& o, hipStream_t s,
+               chfsi_info* info) {
+  Solve S;
+  S.n = n; S.nev = nev; S.nex = nex;
+  S.A = A; S.lda = lda; S.B = B; S.ldb = ldb; S.tol = tol;
+  S.X0 = X0; S.ldx0 = ldx0; S.Lambda0 = Lambda0; S.Lambda = Lambda; S.X = X; S.ldx = ldx;
+  S.work = work; S.work_bytes = work_bytes; S.o = o; S.s = s; S.info = info;
+  CKS(S.setup());
+  for (;;) {
+    CKS(S.begin_loop());
+    if (S.done) break;
+    CKS(S.filter_own());
+    CKS(S.end_loop());
+    if (S.done) break;
+  }
+  return S.finish();
+}
+
+// FP64 filters (Alg. 2) of several solves in lockstep: step i of every
+// solve whose highest degree exceeds i runs in one grouped launch.  The
+// launch arguments of all steps are built on the host and uploaded once;
+// with `graph` the step launches are captured as one HIP graph and
+// launched as a whole.  Device time is shared out by flops.
+int filter_group(hipStream_t s, const std::vector<Solve*>& jobs, GemmArgs* dlist, int* dslots,
+                 size_t cap_entries, size_t cap_slots, bool graph, hipEvent_t e0, hipEvent_t e1) {
+  const int count = (int)jobs.size();
+  int steps = 0;
+  for (Solve* j : jobs) steps = std::max(steps, j->msort.back());
+  std::vector<GemmArgs> list;
+  std::vector<int> slot_begin, step_entry(steps + 1, 0), step_slot(steps + 1, 0), step_count(steps),
+      step_total(steps);
+  std::vector<double> sig(count), sig1(count), fl(count, 0.0);
+  std::vector<int> first(count, 0);
+  for (int q = 0; q < count; ++q) {
+    Solve& S = *jobs[q];
+    sig1[q] = S.e / (S.gamma - S.c);
+    sig[q] = sig1[q];
+    while (first[q] < S.ka && S.msort[first[q]] <= 1) ++first[q];
+  }
+  for (int i = 0; i < steps; ++i) {
+    step_entry[i] = (int)list.size();
+    step_slot[i] = (int)slot_begin.size();
+    int total = 0, cnt = 0;
+    slot_begin.push_back(0);
+    for (int q = 0; q < count; ++q) {
+      Solve& S = *jobs[q];
+      if (S.msort.back() <= i) continue;
+      int sl = 0;
+      const double nn = (double)S.n * S.n;
+      if (i == 0) {
+        // Y_1 = (sigma_1 / e)(H Y_0 - c Y_0)
+        list.push_back(cheb_group_args(S.n, S.ka, S.H, S.ldh, S.b.P0, S.ld, nullptr, S.ld, S.b.P1,
+                                       S.ld, S.c, sig1[q] / S.e, 0.0, &sl));
+        fl[q] += 8.0 * nn * S.ka;
+      } else {
+        const double sn = 1.0 / (2.0 / sig1[q] - sig[q]);
+        zc* cur = (i & 1) ? S.b.P1 : S.b.P0;
+        zc* old = (i & 1) ? S.b.P0 : S.b.P1;
+        const int cols = S.ka - first[q];
+        const size_t off = (size_t)first[q] * S.ld;
+        list.push_back(cheb_group_args(S.n, cols, S.H, S.ldh, cur + off, S.ld, old + off, S.ld,
+                                       old + off, S.ld, S.c, 2.0 * sn / S.e, sn * sig[q], &sl));
+        fl[q] += 8.0 * nn * cols;
+        sig[q] = sn;
+        while (first[q] < S.ka && S.msort[first[q]] <= i + 1) ++first[q];
+      }
+      S.launches += 1;
+      total += sl;
+      slot_begin.push_back(total);
+      ++cnt;
+    }
+    step_count[i] = cnt;
+    step_total[i] = total;
+  }
+  if (list.size() > cap_entries || slot_begin.size() > cap_slots) return CHFSI_INVALID_ARG;
+  CK(hipMemcpyAsync(dlist, list.data(), sizeof(GemmArgs) * list.size(), hipMemcpyHostToDevice, s));
+  CK(hipMemcpyAsync(dslots, slot_begin.data(), sizeof(int) * slot_begin.size(),
+                    hipMemcpyHostToDevice, s));
   CK(hipStreamSynchronize(s));
-  tm.drain();
-  for (int j = 0; j < k; ++j) Lambda[j] = lam_all[ord[j]];
-
-  if (info) {
-    info->iters = it;
-    info->converged = std::min(nl, nev);
-    info->filter_launches = launches;
-    info->cholqr_shifted = shifted;
-    info->matvecs = matvecs;
-    info->filter_matvecs = filter_mv;
-    info->filter_flops = filter_flops;
-    info->filter_seconds = filter_sec;
-    info->filter_iters_fp32 = iters32;
-    info->filter_flops_fp32 = flops32;
-    info->filter_seconds_fp32 = sec32;
-    info->beta = beta;
-    info->norm_h = norm_h;
-    info->max_resid = norm_h > 0.0 ? max_locked_res / norm_h : max_locked_res;
-    info->log_records = log_records;
-    info->learned_cols = learned_cols;
-    info->fallback_cols = fallback_cols;
-    info->learned_raised = learned_raised;
+  CK(hipEventRecord(e0, s));
+  if (graph) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    CK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int err = 0;
+    for (int i = 0; i < steps && !err; ++i)
+      err = cheb_step_group(s, dlist + step_entry[i], dslots + step_slot[i], step_count[i],
+                            step_total[i]);
+    const int cap_err = (int)hipStreamEndCapture(s, &g);
+    if (err || cap_err) {
+      if (g) hipGraphDestroy(g);
+      return CHFSI_DEVICE_ERROR;
+    }
+    err = (int)hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (!err) err = (int)hipGraphLaunch(ge, s);
+    if (!err) err = (int)hipStreamSynchronize(s);
+    if (ge) hipGraphExecDestroy(ge);
+    hipGraphDestroy(g);
+    if (err) return CHFSI_DEVICE_ERROR;
+  } else {
+    for (int i = 0; i < steps; ++i)
+      CK(cheb_step_group(s, dlist + step_entry[i], dslots + step_slot[i], step_count[i],
+                         step_total[i]));
   }
-  if (info) info->total_seconds = elapsed(t_start);
-  return status;
+  CK(hipEventRecord(e1, s));
+  CK(hipEventSynchronize(e1));
+  float ms = 0.f;
+  CK(hipEventElapsedTime(&ms, e0, e1));
+  double ftot = 0.0;
+  for (double f : fl) ftot += f;
+  for (int q = 0; q < count; ++q) {
+    jobs[q]->filter_flops += fl[q];
+    if (ftot > 0.0) jobs[q]->filter_sec += 1e-3 * ms * fl[q] / ftot;
+  }
+  return CHFSI_OK;
+}
+
+// Launch-argument capacity of the batch workspace for `count` solves.
+void batch_caps(int count, const chfsi_opts& o, size_t* entries, size_t* slots) {
+  const size_t steps = (size_t)std::max(std::max(o.deg0, o.deg_max), 1);
+  *entries = steps * (size_t)count;
+  *slots = steps * ((size_t)count + 1);
+}
+
+size_t batch_bytes(int count, const chfsi_opts& o) {
+  size_t entries = 0, slots = 0;
+  batch_caps(count, o, &entries, &slots);
+  Carver c(nullptr);
+  c.take<GemmArgs>(entries);
+  c.take<int>(slots);
+  return c.off + ALIGN;
+}
+
+// Solves in lockstep: every loop runs begin_loop on all unfinished solves,
+// their FP64 filters together (filter_group), their FP32 defect filters one
+// after the other, then end_loop on all.  status[q] receives each solve's
+// result.
+int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void* bwork,
+                     size_t bbytes, bool graph, std::vector<int>& status) {
+  const int count = (int)S.size();
+  size_t cap_entries = 0, cap_slots = 0;
+  batch_caps(count, S[0]->o, &cap_entries, &cap_slots);
+  if (bbytes < batch_bytes(count, S[0]->o)) return CHFSI_INVALID_ARG;
+  Carver cv(bwork);
+  GemmArgs* dlist = cv.take<GemmArgs>(cap_entries);
+  int* dslots = cv.take<int>(cap_slots);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  CK(hipEventCreate(&e0));
+  CK(hipEventCreate(&e1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() {
+      hipEventDestroy(a);
+      hipEventDestroy(b);
+    }
+  } evg{e0, e1};
+  status.assign(count, CHFSI_OK);
+  std::vector<char> failed(count, 0);
+  for (int q = 0; q < count; ++q) {
+    status[q] = S[q]->setup();
+    if (status[q] != CHFSI_OK) failed[q] = 1;
+  }
+  for (;;) {
+    std::vector<Solve*> active, fp64;
+    for (int q = 0; q < count; ++q) {
+      if (failed[q] || S[q]->done) continue;
+      status[q] = S[q]->begin_loop();
+      if (status[q] != CHFSI_OK) {
+        failed[q] = 1;
+        continue;
+      }
+      if (!S[q]->done) active.push_back(S[q].get());
+    }
+    if (active.empty()) break;
+    for (Solve* a : active) {
+      if (a->use32) {
+        const int st = a->filter_own();
+        if (st != CHFSI_OK) return st;
+      } else if (a->ka > 0) {
+        fp64.push_back(a);
+      }
+    }
+    if (!fp64.empty()) CKS(filter_group(s, fp64, dlist, dslots, cap_entries, cap_slots, graph, e0, e1));
+    for (int q = 0; q < count; ++q) {
+      Solve* a = S[q].get();
+      if (failed[q] || std::find(active.begin(), active.end(), a) == active.end()) continue;
+      status[q] = a->end_loop();
+      if (status[q] != CHFSI_OK) failed[q] = 1;
+    }
+  }
+  for (int q = 0; q < count; ++q)
+    if (!failed[q]) status[q] = S[q]->finish();
+  return CHFSI_OK;
 }
 
 int check_ptr(const void* p) { return (p && aligned16(p)) ? CHFSI_OK : CHFSI_INVALID_ARG; }
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+// Argument checks of chfsi_solve (no device calls).
+int validate_solve(int n, int nev, int nex, const void* A, int lda, const void* B, int ldb,
+                   double tol, const void* X0, int ldx0, const double* Lambda0, double* Lambda,
+                   void* X, int ldx, void* work, const chfsi_opts& o) {
+    const int k = nev + nex;
+    if (n < 1 || nev < 1 || nex < 1 || k > n || !(tol > 0.0) || lda < n || ldx < n) return CHFSI_INVALID_ARG;
+    if (check_ptr(A) || check_ptr(X) || check_ptr(work) || !Lambda) return CHFSI_INVALID_ARG;
+    if (B && (ldb < n || !aligned16(B))) return CHFSI_INVALID_ARG;
+    if (X0 && (ldx0 < n || !aligned16(X0))) return CHFSI_INVALID_ARG;
+    if (o.deg0 < 1 || o.deg_max < 1 || o.max_iter < 1 || o.lanczos_steps < 1) return CHFSI_INVALID_ARG;
+    if (o.precision < 0 || o.precision > 1) return CHFSI_INVALID_ARG;
+    if (o.degree_mode < 0 || o.degree_mode > 2 || o.first_rule < 0 || o.first_rule > 1)
+      return CHFSI_INVALID_ARG;
+    if (!(o.degree_jitter >= 0.0) || !std::isfinite(o.degree_jitter)) return CHFSI_INVALID_ARG;
+    if (o.log_capacity < 0 || (o.log_capacity > 0 && !o.log)) return CHFSI_INVALID_ARG;
+    if (o.degree_mode == 2) {
+      if (!o.mlp) return CHFSI_INVALID_ARG;
+      for (int i = 0; i < MLP_PARAMS; ++i)
+        if (!std::isfinite(o.mlp[i])) return CHFSI_NONFINITE;
+    }
+    if (o.precision == 1 && (o.deg0 > CR_ROWS || o.deg_max > CR_ROWS)) return CHFSI_INVALID_ARG;
+    if (X0 == X && ldx0 != ldx) return CHFSI_INVALID_ARG;
+    if (Lambda0) {
+      if (!X0) return CHFSI_INVALID_ARG;
+      for (int j = 0; j < k; ++j) {
+        if (!std::isfinite(Lambda0[j])) return CHFSI_NONFINITE;
+        if (j > 0 && Lambda0[j] < Lambda0[j - 1]) return CHFSI_INVALID_ARG;
+      }
+      if (!(Lambda0[k - 1] > Lambda0[0])) return CHFSI_INVALID_ARG;
+    }
+    return CHFSI_OK;
+}
+
 
 }  // namespace
 }  // namespace chfsi
@@ -1274,6 +1599,73 @@ int chfsi_default_opts(chfsi_opts* o) {
   return CHFSI_OK;
 }
 
+size_t chfsi_batch_workspace_bytes(int count, const chfsi_opts* opts) {
+  if (count < 1) return 0;
+  chfsi_opts o;
+  chfsi_default_opts(&o);
+  if (opts) o = *opts;
+  return batch_bytes(count, o);
+}
+
+int chfsi_solve_batch(int count, const int* n, const int* nev, const int* nex,
+                      const void* const* A, const int* lda, const void* const* B, const int* ldb,
+                      double tol, const void* const* X0, const int* ldx0,
+                      const double* const* Lambda0, double* const* Lambda, void* const* X,
+                      const int* ldx, void* const* work, const size_t* work_bytes,
+                      void* batch_work, size_t batch_work_bytes, const chfsi_opts* opts, int flags,
+                      void* stream, chfsi_info* info, int* status) {
+  try {
+    if (count < 1 || !n || !nev || !nex || !A || !lda || !Lambda || !X || !ldx || !work ||
+        !work_bytes || !status || check_ptr(batch_work) || (flags & ~1))
+      return CHFSI_INVALID_ARG;
+    if ((B && !ldb) || (X0 && !ldx0)) return CHFSI_INVALID_ARG;
+    if ((flags & 1) && !stream) return CHFSI_INVALID_ARG;   // no capture on the null stream
+    chfsi_opts o;
+    chfsi_default_opts(&o);
+    if (opts) o = *opts;
+    o.tol = tol;
+    if (o.log_capacity != 0) return CHFSI_INVALID_ARG;      // no shared log in a batch
+    for (int q = 0; q < count; ++q) {
+      const void* bq = B ? B[q] : nullptr;
+      const void* xq = X0 ? X0[q] : nullptr;
+      const double* lq = Lambda0 ? Lambda0[q] : nullptr;
+      CKS(validate_solve(n[q], nev[q], nex[q], A[q], lda[q], bq, bq ? ldb[q] : 0, tol, xq,
+                         xq ? ldx0[q] : 0, lq, Lambda[q], X[q], ldx[q], work[q], o));
+      for (int r = 0; r < q; ++r)
+        if (work[r] == work[q]) return CHFSI_INVALID_ARG;   // workspaces must be distinct
+    }
+    if (batch_work_bytes < batch_bytes(count, o)) return CHFSI_INVALID_ARG;
+    std::vector<std::unique_ptr<Solve>> S(count);
+    for (int q = 0; q < count; ++q) {
+      S[q].reset(new Solve());
+      Solve& v = *S[q];
+      v.n = n[q]; v.nev = nev[q]; v.nex = nex[q];
+      v.A = (const zc*)A[q]; v.lda = lda[q];
+      v.B = B ? (const zc*)B[q] : nullptr; v.ldb = v.B ? ldb[q] : 0;
+      v.tol = tol;
+      v.X0 = X0 ? (const zc*)X0[q] : nullptr; v.ldx0 = v.X0 ? ldx0[q] : 0;
+      v.Lambda0 = Lambda0 ? Lambda0[q] : nullptr;
+      v.Lambda = Lambda[q]; v.X = (zc*)X[q]; v.ldx = ldx[q];
+      v.work = work[q]; v.work_bytes = work_bytes[q];
+      v.o = o; v.s = as_stream(stream);
+      v.info = info ? &info[q] : nullptr;
+      if (v.info) std::memset(v.info, 0, sizeof(chfsi_info));
+    }
+    std::vector<int> st;
+    CKS(solve_batch_impl(S, as_stream(stream), batch_work, batch_work_bytes, (flags & 1) != 0, st));
+    int worst = CHFSI_OK;
+    for (int q = 0; q < count; ++q) {
+      status[q] = st[q];
+      if (st[q] != CHFSI_OK && (worst == CHFSI_OK || worst == CHFSI_NO_CONVERGENCE)) worst = st[q];
+    }
+    return worst;
+  } catch (const std::bad_alloc&) {
+    return CHFSI_ALLOC_ERROR;
+  } catch (...) {
+    return CHFSI_DEVICE_ERROR;
+  }
+}
+
 const char* chfsi_status_string(int status) {
   switch (status) {
     case CHFSI_OK: return "success";
@@ -1298,6 +1690,7 @@ size_t chfsi_workspace_bytes(int n, int nev, int nex, int generalized, const chf
                      o.precision);
 }
 
+
 int chfsi_solve(int n, int nev, int nex, const void* A, int lda, const void* B, int ldb, double tol,
                 const void* X0, int ldx0, const double* Lambda0, double* Lambda, void* X, int ldx,
                 void* work, size_t work_bytes, const chfsi_opts* opts, void* stream,
@@ -1307,32 +1700,8 @@ int chfsi_solve(int n, int nev, int nex, const void* A, int lda, const void* B, 
     chfsi_default_opts(&o);
     if (opts) o = *opts;
     o.tol = tol;
-    const int k = nev + nex;
-    if (n < 1 || nev < 1 || nex < 1 || k > n || !(tol > 0.0) || lda < n || ldx < n) return CHFSI_INVALID_ARG;
-    if (check_ptr(A) || check_ptr(X) || check_ptr(work) || !Lambda) return CHFSI_INVALID_ARG;
-    if (B && (ldb < n || !aligned16(B))) return CHFSI_INVALID_ARG;
-    if (X0 && (ldx0 < n || !aligned16(X0))) return CHFSI_INVALID_ARG;
-    if (o.deg0 < 1 || o.deg_max < 1 || o.max_iter < 1 || o.lanczos_steps < 1) return CHFSI_INVALID_ARG;
-    if (o.precision < 0 || o.precision > 1) return CHFSI_INVALID_ARG;
-    if (o.degree_mode < 0 || o.degree_mode > 2 || o.first_rule < 0 || o.first_rule > 1)
-      return CHFSI_INVALID_ARG;
-    if (!(o.degree_jitter >= 0.0) || !std::isfinite(o.degree_jitter)) return CHFSI_INVALID_ARG;
-    if (o.log_capacity < 0 || (o.log_capacity > 0 && !o.log)) return CHFSI_INVALID_ARG;
-    if (o.degree_mode == 2) {
-      if (!o.mlp) return CHFSI_INVALID_ARG;
-      for (int i = 0; i < MLP_PARAMS; ++i)
-        if (!std::isfinite(o.mlp[i])) return CHFSI_NONFINITE;
-    }
-    if (o.precision == 1 && (o.deg0 > CR_ROWS || o.deg_max > CR_ROWS)) return CHFSI_INVALID_ARG;
-    if (X0 == X && ldx0 != ldx) return CHFSI_INVALID_ARG;
-    if (Lambda0) {
-      if (!X0) return CHFSI_INVALID_ARG;
-      for (int j = 0; j < k; ++j) {
-        if (!std::isfinite(Lambda0[j])) return CHFSI_NONFINITE;
-        if (j > 0 && Lambda0[j] < Lambda0[j - 1]) return CHFSI_INVALID_ARG;
-      }
-      if (!(Lambda0[k - 1] > Lambda0[0])) return CHFSI_INVALID_ARG;
-    }
+    CKS(validate_solve(n, nev, nex, A, lda, B, ldb, tol, X0, ldx0, Lambda0, Lambda, X, ldx, work,
+                       o));
     if (info) std::memset(info, 0, sizeof(*info));
     return solve_impl(n, nev, nex, (const zc*)A, lda, (const zc*)B, ldb, tol, (const zc*)X0, ldx0,
                       Lambda0, Lambda, (zc*)X, ldx, work, work_bytes, o, as_stream(stream), info);

@@ -68,6 +68,16 @@ int cheb_step(hipStream_t s, int n, int N, const zc* H, long ldh,
               zc* Yout, long ldyout, double shift, double sa, double sb,
               zc* part, size_t part_elems);
 
+// Batched form of cheb_step: the launch arguments of one problem's step
+// (no split-K), and the number of workgroups it needs (a multiple of 8).
+GemmArgs cheb_group_args(int n, int N, const zc* H, long ldh, const zc* Ycur, long ldyc,
+                         const zc* Yold, long ldyo, zc* Yout, long ldyout, double shift, double sa,
+                         double sb, int* slots);
+// One launch running `count` steps; list (device) holds their arguments and
+// slot_begin (device, count + 1 ints, multiples of 8) their workgroup ranges.
+int cheb_step_group(hipStream_t s, const GemmArgs* list, const int* slot_begin, int count,
+                    int total_slots);
+
 // ----- small kernels (blas1.hip) -----
 int col_norms(hipStream_t s, int n, int k, const zc* X, long ldx, double* out);
 int resid_norms(hipStream_t s, int n, int k, const zc* Q, long ldq, const zc* Z, long ldz,

@@ -119,6 +119,28 @@ __device__ __forceinline__ void lower_tile(int t, int& tm, int& tn) {
   tn = t - r * (r + 1) / 2;
 }
 
+// One 64x64 output tile (tile row tm, tile column tn, K chunk `split`) of
+// the launch described by g, with its epilogue.
+template <int OPA, int OPB, int EPI>
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, int tn,
+                                          zc (*As)[BK][PA], zc (*Bs)[BK][PB]);
+
+// Virtual-row scheduling of a rectangular tile set (see zgemm_kernel):
+// returns false when workgroup `local` has no tile.
+__device__ __forceinline__ bool rect_tile(const GemmArgs& g, int local, int& split, int& tm,
+                                          int& tn) {
+  const int xcd = local % NXCD, slot = local / NXCD;
+  const int vrows = g.splits * g.tiles_m;
+  const int rows_x = (vrows - xcd + NXCD - 1) / NXCD;
+  const int ri = slot / g.tiles_n;
+  tn = slot - ri * g.tiles_n;
+  if (ri >= rows_x) return false;
+  const int v = xcd + NXCD * (g.rows_desc ? rows_x - 1 - ri : ri);
+  split = v / g.tiles_m;
+  tm = v - split * g.tiles_m;
+  return true;
+}
+
 // Four resident workgroups per CU (16 waves): the kernel fits in 128
 // registers per lane without spills, with accumulators in VGPRs.
 template <int OPA, int OPB, int EPI>
@@ -139,16 +161,36 @@ __global__ void __launch_bounds__(NT, 4) zgemm_kernel(GemmArgs g) {
     split = logical / g.total_tiles;
     lower_tile(logical - split * g.total_tiles, tm, tn);
   } else {
-    const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
-    const int vrows = g.splits * g.tiles_m;
-    const int rows_x = (vrows - xcd + NXCD - 1) / NXCD;
-    const int ri = slot / g.tiles_n;
-    tn = slot - ri * g.tiles_n;
-    if (ri >= rows_x) return;
-    const int v = xcd + NXCD * (g.rows_desc ? rows_x - 1 - ri : ri);
-    split = v / g.tiles_m;
-    tm = v - split * g.tiles_m;
+    if (!rect_tile(g, blockIdx.x, split, tm, tn)) return;
   }
+  gemm_tile<OPA, OPB, EPI>(g, split, tm, tn, As, Bs);
+}
+
+// Several independent Chebyshev steps (one per problem of a batch) in one
+// launch: problem p owns workgroups [slot_begin[p], slot_begin[p + 1]), a
+// multiple of the XCD count, scheduled inside its range exactly as a launch
+// of its own.
+__global__ void __launch_bounds__(NT, 4) zgemm_group_cheb(const GemmArgs* __restrict__ list,
+                                                           const int* __restrict__ slot_begin,
+                                                           int count) {
+  __shared__ zc As[2][BK][PA];
+  __shared__ zc Bs[2][BK][PB];
+  const int b = blockIdx.x;
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (slot_begin[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  const GemmArgs g = list[lo];
+  int split, tm, tn;
+  if (!rect_tile(g, b - slot_begin[lo], split, tm, tn)) return;
+  gemm_tile<OP_N, OP_N, EPI_CHEB>(g, split, tm, tn, As, Bs);
+}
+
+template <int OPA, int OPB, int EPI>
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, int tn,
+                                          zc (*As)[BK][PA], zc (*Bs)[BK][PB]) {
   const int m0 = tm * BM, n0 = tn * BN;
   int kbeg = split * g.kchunk;
   int kend = min(g.K, kbeg + g.kchunk);
@@ -424,6 +466,29 @@ int zgemm(hipStream_t s, Op opa, Op opb, int M, int N, int K, zc alpha, const zc
   hipLaunchKernelGGL(splitk_reduce, dim3((unsigned)((total + threads - 1) / threads)),
                      dim3(threads), 0, s, M, N, p.splits, (const zc*)work, alpha, beta, C, ldc,
                      g.lower_only);
+  return (int)hipGetLastError();
+}
+
+GemmArgs cheb_group_args(int n, int N, const zc* H, long ldh, const zc* Ycur, long ldyc,
+                         const zc* Yold, long ldyo, zc* Yout, long ldyout, double shift, double sa,
+                         double sb, int* slots) {
+  Plan p = make_plan(n, N, n, false, false);
+  GemmArgs g = {};
+  g.M = n; g.N = N; g.K = n;
+  g.A = H; g.lda = ldh; g.B = Ycur; g.ldb = ldyc; g.C = Yout; g.ldc = ldyout;
+  g.Ycur = Ycur; g.ldyc = ldyc; g.Yold = Yold; g.ldyo = ldyo;
+  g.shift = shift; g.sa = sa; g.sb = sb;
+  g.tiles_m = p.tiles_m; g.tiles_n = p.tiles_n; g.total_tiles = p.total;
+  g.splits = 1;
+  g.kchunk = p.kchunk;
+  *slots = ((p.tiles_m + NXCD - 1) / NXCD) * p.tiles_n * NXCD;
+  return g;
+}
+
+int cheb_step_group(hipStream_t s, const GemmArgs* list, const int* slot_begin, int count,
+                    int total_slots) {
+  if (count <= 0 || total_slots <= 0) return 0;
+  hipLaunchKernelGGL(zgemm_group_cheb, dim3(total_slots), dim3(NT), 0, s, list, slot_begin, count);
   return (int)hipGetLastError();
 }
 
