@@ -107,12 +107,122 @@ def filter_only(conf, degree):
                       "copy_bytes": src.numel() * 8}), flush=True)
 
 
+def kpoints(args):
+    """Batched k-point sequences: 32 independent generalized problems with n
+    uniform in [2000, 9000], nev = 5 %, nex = 1 % of n, 5 steps each
+    (perturbations 1e-2 * 0.5^l).  Step 1 (random starts) is the warm-up;
+    steps 2-5 are timed, every problem warm-started from its previous
+    solution.  Variants: one chfsi_solve_batch call per step (grouped filter
+    launches; FP64, FP64 with graph capture, mixed precision) against 32
+    chfsi_solve calls per step (FP64).  Prints one JSON line."""
+    import torch
+    import paper_1404_4161_amd as ch
+    from workloads import gen
+    dev = "cuda:0"
+    confs = gen.kpoint_configs()
+    count = len(confs)
+    stream = torch.cuda.Stream(device=dev)
+    results = {}
+    shapes = sorted({(c.n, c.k) for c in confs} | {(c.n, max(c.k // 4, 16)) for c in confs})
+    t0 = time.perf_counter()
+    tv, ttf = ch.chfsi_autotune_filter([a for a, _ in shapes], [b for _, b in shapes])
+    log(f"autotune of {len(shapes)} shapes in {time.perf_counter() - t0:.1f}s: "
+        f"variant 1 chosen for {int(tv.sum())}")
+
+    def run(label, precision, batched, graph):
+        t0 = time.perf_counter()
+        seqs = [gen.Sequence(c, kind="torch", device=dev, draw="device") for c in confs]
+        gens = [s_.problems() for s_ in seqs]
+        Bs = [s_.B for s_ in seqs]
+        torch.cuda.synchronize()
+        log(f"[kpoints {label}] generated the first problems in {time.perf_counter() - t0:.1f}s")
+        o = ch.chfsi_default_opts()
+        o.precision = precision
+        works = [torch.empty(ch.chfsi_workspace_bytes(c.n, c.nev, c.nex, True, o),
+                             dtype=torch.uint8, device=dev) for c in confs]
+        Xs = [ch.colmajor(torch.empty((c.n, c.k), dtype=torch.complex128, device=dev))
+              for c in confs]
+        x0s = lam0s = None
+        walls, infos_all = [], []
+        for step in range(confs[0].length):
+            As = [next(g_)[1] for g_ in gens]
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            with torch.cuda.stream(stream):
+                if batched:
+                    st, lams, _, infos, sts = ch.chfsi_solve_batch(
+                        As, Bs, [c.nev for c in confs], [c.nex for c in confs], 1e-10,
+                        X0s=x0s, Lambda0s=lam0s, opts=o, Xs=Xs, works=works, stream=stream,
+                        graph=graph)
+                    if st != 0:
+                        raise RuntimeError(f"chfsi_solve_batch status {st} {sts}")
+                else:
+                    lams, infos = [], []
+                    for q, c in enumerate(confs):
+                        st, lam, _, info = ch.chfsi_solve(
+                            As[q], Bs[q], c.nev, c.nex, 1e-10,
+                            X0=None if x0s is None else x0s[q],
+                            Lambda0=None if lam0s is None else lam0s[q], opts=o, X=Xs[q],
+                            work=works[q], stream=stream)
+                        if st != 0:
+                            raise RuntimeError(f"chfsi_solve status {st}")
+                        lams.append(lam)
+                        infos.append(info)
+            stream.synchronize()
+            wall = time.perf_counter() - ts
+            log(f"[kpoints {label}] step {step + 1}: {wall:.3f}s, loops "
+                f"{min(i['iters'] for i in infos)}-{max(i['iters'] for i in infos)}")
+            if step > 0:
+                walls.append(wall)
+                infos_all.append(infos)
+            x0s, lam0s = Xs, lams
+            del As
+        fl = sum(i["filter_flops"] for inf in infos_all for i in inf)
+        phase_names = ["reduction", "lanczos", "filter", "orthonormalize", "rayleigh_ritz",
+                       "residuals", "locking", "back_transform"]
+        ph = np.sum([i["step_seconds"] for inf in infos_all for i in inf], axis=0) / len(walls)
+        results[label] = {
+            "device_seconds_per_step_summed_over_problems": {
+                nm: round(float(v), 3) for nm, v in zip(phase_names, ph)},
+            "s_per_step": round(statistics.mean(walls), 4),
+            "s_per_step_each": [round(w, 4) for w in walls],
+            "filter_tflops_over_wall": round(fl / sum(walls) / 1e12, 3),
+            "loops_per_step": [sum(i["iters"] for i in inf) for inf in infos_all],
+            "lams_last": [l[:c.nev].copy() for l, c in zip(lam0s, confs)],
+        }
+        del works, Xs, seqs, gens, Bs
+        torch.cuda.empty_cache()
+
+    run("batched fp64", 0, True, False)
+    run("batched fp64 graph", 0, True, True)
+    run("sequential fp64", 0, False, False)
+    run("batched mixed", 1, True, False)
+    ref = results["sequential fp64"]["lams_last"]
+    for lab, r in results.items():
+        r["max_rel_eig_diff_vs_sequential_fp64"] = float(max(
+            np.max(np.abs(a - b) / np.abs(b)) for a, b in zip(r.pop("lams_last"), ref)))
+    out = {
+        "metric": "s per batched sequence step (32 k-point problems) at 1e-10 residual",
+        "autotune": {"shapes": len(shapes), "variant1_chosen": int(tv.sum()),
+                     "mean_tflops_kb8": round(float(ttf[:, 0].mean()), 2),
+                     "mean_tflops_kb16": round(float(ttf[:, 1].mean()), 2)},
+        "workload": "kpoints: 32 generalized complex Hermitian sequences, n uniform in "
+                    "[2000, 9000], nev 5 %, nex 1 %, 5 steps (step 1 untimed)",
+        "n": [c.n for c in confs], "steps": confs[0].length - 1,
+        "speedup_batched_vs_sequential_fp64": round(
+            results["sequential fp64"]["s_per_step"] / results["batched fp64"]["s_per_step"], 3),
+        "variants": results,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=9)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gen-n8000", choices=["gen-n8000", "std-n1000"])
+    ap.add_argument("--workload", default="gen-n8000",
+                    choices=["gen-n8000", "std-n1000", "kpoints"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-degree", type=int, default=40)
     ap.add_argument("--filter-only", action="store_true",
@@ -137,6 +247,9 @@ def main():
     from workloads import gen
 
     ch.lib()   # fail loudly if the HIP library is missing
+    if args.workload == "kpoints":
+        kpoints(args)
+        return
     conf = gen.CONFIGS[args.workload]
     if args.filter_only:
         filter_only(conf, args.degree)
@@ -169,6 +282,16 @@ def main():
     wb = max(ch.chfsi_workspace_bytes(n, nev, nex, B is not None, o) for o in (opts0, opts1))
     work = torch.empty(wb, dtype=torch.uint8, device=dev)
     X = ch.colmajor(torch.empty((n, k), dtype=torch.complex128, device=dev))
+
+    # Filter tile autotuner (untimed): both K-stage variants of the filter
+    # step on the full window and narrower ones; later launches take the
+    # choice of the nearest measured shape.
+    tune_shapes = [(n, k), (n, k // 2), (n, k // 4), (n, max(k // 8, 16))]
+    tv, ttf = ch.chfsi_autotune_filter([a for a, _ in tune_shapes], [b for _, b in tune_shapes])
+    autotune = [{"n": a, "N": b, "variant": int(v), "tflops_kb8": round(float(t[0]), 2),
+                 "tflops_kb16": round(float(t[1]), 2)}
+                for (a, b), v, t in zip(tune_shapes, tv, ttf)]
+    log(f"autotune: {autotune}")
 
     # Degree network (untimed): convergence logs of a sequence with the same
     # recipe under another seed, then training with the library's kernels.
@@ -333,6 +456,7 @@ def main():
                 float(np.max(np.abs(a - b) / np.abs(a))) for a, b in zip(lams64, llams)],
         }
     out["fp64_filter_matvecs_per_step"] = [i["filter_matvecs"] for i in infos]
+    out["filter_autotune"] = autotune
     if train_report is not None:
         out["degree_network"] = train_report
     if not args.no_cpu_baseline:

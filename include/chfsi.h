@@ -230,8 +230,12 @@ int chfsi_solve(int n, int nev, int nex,
  * sequence): `count` problems, each with the arguments of chfsi_solve given
  * by index q (arrays of count entries), run their outer loops in lockstep.
  * Every loop's FP64 filters of all problems share one launch per recurrence
- * step (a grouped MFMA kernel over all problems' tiles); QR, Rayleigh-Ritz
- * and the FP32 defect filters run per problem on the same stream.  Each
+ * step (a grouped MFMA kernel over all problems' tiles) on `stream`; the
+ * per-problem phases (reduction, Lanczos, QR, Rayleigh-Ritz, FP32 defect
+ * filters) run on up to 8 internal streams, each driven by a host thread of
+ * the library with its own rocSOLVER handle, so that different problems'
+ * phases overlap.  Event dependencies order everything after the work
+ * already queued on `stream`, and the call returns when all is done.  Each
  * problem runs the same algorithm as chfsi_solve with the same arguments;
  * only the summation order of the filter products may differ (the grouped
  * launch does not split K).
@@ -400,6 +404,25 @@ int chfsi_mlp_adam(float* params, const float* grad, float* m, float* v, float l
                    void* stream);
 int chfsi_mlp_train(int n, const float* X, const float* T, float* params, int steps, float lr,
                     void* work, size_t work_bytes, void* stream, float* loss_out);
+
+/* Filter tile autotuner.  The Chebyshev-step kernel exists in two variants:
+ * 0 stages K 8 deep through LDS with four workgroups per CU, 1 stages it 16
+ * deep with two per CU.  chfsi_autotune_filter times both on each given
+ * launch shape (an n x n Hermitian-sized operand times an n x N block, the
+ * width N of a filter window; synthetic data in `work`), records the faster
+ * one per device, and every later filter step (single or batched) takes
+ * the choice of the nearest recorded shape (log distance in n and N; with
+ * none recorded, variant 0).
+ *   variant  HOST, count ints out.   tflops  HOST, 2 * count doubles out
+ *   (variant 0 and 1 per shape) or NULL.
+ *   work     device, >= chfsi_autotune_workspace_bytes(max n, max N).
+ * chfsi_autotune_set records a choice directly; chfsi_autotune_reset
+ * clears the current device's table. */
+size_t chfsi_autotune_workspace_bytes(int n_max, int N_max);
+int chfsi_autotune_filter(int count, const int* n, const int* N, void* work, size_t work_bytes,
+                          void* stream, int* variant, double* tflops);
+int chfsi_autotune_set(int n, int N, int variant);
+int chfsi_autotune_reset(void);
 
 /* General complex GEMM on the library's MFMA kernels:
  * C <- alpha op(A) op(B) + beta C with op in {'N', 'C'} (no-op or conjugate

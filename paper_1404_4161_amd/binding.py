@@ -102,6 +102,11 @@ _SIGS = {
     "chfsi_mlp_adam": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_int, c_void_p]),
     "chfsi_mlp_train": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_int, c_float, c_void_p,
                                 c_size_t, c_void_p, POINTER(c_float)]),
+    "chfsi_autotune_workspace_bytes": (c_size_t, [c_int, c_int]),
+    "chfsi_autotune_filter": (c_int, [c_int, POINTER(c_int), POINTER(c_int), c_void_p, c_size_t,
+                                      c_void_p, POINTER(c_int), POINTER(c_double)]),
+    "chfsi_autotune_set": (c_int, [c_int, c_int, c_int]),
+    "chfsi_autotune_reset": (c_int, []),
     "chfsi_zgemm": (c_int, [c_char, c_char, c_int, c_int, c_int, POINTER(c_double), c_void_p,
                             c_int, c_void_p, c_int, POINTER(c_double), c_void_p, c_int, c_void_p,
                             c_size_t, c_void_p]),
@@ -517,3 +522,26 @@ def chfsi_solve_batch(As, Bs, nevs, nexs, tol, X0s=None, opts=None, Lambda0s=Non
         raise ChfsiError(st, "chfsi_solve_batch")
     return (st, [np.array(l[:]) for l in lam], Xs, [i.as_dict() for i in infos],
             [int(v) for v in sts])
+
+
+def chfsi_autotune_filter(ns, Ns, device="cuda", stream=None):
+    """Time both filter-step variants on each (n, N) launch shape and record
+    the faster; returns (variants, tflops (count x 2)) numpy arrays."""
+    torch = _torch()
+    count = len(ns)
+    dev = torch.device(device)
+    wb = int(lib().chfsi_autotune_workspace_bytes(max(ns), max(Ns)))
+    w = _work(wb, dev)
+    v = (c_int * count)()
+    tf = (c_double * (2 * count))()
+    _check(lib().chfsi_autotune_filter(count, (c_int * count)(*ns), (c_int * count)(*Ns), _ptr(w),
+                                       wb, _stream(stream, dev), v, tf), "chfsi_autotune_filter")
+    return np.array(v[:]), np.array(tf[:]).reshape(count, 2)
+
+
+def chfsi_autotune_set(n, N, variant):
+    _check(lib().chfsi_autotune_set(int(n), int(N), int(variant)), "chfsi_autotune_set")
+
+
+def chfsi_autotune_reset():
+    _check(lib().chfsi_autotune_reset(), "chfsi_autotune_reset")

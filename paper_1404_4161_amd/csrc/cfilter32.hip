@@ -20,6 +20,8 @@
 // the FP64 kernel, with K staged 16 deep (the LDS tile has the same size).
 #include "internal.h"
 
+#include <atomic>
+
 #include <algorithm>
 
 namespace chfsi {
@@ -234,7 +236,7 @@ __global__ void to_fp32(long count, const zc* src, cf* dst) {
 }
 
 int device_slots32() {
-  static int cache[64] = {0};
+  static std::atomic<int> cache[64] = {};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
   if (cache[dev] == 0) {

@@ -15,6 +15,7 @@
 #include <limits>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -140,6 +141,9 @@ void carve_step(Carver& c, StepBufs& b, int n, int k, int nev, int lanczos_steps
 
 std::mutex g_handle_mu;
 rocblas_handle g_handles[64] = {};
+// Set by the worker threads of a batched solve: each worker owns a handle,
+// so their reduced eigensolves run concurrently on their own streams.
+thread_local rocblas_handle tl_handle = nullptr;
 
 int get_handle(rocblas_handle* h) {
   int dev = 0;
@@ -390,9 +394,12 @@ int rayleigh_ritz_dev(hipStream_t s, int n, int k, const zc* H, long ldh, const 
            b.scratch_elems));
   CK(herm_from_lower(s, k, b.G, k));
   {
-    std::lock_guard<std::mutex> lk(g_handle_mu);
-    rocblas_handle h;
-    CKS(get_handle(&h));
+    std::unique_lock<std::mutex> lk(g_handle_mu, std::defer_lock);
+    rocblas_handle h = tl_handle;
+    if (!h) {
+      lk.lock();
+      CKS(get_handle(&h));
+    }
     if (rocblas_set_stream(h, s) != rocblas_status_success) return CHFSI_DEVICE_ERROR;
     if (rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_lower, k,
                          (rocblas_double_complex*)b.G, k, b.mu, b.E, b.info) !=
@@ -1418,6 +1425,11 @@ int filter_group(hipStream_t s, const std::vector<Solve*>& jobs, GemmArgs* dlist
   CK(hipMemcpyAsync(dslots, slot_begin.data(), sizeof(int) * slot_begin.size(),
                     hipMemcpyHostToDevice, s));
   CK(hipStreamSynchronize(s));
+  // one tile variant per grouped launch: the tuned choice carrying the most
+  // flops among the problems
+  double w[2] = {0.0, 0.0};
+  for (int q = 0; q < count; ++q) w[filter_variant(jobs[q]->n, jobs[q]->ka)] += fl[q];
+  const int variant = w[1] > w[0] ? 1 : 0;
   CK(hipEventRecord(e0, s));
   if (graph) {
     hipGraph_t g = nullptr;
@@ -1426,7 +1438,7 @@ int filter_group(hipStream_t s, const std::vector<Solve*>& jobs, GemmArgs* dlist
     int err = 0;
     for (int i = 0; i < steps && !err; ++i)
       err = cheb_step_group(s, dlist + step_entry[i], dslots + step_slot[i], step_count[i],
-                            step_total[i]);
+                            step_total[i], variant);
     const int cap_err = (int)hipStreamEndCapture(s, &g);
     if (err || cap_err) {
       if (g) hipGraphDestroy(g);
@@ -1441,7 +1453,7 @@ int filter_group(hipStream_t s, const std::vector<Solve*>& jobs, GemmArgs* dlist
   } else {
     for (int i = 0; i < steps; ++i)
       CK(cheb_step_group(s, dlist + step_entry[i], dslots + step_slot[i], step_count[i],
-                         step_total[i]));
+                         step_total[i], variant));
   }
   CK(hipEventRecord(e1, s));
   CK(hipEventSynchronize(e1));
@@ -1472,10 +1484,17 @@ size_t batch_bytes(int count, const chfsi_opts& o) {
   return c.off + ALIGN;
 }
 
-// Solves in lockstep: every loop runs begin_loop on all unfinished solves,
-// their FP64 filters together (filter_group), their FP32 defect filters one
-// after the other, then end_loop on all.  status[q] receives each solve's
-// result.
+// Solves in lockstep.  Every problem runs on one of up to 8 worker streams,
+// driven by a host thread of its own (with its own rocSOLVER handle), so
+// the per-problem phases -- reduction, Lanczos, QR, Rayleigh-Ritz with its
+// latency-bound reduced eigensolve, locking -- of different problems
+// overlap on the GPU.  Every loop: begin_loop on all unfinished problems
+// (FP32 defect filters run right there, on the problem's stream); the FP64
+// filters of all problems in grouped launches on the caller's stream, after
+// the worker streams' work (events); then end_loop on all.  status[q]
+// receives each problem's result.
+constexpr int BATCH_WORKERS = 8;
+
 int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void* bwork,
                      size_t bbytes, bool graph, std::vector<int>& status) {
   const int count = (int)S.size();
@@ -1485,52 +1504,113 @@ int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void
   Carver cv(bwork);
   GemmArgs* dlist = cv.take<GemmArgs>(cap_entries);
   int* dslots = cv.take<int>(cap_slots);
-  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int dev = 0;
+  CK(hipGetDevice(&dev));
+  const int T = std::min(count, BATCH_WORKERS);
+
+  // resources of the call, released on every path
+  struct Res {
+    std::vector<hipStream_t> st;
+    std::vector<rocblas_handle> h;
+    std::vector<hipEvent_t> ev;
+    ~Res() {
+      for (auto x : st) if (x) { hipStreamSynchronize(x); hipStreamDestroy(x); }
+      for (auto x : h) if (x) rocblas_destroy_handle(x);
+      for (auto x : ev) if (x) hipEventDestroy(x);
+    }
+  } r;
+  r.st.assign(T, nullptr);
+  r.h.assign(T, nullptr);
+  r.ev.assign(T + 3, nullptr);
+  for (int t = 0; t < T; ++t) {
+    CK(hipStreamCreateWithFlags(&r.st[t], hipStreamNonBlocking));
+    if (rocblas_create_handle(&r.h[t]) != rocblas_status_success) return CHFSI_DEVICE_ERROR;
+  }
+  for (auto& e : r.ev) CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  hipEvent_t ev_main = r.ev[T], e0 = nullptr, e1 = nullptr;
   CK(hipEventCreate(&e0));
   CK(hipEventCreate(&e1));
-  struct EvGuard {
-    hipEvent_t a, b;
-    ~EvGuard() {
-      hipEventDestroy(a);
-      hipEventDestroy(b);
-    }
-  } evg{e0, e1};
+  r.ev[T + 1] = e0;
+  r.ev[T + 2] = e1;
+  // inputs written on the caller's stream are visible to the workers
+  CK(hipEventRecord(ev_main, s));
+  for (int t = 0; t < T; ++t) CK(hipStreamWaitEvent(r.st[t], ev_main, 0));
+  for (int q = 0; q < count; ++q) S[q]->s = r.st[q % T];
+
   status.assign(count, CHFSI_OK);
-  std::vector<char> failed(count, 0);
-  for (int q = 0; q < count; ++q) {
+  std::vector<char> failed(count, 0), active(count, 0);
+  // run fn(q) for every selected problem, problems q = t mod T on worker t
+  auto parallel = [&](auto fn) {
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; ++t) {
+      th.emplace_back([&, t]() {
+        hipSetDevice(dev);
+        tl_handle = r.h[t];
+        for (int q = t; q < count; q += T) {
+          try {
+            fn(q);
+          } catch (const std::bad_alloc&) {
+            status[q] = CHFSI_ALLOC_ERROR;
+            failed[q] = 1;
+          } catch (...) {
+            status[q] = CHFSI_DEVICE_ERROR;
+            failed[q] = 1;
+          }
+        }
+        tl_handle = nullptr;
+      });
+    }
+    for (auto& x : th) x.join();
+  };
+
+  parallel([&](int q) {
     status[q] = S[q]->setup();
     if (status[q] != CHFSI_OK) failed[q] = 1;
-  }
+  });
   for (;;) {
-    std::vector<Solve*> active, fp64;
-    for (int q = 0; q < count; ++q) {
-      if (failed[q] || S[q]->done) continue;
+    parallel([&](int q) {
+      active[q] = 0;
+      if (failed[q] || S[q]->done) return;
       status[q] = S[q]->begin_loop();
+      if (status[q] == CHFSI_OK && !S[q]->done && S[q]->use32) status[q] = S[q]->filter_own();
       if (status[q] != CHFSI_OK) {
         failed[q] = 1;
-        continue;
+        return;
       }
-      if (!S[q]->done) active.push_back(S[q].get());
-    }
-    if (active.empty()) break;
-    for (Solve* a : active) {
-      if (a->use32) {
-        const int st = a->filter_own();
-        if (st != CHFSI_OK) return st;
-      } else if (a->ka > 0) {
-        fp64.push_back(a);
-      }
-    }
-    if (!fp64.empty()) CKS(filter_group(s, fp64, dlist, dslots, cap_entries, cap_slots, graph, e0, e1));
+      if (!S[q]->done) active[q] = 1;
+    });
+    std::vector<Solve*> fp64;
+    bool any = false;
     for (int q = 0; q < count; ++q) {
-      Solve* a = S[q].get();
-      if (failed[q] || std::find(active.begin(), active.end(), a) == active.end()) continue;
-      status[q] = a->end_loop();
-      if (status[q] != CHFSI_OK) failed[q] = 1;
+      if (!active[q]) continue;
+      any = true;
+      if (!S[q]->use32 && S[q]->ka > 0) fp64.push_back(S[q].get());
     }
+    if (!any) break;
+    if (!fp64.empty()) {
+      for (int t = 0; t < T; ++t) {
+        CK(hipEventRecord(r.ev[t], r.st[t]));
+        CK(hipStreamWaitEvent(s, r.ev[t], 0));
+      }
+      CKS(filter_group(s, fp64, dlist, dslots, cap_entries, cap_slots, graph, e0, e1));
+      CK(hipEventRecord(ev_main, s));
+      for (int t = 0; t < T; ++t) CK(hipStreamWaitEvent(r.st[t], ev_main, 0));
+    }
+    parallel([&](int q) {
+      if (!active[q]) return;
+      status[q] = S[q]->end_loop();
+      if (status[q] != CHFSI_OK) failed[q] = 1;
+    });
   }
-  for (int q = 0; q < count; ++q)
+  parallel([&](int q) {
     if (!failed[q]) status[q] = S[q]->finish();
+  });
+  // outputs complete on the workers before the caller's stream goes on
+  for (int t = 0; t < T; ++t) {
+    CK(hipEventRecord(r.ev[t], r.st[t]));
+    CK(hipStreamWaitEvent(s, r.ev[t], 0));
+  }
+  CK(hipStreamSynchronize(s));
   return CHFSI_OK;
 }
 
@@ -2024,6 +2104,60 @@ int chfsi_mlp_train(int n, const float* X, const float* T, float* params, int st
   } catch (...) {
     return CHFSI_DEVICE_ERROR;
   }
+}
+
+size_t chfsi_autotune_workspace_bytes(int n_max, int N_max) {
+  if (n_max < 1 || N_max < 1) return 0;
+  Carver c(nullptr);
+  c.take<zc>((size_t)n_max * n_max);
+  c.take<zc>((size_t)n_max * N_max);
+  c.take<zc>((size_t)n_max * N_max);
+  return c.off + ALIGN;
+}
+
+int chfsi_autotune_filter(int count, const int* n, const int* N, void* work, size_t work_bytes,
+                          void* stream, int* variant, double* tflops) {
+  try {
+    if (count < 0 || (count > 0 && (!n || !N || !variant)) || check_ptr(work)) return CHFSI_INVALID_ARG;
+    int nmax = 1, Nmax = 1;
+    for (int i = 0; i < count; ++i) {
+      if (n[i] < 1 || N[i] < 1 || N[i] > n[i]) return CHFSI_INVALID_ARG;
+      nmax = std::max(nmax, n[i]);
+      Nmax = std::max(Nmax, N[i]);
+    }
+    if (work_bytes < chfsi_autotune_workspace_bytes(nmax, Nmax)) return CHFSI_INVALID_ARG;
+    hipStream_t s = as_stream(stream);
+    Carver cv(work);
+    zc* H = cv.take<zc>((size_t)nmax * nmax);
+    zc* Y0 = cv.take<zc>((size_t)nmax * Nmax);
+    zc* Y1 = cv.take<zc>((size_t)nmax * Nmax);
+    CK(fill_counter_random(s, nmax, nmax, H, nmax, 1, 1));
+    for (int i = 0; i < count; ++i) {
+      CK(fill_counter_random(s, n[i], N[i], Y0, n[i], 2, 1));
+      CK(fill_counter_random(s, n[i], N[i], Y1, n[i], 3, 1));
+      double tf[2] = {0.0, 0.0};
+      CK(tune_filter_shape(s, n[i], N[i], H, Y0, Y1, &variant[i], tf));
+      if (tflops) {
+        tflops[2 * i] = tf[0];
+        tflops[2 * i + 1] = tf[1];
+      }
+    }
+    CK(hipStreamSynchronize(s));
+    return CHFSI_OK;
+  } catch (...) {
+    return CHFSI_DEVICE_ERROR;
+  }
+}
+
+int chfsi_autotune_set(int n, int N, int variant) {
+  if (n < 1 || N < 1 || variant < 0 || variant > 1) return CHFSI_INVALID_ARG;
+  tune_set(n, N, variant);
+  return CHFSI_OK;
+}
+
+int chfsi_autotune_reset(void) {
+  tune_reset();
+  return CHFSI_OK;
 }
 
 int chfsi_zgemm(char opa, char opb, int M, int N, int K, const double* alpha, const void* A,

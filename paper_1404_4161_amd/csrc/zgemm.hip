@@ -22,7 +22,12 @@
 // strip in that XCD's L2.
 #include "internal.h"
 
+#include <atomic>
+
 #include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <vector>
 
 namespace chfsi {
 
@@ -42,55 +47,56 @@ __device__ __forceinline__ zc cmul(zc a, zc b) {
   return zc{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
-// Global -> registers for one BK x BM stage of op(A).
-template <int OPA>
-__device__ __forceinline__ void load_a(const GemmArgs& g, int m0, int k0, int kend, zc r[2]) {
+// Global -> registers for one KB x BM stage of op(A) (KB / 4 elements per
+// thread).
+template <int OPA, int KB>
+__device__ __forceinline__ void load_a(const GemmArgs& g, int m0, int k0, int kend, zc r[KB / 4]) {
   const int t = threadIdx.x;
   if (OPA == OP_N) {            // (m, k) = A[m + k lda], m contiguous
     const int m = m0 + (t & 63);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < KB / 4; ++i) {
       const int k = k0 + (t >> 6) + 4 * i;
       r[i] = (m < g.M && k < kend) ? g.A[m + (long)k * g.lda] : zc{0.0, 0.0};
     }
   } else {                      // (m, k) = conj(A[k + m lda]), k contiguous
-    const int k = k0 + (t & 7);
+    const int k = k0 + (t & (KB - 1));
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int m = m0 + (t >> 3) + 32 * i;
+    for (int i = 0; i < KB / 4; ++i) {
+      const int m = m0 + t / KB + (NT / KB) * i;
       zc v = (m < g.M && k < kend) ? g.A[k + (long)m * g.lda] : zc{0.0, 0.0};
       r[i] = zc{v.x, -v.y};
     }
   }
 }
 
-template <int OPA>
-__device__ __forceinline__ void store_a(zc (*As)[PA], const zc r[2]) {
+template <int OPA, int KB>
+__device__ __forceinline__ void store_a(zc (*As)[PA], const zc r[KB / 4]) {
   const int t = threadIdx.x;
   if (OPA == OP_N) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) As[(t >> 6) + 4 * i][t & 63] = r[i];
+    for (int i = 0; i < KB / 4; ++i) As[(t >> 6) + 4 * i][t & 63] = r[i];
   } else {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) As[t & 7][(t >> 3) + 32 * i] = r[i];
+    for (int i = 0; i < KB / 4; ++i) As[t & (KB - 1)][t / KB + (NT / KB) * i] = r[i];
   }
 }
 
-// Global -> registers for one BK x BN stage of op(B).
-template <int OPB>
-__device__ __forceinline__ void load_b(const GemmArgs& g, int n0, int k0, int kend, zc r[2]) {
+// Global -> registers for one KB x BN stage of op(B).
+template <int OPB, int KB>
+__device__ __forceinline__ void load_b(const GemmArgs& g, int n0, int k0, int kend, zc r[KB / 4]) {
   const int t = threadIdx.x;
   if (OPB == OP_N) {            // (k, n) = B[k + n ldb], k contiguous
-    const int k = k0 + (t & 7);
+    const int k = k0 + (t & (KB - 1));
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int n = n0 + (t >> 3) + 32 * i;
+    for (int i = 0; i < KB / 4; ++i) {
+      const int n = n0 + t / KB + (NT / KB) * i;
       r[i] = (n < g.N && k < kend) ? g.B[k + (long)n * g.ldb] : zc{0.0, 0.0};
     }
   } else {                      // (k, n) = conj(B[n + k ldb]), n contiguous
     const int n = n0 + (t & 63);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < KB / 4; ++i) {
       const int k = k0 + (t >> 6) + 4 * i;
       zc v = (n < g.N && k < kend) ? g.B[n + (long)k * g.ldb] : zc{0.0, 0.0};
       r[i] = zc{v.x, -v.y};
@@ -98,15 +104,15 @@ __device__ __forceinline__ void load_b(const GemmArgs& g, int n0, int k0, int ke
   }
 }
 
-template <int OPB>
-__device__ __forceinline__ void store_b(zc (*Bs)[PB], const zc r[2]) {
+template <int OPB, int KB>
+__device__ __forceinline__ void store_b(zc (*Bs)[PB], const zc r[KB / 4]) {
   const int t = threadIdx.x;
   if (OPB == OP_N) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) Bs[t & 7][(t >> 3) + 32 * i] = r[i];
+    for (int i = 0; i < KB / 4; ++i) Bs[t & (KB - 1)][t / KB + (NT / KB) * i] = r[i];
   } else {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) Bs[(t >> 6) + 4 * i][t & 63] = r[i];
+    for (int i = 0; i < KB / 4; ++i) Bs[(t >> 6) + 4 * i][t & 63] = r[i];
   }
 }
 
@@ -120,10 +126,10 @@ __device__ __forceinline__ void lower_tile(int t, int& tm, int& tn) {
 }
 
 // One 64x64 output tile (tile row tm, tile column tn, K chunk `split`) of
-// the launch described by g, with its epilogue.
-template <int OPA, int OPB, int EPI>
+// the launch described by g, with its epilogue; K staged KB deep in LDS.
+template <int OPA, int OPB, int EPI, int KB>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, int tn,
-                                          zc (*As)[BK][PA], zc (*Bs)[BK][PB]);
+                                          zc (*As)[KB][PA], zc (*Bs)[KB][PB]);
 
 // Virtual-row scheduling of a rectangular tile set (see zgemm_kernel):
 // returns false when workgroup `local` has no tile.
@@ -141,12 +147,13 @@ __device__ __forceinline__ bool rect_tile(const GemmArgs& g, int local, int& spl
   return true;
 }
 
-// Four resident workgroups per CU (16 waves): the kernel fits in 128
-// registers per lane without spills, with accumulators in VGPRs.
-template <int OPA, int OPB, int EPI>
-__global__ void __launch_bounds__(NT, 4) zgemm_kernel(GemmArgs g) {
-  __shared__ zc As[2][BK][PA];
-  __shared__ zc Bs[2][BK][PB];
+// KB = 8: four resident workgroups per CU (16 waves); the kernel fits in
+// 128 registers per lane without spills, with accumulators in VGPRs.
+// KB = 16 (twice the LDS per workgroup): two per CU.
+template <int OPA, int OPB, int EPI, int KB>
+__global__ void __launch_bounds__(NT, KB == 8 ? 4 : 2) zgemm_kernel(GemmArgs g) {
+  __shared__ zc As[2][KB][PA];
+  __shared__ zc Bs[2][KB][PB];
 
   // Tile scheduling.  Workgroups are dispatched round-robin over the XCDs
   // (hardware id w runs on XCD w % 8).  For rectangular tile sets XCD x owns
@@ -163,18 +170,19 @@ __global__ void __launch_bounds__(NT, 4) zgemm_kernel(GemmArgs g) {
   } else {
     if (!rect_tile(g, blockIdx.x, split, tm, tn)) return;
   }
-  gemm_tile<OPA, OPB, EPI>(g, split, tm, tn, As, Bs);
+  gemm_tile<OPA, OPB, EPI, KB>(g, split, tm, tn, As, Bs);
 }
 
 // Several independent Chebyshev steps (one per problem of a batch) in one
 // launch: problem p owns workgroups [slot_begin[p], slot_begin[p + 1]), a
 // multiple of the XCD count, scheduled inside its range exactly as a launch
 // of its own.
-__global__ void __launch_bounds__(NT, 4) zgemm_group_cheb(const GemmArgs* __restrict__ list,
-                                                           const int* __restrict__ slot_begin,
-                                                           int count) {
-  __shared__ zc As[2][BK][PA];
-  __shared__ zc Bs[2][BK][PB];
+template <int KB>
+__global__ void __launch_bounds__(NT, KB == 8 ? 4 : 2)
+    zgemm_group_cheb(const GemmArgs* __restrict__ list, const int* __restrict__ slot_begin,
+                     int count) {
+  __shared__ zc As[2][KB][PA];
+  __shared__ zc Bs[2][KB][PB];
   const int b = blockIdx.x;
   int lo = 0, hi = count;
   while (hi - lo > 1) {
@@ -185,12 +193,12 @@ __global__ void __launch_bounds__(NT, 4) zgemm_group_cheb(const GemmArgs* __rest
   const GemmArgs g = list[lo];
   int split, tm, tn;
   if (!rect_tile(g, b - slot_begin[lo], split, tm, tn)) return;
-  gemm_tile<OP_N, OP_N, EPI_CHEB>(g, split, tm, tn, As, Bs);
+  gemm_tile<OP_N, OP_N, EPI_CHEB, KB>(g, split, tm, tn, As, Bs);
 }
 
-template <int OPA, int OPB, int EPI>
+template <int OPA, int OPB, int EPI, int KB>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, int tn,
-                                          zc (*As)[BK][PA], zc (*Bs)[BK][PB]) {
+                                          zc (*As)[KB][PA], zc (*Bs)[KB][PB]) {
   const int m0 = tm * BM, n0 = tn * BN;
   int kbeg = split * g.kchunk;
   int kend = min(g.K, kbeg + g.kchunk);
@@ -212,13 +220,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, 
       accI[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     }
 
-  const int nk = (kend - kbeg + BK - 1) / BK;
-  zc ra[2], rb[2];
+  const int nk = (kend - kbeg + KB - 1) / KB;
+  zc ra[KB / 4], rb[KB / 4];
   if (nk > 0) {
-    load_a<OPA>(g, m0, kbeg, kend, ra);
-    load_b<OPB>(g, n0, kbeg, kend, rb);
-    store_a<OPA>(As[0], ra);
-    store_b<OPB>(Bs[0], rb);
+    load_a<OPA, KB>(g, m0, kbeg, kend, ra);
+    load_b<OPB, KB>(g, n0, kbeg, kend, rb);
+    store_a<OPA, KB>(As[0], ra);
+    store_b<OPB, KB>(Bs[0], rb);
   }
   __syncthreads();
 
@@ -226,12 +234,12 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, 
     const int cur = kt & 1;
     const bool more = kt + 1 < nk;
     if (more) {
-      const int k0 = kbeg + (kt + 1) * BK;
-      load_a<OPA>(g, m0, k0, kend, ra);
-      load_b<OPB>(g, n0, k0, kend, rb);
+      const int k0 = kbeg + (kt + 1) * KB;
+      load_a<OPA, KB>(g, m0, k0, kend, ra);
+      load_b<OPB, KB>(g, n0, k0, kend, rb);
     }
 #pragma unroll
-    for (int kk = 0; kk < BK / 4; ++kk) {
+    for (int kk = 0; kk < KB / 4; ++kk) {
       zc a[2], b[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) a[i] = As[cur][kk * 4 + lk][wm * 32 + i * 16 + lr];
@@ -255,8 +263,8 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, 
         for (int j = 0; j < 2; ++j) accI[i][j] = mfma(a[i].y, b[j].x, accI[i][j]);
     }
     if (more) {
-      store_a<OPA>(As[cur ^ 1], ra);
-      store_b<OPB>(Bs[cur ^ 1], rb);
+      store_a<OPA, KB>(As[cur ^ 1], ra);
+      store_b<OPB, KB>(Bs[cur ^ 1], rb);
     }
     __syncthreads();
   }
@@ -346,7 +354,7 @@ __global__ void cheb_reduce(int M, int N, int splits, const zc* part, const zc* 
 
 // Resident workgroup slots of the device (CUs x 4), cached per device.
 int device_slots() {
-  static int cache[64] = {0};
+  static std::atomic<int> cache[64] = {};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
   if (cache[dev] == 0) {
@@ -405,7 +413,7 @@ Plan make_plan(int M, int N, int K, bool lower_only, bool allow_split) {
   return p;
 }
 
-template <int OPA, int OPB, int EPI>
+template <int OPA, int OPB, int EPI, int KB = BK>
 int launch(hipStream_t s, GemmArgs& g) {
   int grid;
   if (g.lower_only) {
@@ -417,7 +425,7 @@ int launch(hipStream_t s, GemmArgs& g) {
   // rows whose K range is longest first (triangular A with the long rows at
   // the bottom), so the tail of the launch is made of short tiles
   g.rows_desc = (g.ktri == KTRI_A_LOWER) ? 1 : 0;
-  hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, EPI>), dim3(grid), dim3(NT), 0, s, g);
+  hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, EPI, KB>), dim3(grid), dim3(NT), 0, s, g);
   return (int)hipGetLastError();
 }
 
@@ -429,7 +437,102 @@ int dispatch(hipStream_t s, Op opa, Op opb, GemmArgs& g) {
   return launch<OP_C, OP_C, EPI>(s, g);
 }
 
+// Filter tile autotuner: measured (n, N) launch shapes and the faster
+// K-stage depth for each, per device.  A launch takes the choice of the
+// nearest measured shape (log distance); with no measurement, KB = 8.
+struct TuneEntry {
+  int n, N, variant;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune[64];
+
+int current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return -1;
+  return dev;
+}
+
+template <int EPI>
+int launch_cheb_variant(hipStream_t s, GemmArgs& g, int variant) {
+  if (variant == 1) return launch<OP_N, OP_N, EPI, 16>(s, g);
+  return launch<OP_N, OP_N, EPI, 8>(s, g);
+}
+
 }  // namespace
+
+int filter_variant(int n, int N) {
+  const int dev = current_device();
+  if (dev < 0) return 0;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const auto& t = g_tune[dev];
+  int best = 0;
+  double bd = 1e300;
+  for (const auto& e : t) {
+    const double a = std::log((double)n / e.n), b = std::log((double)N / e.N);
+    const double d = a * a + b * b;
+    if (d < bd) {
+      bd = d;
+      best = e.variant;
+    }
+  }
+  return best;
+}
+
+void tune_set(int n, int N, int variant) {
+  const int dev = current_device();
+  if (dev < 0) return;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto& t = g_tune[dev];
+  for (auto& e : t)
+    if (e.n == n && e.N == N) {
+      e.variant = variant;
+      return;
+    }
+  t.push_back({n, N, variant});
+}
+
+void tune_reset() {
+  const int dev = current_device();
+  if (dev < 0) return;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[dev].clear();
+}
+
+int tune_filter_shape(hipStream_t s, int n, int N, const zc* H, zc* Y0, zc* Y1, int* variant,
+                      double tf[2]) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess) return (int)hipErrorUnknown;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return (int)hipErrorUnknown;
+  }
+  int err = 0;
+  const int reps = 3;
+  for (int v = 0; v < 2 && !err; ++v) {
+    Plan p = make_plan(n, N, n, false, false);
+    GemmArgs g = {};
+    g.M = n; g.N = N; g.K = n;
+    g.A = H; g.lda = n; g.B = Y0; g.ldb = n; g.C = Y1; g.ldc = n;
+    g.Ycur = Y0; g.ldyc = n; g.Yold = Y1; g.ldyo = n;
+    g.shift = 0.25; g.sa = 1e-3; g.sb = 0.5;
+    g.tiles_m = p.tiles_m; g.tiles_n = p.tiles_n; g.total_tiles = p.total;
+    g.splits = 1; g.kchunk = p.kchunk;
+    err = launch_cheb_variant<EPI_CHEB>(s, g, v);             // warm-up
+    if (!err) err = (int)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && !err; ++r) err = launch_cheb_variant<EPI_CHEB>(s, g, v);
+    if (!err) err = (int)hipEventRecord(e1, s);
+    if (!err) err = (int)hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (!err) err = (int)hipEventElapsedTime(&ms, e0, e1);
+    tf[v] = err ? 0.0 : 8.0 * (double)n * n * N * reps / (1e-3 * ms) / 1e12;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (err) return err;
+  *variant = tf[1] > tf[0] ? 1 : 0;
+  tune_set(n, N, *variant);
+  return 0;
+}
 
 size_t zgemm_work_elems(int M, int N, int K) {
   Plan p = make_plan(M, N, K, false, true);
@@ -486,9 +589,14 @@ GemmArgs cheb_group_args(int n, int N, const zc* H, long ldh, const zc* Ycur, lo
 }
 
 int cheb_step_group(hipStream_t s, const GemmArgs* list, const int* slot_begin, int count,
-                    int total_slots) {
+                    int total_slots, int variant) {
   if (count <= 0 || total_slots <= 0) return 0;
-  hipLaunchKernelGGL(zgemm_group_cheb, dim3(total_slots), dim3(NT), 0, s, list, slot_begin, count);
+  if (variant == 1)
+    hipLaunchKernelGGL(zgemm_group_cheb<16>, dim3(total_slots), dim3(NT), 0, s, list, slot_begin,
+                       count);
+  else
+    hipLaunchKernelGGL(zgemm_group_cheb<8>, dim3(total_slots), dim3(NT), 0, s, list, slot_begin,
+                       count);
   return (int)hipGetLastError();
 }
 
@@ -511,7 +619,7 @@ int cheb_step(hipStream_t s, int n, int N, const zc* H, long ldh, const zc* Ycur
   if (splits == 1) {
     g.splits = 1;
     g.kchunk = p.kchunk;
-    return launch<OP_N, OP_N, EPI_CHEB>(s, g);
+    return launch_cheb_variant<EPI_CHEB>(s, g, filter_variant(n, N));
   }
   int chunk = (n + splits - 1) / splits;
   chunk = ((chunk + BK - 1) / BK) * BK;

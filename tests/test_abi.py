@@ -151,3 +151,21 @@ def test_degree_features_match_oracle():
         n_ok += 1
         assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(ref).max()), (mu, res, gap)
     assert n_ok > 100
+
+
+def test_autotuner_and_batch_argument_checks():
+    lib = ch.lib()
+    assert lib.chfsi_autotune_set(0, 5, 0) == ch.binding.CHFSI_INVALID_ARG
+    assert lib.chfsi_autotune_set(10, 5, 2) == ch.binding.CHFSI_INVALID_ARG
+    assert lib.chfsi_autotune_workspace_bytes(100, 10) >= 16 * (100 * 100 + 2 * 100 * 10)
+    n = (ctypes.c_int * 1)(10)
+    N = (ctypes.c_int * 1)(20)                       # N > n
+    v = (ctypes.c_int * 1)()
+    assert lib.chfsi_autotune_filter(1, n, N, ctypes.c_void_p(256), 1 << 30, None, v, None) == \
+        ch.binding.CHFSI_INVALID_ARG
+    assert ch.chfsi_batch_workspace_bytes(0) == 0
+    assert ch.chfsi_batch_workspace_bytes(4) > 0
+    st = (ctypes.c_int * 1)()
+    assert lib.chfsi_solve_batch(0, None, None, None, None, None, None, None, 1e-10, None, None,
+                                 None, None, None, None, None, None, None, 0, None, 0, None, None,
+                                 st) == ch.binding.CHFSI_INVALID_ARG

@@ -130,3 +130,24 @@ def test_batch_rejects_bad_arguments():
     with pytest.raises(ch.ChfsiError):             # graph capture on the null stream
         ch.chfsi_solve_batch(As, Bs, nevs, nexs, 1e-10, graph=True,
                              stream=torch.cuda.default_stream())
+
+
+def test_batch_with_the_second_tile_variant():
+    """The grouped launch with the 16-deep K stage (forced through the
+    autotuner's table) gives the same eigenvalues as the default."""
+    seqs, probs = _batch(length=1, cfg0=780)
+    nevs = [p[1] for p in SIZES]
+    nexs = [p[2] for p in SIZES]
+    As = [dev(p[0]) for p in probs]
+    Bs = [dev(s.B) if s.B is not None else None for s in seqs]
+    r0 = ch.chfsi_solve_batch(As, Bs, nevs, nexs, 1e-10)
+    try:
+        for (n, nev, nex, g) in SIZES:
+            ch.chfsi_autotune_set(n, nev + nex, 1)
+        r1 = ch.chfsi_solve_batch(As, Bs, nevs, nexs, 1e-10)
+    finally:
+        ch.chfsi_autotune_reset()
+    for q, (n, nev, nex, g) in enumerate(SIZES):
+        ref = _ref(probs[q][0], seqs[q].B, nev)
+        assert np.abs(r1[1][q][:nev] - ref).max() <= RTOL * np.abs(ref).min()
+        assert np.abs(r1[1][q][:nev] - r0[1][q][:nev]).max() <= 1e-12 * np.abs(ref).min()

@@ -192,3 +192,32 @@ def test_defect_filter_matches_oracle_with_error_scaling_like_the_residual(delta
     bound = 1e3 * 2.0 ** -24 * (res / norm_h) * growth + 1e-13
     assert np.all(err <= bound), (err / bound).max()
     assert f32 == pytest.approx(8.0 * n * n * sum(m - 1 for m in deg))
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_filter_tile_variants_match_oracle(variant):
+    """Both K-stage variants of the filter step give the oracle's filter
+    (the autotuner only chooses between them)."""
+    n, k = 333, 70
+    lam, h = _herm_problem(n, 31)
+    degrees = np.sort(np.random.default_rng(5).integers(1, 12, k)).tolist()
+    y0 = _rand(n, k, 32)
+    ref = chebyshev.chebyshev_filter(h, y0, degrees, 10.0, 31.0, -21.0)
+    try:
+        ch.chfsi_autotune_set(n, k, variant)
+        yd = dev(y0)
+        ch.chfsi_filter(dev(h), yd, degrees, 10.0, 31.0, -21.0)
+    finally:
+        ch.chfsi_autotune_reset()
+    assert rel_col_err(host(yd), ref).max() < 1e-11
+
+
+def test_autotuner_records_a_choice_per_shape():
+    ch.chfsi_autotune_reset()
+    try:
+        v, tf = ch.chfsi_autotune_filter([700, 1300], [64, 130])
+        assert v.shape == (2,) and set(v.tolist()) <= {0, 1}
+        assert np.all(tf > 0)
+        assert np.array_equal(v, np.argmax(tf, axis=1))
+    finally:
+        ch.chfsi_autotune_reset()

@@ -226,14 +226,24 @@ def small_config(name: str, n: int, nev: int, nex: int, generalized: bool, lengt
 
 
 class Sequence:
-    """Lazily generated sequence A^(1..N) (and the fixed B)."""
+    """Lazily generated sequence A^(1..N) (and the fixed B).
 
-    def __init__(self, conf: SequenceConfig, kind: str = "numpy", device: str = "cuda:0"):
+    draw="host" (default) takes every Gaussian draw from numpy's PCG64 as
+    documented above.  draw="device" (torch backend only) takes the n x n
+    Gaussian draws from torch's generator on the device, seeded with the
+    same 1000 cfg + role: much faster for large batches, but not the numbers
+    the host draws give (the spectrum is still drawn on the host)."""
+
+    def __init__(self, conf: SequenceConfig, kind: str = "numpy", device: str = "cuda:0",
+                 draw: str = "host"):
         self.conf = conf
         self.be = backend(kind, device)
+        if draw not in ("host", "device") or (draw == "device" and kind != "torch"):
+            raise ValueError("draw='device' needs the torch backend")
+        self.draw = draw
         n = conf.n
         self.lam = spectrum(n, rng(conf.cfg, ROLE_SPECTRUM))
-        z = self.be.asarray(complex_gaussian(rng(conf.cfg, ROLE_Q), n, n))
+        z = self._gauss(ROLE_Q, n, n)
         q = self.be.qr_unitary(z)
         del z
         self._a = self.be.from_spectrum(q, self.lam)
@@ -241,17 +251,25 @@ class Sequence:
         self._l = 1
         self.B = None
         if conf.generalized:
-            m = self.be.asarray(complex_gaussian(rng(conf.cfg, ROLE_B), n, n))
+            m = self._gauss(ROLE_B, n, n)
             g = self.be.hpd_unit(m)
             del m
             self.B = self.be.identity_plus(g, conf.b_weight)
+
+    def _gauss(self, role, rows, cols):
+        if self.draw == "host":
+            return self.be.asarray(complex_gaussian(rng(self.conf.cfg, role), rows, cols))
+        torch = self.be.torch
+        g = torch.Generator(device=self.be.device)
+        g.manual_seed(1000 * self.conf.cfg + role)
+        z = torch.randn((cols, rows), dtype=torch.complex128, device=self.be.device, generator=g)
+        return z.transpose(0, 1)   # column-major view, E|z|^2 = 1
 
     def problems(self):
         """Yield (l, A^(l)) for l = 1..N; A^(l) is the backend's array."""
         yield 1, self._a
         for l in range(1, self.conf.length):
-            h = self.be.herm_unit(self.be.asarray(
-                complex_gaussian(rng(self.conf.cfg, ROLE_PERTURB + l), self.conf.n, self.conf.n)))
+            h = self.be.herm_unit(self._gauss(ROLE_PERTURB + l, self.conf.n, self.conf.n))
             self._a = self.be.axpy(self._a, self.conf.delta(l), h)
             del h
             yield l + 1, self._a
@@ -286,3 +304,20 @@ def random_block(n: int, k: int, seed: int) -> np.ndarray:
 def variant(conf: SequenceConfig, cfg: int, name: str = None) -> SequenceConfig:
     """The same recipe under another seed namespace (e.g. training data)."""
     return dataclasses.replace(conf, cfg=cfg, name=name or f"{conf.name}@{cfg}")
+
+
+def kpoint_configs(count: int = 32, nmin: int = 2000, nmax: int = 9000, length: int = 5,
+                   cfg_base: int = 300, seed: int = 3) -> List[SequenceConfig]:
+    """Independent k-point sequences of one self-consistency run: n uniform
+    in [nmin, nmax] (seeded), nev = 5 % and nex = 1 % of n, generalized with
+    its own B, perturbations 1e-2 * 0.5^l (the n = 8000 schedule)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    ns = g.integers(nmin, nmax + 1, size=count)
+    out = []
+    for q, n in enumerate(ns):
+        n = int(n)
+        nev = max(1, int(round(0.05 * n)))
+        nex = max(1, int(round(0.01 * n)))
+        out.append(SequenceConfig(f"kpoint{q}-n{n}", cfg_base + q, n, nev, nex, True, length,
+                                  _decay(1e-2)))
+    return out
