@@ -325,12 +325,13 @@ def main():
         """Warm-up problem(s), then the timed steps; returns per-step infos,
         wall times, eigenvalues and the elapsed time of the timed region."""
         x_prev, lam_prev = None, None
+        rates = np.full(k, np.nan) if opts.degree_mode == 3 else None
 
         def solve(a):
             st, lam, x, info = ch.chfsi_solve(
                 a, B, nev, nex, conf.tol, X0=x_prev, opts=opts, X=X, work=work, stream=stream,
                 Lambda0=None if (args.no_lambda0 or x_prev is None) else lam_prev,
-                mlp=blob if opts.degree_mode == 2 else None)
+                mlp=blob if opts.degree_mode == 2 else None, seq_rates=rates)
             if st != 0:
                 raise RuntimeError(f"chfsi_solve status {st}")
             return lam, info
@@ -366,6 +367,12 @@ def main():
             o = ch.chfsi_default_opts()
             o.precision, o.degree_mode, o.first_rule = prec, 2, fr
             learned_runs[label] = run_sequence(o, label)
+    # Multiple Optimization: degrees calibrated by each eigenvector's speed
+    # measured earlier in the sequence (no training)
+    for label, prec, fr in (("mixed+seqcal", 1, 0), ("fp64+seqcal", 0, 1)):
+        o = ch.chfsi_default_opts()
+        o.precision, o.degree_mode, o.first_rule = prec, 3, fr
+        learned_runs[label] = run_sequence(o, label)
 
     flops = sum(i["filter_flops"] for i in infos)
     fsec = sum(i["filter_seconds"] for i in infos)
@@ -439,7 +446,9 @@ def main():
         out[label] = {
             "precision": "FP32 defect filter where the residuals allow" if label.startswith("mixed")
                          else "FP64 filter",
-            "degrees": "learned (network trained on logs of another sequence; rule fallback)",
+            "degrees": ("learned (network trained on logs of another sequence; rule fallback)"
+                        if "learned" in label else
+                        "sequence-calibrated (speeds measured earlier in the sequence; rule floor)"),
             "first_loop_degrees": ("deg0" if label.startswith("mixed") else
                                    "from the residuals of X0 (one extra product H X0)"),
             "ms_per_step": round(1e3 * lelapsed / args.steps, 3),

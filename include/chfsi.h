@@ -61,6 +61,12 @@ extern "C" {
  *                 (see chfsi_degrees_learned); the analytic degree stays
  *                 the floor of every learned degree and the fallback for
  *                 inputs outside the network's training range.
+ *                 3 = sequence-calibrated (Multiple Optimization): the
+ *                 rule's rate of each vector is divided by its speed
+ *                 measured earlier in the sequence (seq_rates), m_j =
+ *                 max(rule_j, ceil(m_a,j * f / speed_j)) with f = 1.25 in a
+ *                 loop that can finish every wanted vector and 1 otherwise;
+ *                 vectors without a measured speed take the rule.
  *   reuse_b_factor  1 (default): keep the Cholesky factor of B and its
  *                 inverse in the workspace and reuse them on the next call
  *                 with the same workspace when B is bitwise unchanged (a
@@ -93,7 +99,16 @@ extern "C" {
  *                 filtered wanted vector and loop (layout below).  The
  *                 number written is info->log_records.
  *   mlp           HOST, CHFSI_MLP_PARAMS floats: the degree network used by
- *                 degree_mode 2 (required then; read once per call). */
+ *                 degree_mode 2 (required then; read once per call).
+ *   seq_rates     HOST, k doubles in/out, or NULL (required by degree_mode
+ *                 3): per eigenvector (in the order of X0 / Lambda), its
+ *                 convergence speed relative to the analytic model of
+ *                 eq. (resl), ln(Res_before / Res_after) / (m ln|rho|),
+ *                 last measured (NaN when unknown; an FP32 loop counts only
+ *                 where Res_after > 1e3 eps32 Res_before).  On
+ *                 input (with X0) the speeds of the previous problem; on
+ *                 output this problem's, in the order of Lambda.  Passing
+ *                 the array along a sequence carries the calibration. */
 typedef struct chfsi_opts {
   double tol;
   int deg0;
@@ -110,6 +125,7 @@ typedef struct chfsi_opts {
   int log_capacity;
   double* log;
   const float* mlp;
+  double* seq_rates;
 } chfsi_opts;
 
 /* Per-solve statistics (all optional to read).
@@ -245,7 +261,8 @@ int chfsi_solve(int n, int nev, int nex,
  *               pairwise distinct; B's factor is reused per workspace.
  *   batch_work  device, >= chfsi_batch_workspace_bytes(count, opts): the
  *               launch arguments of the grouped filter.
- *   opts        shared by all problems; log_capacity must be 0.
+ *   opts        shared by all problems; log_capacity must be 0 and
+ *               seq_rates NULL (degree_mode 3 is not available here).
  *   flags       bit 0: capture each loop's grouped filter launches as one
  *               HIP graph and launch it (needs a non-NULL stream).
  *   info        NULL or count statistics records.
@@ -382,6 +399,18 @@ int chfsi_degrees_learned(int k, const double* mu, const double* res, int n_want
                           double alpha, double beta, double gamma, double norm_h, double tol_abs,
                           int loop, int deg_max, const float* params, void* work,
                           size_t work_bytes, void* stream, int* deg, float* pred, int* src);
+
+/* Sequence-calibrated degrees (degree_mode 3), host only: with speed_j the
+ * measured speed of vector j (NaN when unknown) and m_a,j the analytic
+ * continuous degree, m_j = max(r_j, ceil(m_a,j * f / speed_j)) clamped to
+ * [1, deg_max] (r_j: chfsi_degrees), f = 1.25 when every calibrated
+ * ceil(m_a,j / speed_j) and every uncalibrated ceil(m_a,j) is <= deg_max,
+ * else 1.  Unknown speeds take r_j; guards and vectors with |t_j| <= 1 the
+ * largest wanted degree.  speed may be NULL (all unknown).  src: HOST k
+ * ints out or NULL (0 rule, 1 calibrated, 2 guard fill). */
+int chfsi_degrees_sequence(int k, const double* mu, const double* res, const double* speed,
+                           int n_wanted, double alpha, double beta, double tol_abs, int deg_max,
+                           int* deg, int* src);
 
 /* Training and inference kernels of the degree network (device buffers,
  * FP32).  X is n x 8 row-major, T and y hold n floats, params / grad / m /

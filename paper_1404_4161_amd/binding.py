@@ -31,7 +31,8 @@ class ChfsiOpts(Structure):
                 ("lanczos_steps", c_int), ("alpha_rule", c_int), ("degree_mode", c_int),
                 ("reuse_b_factor", c_int), ("precision", c_int), ("seed", c_ulonglong),
                 ("degree_jitter", c_double), ("first_rule", c_int), ("log_capacity", c_int),
-                ("log", POINTER(c_double)), ("mlp", POINTER(c_float))]
+                ("log", POINTER(c_double)), ("mlp", POINTER(c_float)),
+                ("seq_rates", POINTER(c_double))]
 
 
 class ChfsiInfo(Structure):
@@ -95,6 +96,9 @@ _SIGS = {
                                       c_double, c_double, c_double, c_double, c_int, c_int,
                                       POINTER(c_float), c_void_p, c_size_t, c_void_p,
                                       POINTER(c_int), POINTER(c_float), POINTER(c_int)]),
+    "chfsi_degrees_sequence": (c_int, [c_int, POINTER(c_double), POINTER(c_double),
+                                       POINTER(c_double), c_int, c_double, c_double, c_double,
+                                       c_int, POINTER(c_int), POINTER(c_int)]),
     "chfsi_mlp_workspace_bytes": (c_size_t, [c_int]),
     "chfsi_mlp_forward": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "chfsi_mlp_gradient": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -209,11 +213,12 @@ def chfsi_workspace_bytes(n, nev, nex, generalized, opts=None):
 
 
 def chfsi_solve(A, B, nev, nex, tol, X0=None, opts=None, X=None, work=None, stream=None,
-                raise_on_error=True, Lambda0=None, log=None, mlp=None):
+                raise_on_error=True, Lambda0=None, log=None, mlp=None, seq_rates=None):
     """Solve A x = lambda B x (B None: standard).  Lambda0: the Ritz values
     that go with X0 (optional).  log: float64 numpy array (cap, 24) that
     receives convergence records (opts.log / log_capacity); mlp: float32
-    numpy blob of the degree network (opts.mlp).  Returns (status,
+    numpy blob of the degree network (opts.mlp); seq_rates: float64 numpy
+    array of k per-vector speeds, in/out (opts.seq_rates).  Returns (status,
     Lambda[k] numpy, X (n x k column-major tensor), info dict)."""
     torch = _torch()
     n = A.shape[0]
@@ -232,6 +237,11 @@ def chfsi_solve(A, B, nev, nex, tol, X0=None, opts=None, X=None, work=None, stre
         if mlp.dtype != np.float32 or not mlp.flags.c_contiguous or mlp.size != CHFSI_MLP_PARAMS:
             raise ValueError("mlp must be a contiguous float32 blob of CHFSI_MLP_PARAMS entries")
         o.mlp = mlp.ctypes.data_as(POINTER(c_float))
+    if seq_rates is not None:
+        if seq_rates.dtype != np.float64 or not seq_rates.flags.c_contiguous \
+                or seq_rates.size != k:
+            raise ValueError("seq_rates must be a contiguous float64 array of k entries")
+        o.seq_rates = seq_rates.ctypes.data_as(POINTER(c_double))
     wb = chfsi_workspace_bytes(n, nev, nex, B is not None, o)
     w = _work(wb, dev, work)
     lam = (c_double * k)()
@@ -545,3 +555,17 @@ def chfsi_autotune_set(n, N, variant):
 
 def chfsi_autotune_reset():
     _check(lib().chfsi_autotune_reset(), "chfsi_autotune_reset")
+
+
+def chfsi_degrees_sequence(mu, res, speed, n_wanted, alpha, beta, tol_abs, deg_max=40):
+    """Sequence-calibrated degrees (host); returns (deg, src) numpy arrays."""
+    k = len(mu)
+    m = (c_double * k)(*[float(x) for x in mu])
+    r = (c_double * k)(*[float(x) for x in res])
+    sp = None if speed is None else (c_double * k)(*[float(x) for x in speed])
+    d = (c_int * k)()
+    sr = (c_int * k)()
+    _check(lib().chfsi_degrees_sequence(k, m, r, sp, int(n_wanted), float(alpha), float(beta),
+                                        float(tol_abs), int(deg_max), d, sr),
+           "chfsi_degrees_sequence")
+    return np.array(d[:], dtype=np.int64), np.array(sr[:], dtype=np.int64)

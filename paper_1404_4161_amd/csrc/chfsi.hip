@@ -750,6 +750,62 @@ double splitmix_host(unsigned long long seed, int stream, unsigned long long i) 
 constexpr int STREAM_JITTER = 3;
 constexpr double MLP_OOD = 6.0;   // standardised features beyond this use the rule
 
+// Sequence-calibrated degrees (degree_mode 3, Multiple Optimization read
+// from eq. resl): the rate of vector j is corrected by its speed measured
+// earlier in the sequence, speed[j] = observed ln(Res_before / Res_after) /
+// (m ln|rho|) (NaN when unknown): m_j = max(rule_j, ceil(m_a,j * f / speed_j))
+// with f = SEQ_MARGIN in a loop that can finish every wanted vector (all
+// such degrees within deg_max) and 1 otherwise.  Unknown speeds and vectors
+// without a rate take the rule.  Guards take the largest wanted degree.
+constexpr double SEQ_MARGIN = 1.25;
+
+int sequence_degrees(int k, const double* mu, const double* res, const double* speed,
+                     int n_wanted, double alpha, double beta, double tol_abs, int deg_max,
+                     int* deg, int* src) {
+  std::vector<int> rule(k);
+  degrees_host(k, mu, res, n_wanted, alpha, beta, tol_abs, deg_max, rule.data());
+  const double c = 0.5 * (alpha + beta), e = 0.5 * (beta - alpha);
+  const int nw = std::min(n_wanted, k);
+  std::vector<double> need(k, 0.0);
+  std::vector<char> rate(k, 0), cal(k, 0);
+  bool finishing = true;
+  for (int j = 0; j < nw; ++j) {
+    const double t = (mu[j] - c) / e;
+    if (!(std::fabs(t) > 1.0)) continue;
+    rate[j] = 1;
+    const double lr = std::log(std::fabs(t) + std::sqrt(t * t - 1.0));
+    const double m_a = std::log(std::max(res[j] / tol_abs, 1.0)) / lr;
+    const double sp = speed ? speed[j] : NAN;
+    cal[j] = std::isfinite(sp) && sp > 0.0;
+    need[j] = cal[j] ? m_a / sp : m_a;
+    if (!(std::ceil(need[j]) <= (double)deg_max)) finishing = false;
+  }
+  const double f = finishing ? SEQ_MARGIN : 1.0;
+  int fill = 0;
+  bool any = false;
+  for (int j = 0; j < k; ++j) {
+    src[j] = 2;
+    if (!rate[j]) continue;
+    int m = rule[j];
+    if (cal[j]) {
+      const double mc = need[j] * f;
+      const int mm = std::isfinite(mc) ? (int)std::min<double>(std::ceil(mc), (double)deg_max)
+                                       : deg_max;
+      m = std::min(std::max(std::max(mm, 1), rule[j]), deg_max);
+      src[j] = 1;
+    } else {
+      src[j] = 0;
+    }
+    deg[j] = m;
+    fill = any ? std::max(fill, m) : m;
+    any = true;
+  }
+  if (!any) fill = deg_max;
+  for (int j = 0; j < k; ++j)
+    if (src[j] == 2) deg[j] = fill;
+  return CHFSI_OK;
+}
+
 // Learned degrees (the rule of chfsi_degrees_learned).  prm_host is the
 // caller's blob, prm_dev its device copy; x_dev / y_dev hold k rows.
 // src (k ints) receives 0 rule fallback, 1 network, 2 guard fill; feats
@@ -894,10 +950,16 @@ struct Solve {
   // the current loop
   int ka = 0, nw_loop = 0;
   double c = 0.0, e = 0.0;
-  bool use32 = false, logging = false, own_filter = false;
+  bool use32 = false, logging = false, own_filter = false, res_known_before = false;
   std::vector<char> capped;
   std::vector<double> pending;
   std::vector<int> order, msort;
+  // per active position: convergence speed of the vector relative to the
+  // analytic model (measured in this call, or carried in from the previous
+  // problem through opts.seq_rates; NaN when unknown), and this loop's
+  // residual and ln|rho| before the filter
+  std::vector<double> speed, res_before, lnrho;
+  std::vector<double> speed_locked;
 
   ~Solve() {
     if (fe0) hipEventDestroy(fe0);
@@ -1013,6 +1075,9 @@ struct Solve {
     if (o.degree_mode == 2)
       CK(hipMemcpyAsync(sb.mlp_p, o.mlp, sizeof(float) * MLP_PARAMS, hipMemcpyHostToDevice, s));
     have_res = !(X0 && Lambda0);
+    speed.assign(k, NAN);
+    if (X0 && o.seq_rates)
+      for (int j = 0; j < k; ++j) speed[j] = o.seq_rates[j];
     if (o.precision == 1) CK(matrix_to_fp32(s, n, H, ldh, b.H32));
     CK(hipEventCreate(&fe0));
     CK(hipEventCreate(&fe1));
@@ -1031,7 +1096,15 @@ struct Solve {
     std::vector<int> rule(ka_);
     degrees_host(ka_, mu.data(), res.data(), nev - nl, alpha, beta, tol_abs, o.deg_max,
                  rule.data());
-    if (o.degree_mode == 2) {
+    if (o.degree_mode == 3) {
+      CKS(sequence_degrees(ka_, mu.data(), res.data(), speed.data(), nev - nl, alpha, beta,
+                           tol_abs, o.deg_max, deg.data(), dsrc.data()));
+      for (int j = 0; j < nw; ++j) {
+        if (dsrc[j] == 1) ++learned_cols;
+        if (dsrc[j] == 1 && deg[j] > rule[j]) ++learned_raised;
+        if (dsrc[j] == 0) ++fallback_cols;
+      }
+    } else if (o.degree_mode == 2) {
       bool finishing = false;
       CKS(learned_degrees(s, ka_, mu.data(), res.data(), nev - nl, alpha, beta, gamma, norm_h,
                           tol_abs, loop, o.deg_max, o.mlp, sb.mlp_p, sb.mlp_x, sb.mlp_y,
@@ -1131,6 +1204,7 @@ struct Solve {
         }
       }
     }
+    res_known_before = have_res;
     logging = o.log && log_records < o.log_capacity && have_res;
     pending.clear();
     if (logging) {
@@ -1152,6 +1226,12 @@ struct Solve {
         degree_features(mu[j], res[j], gap, alpha, beta, gamma, norm_h, tol_abs, it, r + 16,
                         nullptr);
       }
+    }
+    res_before.assign(res.begin(), res.begin() + ka);
+    lnrho.assign(ka, 0.0);
+    for (int j = 0; j < ka; ++j) {
+      const double t = (mu[j] - c) / e;
+      if (std::fabs(t) > 1.0) lnrho[j] = std::log(std::fabs(t) + std::sqrt(t * t - 1.0));
     }
     // columns sorted by ascending degree (stable)
     order.resize(ka);
@@ -1227,8 +1307,22 @@ struct Solve {
       filter_sec += 1e-3 * ms;
       if (use32) sec32 += 1e-3 * ms;
     }
+    // measured speed of each wanted vector; residuals below 1e-2 tol count
+    // as that; an FP32 loop counts only where the residual stayed far above
+    // its rounding floor (about eps32 times the residual before)
+    const bool measured = res_known_before;
     have_res = true;
     tm.drain();
+    if (measured) {
+      const double floor32 = 1e3 * std::ldexp(1.0, -24);
+      for (int j = 0; j < nw_loop; ++j) {
+        if (!(lnrho[j] > 0.0) || !(res_before[j] > tol_abs) || deg[j] < 1) continue;
+        if (use32 && !(res[j] > floor32 * res_before[j])) continue;
+        const double after = std::max(res[j], 1e-2 * tol_abs);
+        const double sp = std::log(res_before[j] / after) / (deg[j] * lnrho[j]);
+        speed[j] = std::min(std::max(sp, 0.05), 8.0);
+      }
+    }
     if (logging) {
       for (int j = 0; j < nw_loop && log_records < o.log_capacity; ++j) {
         double* r = &pending[(size_t)j * CHFSI_LOG_FIELDS];
@@ -1256,17 +1350,21 @@ struct Solve {
       tm.end();
       for (int j : lock_idx) {
         lam_locked.push_back(mu[j]);
+        speed_locked.push_back(speed[j]);
         max_locked_res = std::max(max_locked_res, res[j]);
       }
-      std::vector<double> mu2, res2;
+      std::vector<double> mu2, res2, sp2;
       for (int j : keep_idx) {
         mu2.push_back(mu[j]);
         res2.push_back(res[j]);
+        sp2.push_back(speed[j]);
       }
       mu.assign(k, 0.0);
       res.assign(k, 0.0);
+      speed.assign(k, NAN);
       std::copy(mu2.begin(), mu2.end(), mu.begin());
       std::copy(res2.begin(), res2.end(), res.begin());
+      std::copy(sp2.begin(), sp2.end(), speed.begin());
       nl += (int)lock_idx.size();
     }
     if (nl >= nev) {
@@ -1318,6 +1416,12 @@ struct Solve {
     CK(hipStreamSynchronize(s));
     tm.drain();
     for (int j = 0; j < k; ++j) Lambda[j] = lam_all[ord[j]];
+    if (o.seq_rates) {
+      std::vector<double> sp_all(k, NAN);
+      for (int j = 0; j < nl; ++j) sp_all[j] = speed_locked[j];
+      for (int j = 0; j < kact; ++j) sp_all[nl + j] = speed[j];
+      for (int j = 0; j < k; ++j) o.seq_rates[j] = sp_all[ord[j]];
+    }
 
     if (info) {
       info->iters = it;
@@ -1629,8 +1733,9 @@ int validate_solve(int n, int nev, int nex, const void* A, int lda, const void* 
     if (X0 && (ldx0 < n || !aligned16(X0))) return CHFSI_INVALID_ARG;
     if (o.deg0 < 1 || o.deg_max < 1 || o.max_iter < 1 || o.lanczos_steps < 1) return CHFSI_INVALID_ARG;
     if (o.precision < 0 || o.precision > 1) return CHFSI_INVALID_ARG;
-    if (o.degree_mode < 0 || o.degree_mode > 2 || o.first_rule < 0 || o.first_rule > 1)
+    if (o.degree_mode < 0 || o.degree_mode > 3 || o.first_rule < 0 || o.first_rule > 1)
       return CHFSI_INVALID_ARG;
+    if (o.degree_mode == 3 && !o.seq_rates) return CHFSI_INVALID_ARG;
     if (!(o.degree_jitter >= 0.0) || !std::isfinite(o.degree_jitter)) return CHFSI_INVALID_ARG;
     if (o.log_capacity < 0 || (o.log_capacity > 0 && !o.log)) return CHFSI_INVALID_ARG;
     if (o.degree_mode == 2) {
@@ -1676,6 +1781,7 @@ int chfsi_default_opts(chfsi_opts* o) {
   o->log_capacity = 0;
   o->log = nullptr;
   o->mlp = nullptr;
+  o->seq_rates = nullptr;
   return CHFSI_OK;
 }
 
@@ -1704,7 +1810,7 @@ int chfsi_solve_batch(int count, const int* n, const int* nev, const int* nex,
     chfsi_default_opts(&o);
     if (opts) o = *opts;
     o.tol = tol;
-    if (o.log_capacity != 0) return CHFSI_INVALID_ARG;      // no shared log in a batch
+    if (o.log_capacity != 0 || o.seq_rates) return CHFSI_INVALID_ARG;   // no shared host arrays
     for (int q = 0; q < count; ++q) {
       const void* bq = B ? B[q] : nullptr;
       const void* xq = X0 ? X0[q] : nullptr;
@@ -1999,6 +2105,19 @@ int chfsi_degree_features(double mu, double res, double gap, double alpha, doubl
   return degree_features(mu, res, gap, alpha, beta, gamma, norm_h, tol_abs, loop, f, nullptr)
              ? CHFSI_OK
              : CHFSI_INVALID_ARG;
+}
+
+int chfsi_degrees_sequence(int k, const double* mu, const double* res, const double* speed,
+                           int n_wanted, double alpha, double beta, double tol_abs, int deg_max,
+                           int* deg, int* src) {
+  if (k < 1 || !mu || !res || !deg || !(beta > alpha) || !(tol_abs > 0.0) || deg_max < 1 ||
+      n_wanted < 0)
+    return CHFSI_INVALID_ARG;
+  std::vector<int> sv(k);
+  CKS(sequence_degrees(k, mu, res, speed, n_wanted, alpha, beta, tol_abs, deg_max, deg,
+                       sv.data()));
+  if (src) std::copy(sv.begin(), sv.end(), src);
+  return CHFSI_OK;
 }
 
 size_t chfsi_mlp_workspace_bytes(int n) {

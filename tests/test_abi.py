@@ -169,3 +169,36 @@ def test_autotuner_and_batch_argument_checks():
     assert lib.chfsi_solve_batch(0, None, None, None, None, None, None, None, 1e-10, None, None,
                                  None, None, None, None, None, None, None, 0, None, 0, None, None,
                                  st) == ch.binding.CHFSI_INVALID_ARG
+
+
+def test_sequence_calibrated_degrees_follow_their_definition():
+    """degree_mode 3's rule (parity unpinned: the paper defers Multiple
+    Optimization to another paper; checked against its stated definition
+    and the analytic rule it falls back to)."""
+    import math
+    from oracle import chebyshev
+    g = np.random.default_rng(4)
+    k, nw = 40, 30
+    mu = np.sort(np.concatenate([g.uniform(-24, -11, k - 4), g.uniform(-9, 20, 4)]))
+    res = 10.0 ** g.uniform(-9, -3, k)
+    alpha, beta, tol_abs = mu[-1], 60.0, 6e-9
+    rule = ochfsi.degree_rule(mu, res, nw, alpha, beta, tol_abs, 40)
+    # unknown speeds: the rule
+    d, src = ch.chfsi_degrees_sequence(mu, res, None, nw, alpha, beta, tol_abs, 40)
+    assert np.array_equal(d, rule)
+    # half speed everywhere, every vector can finish: ceil(1.25 * 2 m_a)
+    c, e = 0.5 * (alpha + beta), 0.5 * (beta - alpha)
+    r = chebyshev.rho((mu - c) / e)
+    speed = np.full(k, 0.5)
+    d, src = ch.chfsi_degrees_sequence(mu, res, speed, nw, alpha, beta, tol_abs, 400)
+    rule400 = ochfsi.degree_rule(mu, res, nw, alpha, beta, tol_abs, 400)
+    for j in range(nw):
+        if r[j] > 1:
+            m_a = math.log(max(res[j] / tol_abs, 1.0)) / math.log(r[j])
+            lo, hi = math.ceil(2.5 * m_a - 1e-9), math.ceil(2.5 * m_a + 1e-9)
+            assert max(lo, 1, rule400[j]) <= d[j] <= max(hi, 1, rule400[j])
+            assert src[j] == 1
+    assert np.all(d[nw:] == d[:nw].max())
+    # a vector that cannot finish under the cap: no margin, speed only
+    d2, _ = ch.chfsi_degrees_sequence(mu, res, speed, nw, alpha, beta, tol_abs, 5)
+    assert np.all(d2 <= 5) and np.all(d2 >= np.minimum(rule, 5))

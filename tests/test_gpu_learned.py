@@ -77,3 +77,37 @@ def test_learned_degrees_need_fewer_loops_than_the_rule(network):
     print("rule (loops, matvecs):", totals[0], "learned:", totals[2])
     assert totals[2][0] <= 0.8 * totals[0][0], totals
     assert totals[2][1] <= 1.15 * totals[0][1], totals
+
+
+@pytest.mark.timeout(600)
+def test_sequence_calibrated_degrees_need_fewer_loops():
+    """Multiple Optimization (degree_mode 3): each eigenvector's speed
+    measured in one problem (or an earlier loop) corrects its degree later.
+    Along a sequence it needs fewer loops than the rule, with the oracle's
+    eigenvalues."""
+    seq, probs = _problems(513)
+    host_b = seq.B.cpu().numpy()
+    k = NEV + NEX
+    totals = {}
+    for mode in (0, 3):
+        o = ch.chfsi_default_opts()
+        o.first_rule, o.degree_mode = 1, mode
+        rates = np.full(k, np.nan)
+        x = lam = None
+        loops = mv = 0
+        for l, a in enumerate(probs):
+            st, lam, x, info = ch.chfsi_solve(a, seq.B, NEV, NEX, 1e-10, X0=x,
+                                              Lambda0=lam if x is not None else None, opts=o,
+                                              seq_rates=rates)
+            assert st == 0
+            if l > 0:               # the cold first problem is the same for both
+                loops += info["iters"]
+                mv += info["matvecs"]
+            h, _ = ochfsi.reduce_to_standard(a.cpu().numpy(), host_b)
+            ref = eigh.eigvalsh(h)[:NEV]
+            assert np.abs(lam[:NEV] - ref).max() <= 1e-10 * np.abs(ref).min(), (mode, l)
+            assert np.all(np.isfinite(rates[:NEV]) | (l == 0))
+        totals[mode] = (loops, mv)
+    print("rule (loops, matvecs):", totals[0], "sequence-calibrated:", totals[3])
+    assert totals[3][0] < totals[0][0], totals
+    assert totals[3][1] <= 1.2 * totals[0][1], totals
