@@ -35,21 +35,22 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 
 # HBM bytes of one full-width filter step (n = 8000, N = 480), from the two
 # rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) calibrated on a 1 GiB
-# copy; valid only for the kernel source it was measured on.
+# copy, per tile variant of the step kernel; valid only for the kernel
+# source it was measured on.
 TRAFFIC_MEASURED = {
-    "zgemm_sha256": "a171d3bd7ee8b827a0282d158334bab2018fd744e84609e099af6c3bc72ee002",
-    "bytes_per_full_width_step": 4.724e9,
+    "zgemm_sha256": "e8dd339e55be54a5fb2a0b37e5795dc92f0aadd0164bab55c81d816423505561",
+    "bytes_per_full_width_step": {0: 4.681e9, 1: 2.375e9},
     "algorithmic_bytes_per_full_width_step": 1.208e9,
 }
 
 
-def traffic_entry():
+def traffic_entry(variant):
     import hashlib
     src = os.path.join(ROOT, "paper_1404_4161_amd", "csrc", "zgemm.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if sha != TRAFFIC_MEASURED["zgemm_sha256"]:
         return None
-    return round(TRAFFIC_MEASURED["bytes_per_full_width_step"] / 1e9, 3)
+    return round(TRAFFIC_MEASURED["bytes_per_full_width_step"][int(variant)] / 1e9, 3)
 
 
 def log(msg):
@@ -91,6 +92,8 @@ def filter_only(conf, degree):
     dst.copy_(src)
     torch.cuda.synchronize()
     n, k = conf.n, conf.k
+    # the launch variant the benchmark would take for this shape
+    v, _ = ch.chfsi_autotune_filter([n], [k])
     g = torch.Generator(device=dev)
     g.manual_seed(0)
     h = torch.randn(n, n, dtype=torch.complex128, device=dev, generator=g)
@@ -102,6 +105,7 @@ def filter_only(conf, degree):
     flops, launches = ch.chfsi_filter(h, y, [degree] * k, 0.0, nrm, -1.05 * nrm)
     dt = time.perf_counter() - t
     print(json.dumps({"mode": "filter-only", "n": n, "k": k, "degree": degree,
+                      "variant": int(v[0]),
                       "launches": launches, "seconds": round(dt, 6),
                       "tflops_wall": round(flops / dt / 1e12, 3),
                       "copy_bytes": src.numel() * 8}), flush=True)
@@ -119,7 +123,7 @@ def kpoints(args):
     import paper_1404_4161_amd as ch
     from workloads import gen
     dev = "cuda:0"
-    confs = gen.kpoint_configs()
+    confs = gen.kpoint_configs()[:args.kp_count]
     count = len(confs)
     stream = torch.cuda.Stream(device=dev)
     results = {}
@@ -193,13 +197,17 @@ def kpoints(args):
         del works, Xs, seqs, gens, Bs
         torch.cuda.empty_cache()
 
-    run("batched fp64", 0, True, False)
-    run("batched fp64 graph", 0, True, True)
-    run("sequential fp64", 0, False, False)
-    run("batched mixed", 1, True, False)
-    ref = results["sequential fp64"]["lams_last"]
+    variants = {"batched-fp64": ("batched fp64", 0, True, False),
+                "batched-fp64-graph": ("batched fp64 graph", 0, True, True),
+                "sequential-fp64": ("sequential fp64", 0, False, False),
+                "batched-mixed": ("batched mixed", 1, True, False)}
+    chosen = args.kp_variants.split(",")
+    for key in chosen:
+        run(*variants[key])
+    ref_key = "sequential fp64" if "sequential-fp64" in chosen else variants[chosen[0]][0]
+    ref = results[ref_key]["lams_last"]
     for lab, r in results.items():
-        r["max_rel_eig_diff_vs_sequential_fp64"] = float(max(
+        r[f"max_rel_eig_diff_vs_{ref_key.replace(' ', '_')}"] = float(max(
             np.max(np.abs(a - b) / np.abs(b)) for a, b in zip(r.pop("lams_last"), ref)))
     out = {
         "metric": "s per batched sequence step (32 k-point problems) at 1e-10 residual",
@@ -209,8 +217,9 @@ def kpoints(args):
         "workload": "kpoints: 32 generalized complex Hermitian sequences, n uniform in "
                     "[2000, 9000], nev 5 %, nex 1 %, 5 steps (step 1 untimed)",
         "n": [c.n for c in confs], "steps": confs[0].length - 1,
-        "speedup_batched_vs_sequential_fp64": round(
-            results["sequential fp64"]["s_per_step"] / results["batched fp64"]["s_per_step"], 3),
+        "speedup_batched_vs_sequential_fp64": (round(
+            results["sequential fp64"]["s_per_step"] / results["batched fp64"]["s_per_step"], 3)
+            if {"sequential fp64", "batched fp64"} <= set(results) else None),
         "variants": results,
     }
     print(json.dumps(out), flush=True)
@@ -230,6 +239,10 @@ def main():
                          "uniform degree) after a 1 GiB device copy used to calibrate "
                          "hardware byte counters; for profiler runs")
     ap.add_argument("--degree", type=int, default=4)
+    ap.add_argument("--kp-count", type=int, default=32,
+                    help="k-point workload: number of problems (32 in the full workload)")
+    ap.add_argument("--kp-variants", default="batched-fp64,batched-fp64-graph,sequential-fp64,"
+                                             "batched-mixed")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training the degree network and the learned-degree sequences")
     ap.add_argument("--train-steps", type=int, default=1500)
@@ -421,7 +434,8 @@ def main():
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(tflops / PEAK_FP64_TFLOPS, 4),
-            "traffic": traffic_entry(),
+            "traffic": traffic_entry(tv[0]),
+            "tile_variant_full_width": int(tv[0]),
             "traffic_unit": "GB per full-width step (n=8000, N=480), HBM, from FETCH_SIZE/WRITE_SIZE",
             "algorithmic_bytes_full_width_gb": 1.208,
             "avg_launch_us": round(avg_launch * 1e6, 2),

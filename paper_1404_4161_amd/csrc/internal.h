@@ -16,6 +16,7 @@ enum Epi {
   EPI_STORE = 0,     // C = alpha * acc + beta * C
   EPI_CHEB = 1,      // Yout = sa * (acc - shift * Ycur) - sb * Yold  (three-term step)
   EPI_PARTIAL = 2,   // raw partial sums of a split-K launch
+  EPI_PARTIAL_CHEB = 3,   // the same for a filter step (a kernel name of its own)
 };
 
 struct GemmArgs {
@@ -168,7 +169,7 @@ constexpr int MLP_B3 = MLP_W3 + MLP_H;
 constexpr int MLP_MARGIN = MLP_B3 + 1;
 constexpr int MLP_PARAMS = MLP_MARGIN + 1;
 // Samples per partial sum of the gradient reduction.
-constexpr int MLP_CHUNK = 2048;
+constexpr int MLP_CHUNK = 256;
 
 // Device floats used by mlp_gradient for n samples.
 size_t mlp_grad_work_floats(int n);

@@ -105,8 +105,8 @@ __global__ void __launch_bounds__(NT) k_mlp_fwd_bwd(int n, const float* X, const
 
 // Gradient partial sums: thread p of grid row c adds the contributions of
 // samples [c * MLP_CHUNK, (c + 1) * MLP_CHUNK) to parameter p, in sample
-// order.  The chunk sums are then added in chunk order, so the result does
-// not depend on scheduling.
+// order (W2 in k_mlp_grad_w2).  The chunk sums are then added in chunk
+// order, so the result does not depend on scheduling.
 __global__ void __launch_bounds__(NT) k_mlp_grad_partial(int n, const float* Z, const float* H1,
                                                          const float* H2, const float* D1,
                                                          const float* D2, const float* DY,
@@ -123,8 +123,7 @@ __global__ void __launch_bounds__(NT) k_mlp_grad_partial(int n, const float* Z, 
     const int a = p - MLP_B1;
     for (int s = s0; s < s1; ++s) g += D1[(long)s * MLP_H + a];
   } else if (p >= MLP_W2 && p < MLP_B2) {
-    const int a = (p - MLP_W2) / MLP_H, b = (p - MLP_W2) % MLP_H;
-    for (int s = s0; s < s1; ++s) g += D2[(long)s * MLP_H + a] * H1[(long)s * MLP_H + b];
+    return;   // k_mlp_grad_w2
   } else if (p >= MLP_B2 && p < MLP_W3) {
     const int a = p - MLP_B2;
     for (int s = s0; s < s1; ++s) g += D2[(long)s * MLP_H + a];
@@ -135,6 +134,53 @@ __global__ void __launch_bounds__(NT) k_mlp_grad_partial(int n, const float* Z, 
     for (int s = s0; s < s1; ++s) g += DY[s];
   }
   part[(long)blockIdx.y * MLP_PARAMS + p] = g;   // 0 for the statistics and the margin
+}
+
+// W2 part of the same partial sums: G[a][b] = sum_s D2[s][a] H1[s][b] over
+// the chunk's samples.  The chunk's D2 and H1 rows are staged through LDS
+// 64 samples at a time; thread t accumulates the 4 x 4 block of (a, b)
+// with a = 4 (t / 16) + i, b = 4 (t % 16) + j, samples in order.
+__global__ void __launch_bounds__(NT) k_mlp_grad_w2(int n, const float* H1, const float* D2,
+                                                    float* part) {
+  constexpr int TS = 64;
+  __shared__ float d2s[TS][MLP_H + 1];
+  __shared__ float h1s[TS][MLP_H + 1];
+  const int t = threadIdx.x;
+  const int a0 = 4 * (t >> 4), b0 = 4 * (t & 15);
+  const int s0 = blockIdx.x * MLP_CHUNK;
+  const int s1 = min(n, s0 + MLP_CHUNK);
+  float acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+  for (int base = s0; base < s1; base += TS) {
+    const int cnt = min(TS, s1 - base);
+    for (int e = t; e < TS * MLP_H; e += NT) {
+      const int r = e / MLP_H, c = e % MLP_H;
+      const bool in = r < cnt;
+      d2s[r][c] = in ? D2[(long)(base + r) * MLP_H + c] : 0.f;
+      h1s[r][c] = in ? H1[(long)(base + r) * MLP_H + c] : 0.f;
+    }
+    __syncthreads();
+    for (int r = 0; r < cnt; ++r) {
+      float av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) av[i] = d2s[r][a0 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = h1s[r][b0 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+    }
+    __syncthreads();
+  }
+  float* out = part + (long)blockIdx.x * MLP_PARAMS + MLP_W2;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[(a0 + i) * MLP_H + b0 + j] = acc[i][j];
 }
 
 __global__ void __launch_bounds__(NT) k_mlp_grad_final(int chunks, const float* part, float* G) {
@@ -201,6 +247,10 @@ int mlp_gradient(hipStream_t s, int n, const float* X, const float* T, const flo
   hipLaunchKernelGGL(k_mlp_grad_partial, dim3(pblocks, chunks), dim3(NT), 0, s, n,
                      (const float*)Z, (const float*)H1, (const float*)H2, (const float*)D1,
                      (const float*)D2, (const float*)DY, gpart);
+  e = (int)hipGetLastError();
+  if (e) return e;
+  hipLaunchKernelGGL(k_mlp_grad_w2, dim3(chunks), dim3(NT), 0, s, n, (const float*)H1,
+                     (const float*)D2, gpart);
   e = (int)hipGetLastError();
   if (e) return e;
   hipLaunchKernelGGL(k_mlp_grad_final, dim3(pblocks), dim3(NT), 0, s, chunks, (const float*)gpart,

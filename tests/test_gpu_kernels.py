@@ -218,6 +218,7 @@ def test_autotuner_records_a_choice_per_shape():
         v, tf = ch.chfsi_autotune_filter([700, 1300], [64, 130])
         assert v.shape == (2,) and set(v.tolist()) <= {0, 1}
         assert np.all(tf > 0)
-        assert np.array_equal(v, np.argmax(tf, axis=1))
+        # the deeper K stage only when it is clearly (2 %) faster
+        assert np.array_equal(v, (tf[:, 1] > 1.02 * tf[:, 0]).astype(int))
     finally:
         ch.chfsi_autotune_reset()
