@@ -133,7 +133,7 @@ def kpoints(args):
     log(f"autotune of {len(shapes)} shapes in {time.perf_counter() - t0:.1f}s: "
         f"variant 1 chosen for {int(tv.sum())}")
 
-    def run(label, precision, batched, graph):
+    def run(label, precision, batched, graph, serial=False):
         t0 = time.perf_counter()
         seqs = [gen.Sequence(c, kind="torch", device=dev, draw="device") for c in confs]
         gens = [s_.problems() for s_ in seqs]
@@ -157,7 +157,7 @@ def kpoints(args):
                     st, lams, _, infos, sts = ch.chfsi_solve_batch(
                         As, Bs, [c.nev for c in confs], [c.nex for c in confs], 1e-10,
                         X0s=x0s, Lambda0s=lam0s, opts=o, Xs=Xs, works=works, stream=stream,
-                        graph=graph)
+                        graph=graph, serial=serial)
                     if st != 0:
                         raise RuntimeError(f"chfsi_solve_batch status {st} {sts}")
                 else:
@@ -200,7 +200,8 @@ def kpoints(args):
     variants = {"batched-fp64": ("batched fp64", 0, True, False),
                 "batched-fp64-graph": ("batched fp64 graph", 0, True, True),
                 "sequential-fp64": ("sequential fp64", 0, False, False),
-                "batched-mixed": ("batched mixed", 1, True, False)}
+                "batched-mixed": ("batched mixed", 1, True, False),
+                "batched-fp64-serial": ("batched fp64 serial", 0, True, False, True)}
     chosen = args.kp_variants.split(",")
     for key in chosen:
         run(*variants[key])

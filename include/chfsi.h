@@ -265,6 +265,9 @@ int chfsi_solve(int n, int nev, int nex,
  *               seq_rates NULL (degree_mode 3 is not available here).
  *   flags       bit 0: capture each loop's grouped filter launches as one
  *               HIP graph and launch it (needs a non-NULL stream).
+ *               bit 1: serial -- one internal stream driven by the calling
+ *               thread (no worker threads; the per-problem phases of
+ *               different problems do not overlap).
  *   info        NULL or count statistics records.
  *   status      HOST, count ints out: each problem's status.
  * Returns CHFSI_OK when every problem converged, else the first error

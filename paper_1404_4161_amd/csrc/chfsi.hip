@@ -1600,7 +1600,7 @@ size_t batch_bytes(int count, const chfsi_opts& o) {
 constexpr int BATCH_WORKERS = 8;
 
 int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void* bwork,
-                     size_t bbytes, bool graph, std::vector<int>& status) {
+                     size_t bbytes, bool graph, bool serial, std::vector<int>& status) {
   const int count = (int)S.size();
   size_t cap_entries = 0, cap_slots = 0;
   batch_caps(count, S[0]->o, &cap_entries, &cap_slots);
@@ -1610,7 +1610,7 @@ int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void
   int* dslots = cv.take<int>(cap_slots);
   int dev = 0;
   CK(hipGetDevice(&dev));
-  const int T = std::min(count, BATCH_WORKERS);
+  const int T = serial ? 1 : std::min(count, BATCH_WORKERS);
 
   // resources of the call, released on every path
   struct Res {
@@ -1645,25 +1645,28 @@ int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void
   std::vector<char> failed(count, 0), active(count, 0);
   // run fn(q) for every selected problem, problems q = t mod T on worker t
   auto parallel = [&](auto fn) {
-    std::vector<std::thread> th;
-    for (int t = 0; t < T; ++t) {
-      th.emplace_back([&, t]() {
-        hipSetDevice(dev);
-        tl_handle = r.h[t];
-        for (int q = t; q < count; q += T) {
-          try {
-            fn(q);
-          } catch (const std::bad_alloc&) {
-            status[q] = CHFSI_ALLOC_ERROR;
-            failed[q] = 1;
-          } catch (...) {
-            status[q] = CHFSI_DEVICE_ERROR;
-            failed[q] = 1;
-          }
+    auto work = [&](int t) {
+      hipSetDevice(dev);
+      tl_handle = r.h[t];
+      for (int q = t; q < count; q += T) {
+        try {
+          fn(q);
+        } catch (const std::bad_alloc&) {
+          status[q] = CHFSI_ALLOC_ERROR;
+          failed[q] = 1;
+        } catch (...) {
+          status[q] = CHFSI_DEVICE_ERROR;
+          failed[q] = 1;
         }
-        tl_handle = nullptr;
-      });
+      }
+      tl_handle = nullptr;
+    };
+    if (serial) {            // the calling thread drives the one worker stream
+      work(0);
+      return;
     }
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; ++t) th.emplace_back(work, t);
     for (auto& x : th) x.join();
   };
 
@@ -1802,7 +1805,7 @@ int chfsi_solve_batch(int count, const int* n, const int* nev, const int* nex,
                       void* stream, chfsi_info* info, int* status) {
   try {
     if (count < 1 || !n || !nev || !nex || !A || !lda || !Lambda || !X || !ldx || !work ||
-        !work_bytes || !status || check_ptr(batch_work) || (flags & ~1))
+        !work_bytes || !status || check_ptr(batch_work) || (flags & ~3))
       return CHFSI_INVALID_ARG;
     if ((B && !ldb) || (X0 && !ldx0)) return CHFSI_INVALID_ARG;
     if ((flags & 1) && !stream) return CHFSI_INVALID_ARG;   // no capture on the null stream
@@ -1838,7 +1841,8 @@ int chfsi_solve_batch(int count, const int* n, const int* nev, const int* nex,
       if (v.info) std::memset(v.info, 0, sizeof(chfsi_info));
     }
     std::vector<int> st;
-    CKS(solve_batch_impl(S, as_stream(stream), batch_work, batch_work_bytes, (flags & 1) != 0, st));
+    CKS(solve_batch_impl(S, as_stream(stream), batch_work, batch_work_bytes, (flags & 1) != 0,
+                         (flags & 2) != 0, st));
     int worst = CHFSI_OK;
     for (int q = 0; q < count; ++q) {
       status[q] = st[q];

@@ -88,7 +88,10 @@ def test_batch_graph_capture_gives_the_same_result():
     stream = torch.cuda.Stream()
     r0 = ch.chfsi_solve_batch(As, Bs, nevs, nexs, 1e-10, stream=stream)
     r1 = ch.chfsi_solve_batch(As, Bs, nevs, nexs, 1e-10, stream=stream, graph=True)
-    assert r0[0] == r1[0] == 0
+    r2 = ch.chfsi_solve_batch(As, Bs, nevs, nexs, 1e-10, stream=stream, serial=True)
+    assert r0[0] == r1[0] == r2[0] == 0
+    for q in range(len(SIZES)):      # one driving thread: the same arithmetic
+        assert np.array_equal(r0[1][q], r2[1][q])
     for q in range(len(SIZES)):
         assert np.array_equal(r0[1][q], r1[1][q])
         assert torch.equal(r0[2][q], r1[2][q])
