@@ -38,8 +38,8 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 # copy, per tile variant of the step kernel; valid only for the kernel
 # source it was measured on.
 TRAFFIC_MEASURED = {
-    "zgemm_sha256": "e8dd339e55be54a5fb2a0b37e5795dc92f0aadd0164bab55c81d816423505561",
-    "bytes_per_full_width_step": {0: 4.681e9, 1: 2.375e9},
+    "zgemm_sha256": "b5ca74ccbdf3ae5ba5ccd621dd435a0cc53f8c8144f919e4da1010122d255f7b",
+    "bytes_per_full_width_step": {0: 4.657e9, 1: 2.361e9, 2: 1.697e9},
     "algorithmic_bytes_per_full_width_step": 1.208e9,
 }
 
@@ -300,10 +300,10 @@ def main():
     # Filter tile autotuner (untimed): both K-stage variants of the filter
     # step on the full window and narrower ones; later launches take the
     # choice of the nearest measured shape.
-    tune_shapes = [(n, k), (n, k // 2), (n, k // 4), (n, max(k // 8, 16))]
+    tune_shapes = [(n, k), (n, (3 * k) // 4), (n, k // 2), (n, k // 4), (n, max(k // 8, 16))]
     tv, ttf = ch.chfsi_autotune_filter([a for a, _ in tune_shapes], [b for _, b in tune_shapes])
     autotune = [{"n": a, "N": b, "variant": int(v), "tflops_kb8": round(float(t[0]), 2),
-                 "tflops_kb16": round(float(t[1]), 2)}
+                 "tflops_kb16": round(float(t[1]), 2), "tflops_wide": round(float(t[2]), 2)}
                 for (a, b), v, t in zip(tune_shapes, tv, ttf)]
     log(f"autotune: {autotune}")
 

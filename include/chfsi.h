@@ -437,16 +437,20 @@ int chfsi_mlp_adam(float* params, const float* grad, float* m, float* v, float l
 int chfsi_mlp_train(int n, const float* X, const float* T, float* params, int steps, float lr,
                     void* work, size_t work_bytes, void* stream, float* loss_out);
 
-/* Filter tile autotuner.  The Chebyshev-step kernel exists in two variants:
- * 0 stages K 8 deep through LDS with four workgroups per CU, 1 stages it 16
- * deep with two per CU.  chfsi_autotune_filter times both on each given
+/* Filter tile autotuner.  The Chebyshev-step kernel exists in three
+ * variants: 0 (64 x 64 tiles) stages K 8 deep through LDS with four
+ * workgroups per CU, 1 stages it 16 deep with two per CU, 2 uses 128 x 128
+ * tiles of 16 waves (one workgroup per CU; windows of N >= 256 columns, and
+ * not in the grouped launches of chfsi_solve_batch, which take 0 instead).
+ * Another variant than 0 is kept only when it is 2 % faster.
+ * chfsi_autotune_filter times them on each given
  * launch shape (an n x n Hermitian-sized operand times an n x N block, the
  * width N of a filter window; synthetic data in `work`), records the faster
  * one per device, and every later filter step (single or batched) takes
  * the choice of the nearest recorded shape (log distance in n and N; with
  * none recorded, variant 0).
- *   variant  HOST, count ints out.   tflops  HOST, 2 * count doubles out
- *   (variant 0 and 1 per shape) or NULL.
+ *   variant  HOST, count ints out.   tflops  HOST, 3 * count doubles out
+ *   (variants 0, 1, 2 per shape; 0.0 where not timed) or NULL.
  *   work     device, >= chfsi_autotune_workspace_bytes(max n, max N).
  * chfsi_autotune_set records a choice directly; chfsi_autotune_reset
  * clears the current device's table. */

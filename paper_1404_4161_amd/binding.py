@@ -537,17 +537,17 @@ def chfsi_solve_batch(As, Bs, nevs, nexs, tol, X0s=None, opts=None, Lambda0s=Non
 
 def chfsi_autotune_filter(ns, Ns, device="cuda", stream=None):
     """Time both filter-step variants on each (n, N) launch shape and record
-    the faster; returns (variants, tflops (count x 2)) numpy arrays."""
+    the fastest; returns (variants, tflops (count x 3)) numpy arrays."""
     torch = _torch()
     count = len(ns)
     dev = torch.device(device)
     wb = int(lib().chfsi_autotune_workspace_bytes(max(ns), max(Ns)))
     w = _work(wb, dev)
     v = (c_int * count)()
-    tf = (c_double * (2 * count))()
+    tf = (c_double * (3 * count))()
     _check(lib().chfsi_autotune_filter(count, (c_int * count)(*ns), (c_int * count)(*Ns), _ptr(w),
                                        wb, _stream(stream, dev), v, tf), "chfsi_autotune_filter")
-    return np.array(v[:]), np.array(tf[:]).reshape(count, 2)
+    return np.array(v[:]), np.array(tf[:]).reshape(count, 3)
 
 
 def chfsi_autotune_set(n, N, variant):

@@ -1532,7 +1532,7 @@ int filter_group(hipStream_t s, const std::vector<Solve*>& jobs, GemmArgs* dlist
   // one tile variant per grouped launch: the tuned choice carrying the most
   // flops among the problems
   double w[2] = {0.0, 0.0};
-  for (int q = 0; q < count; ++q) w[filter_variant(jobs[q]->n, jobs[q]->ka)] += fl[q];
+  for (int q = 0; q < count; ++q) w[filter_variant(jobs[q]->n, jobs[q]->ka) == 1 ? 1 : 0] += fl[q];
   const int variant = w[1] > w[0] ? 1 : 0;
   CK(hipEventRecord(e0, s));
   if (graph) {
@@ -2258,12 +2258,10 @@ int chfsi_autotune_filter(int count, const int* n, const int* N, void* work, siz
     for (int i = 0; i < count; ++i) {
       CK(fill_counter_random(s, n[i], N[i], Y0, n[i], 2, 1));
       CK(fill_counter_random(s, n[i], N[i], Y1, n[i], 3, 1));
-      double tf[2] = {0.0, 0.0};
+      double tf[3] = {0.0, 0.0, 0.0};
       CK(tune_filter_shape(s, n[i], N[i], H, Y0, Y1, &variant[i], tf));
-      if (tflops) {
-        tflops[2 * i] = tf[0];
-        tflops[2 * i + 1] = tf[1];
-      }
+      if (tflops)
+        for (int v = 0; v < 3; ++v) tflops[3 * i + v] = tf[v];
     }
     CK(hipStreamSynchronize(s));
     return CHFSI_OK;
@@ -2273,7 +2271,7 @@ int chfsi_autotune_filter(int count, const int* n, const int* N, void* work, siz
 }
 
 int chfsi_autotune_set(int n, int N, int variant) {
-  if (n < 1 || N < 1 || variant < 0 || variant > 1) return CHFSI_INVALID_ARG;
+  if (n < 1 || N < 1 || variant < 0 || variant > 2) return CHFSI_INVALID_ARG;
   tune_set(n, N, variant);
   return CHFSI_OK;
 }

@@ -77,7 +77,7 @@ GemmArgs cheb_group_args(int n, int N, const zc* H, long ldh, const zc* Ycur, lo
 // One launch running `count` steps; list (device) holds their arguments and
 // slot_begin (device, count + 1 ints, multiples of 8) their workgroup ranges.
 // variant: K-stage depth of the tile (0: 8, four workgroups per CU; 1: 16,
-// two per CU).
+// two per CU); the wide variant 2 of single steps runs as 0 here.
 int cheb_step_group(hipStream_t s, const GemmArgs* list, const int* slot_begin, int count,
                     int total_slots, int variant);
 
@@ -85,11 +85,12 @@ int cheb_step_group(hipStream_t s, const GemmArgs* list, const int* slot_begin, 
 // n x n by n x N step (nearest measured shape; 0 when none).
 // tune_filter_shape: times both variants of a step on the given buffers
 // (H n x n, Y0 and Y1 n x N, ld n; Y1 is overwritten), records the faster
-// and returns it with the TFLOP/s of each.  tune_set / tune_reset edit the
+// and returns it with the TFLOP/s of each (variant 2, 128 x 128 tiles, only
+// for N >= 256; tf[2] = 0 otherwise).  tune_set / tune_reset edit the
 // table directly.
 int filter_variant(int n, int N);
 int tune_filter_shape(hipStream_t s, int n, int N, const zc* H, zc* Y0, zc* Y1, int* variant,
-                      double tf[2]);
+                      double tf[3]);
 void tune_set(int n, int N, int variant);
 void tune_reset();
 

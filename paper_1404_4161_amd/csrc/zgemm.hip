@@ -196,6 +196,105 @@ __global__ void __launch_bounds__(NT, KB == 8 ? 4 : 2)
   gemm_tile<OP_N, OP_N, EPI_CHEB, KB>(g, split, tm, tn, As, Bs);
 }
 
+// Wide filter step (tile variant 2): 128 x 128 output tiles, 16 waves in a
+// 4 x 4 grid of 32 x 32 sub-tiles, K 8 deep; one workgroup per CU.  Twice
+// the reuse of each H element in LDS of the 64 x 64 tile, for wide windows.
+constexpr int WBM = 128, WBN = 128, WNT = 1024, WPA = WBM + 1, WPB = WBN + 1;
+
+__global__ void __launch_bounds__(WNT, 1) cheb_wide_kernel(GemmArgs g) {
+  __shared__ zc As[2][BK][WPA];
+  __shared__ zc Bs[2][BK][WPB];
+  const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
+  const int rows_x = (g.tiles_m - xcd + NXCD - 1) / NXCD;
+  const int ri = slot / g.tiles_n;
+  const int tn = slot - ri * g.tiles_n;
+  if (ri >= rows_x) return;
+  const int tm = xcd + NXCD * ri;
+  const int m0 = tm * WBM, n0 = tn * WBN;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave & 3, wn = wave >> 2;
+  const int lr = lane & 15, lk = lane >> 4;
+  d4 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      accI[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+  // one element of each operand per thread and stage: A (m, k) with m
+  // contiguous, B (k, n) with k contiguous
+  const int am = m0 + (t & (WBM - 1)), ak = t / WBM;
+  const int bk = t & (BK - 1), bn = n0 + t / BK;
+  const int nk = (g.K + BK - 1) / BK;
+  zc ra = zc{0.0, 0.0}, rb = zc{0.0, 0.0};
+  auto load = [&](int k0) {
+    const int ka = k0 + ak, kb = k0 + bk;
+    ra = (am < g.M && ka < g.K) ? g.A[am + (long)ka * g.lda] : zc{0.0, 0.0};
+    rb = (bn < g.N && kb < g.K) ? g.B[kb + (long)bn * g.ldb] : zc{0.0, 0.0};
+  };
+  if (nk > 0) {
+    load(0);
+    As[0][ak][t & (WBM - 1)] = ra;
+    Bs[0][bk][t / BK] = rb;
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) load((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      zc a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[cur][kk * 4 + lk][wm * 32 + i * 16 + lr];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[cur][kk * 4 + lk][wn * 32 + j * 16 + lr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) accR[i][j] = mfma(a[i].x, b[j].x, accR[i][j]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) accI[i][j] = mfma(a[i].x, b[j].y, accI[i][j]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) accR[i][j] = mfma(-a[i].y, b[j].y, accR[i][j]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) accI[i][j] = mfma(a[i].y, b[j].x, accI[i][j]);
+    }
+    if (more) {
+      As[cur ^ 1][ak][t & (WBM - 1)] = ra;
+      Bs[cur ^ 1][bk][t / BK] = rb;
+    }
+    __syncthreads();
+  }
+  // epilogue of the three-term step (FP64 MFMA output: row (l / 16) + 4 r)
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 32 + i * 16 + lk + 4 * r;
+        const int col = n0 + wn * 32 + j * 16 + lr;
+        if (row >= g.M || col >= g.N) continue;
+        const zc yc = g.Ycur[row + (long)col * g.ldyc];
+        zc out = zc{g.sa * (accR[i][j][r] - g.shift * yc.x), g.sa * (accI[i][j][r] - g.shift * yc.y)};
+        if (g.sb != 0.0) {
+          const zc yo = g.Yold[row + (long)col * g.ldyo];
+          out.x -= g.sb * yo.x;
+          out.y -= g.sb * yo.y;
+        }
+        g.C[row + (long)col * g.ldc] = out;
+      }
+}
+
 template <int OPA, int OPB, int EPI, int KB>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, int tn,
                                           zc (*As)[KB][PA], zc (*Bs)[KB][PB]) {
@@ -452,11 +551,25 @@ int current_device() {
   return dev;
 }
 
+// Variant 2 (wide tiles) exists for the unsplit filter step only.
+int launch_cheb_wide(hipStream_t s, const GemmArgs& g0) {
+  GemmArgs g = g0;
+  g.tiles_m = (g.M + WBM - 1) / WBM;
+  g.tiles_n = (g.N + WBN - 1) / WBN;
+  const int grid = ((g.tiles_m + NXCD - 1) / NXCD) * g.tiles_n * NXCD;
+  hipLaunchKernelGGL(cheb_wide_kernel, dim3(grid), dim3(WNT), 0, s, g);
+  return (int)hipGetLastError();
+}
+
 template <int EPI>
 int launch_cheb_variant(hipStream_t s, GemmArgs& g, int variant) {
+  if (variant == 2 && EPI == EPI_CHEB && g.splits == 1) return launch_cheb_wide(s, g);
   if (variant == 1) return launch<OP_N, OP_N, EPI, 16>(s, g);
   return launch<OP_N, OP_N, EPI, 8>(s, g);
 }
+
+// Variant 2 needs a window of at least this many columns.
+constexpr int WIDE_MIN_N = 256;
 
 }  // namespace
 
@@ -475,6 +588,7 @@ int filter_variant(int n, int N) {
       best = e.variant;
     }
   }
+  if (best == 2 && N < WIDE_MIN_N) best = 0;
   return best;
 }
 
@@ -499,7 +613,7 @@ void tune_reset() {
 }
 
 int tune_filter_shape(hipStream_t s, int n, int N, const zc* H, zc* Y0, zc* Y1, int* variant,
-                      double tf[2]) {
+                      double tf[3]) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess) return (int)hipErrorUnknown;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -514,14 +628,15 @@ int tune_filter_shape(hipStream_t s, int n, int N, const zc* H, zc* Y0, zc* Y1, 
   g.shift = 0.25; g.sa = 1e-3; g.sb = 0.5;
   g.tiles_m = p.tiles_m; g.tiles_n = p.tiles_n; g.total_tiles = p.total;
   g.splits = 1; g.kchunk = p.kchunk;
-  // rounds alternate the two variants (two launches each); the best round
-  // of each counts
+  // rounds alternate the variants (two launches each); the best round of
+  // each counts
   const int rounds = 4, reps = 2;
-  float best[2] = {1e30f, 1e30f};
-  int err = launch_cheb_variant<EPI_CHEB>(s, g, 0);
-  if (!err) err = launch_cheb_variant<EPI_CHEB>(s, g, 1);
+  const int nv = N >= WIDE_MIN_N ? 3 : 2;
+  float best[3] = {1e30f, 1e30f, 1e30f};
+  int err = 0;
+  for (int v = 0; v < nv && !err; ++v) err = launch_cheb_variant<EPI_CHEB>(s, g, v);
   for (int r = 0; r < rounds && !err; ++r) {
-    for (int v = 0; v < 2 && !err; ++v) {
+    for (int v = 0; v < nv && !err; ++v) {
       err = (int)hipEventRecord(e0, s);
       for (int i = 0; i < reps && !err; ++i) err = launch_cheb_variant<EPI_CHEB>(s, g, v);
       if (!err) err = (int)hipEventRecord(e1, s);
@@ -534,9 +649,13 @@ int tune_filter_shape(hipStream_t s, int n, int N, const zc* H, zc* Y0, zc* Y1, 
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (err) return err;
-  for (int v = 0; v < 2; ++v) tf[v] = 8.0 * (double)n * n * N * reps / (1e-3 * best[v]) / 1e12;
-  // the deeper stage only when clearly faster
-  *variant = tf[1] > 1.02 * tf[0] ? 1 : 0;
+  for (int v = 0; v < 3; ++v)
+    tf[v] = v < nv ? 8.0 * (double)n * n * N * reps / (1e-3 * best[v]) / 1e12 : 0.0;
+  // another variant than the default only when clearly (2 %) faster
+  int pick = 0;
+  for (int v = 1; v < nv; ++v)
+    if (tf[v] > 1.02 * tf[0] && tf[v] > tf[pick]) pick = v;
+  *variant = pick;
   tune_set(n, N, *variant);
   return 0;
 }
@@ -598,7 +717,7 @@ GemmArgs cheb_group_args(int n, int N, const zc* H, long ldh, const zc* Ycur, lo
 int cheb_step_group(hipStream_t s, const GemmArgs* list, const int* slot_begin, int count,
                     int total_slots, int variant) {
   if (count <= 0 || total_slots <= 0) return 0;
-  if (variant == 1)
+  if (variant == 1)   // (the wide variant has no grouped form: 8-deep tiles)
     hipLaunchKernelGGL(zgemm_group_cheb<16>, dim3(total_slots), dim3(NT), 0, s, list, slot_begin,
                        count);
   else

@@ -194,11 +194,12 @@ def test_defect_filter_matches_oracle_with_error_scaling_like_the_residual(delta
     assert f32 == pytest.approx(8.0 * n * n * sum(m - 1 for m in deg))
 
 
-@pytest.mark.parametrize("variant", [0, 1])
-def test_filter_tile_variants_match_oracle(variant):
-    """Both K-stage variants of the filter step give the oracle's filter
-    (the autotuner only chooses between them)."""
-    n, k = 333, 70
+@pytest.mark.parametrize("variant,k", [(0, 70), (1, 70), (2, 300)])
+def test_filter_tile_variants_match_oracle(variant, k):
+    """Every tile variant of the filter step gives the oracle's filter (the
+    autotuner only chooses between them); the wide variant runs while the
+    window is at least 256 columns wide, then the default takes over."""
+    n = 333
     lam, h = _herm_problem(n, 31)
     degrees = np.sort(np.random.default_rng(5).integers(1, 12, k)).tolist()
     y0 = _rand(n, k, 32)
@@ -215,10 +216,14 @@ def test_filter_tile_variants_match_oracle(variant):
 def test_autotuner_records_a_choice_per_shape():
     ch.chfsi_autotune_reset()
     try:
-        v, tf = ch.chfsi_autotune_filter([700, 1300], [64, 130])
-        assert v.shape == (2,) and set(v.tolist()) <= {0, 1}
-        assert np.all(tf > 0)
-        # the deeper K stage only when it is clearly (2 %) faster
-        assert np.array_equal(v, (tf[:, 1] > 1.02 * tf[:, 0]).astype(int))
+        v, tf = ch.chfsi_autotune_filter([700, 1300, 1300], [64, 130, 300])
+        assert v.shape == (3,) and set(v.tolist()) <= {0, 1, 2}
+        assert np.all(tf[:, :2] > 0) and np.all(tf[:2, 2] == 0) and tf[2, 2] > 0
+        # another variant only when it is clearly (2 %) faster than the default
+        for q in range(3):
+            if v[q] == 0:
+                assert np.all(tf[q, 1:] <= 1.02 * tf[q, 0])
+            else:
+                assert tf[q, v[q]] > 1.02 * tf[q, 0] and tf[q, v[q]] == tf[q].max()
     finally:
         ch.chfsi_autotune_reset()
