@@ -17,7 +17,8 @@
 // vectors accurate to about eps_fp32 * ||R|| / ||H|| times the filter
 // growth -- far below the residual the filter is aiming at once the
 // residuals are small.  The GEMM is the same 64x64-tile, 4-wave design as
-// the FP64 kernel, with K staged 16 deep (the LDS tile has the same size).
+// the FP64 kernel, with K staged 16 deep (the LDS tile has the same size),
+// and a 128x128-tile, 16-wave form for wide unsplit windows.
 #include "internal.h"
 
 #include <atomic>
@@ -171,6 +172,116 @@ __global__ void __launch_bounds__(NT, 4) defect_gemm(DefArgs g) {
       }
 }
 
+// Wide defect step for unsplit launches of wide windows: 128 x 128 output
+// tiles, 16 waves in a 4 x 4 grid of 32 x 32 sub-tiles, K 16 deep, one
+// workgroup per CU (each H element staged in LDS serves 128 columns).
+constexpr int WBM = 128, WBN = 128, WNT = 1024, WPA = WBM + 1, WPB = WBN + 1;
+constexpr int WIDE_MIN_N = 384;
+
+__global__ void __launch_bounds__(WNT, 1) defect_gemm_wide(DefArgs g) {
+  __shared__ cf As[2][BK][WPA];
+  __shared__ cf Bs[2][BK][WPB];
+  const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
+  const int rows_x = (g.tiles_m - xcd + NXCD - 1) / NXCD;
+  const int ri = slot / g.tiles_n;
+  const int tn = slot - ri * g.tiles_n;
+  if (ri >= rows_x) return;
+  const int tm = xcd + NXCD * ri;
+  const int m0 = tm * WBM, n0 = tn * WBN;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave & 3, wn = wave >> 2;
+  const int lr = lane & 15, lk = lane >> 4;
+  f4 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      accI[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  // two elements of each operand per thread and stage
+  constexpr int LE = BK * WBM / WNT;
+  cf ra[LE], rb[LE];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < LE; ++i) {
+      const int idx = t + i * WNT;
+      const int m = m0 + idx % WBM, k = k0 + idx / WBM;          // A: m contiguous
+      ra[i] = (m < g.M && k < g.K) ? g.A[m + (long)k * g.lda] : cf{0.f, 0.f};
+      const int kb = k0 + idx % BK, n = n0 + idx / BK;           // B: k contiguous
+      rb[i] = (n < g.N && kb < g.K) ? g.Ecur[kb + (long)n * g.lde] : cf{0.f, 0.f};
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < LE; ++i) {
+      const int idx = t + i * WNT;
+      As[buf][idx / WBM][idx % WBM] = ra[i];
+      Bs[buf][idx % BK][idx / BK] = rb[i];
+    }
+  };
+  const int nk = (g.K + BK - 1) / BK;
+  if (nk > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) load((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 4; ++kk) {
+      cf a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[cur][kk * 4 + lk][wm * 32 + i * 16 + lr];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[cur][kk * 4 + lk][wn * 32 + j * 16 + lr];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) accR[i][j] = mfma32(a[i].x, b[j].x, accR[i][j]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) accI[i][j] = mfma32(a[i].x, b[j].y, accI[i][j]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) accR[i][j] = mfma32(-a[i].y, b[j].y, accR[i][j]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) accI[i][j] = mfma32(a[i].y, b[j].x, accI[i][j]);
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+  }
+  // FP32 MFMA output: row 4 (l / 16) + r, column l % 16
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm * 32 + i * 16 + 4 * lk + r;
+        const int col = n0 + wn * 32 + j * 16 + lr;
+        if (row >= g.M || col >= g.N) continue;
+        const cf ec = g.Ecur[row + (long)col * g.lde];
+        const cf rr = g.R[row + (long)col * g.ldr];
+        const float crj = g.cr[col];
+        cf out = cf{g.sa * (accR[i][j][r] - g.shift * ec.x) + crj * rr.x,
+                    g.sa * (accI[i][j][r] - g.shift * ec.y) + crj * rr.y};
+        if (g.sb != 0.f) {
+          const cf eo = g.Eold[row + (long)col * g.lde];
+          out.x -= g.sb * eo.x;
+          out.y -= g.sb * eo.y;
+        }
+        g.Eout[row + (long)col * g.lde] = out;
+      }
+}
+
 __global__ void defect_reduce(int M, int N, int splits, const cf* part, const cf* Ecur,
                               const cf* Eold, cf* Eout, long lde, const cf* R, long ldr,
                               const float* cr, float shift, float sa, float sb) {
@@ -314,6 +425,14 @@ int defect_step(hipStream_t s, int n, int N, const void* H32, const void* Ecur, 
   g.kchunk = chunk;
   g.splits = (n + chunk - 1) / chunk;
   const int grid = ((g.splits * g.tiles_m + NXCD - 1) / NXCD) * g.tiles_n * NXCD;
+  if (g.splits == 1 && N >= WIDE_MIN_N) {
+    DefArgs w = g;
+    w.tiles_m = (n + WBM - 1) / WBM;
+    w.tiles_n = (N + WBN - 1) / WBN;
+    const int wgrid = ((w.tiles_m + NXCD - 1) / NXCD) * w.tiles_n * NXCD;
+    hipLaunchKernelGGL(defect_gemm_wide, dim3(wgrid), dim3(WNT), 0, s, w);
+    return (int)hipGetLastError();
+  }
   if (g.splits == 1) {
     hipLaunchKernelGGL(defect_gemm<0>, dim3(grid), dim3(NT), 0, s, g);
     return (int)hipGetLastError();
