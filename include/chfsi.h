@@ -245,8 +245,9 @@ int chfsi_solve(int n, int nev, int nex,
  * self-consistency step, Sec. 1 / Sec. 4: every k-point gives its own
  * sequence): `count` problems, each with the arguments of chfsi_solve given
  * by index q (arrays of count entries), run their outer loops in lockstep.
- * Every loop's FP64 filters of all problems share one launch per recurrence
- * step (a grouped MFMA kernel over all problems' tiles) on `stream`; the
+ * The problems form two groups that alternate on `stream`; every loop's
+ * FP64 filters of a group share one launch per recurrence step (a grouped
+ * MFMA kernel over all its problems' tiles) on `stream`; the
  * per-problem phases (reduction, Lanczos, QR, Rayleigh-Ritz, FP32 defect
  * filters) run on up to 8 internal streams, each driven by a host thread of
  * the library with its own rocSOLVER handle, so that different problems'

@@ -1468,111 +1468,155 @@ int solve_impl(int n, int nev, int nex, const zc* A, int lda, const zc* B, int l
   return S.finish();
 }
 
-// FP64 filters (Alg. 2) of several solves in lockstep: step i of every
-// solve whose highest degree exceeds i runs in one grouped launch.  The
-// launch arguments of all steps are built on the host and uploaded once;
-// with `graph` the step launches are captured as one HIP graph and
-// launched as a whole.  Device time is shared out by flops.
-int filter_group(hipStream_t s, const std::vector<Solve*>& jobs, GemmArgs* dlist, int* dslots,
-                 size_t cap_entries, size_t cap_slots, bool graph, hipEvent_t e0, hipEvent_t e1) {
-  const int count = (int)jobs.size();
-  int steps = 0;
-  for (Solve* j : jobs) steps = std::max(steps, j->msort.back());
-  std::vector<GemmArgs> list;
-  std::vector<int> slot_begin, step_entry(steps + 1, 0), step_slot(steps + 1, 0), step_count(steps),
-      step_total(steps);
-  std::vector<double> sig(count), sig1(count), fl(count, 0.0);
-  std::vector<int> first(count, 0);
-  for (int q = 0; q < count; ++q) {
-    Solve& S = *jobs[q];
-    sig1[q] = S.e / (S.gamma - S.c);
-    sig[q] = sig1[q];
-    while (first[q] < S.ka && S.msort[first[q]] <= 1) ++first[q];
+// FP64 filters (Alg. 2) of a group of solves: step i of every solve whose
+// highest degree exceeds i runs in one grouped launch.  launch() builds the
+// launch arguments of all steps in pinned host memory, copies them to the
+// device and queues the steps on the stream (optionally captured as one HIP
+// graph) without waiting; finish() waits for them and shares the device
+// time out by flops.
+struct FilterGroup {
+  GemmArgs* dlist = nullptr;   // device argument lists (batch workspace)
+  int* dslots = nullptr;
+  GemmArgs* hlist = nullptr;   // pinned staging
+  int* hslots = nullptr;
+  size_t cap_entries = 0, cap_slots = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<Solve*> jobs;
+  std::vector<double> fl;
+  bool pending = false;
+
+  ~FilterGroup() {
+    if (gexec) hipGraphExecDestroy(gexec);
+    if (graph) hipGraphDestroy(graph);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (hlist) hipHostFree(hlist);
+    if (hslots) hipHostFree(hslots);
   }
-  for (int i = 0; i < steps; ++i) {
-    step_entry[i] = (int)list.size();
-    step_slot[i] = (int)slot_begin.size();
-    int total = 0, cnt = 0;
-    slot_begin.push_back(0);
+
+  int init(GemmArgs* dl, int* ds, size_t ce, size_t cs) {
+    dlist = dl;
+    dslots = ds;
+    cap_entries = ce;
+    cap_slots = cs;
+    CK(hipHostMalloc((void**)&hlist, sizeof(GemmArgs) * std::max<size_t>(ce, 1)));
+    CK(hipHostMalloc((void**)&hslots, sizeof(int) * std::max<size_t>(cs, 1)));
+    CK(hipEventCreate(&e0));
+    CK(hipEventCreate(&e1));
+    return CHFSI_OK;
+  }
+
+  int launch(hipStream_t s, const std::vector<Solve*>& js, bool use_graph) {
+    jobs = js;
+    const int count = (int)jobs.size();
+    int steps = 0;
+    for (Solve* j : jobs) steps = std::max(steps, j->msort.back());
+    std::vector<int> step_entry(steps + 1, 0), step_slot(steps + 1, 0), step_count(steps),
+        step_total(steps);
+    std::vector<double> sig(count), sig1(count);
+    std::vector<int> first(count, 0);
+    fl.assign(count, 0.0);
     for (int q = 0; q < count; ++q) {
       Solve& S = *jobs[q];
-      if (S.msort.back() <= i) continue;
-      int sl = 0;
-      const double nn = (double)S.n * S.n;
-      if (i == 0) {
-        // Y_1 = (sigma_1 / e)(H Y_0 - c Y_0)
-        list.push_back(cheb_group_args(S.n, S.ka, S.H, S.ldh, S.b.P0, S.ld, nullptr, S.ld, S.b.P1,
-                                       S.ld, S.c, sig1[q] / S.e, 0.0, &sl));
-        fl[q] += 8.0 * nn * S.ka;
-      } else {
-        const double sn = 1.0 / (2.0 / sig1[q] - sig[q]);
-        zc* cur = (i & 1) ? S.b.P1 : S.b.P0;
-        zc* old = (i & 1) ? S.b.P0 : S.b.P1;
-        const int cols = S.ka - first[q];
-        const size_t off = (size_t)first[q] * S.ld;
-        list.push_back(cheb_group_args(S.n, cols, S.H, S.ldh, cur + off, S.ld, old + off, S.ld,
-                                       old + off, S.ld, S.c, 2.0 * sn / S.e, sn * sig[q], &sl));
-        fl[q] += 8.0 * nn * cols;
-        sig[q] = sn;
-        while (first[q] < S.ka && S.msort[first[q]] <= i + 1) ++first[q];
+      sig1[q] = S.e / (S.gamma - S.c);
+      sig[q] = sig1[q];
+      while (first[q] < S.ka && S.msort[first[q]] <= 1) ++first[q];
+    }
+    size_t ne = 0, ns = 0;
+    for (int i = 0; i < steps; ++i) {
+      step_entry[i] = (int)ne;
+      step_slot[i] = (int)ns;
+      int total = 0, cnt = 0;
+      if (ns >= cap_slots) return CHFSI_INVALID_ARG;
+      hslots[ns++] = 0;
+      for (int q = 0; q < count; ++q) {
+        Solve& S = *jobs[q];
+        if (S.msort.back() <= i) continue;
+        if (ne >= cap_entries || ns >= cap_slots) return CHFSI_INVALID_ARG;
+        int sl = 0;
+        const double nn = (double)S.n * S.n;
+        if (i == 0) {
+          // Y_1 = (sigma_1 / e)(H Y_0 - c Y_0)
+          hlist[ne++] = cheb_group_args(S.n, S.ka, S.H, S.ldh, S.b.P0, S.ld, nullptr, S.ld,
+                                        S.b.P1, S.ld, S.c, sig1[q] / S.e, 0.0, &sl);
+          fl[q] += 8.0 * nn * S.ka;
+        } else {
+          const double sn = 1.0 / (2.0 / sig1[q] - sig[q]);
+          zc* cur = (i & 1) ? S.b.P1 : S.b.P0;
+          zc* old = (i & 1) ? S.b.P0 : S.b.P1;
+          const int cols = S.ka - first[q];
+          const size_t off = (size_t)first[q] * S.ld;
+          hlist[ne++] = cheb_group_args(S.n, cols, S.H, S.ldh, cur + off, S.ld, old + off, S.ld,
+                                        old + off, S.ld, S.c, 2.0 * sn / S.e, sn * sig[q], &sl);
+          fl[q] += 8.0 * nn * cols;
+          sig[q] = sn;
+          while (first[q] < S.ka && S.msort[first[q]] <= i + 1) ++first[q];
+        }
+        S.launches += 1;
+        total += sl;
+        hslots[ns++] = total;
+        ++cnt;
       }
-      S.launches += 1;
-      total += sl;
-      slot_begin.push_back(total);
-      ++cnt;
+      step_count[i] = cnt;
+      step_total[i] = total;
     }
-    step_count[i] = cnt;
-    step_total[i] = total;
-  }
-  if (list.size() > cap_entries || slot_begin.size() > cap_slots) return CHFSI_INVALID_ARG;
-  CK(hipMemcpyAsync(dlist, list.data(), sizeof(GemmArgs) * list.size(), hipMemcpyHostToDevice, s));
-  CK(hipMemcpyAsync(dslots, slot_begin.data(), sizeof(int) * slot_begin.size(),
-                    hipMemcpyHostToDevice, s));
-  CK(hipStreamSynchronize(s));
-  // one tile variant per grouped launch: the tuned choice carrying the most
-  // flops among the problems
-  double w[2] = {0.0, 0.0};
-  for (int q = 0; q < count; ++q) w[filter_variant(jobs[q]->n, jobs[q]->ka) == 1 ? 1 : 0] += fl[q];
-  const int variant = w[1] > w[0] ? 1 : 0;
-  CK(hipEventRecord(e0, s));
-  if (graph) {
-    hipGraph_t g = nullptr;
-    hipGraphExec_t ge = nullptr;
-    CK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    int err = 0;
-    for (int i = 0; i < steps && !err; ++i)
-      err = cheb_step_group(s, dlist + step_entry[i], dslots + step_slot[i], step_count[i],
-                            step_total[i], variant);
-    const int cap_err = (int)hipStreamEndCapture(s, &g);
-    if (err || cap_err) {
-      if (g) hipGraphDestroy(g);
-      return CHFSI_DEVICE_ERROR;
+    CK(hipMemcpyAsync(dlist, hlist, sizeof(GemmArgs) * ne, hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(dslots, hslots, sizeof(int) * ns, hipMemcpyHostToDevice, s));
+    // one tile variant per grouped launch: the tuned choice carrying the
+    // most flops among the problems
+    double w[2] = {0.0, 0.0};
+    for (int q = 0; q < count; ++q)
+      w[filter_variant(jobs[q]->n, jobs[q]->ka) == 1 ? 1 : 0] += fl[q];
+    const int variant = w[1] > w[0] ? 1 : 0;
+    CK(hipEventRecord(e0, s));
+    if (use_graph) {
+      CK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      int err = 0;
+      for (int i = 0; i < steps && !err; ++i)
+        err = cheb_step_group(s, dlist + step_entry[i], dslots + step_slot[i], step_count[i],
+                              step_total[i], variant);
+      const int cap_err = (int)hipStreamEndCapture(s, &graph);
+      if (err || cap_err) return CHFSI_DEVICE_ERROR;
+      CK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+      CK(hipGraphLaunch(gexec, s));
+    } else {
+      for (int i = 0; i < steps; ++i)
+        CK(cheb_step_group(s, dlist + step_entry[i], dslots + step_slot[i], step_count[i],
+                           step_total[i], variant));
     }
-    err = (int)hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    if (!err) err = (int)hipGraphLaunch(ge, s);
-    if (!err) err = (int)hipStreamSynchronize(s);
-    if (ge) hipGraphExecDestroy(ge);
-    hipGraphDestroy(g);
-    if (err) return CHFSI_DEVICE_ERROR;
-  } else {
-    for (int i = 0; i < steps; ++i)
-      CK(cheb_step_group(s, dlist + step_entry[i], dslots + step_slot[i], step_count[i],
-                         step_total[i], variant));
+    CK(hipEventRecord(e1, s));
+    pending = true;
+    return CHFSI_OK;
   }
-  CK(hipEventRecord(e1, s));
-  CK(hipEventSynchronize(e1));
-  float ms = 0.f;
-  CK(hipEventElapsedTime(&ms, e0, e1));
-  double ftot = 0.0;
-  for (double f : fl) ftot += f;
-  for (int q = 0; q < count; ++q) {
-    jobs[q]->filter_flops += fl[q];
-    if (ftot > 0.0) jobs[q]->filter_sec += 1e-3 * ms * fl[q] / ftot;
-  }
-  return CHFSI_OK;
-}
 
-// Launch-argument capacity of the batch workspace for `count` solves.
+  int finish() {
+    if (!pending) return CHFSI_OK;
+    pending = false;
+    CK(hipEventSynchronize(e1));
+    if (gexec) {
+      hipGraphExecDestroy(gexec);
+      gexec = nullptr;
+    }
+    if (graph) {
+      hipGraphDestroy(graph);
+      graph = nullptr;
+    }
+    float ms = 0.f;
+    CK(hipEventElapsedTime(&ms, e0, e1));
+    double ftot = 0.0;
+    for (double f : fl) ftot += f;
+    for (size_t q = 0; q < jobs.size(); ++q) {
+      jobs[q]->filter_flops += fl[q];
+      if (ftot > 0.0) jobs[q]->filter_sec += 1e-3 * ms * fl[q] / ftot;
+    }
+    return CHFSI_OK;
+  }
+};
+
+// Launch-argument capacity of the batch workspace for `count` solves (two
+// groups).
 void batch_caps(int count, const chfsi_opts& o, size_t* entries, size_t* slots) {
   const size_t steps = (size_t)std::max(std::max(o.deg0, o.deg_max), 1);
   *entries = steps * (size_t)count;
@@ -1583,20 +1627,24 @@ size_t batch_bytes(int count, const chfsi_opts& o) {
   size_t entries = 0, slots = 0;
   batch_caps(count, o, &entries, &slots);
   Carver c(nullptr);
-  c.take<GemmArgs>(entries);
-  c.take<int>(slots);
+  for (int g = 0; g < 2; ++g) {
+    c.take<GemmArgs>(entries);
+    c.take<int>(slots);
+  }
   return c.off + ALIGN;
 }
 
-// Solves in lockstep.  Every problem runs on one of up to 8 worker streams,
-// driven by a host thread of its own (with its own rocSOLVER handle), so
-// the per-problem phases -- reduction, Lanczos, QR, Rayleigh-Ritz with its
-// latency-bound reduced eigensolve, locking -- of different problems
-// overlap on the GPU.  Every loop: begin_loop on all unfinished problems
-// (FP32 defect filters run right there, on the problem's stream); the FP64
-// filters of all problems in grouped launches on the caller's stream, after
-// the worker streams' work (events); then end_loop on all.  status[q]
-// receives each problem's result.
+// Solves of a batch, run as two pipelined groups.  Every problem runs on one
+// of up to 8 worker streams, driven by a host thread of its group with its
+// own rocSOLVER handle, so the per-problem phases -- reduction, Lanczos, QR,
+// Rayleigh-Ritz with its latency-bound reduced eigensolve, locking -- of
+// different problems overlap on the GPU.  Each group runs its loops in
+// lockstep: begin_loop on its unfinished problems (FP32 defect filters run
+// right there, on the problem's stream), its FP64 filters in grouped
+// launches on the caller's stream, end_loop.  The two groups alternate on
+// the caller's stream, so one group's QR / Rayleigh-Ritz / locking run while
+// the other group's filter occupies the matrix cores.  With `serial`, one
+// group, one stream, no threads.  status[q] receives each problem's result.
 constexpr int BATCH_WORKERS = 8;
 
 int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void* bwork,
@@ -1605,12 +1653,24 @@ int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void
   size_t cap_entries = 0, cap_slots = 0;
   batch_caps(count, S[0]->o, &cap_entries, &cap_slots);
   if (bbytes < batch_bytes(count, S[0]->o)) return CHFSI_INVALID_ARG;
-  Carver cv(bwork);
-  GemmArgs* dlist = cv.take<GemmArgs>(cap_entries);
-  int* dslots = cv.take<int>(cap_slots);
   int dev = 0;
   CK(hipGetDevice(&dev));
+  const int ngroups = (serial || count < 2) ? 1 : 2;
   const int T = serial ? 1 : std::min(count, BATCH_WORKERS);
+
+  // groups: problems by decreasing n dealt alternately; worker threads and
+  // streams split between the groups
+  std::vector<int> byn(count);
+  std::iota(byn.begin(), byn.end(), 0);
+  std::stable_sort(byn.begin(), byn.end(), [&](int a, int b) { return S[a]->n > S[b]->n; });
+  std::vector<std::vector<int>> members(ngroups);
+  for (int i = 0; i < count; ++i) members[i % ngroups].push_back(byn[i]);
+  std::vector<int> t0(ngroups), tn(ngroups);
+  for (int g = 0; g < ngroups; ++g) {
+    tn[g] = ngroups == 1 ? T : std::max(1, T / 2);
+    t0[g] = g * (T / ngroups);
+    tn[g] = std::min(tn[g], (int)members[g].size());
+  }
 
   // resources of the call, released on every path
   struct Res {
@@ -1625,30 +1685,40 @@ int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void
   } r;
   r.st.assign(T, nullptr);
   r.h.assign(T, nullptr);
-  r.ev.assign(T + 3, nullptr);
+  r.ev.assign(T + 1, nullptr);
   for (int t = 0; t < T; ++t) {
     CK(hipStreamCreateWithFlags(&r.st[t], hipStreamNonBlocking));
     if (rocblas_create_handle(&r.h[t]) != rocblas_status_success) return CHFSI_DEVICE_ERROR;
   }
   for (auto& e : r.ev) CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  hipEvent_t ev_main = r.ev[T], e0 = nullptr, e1 = nullptr;
-  CK(hipEventCreate(&e0));
-  CK(hipEventCreate(&e1));
-  r.ev[T + 1] = e0;
-  r.ev[T + 2] = e1;
+  hipEvent_t ev_main = r.ev[T];
+  std::vector<FilterGroup> fg(ngroups);
+  Carver cv(bwork);
+  for (int g = 0; g < ngroups; ++g) {
+    GemmArgs* dl = cv.take<GemmArgs>(cap_entries);
+    int* ds = cv.take<int>(cap_slots);
+    CKS(fg[g].init(dl, ds, cap_entries, cap_slots));
+  }
   // inputs written on the caller's stream are visible to the workers
   CK(hipEventRecord(ev_main, s));
   for (int t = 0; t < T; ++t) CK(hipStreamWaitEvent(r.st[t], ev_main, 0));
-  for (int q = 0; q < count; ++q) S[q]->s = r.st[q % T];
+  std::vector<int> thread_of(count, 0);
+  for (int g = 0; g < ngroups; ++g)
+    for (size_t i = 0; i < members[g].size(); ++i) {
+      const int q = members[g][i];
+      thread_of[q] = t0[g] + (int)(i % tn[g]);
+      S[q]->s = r.st[thread_of[q]];
+    }
 
   status.assign(count, CHFSI_OK);
   std::vector<char> failed(count, 0), active(count, 0);
-  // run fn(q) for every selected problem, problems q = t mod T on worker t
-  auto parallel = [&](auto fn) {
+  // run fn(q) for the group's problems, each on its worker's host thread
+  auto parallel = [&](int g, auto fn) {
     auto work = [&](int t) {
       hipSetDevice(dev);
       tl_handle = r.h[t];
-      for (int q = t; q < count; q += T) {
+      for (int q : members[g]) {
+        if (thread_of[q] != t) continue;
         try {
           fn(q);
         } catch (const std::bad_alloc&) {
@@ -1666,16 +1736,14 @@ int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void
       return;
     }
     std::vector<std::thread> th;
-    for (int t = 0; t < T; ++t) th.emplace_back(work, t);
+    for (int t = t0[g]; t < t0[g] + tn[g]; ++t) th.emplace_back(work, t);
     for (auto& x : th) x.join();
   };
-
-  parallel([&](int q) {
-    status[q] = S[q]->setup();
-    if (status[q] != CHFSI_OK) failed[q] = 1;
-  });
-  for (;;) {
-    parallel([&](int q) {
+  // begin_loop on the group's unfinished problems, then its grouped filter
+  // queued on the caller's stream after their workers' work; returns whether
+  // the group still has work
+  auto begin_and_launch = [&](int g, bool& live) -> int {
+    parallel(g, [&](int q) {
       active[q] = 0;
       if (failed[q] || S[q]->done) return;
       status[q] = S[q]->begin_loop();
@@ -1687,31 +1755,55 @@ int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void
       if (!S[q]->done) active[q] = 1;
     });
     std::vector<Solve*> fp64;
-    bool any = false;
-    for (int q = 0; q < count; ++q) {
+    live = false;
+    for (int q : members[g]) {
       if (!active[q]) continue;
-      any = true;
+      live = true;
       if (!S[q]->use32 && S[q]->ka > 0) fp64.push_back(S[q].get());
     }
-    if (!any) break;
-    if (!fp64.empty()) {
-      for (int t = 0; t < T; ++t) {
-        CK(hipEventRecord(r.ev[t], r.st[t]));
-        CK(hipStreamWaitEvent(s, r.ev[t], 0));
-      }
-      CKS(filter_group(s, fp64, dlist, dslots, cap_entries, cap_slots, graph, e0, e1));
-      CK(hipEventRecord(ev_main, s));
-      for (int t = 0; t < T; ++t) CK(hipStreamWaitEvent(r.st[t], ev_main, 0));
+    if (fp64.empty()) return CHFSI_OK;
+    for (int t = t0[g]; t < t0[g] + tn[g]; ++t) {
+      CK(hipEventRecord(r.ev[t], r.st[t]));
+      CK(hipStreamWaitEvent(s, r.ev[t], 0));
     }
-    parallel([&](int q) {
-      if (!active[q]) return;
-      status[q] = S[q]->end_loop();
+    CKS(fg[g].launch(s, fp64, graph));
+    // the group's workers continue after its filter
+    for (int t = t0[g]; t < t0[g] + tn[g]; ++t) CK(hipStreamWaitEvent(r.st[t], fg[g].e1, 0));
+    return CHFSI_OK;
+  };
+
+  for (int g = 0; g < ngroups; ++g)
+    parallel(g, [&](int q) {
+      status[q] = S[q]->setup();
       if (status[q] != CHFSI_OK) failed[q] = 1;
     });
+  std::vector<char> live(ngroups, 0);
+  for (int g = 0; g < ngroups; ++g) {
+    bool l = false;
+    CKS(begin_and_launch(g, l));
+    live[g] = l;
   }
-  parallel([&](int q) {
-    if (!failed[q]) status[q] = S[q]->finish();
-  });
+  for (;;) {
+    bool any = false;
+    for (int g = 0; g < ngroups; ++g) {
+      if (!live[g]) continue;
+      CKS(fg[g].finish());
+      parallel(g, [&](int q) {
+        if (!active[q]) return;
+        status[q] = S[q]->end_loop();
+        if (status[q] != CHFSI_OK) failed[q] = 1;
+      });
+      bool l = false;
+      CKS(begin_and_launch(g, l));
+      live[g] = l;
+      any = any || l;
+    }
+    if (!any) break;
+  }
+  for (int g = 0; g < ngroups; ++g)
+    parallel(g, [&](int q) {
+      if (!failed[q]) status[q] = S[q]->finish();
+    });
   // outputs complete on the workers before the caller's stream goes on
   for (int t = 0; t < T; ++t) {
     CK(hipEventRecord(r.ev[t], r.st[t]));

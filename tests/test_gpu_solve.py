@@ -123,6 +123,36 @@ def test_solve_edge_cases_tiny_and_full_block():
     assert np.abs(lam[:60] - lamv[:60]).max() < 1e-10 * 5
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_degenerate_and_clustered_spectrum(precision):
+    """Exactly repeated eigenvalues (multiplicity 4 at the bottom, 3 at the
+    edge of the wanted set, a pair split across nev) and a tight cluster:
+    the eigenvalues match the prescribed spectrum, and the returned vectors
+    of a repeated eigenvalue span its eigenspace (residuals + B-orthonormality)."""
+    n, nev, nex = 300, 20, 6
+    g = np.random.default_rng(17)
+    lamv = np.sort(np.concatenate([
+        [-20.0] * 4,                       # multiplicity 4 at the bottom
+        np.linspace(-19.5, -17.0, 11),
+        [-16.5] * 3,                       # multiplicity 3 inside the wanted set
+        [-16.0, -16.0],                    # a pair split by nev (indices 19, 20)
+        -15.9 + 1e-9 * np.arange(4),       # a cluster 1e-9 wide
+        g.uniform(-14.0, 30.0, n - 24)]))
+    a = gen.prescribed_problem(n, lamv, 18)
+    opts = _opts(precision=precision)
+    st, lam, xd, info = ch.chfsi_solve(dev(a), None, nev, nex, 1e-10, opts=opts)
+    assert st == 0
+    assert np.abs(lam[:nev] - lamv[:nev]).max() <= RTOL * np.abs(lamv[:nev]).min()
+    _check_pairs(a, None, lam, host(xd), nev, 1e-10, info["norm_h"])
+    # the 4-fold eigenspace is spanned: A = Q diag(lamv) Q^H, so it is the
+    # span of the first 4 columns of the generator's Q
+    x4 = host(xd)[:, :4]
+    q = gen._NumpyBackend().qr_unitary(gen.complex_gaussian(
+        np.random.Generator(np.random.PCG64(18)), n, n))
+    u4 = q[:, :4]
+    assert np.abs(u4 @ (u4.conj().T @ x4) - x4).max() < 1e-8
+
+
 def test_solve_fixed_degree_and_literal_alpha_modes():
     conf = gen.small_config("m", 250, 10, 4, False, length=1, cfg=90)
     a = next(gen.Sequence(conf).problems())[1]
