@@ -232,7 +232,7 @@ def main():
     ap.add_argument("--steps", type=int, default=9)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gen-n8000",
-                    choices=["gen-n8000", "std-n1000", "kpoints"])
+                    choices=["gen-n8000", "std-n1000", "std-n20000", "kpoints"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-degree", type=int, default=40)
     ap.add_argument("--filter-only", action="store_true",
@@ -277,7 +277,9 @@ def main():
                                   conf.deg0)
     dev = "cuda:0"
     t0 = time.perf_counter()
-    seq = gen.Sequence(conf, kind="torch", device=dev)
+    # large problems draw their Gaussian matrices on the GPU (much faster)
+    draw = "device" if conf.n > 10000 else "host"
+    seq = gen.Sequence(conf, kind="torch", device=dev, draw=draw)
     problems = []
     for l, a in seq.problems():
         problems.append(a)
@@ -314,7 +316,7 @@ def main():
         from paper_1404_4161_amd import learned
         t0 = time.perf_counter()
         tconf = gen.variant(conf, conf.cfg + 100)
-        tseq = gen.Sequence(tconf, kind="torch", device=dev)
+        tseq = gen.Sequence(tconf, kind="torch", device=dev, draw=draw)
         tprobs = [a.clone() for l, a in tseq.problems() if l <= min(tconf.length, total)]
         buf = learned.LogBuffer(400_000)
         tw = torch.empty(wb, dtype=torch.uint8, device=dev)
@@ -487,7 +489,9 @@ def main():
         del problems
         torch.cuda.empty_cache()
         log("timing the CPU oracle's filter on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(a1_host, k, args.cpu_degree)
+        # a bounded sample: about k (8000 / n)^2 columns (all of them at n = 8000)
+        cols = max(16, min(k, int(round(k * (8000.0 / n) ** 2))))
+        out["cpu_baseline"] = cpu_baseline(a1_host, cols, args.cpu_degree)
     print(json.dumps(out), flush=True)
 
 
