@@ -201,6 +201,7 @@ def kpoints(args):
                 "batched-fp64-graph": ("batched fp64 graph", 0, True, True),
                 "sequential-fp64": ("sequential fp64", 0, False, False),
                 "batched-mixed": ("batched mixed", 1, True, False),
+                "batched-mixed-bf16": ("batched mixed bf16", 2, True, False),
                 "batched-fp64-serial": ("batched fp64 serial", 0, True, False, True)}
     chosen = args.kp_variants.split(",")
     for key in chosen:
@@ -243,9 +244,11 @@ def main():
     ap.add_argument("--kp-count", type=int, default=32,
                     help="k-point workload: number of problems (32 in the full workload)")
     ap.add_argument("--kp-variants", default="batched-fp64,batched-fp64-graph,sequential-fp64,"
-                                             "batched-mixed")
+                                             "batched-mixed,batched-mixed-bf16")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training the degree network and the learned-degree sequences")
+    ap.add_argument("--no-bf16", action="store_true",
+                    help="skip the sequences with BF16-split defect steps (precision 2)")
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--no-lambda0", action="store_true",
                     help="warm-start from the previous Ritz vectors only (one extra QR + "
@@ -295,7 +298,10 @@ def main():
     opts0 = ch.chfsi_default_opts()
     opts1 = ch.chfsi_default_opts()
     opts1.precision = 1
-    wb = max(ch.chfsi_workspace_bytes(n, nev, nex, B is not None, o) for o in (opts0, opts1))
+    opts2 = ch.chfsi_default_opts()
+    opts2.precision = 2
+    wb = max(ch.chfsi_workspace_bytes(n, nev, nex, B is not None, o)
+             for o in (opts0, opts1, opts2))
     work = torch.empty(wb, dtype=torch.uint8, device=dev)
     X = ch.colmajor(torch.empty((n, k), dtype=torch.complex128, device=dev))
 
@@ -375,20 +381,26 @@ def main():
 
     infos, walls, lams64, elapsed = run_sequence(opts0, "fp64")
     minfos, mwalls, lams32, melapsed = run_sequence(opts1, "mixed")
-    learned_runs = {}
+    # further variants: (label, precision, degree_mode, first_rule).  Mixed
+    # precision keeps deg0 in the first loop of a warm start (FP32 defect
+    # form); FP64 takes the first loop's degrees from X0's residuals.
+    # degree_mode 2: the learned network; 3: Multiple Optimization (each
+    # eigenvector's speed measured earlier in the sequence, no training).
+    plan = []
     if blob is not None:
-        # mixed: the first loop of a warm start stays at deg0 (FP32 defect
-        # form); FP64: the first loop's degrees come from X0's residuals
-        for label, prec, fr in (("mixed+learned", 1, 0), ("fp64+learned", 0, 1)):
-            o = ch.chfsi_default_opts()
-            o.precision, o.degree_mode, o.first_rule = prec, 2, fr
-            learned_runs[label] = run_sequence(o, label)
-    # Multiple Optimization: degrees calibrated by each eigenvector's speed
-    # measured earlier in the sequence (no training)
-    for label, prec, fr in (("mixed+seqcal", 1, 0), ("fp64+seqcal", 0, 1)):
+        plan += [("mixed+learned", 1, 2, 0), ("fp64+learned", 0, 2, 1)]
+    plan += [("mixed+seqcal", 1, 3, 0), ("fp64+seqcal", 0, 3, 1)]
+    if not args.no_bf16:
+        plan += [("mixed-bf16", 2, 0, 0), ("mixed-bf16+seqcal", 2, 3, 0)]
+        if blob is not None:
+            plan.append(("mixed-bf16+learned", 2, 2, 0))
+    learned_runs = {}
+    variant_modes = {}
+    for label, prec, mode, fr in plan:
         o = ch.chfsi_default_opts()
-        o.precision, o.degree_mode, o.first_rule = prec, 3, fr
+        o.precision, o.degree_mode, o.first_rule = prec, mode, fr
         learned_runs[label] = run_sequence(o, label)
+        variant_modes[label] = (prec, mode)
 
     flops = sum(i["filter_flops"] for i in infos)
     fsec = sum(i["filter_seconds"] for i in infos)
@@ -458,15 +470,25 @@ def main():
             "max_rel_eig_diff_vs_fp64_per_step": eig_diff,
         },
     }
+    precision_text = {
+        0: "FP64 filter",
+        1: "FP32 defect filter where the residuals allow",
+        2: ("FP32 defect filter where the residuals allow; its early steps with BF16-split "
+            "products (3 BF16 MFMA products, FP32 accumulate) where their rounding is damped "
+            "enough"),
+    }
+    degree_text = {
+        0: "analytic rule (Sec. 3.1.1)",
+        2: "learned (network trained on logs of another sequence; rule fallback)",
+        3: "sequence-calibrated (speeds measured earlier in the sequence; rule floor)",
+    }
     for label, (linfos, lwalls, llams, lelapsed) in learned_runs.items():
         lph = np.sum([i["step_seconds"] for i in linfos], axis=0) / args.steps
+        prec, mode = variant_modes[label]
         out[label] = {
-            "precision": "FP32 defect filter where the residuals allow" if label.startswith("mixed")
-                         else "FP64 filter",
-            "degrees": ("learned (network trained on logs of another sequence; rule fallback)"
-                        if "learned" in label else
-                        "sequence-calibrated (speeds measured earlier in the sequence; rule floor)"),
-            "first_loop_degrees": ("deg0" if label.startswith("mixed") else
+            "precision": precision_text[prec],
+            "degrees": degree_text[mode],
+            "first_loop_degrees": ("deg0" if prec >= 1 else
                                    "from the residuals of X0 (one extra product H X0)"),
             "ms_per_step": round(1e3 * lelapsed / args.steps, 3),
             "s_per_sequence_step_median": round(statistics.median(lwalls), 4),
@@ -481,6 +503,14 @@ def main():
             "max_rel_eig_diff_vs_fp64_per_step": [
                 float(np.max(np.abs(a - b) / np.abs(a))) for a, b in zip(lams64, llams)],
         }
+        if prec == 2:
+            f16 = sum(i["filter_flops_bf16"] for i in linfos)
+            f32 = sum(i["filter_flops_fp32"] for i in linfos)
+            out[label]["bf16_steps_per_step"] = [i["filter_steps_bf16"] for i in linfos]
+            out[label]["bf16_share_of_defect_flops"] = round(f16 / max(f16 + f32, 1.0), 3)
+            lsec = sum(i["filter_seconds"] for i in linfos)
+            out[label]["filter_effective_tflops"] = round(
+                sum(i["filter_flops"] for i in linfos) / lsec / 1e12, 3)
     out["fp64_filter_matvecs_per_step"] = [i["filter_matvecs"] for i in infos]
     out["filter_autotune"] = autotune
     if train_report is not None:

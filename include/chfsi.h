@@ -81,6 +81,15 @@ extern "C" {
  *                 filter runs in complex FP32 on the defect
  *                 E = p(Ht) Q - Q p(mu_t) of the Ritz vectors Q; QR,
  *                 Rayleigh-Ritz, residuals and locking stay FP64.
+ *                 2: as 1, and inside such a filter each recurrence step
+ *                 whose rounding is damped enough by the steps after it
+ *                 runs its product in BF16 (two-term BF16 splits of H and
+ *                 E, three v_mfma_f32_16x16x32_bf16 products, FP32
+ *                 accumulation; error about 3 * 2^-16 of the defect): per
+ *                 step i and wanted vector j with m_j > i, the floor
+ *                 3 * 2^-16 * rel_j * |rho_j|^-(m_j - i - 1) must be 100x
+ *                 below max(tol, rel_j |rho_j|^-m_j), rel_j = residual /
+ *                 norm_h (eq. resl).  Needs n^2 * 8 more bytes of work.
  *   seed          seed of the SplitMix64 counter-based generator used for
  *                 the Lanczos start vector and a random start block.
  *   degree_jitter 0 (default), or s > 0: every wanted vector's degree m is
@@ -154,6 +163,8 @@ typedef struct chfsi_info {
   int learned_cols;        /* wanted column degrees taken from the network       */
   int fallback_cols;       /* wanted column degrees that fell back to the rule   */
   int learned_raised;      /* network degrees above the rule's degree            */
+  int filter_steps_bf16;   /* defect-filter steps run with BF16-split products   */
+  double filter_flops_bf16;/* 8 n^2 per column of those steps                    */
 } chfsi_info;
 
 /* Convergence log record (CHFSI_LOG_FIELDS doubles), one per wanted vector
@@ -324,6 +335,22 @@ int chfsi_filter_defect(int n, int k, const void* H, int ldh, const void* Q, int
                         const void* Z, int ldz, const double* mu, const int* degrees, double c,
                         double e, double gamma, void* Y, int ldy, void* work, size_t work_bytes,
                         void* stream, double* flops_out);
+
+/* chfsi_filter_defect with its first bf16_steps recurrence steps (E_i ->
+ * E_{i+1}, i = 1 .. bf16_steps) run in BF16-split form (precision 2 of
+ * chfsi_opts: H and E_i each split into two BF16 words, three
+ * v_mfma_f32_16x16x32_bf16 products per real product, FP32 accumulation,
+ * E kept in FP32 between steps); the later steps run in FP32.  bf16_steps
+ * = 0 gives chfsi_filter_defect's result.  Same arguments and limits as
+ * chfsi_filter_defect; work >= chfsi_defect_split_workspace_bytes(n, k).
+ *   flops_bf16_out, flops_fp32_out  NULL or the algorithmic flops (8 n^2
+ *               per column and step) of the BF16 and of the FP32 steps. */
+size_t chfsi_defect_split_workspace_bytes(int n, int k);
+int chfsi_filter_defect_split(int n, int k, const void* H, int ldh, const void* Q, int ldq,
+                              const void* Z, int ldz, const double* mu, const int* degrees,
+                              double c, double e, double gamma, int bf16_steps, void* Y, int ldy,
+                              void* work, size_t work_bytes, void* stream,
+                              double* flops_bf16_out, double* flops_fp32_out);
 
 /* Orthonormalise the n x k block Y against the n x nl locked block QL
  * (two projection passes, QL^H QL = I assumed) and then by CholeskyQR2,

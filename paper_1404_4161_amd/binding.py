@@ -45,7 +45,8 @@ class ChfsiInfo(Structure):
                 ("max_resid", c_double), ("beta", c_double), ("norm_h", c_double),
                 ("step_seconds", c_double * 8), ("filter_flops_fp32", c_double),
                 ("filter_seconds_fp32", c_double), ("log_records", c_int),
-                ("learned_cols", c_int), ("fallback_cols", c_int), ("learned_raised", c_int)]
+                ("learned_cols", c_int), ("fallback_cols", c_int), ("learned_raised", c_int),
+                ("filter_steps_bf16", c_int), ("filter_flops_bf16", c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "step_seconds"}
@@ -77,6 +78,12 @@ _SIGS = {
                                     c_int, POINTER(c_double), POINTER(c_int), c_double, c_double,
                                     c_double, c_void_p, c_int, c_void_p, c_size_t, c_void_p,
                                     POINTER(c_double)]),
+    "chfsi_defect_split_workspace_bytes": (c_size_t, [c_int, c_int]),
+    "chfsi_filter_defect_split": (c_int, [c_int, c_int, c_void_p, c_int, c_void_p, c_int,
+                                          c_void_p, c_int, POINTER(c_double), POINTER(c_int),
+                                          c_double, c_double, c_double, c_int, c_void_p, c_int,
+                                          c_void_p, c_size_t, c_void_p, POINTER(c_double),
+                                          POINTER(c_double)]),
     "chfsi_orthonormalize": (c_int, [c_int, c_int, c_void_p, c_int, c_int, c_void_p, c_int,
                                      c_void_p, c_size_t, c_void_p, POINTER(c_int)]),
     "chfsi_rayleigh_ritz": (c_int, [c_int, c_int, c_void_p, c_int, c_void_p, c_int, c_void_p,
@@ -132,6 +139,11 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1404_4161_amd.build`")
+        # torch first: its HIP runtime (libamdhip64, soname libamdhip64.so.7)
+        # is then the one libchfsi.so binds to.  Loaded the other way round,
+        # the process would hold two HIP runtimes and only one of them can
+        # open the GPU.
+        _torch()
         l = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(l, name)
@@ -292,6 +304,27 @@ def chfsi_filter_defect(H, Q, Z, mu, degrees, c, e, gamma, Y=None, work=None, st
                                      _stream(stream, Q.device), ctypes.byref(fl)),
            "chfsi_filter_defect")
     return Y, fl.value
+
+
+def chfsi_filter_defect_split(H, Q, Z, mu, degrees, c, e, gamma, bf16_steps, Y=None, work=None,
+                              stream=None):
+    """chfsi_filter_defect with its first bf16_steps steps in BF16-split
+    form; returns (Y, BF16-step flops, FP32-step flops)."""
+    torch = _torch()
+    n, k = Q.shape
+    if Y is None:
+        Y = colmajor(torch.empty((n, k), dtype=torch.complex128, device=Q.device))
+    m = (c_double * k)(*[float(x) for x in mu])
+    deg = (c_int * k)(*[int(x) for x in degrees])
+    wb = int(lib().chfsi_defect_split_workspace_bytes(n, k))
+    w = _work(wb, Q.device, work)
+    f16, f32 = c_double(0.0), c_double(0.0)
+    _check(lib().chfsi_filter_defect_split(n, k, _ptr(H), _ld(H), _ptr(Q), _ld(Q), _ptr(Z),
+                                           _ld(Z), m, deg, c, e, gamma, int(bf16_steps), _ptr(Y),
+                                           _ld(Y), _ptr(w), wb, _stream(stream, Q.device),
+                                           ctypes.byref(f16), ctypes.byref(f32)),
+           "chfsi_filter_defect_split")
+    return Y, f16.value, f32.value
 
 
 def chfsi_orthonormalize(Y, QL=None, work=None, stream=None):

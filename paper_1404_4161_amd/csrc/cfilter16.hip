@@ -1,0 +1,343 @@
+// BF16-split form of the defect step of the mixed-precision Chebyshev
+// filter, on v_mfma_f32_16x16x32_bf16 with FP32 accumulation.
+//
+// The defect recurrence (the FP32 form is described in cfilter32.hip)
+//   E_{i+1} = 2 sigma_{i+1} (Ht E_i + R diag(p_i(mu_t)) / e) - sigma_{i+1} sigma_i E_{i-1}
+// keeps E in FP32 between steps.  Here the product H E_i is formed from
+// two-term BF16 splits of both operands: x = x_hi + x_lo with
+// x_hi = bf16(x) and x_lo = bf16(x - x_hi), both rounded to nearest even,
+// and a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi (three BF16 products into one
+// FP32 accumulator).  The dropped terms (a_lo b_lo and the parts of a and b
+// beyond the two BF16 words) are at most about 3 * 2^-16 |a| |b|, so the
+// step's error is that fraction of |H| |E_i|: like the FP32 step it scales
+// with the residuals, 2^8 times coarser.  A step of the filter may use this
+// form when its error, damped by the steps after it (eq. resl), stays
+// far below what the filter aims at (the solver's schedule decides per
+// step).  BF16 keeps the exponent range of FP32, so the splits need no
+// per-column scaling: every defect column here is many orders of magnitude
+// above the smallest normal FP32 number.
+//
+// Operand layout ("split panel"): a complex matrix is stored as rows r of a
+// reduction index k padded to Kp (a multiple of 32, zero filled); row r
+// holds Kp / 8 groups of 64 bytes, group g = the four planes re_hi, im_hi,
+// re_lo, im_lo of k = 8g .. 8g + 7, 8 BF16 each.  H is stored by its rows
+// (r = m, k = column of H); E_i by its columns (r = column, k = row).  One
+// 16-byte LDS read then gives an MFMA lane its 8 consecutive k of a plane.
+#include "internal.h"
+
+#include <algorithm>
+
+namespace chfsi {
+
+namespace {
+
+typedef float2 cf;
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int SBM = 64, SBN = 64, SBK = 32, SNT = 256;
+constexpr int GROUP_B = 64;                    // bytes per (row, 8 k) group
+constexpr int ROWB = (SBK / 8) * GROUP_B + 16; // LDS bytes per tile row (+16 B pad)
+constexpr int NXCD = 8;
+
+__device__ __forceinline__ unsigned bf16_rne(float x) {
+  const unsigned u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ float bf16_val(unsigned h) { return __uint_as_float(h << 16); }
+
+// hi and lo BF16 words of x
+__device__ __forceinline__ void split1(float x, unsigned& hi, unsigned& lo) {
+  hi = bf16_rne(x);
+  lo = bf16_rne(x - bf16_val(hi));
+}
+
+// the four planes of 8 complex values -> 4 x 16 bytes
+__device__ __forceinline__ void split8(const cf* v, uint4* planes) {
+  unsigned rh[8], ih[8], rl[8], il[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    split1(v[i].x, rh[i], rl[i]);
+    split1(v[i].y, ih[i], il[i]);
+  }
+  auto pack = [](const unsigned* w) {
+    return uint4{w[0] | (w[1] << 16), w[2] | (w[3] << 16), w[4] | (w[5] << 16),
+                 w[6] | (w[7] << 16)};
+  };
+  planes[0] = pack(rh);
+  planes[1] = pack(ih);
+  planes[2] = pack(rl);
+  planes[3] = pack(il);
+}
+
+__device__ __forceinline__ f4 mfma16(const bf8& a, const bf8& b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ bf8 as_bf8(uint4 v) { return __builtin_bit_cast(bf8, v); }
+
+__device__ __forceinline__ uint4 neg_bf16(uint4 v) {
+  const unsigned s = 0x80008000u;
+  return uint4{v.x ^ s, v.y ^ s, v.z ^ s, v.w ^ s};
+}
+
+struct SplitArgs {
+  int M, N, Kp;
+  const char* As; long a_row;   // split panel of H (rows m), bytes per row
+  const char* Bs; long b_row;   // split panel of E_i (rows = columns of the window)
+  const cf* Ecur; long lde;     // E_i in FP32
+  const cf* Eold;               // E_{i-1}
+  cf* Eout;                     // E_{i+1} (may alias Eold)
+  const cf* R; long ldr;        // residual block (FP32)
+  const float* cr;              // per-column coefficient of R
+  float shift, sa, sb;
+  char* Bnext;                  // split panel of E_{i+1} (same geometry as Bs) or null
+  int tiles_m, tiles_n;
+};
+
+// One defect step: 64 x 64 complex output tiles, 4 waves of 32 x 32, K
+// staged 32 deep (two stages of 2 x 64 rows x 272 B of LDS: 68 KB, two
+// workgroups per CU); tile rows interleaved over the 8 XCDs.
+__global__ void __launch_bounds__(SNT, 2) defect_gemm_split(SplitArgs g) {
+  __shared__ __attribute__((aligned(16))) char lds[2][2][SBM * ROWB];
+  const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
+  const int rows_x = (g.tiles_m - xcd + NXCD - 1) / NXCD;
+  const int ri = slot / g.tiles_n;
+  const int tn = slot - ri * g.tiles_n;
+  if (ri >= rows_x) return;
+  const int tm = xcd + NXCD * ri;
+  const int m0 = tm * SBM, n0 = tn * SBN;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int lr = lane & 15, lg = lane >> 4;
+
+  f4 accR[2][2], accI[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accR[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+      accI[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  // staging: 16 chunks of 16 B per tile row and stage; 4 chunks of each
+  // operand per thread
+  uint4 ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = t + SNT * i;
+      const int row = c >> 4, ch = c & 15;
+      const long koff = (long)k0 * 8 + ch * 16;
+      const int gm = m0 + row, gn = n0 + row;
+      ra[i] = gm < g.M ? *(const uint4*)(g.As + gm * g.a_row + koff) : uint4{0u, 0u, 0u, 0u};
+      rb[i] = gn < g.N ? *(const uint4*)(g.Bs + gn * g.b_row + koff) : uint4{0u, 0u, 0u, 0u};
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int c = t + SNT * i;
+      const int row = c >> 4, ch = c & 15;
+      *(uint4*)(&lds[buf][0][row * ROWB + ch * 16]) = ra[i];
+      *(uint4*)(&lds[buf][1][row * ROWB + ch * 16]) = rb[i];
+    }
+  };
+  const int nk = g.Kp / SBK;
+  if (nk > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) load((kt + 1) * SBK);
+    uint4 a[2][4], b[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const char* p = &lds[cur][0][(wm * 32 + i * 16 + lr) * ROWB + lg * GROUP_B];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[i][q] = *(const uint4*)(p + 16 * q);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const char* p = &lds[cur][1][(wn * 32 + j * 16 + lr) * ROWB + lg * GROUP_B];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[j][q] = *(const uint4*)(p + 16 * q);
+    }
+    // planes: 0 re_hi, 1 im_hi, 2 re_lo, 3 im_lo
+    // real part: Ar Br - Ai Bi (the A imaginary planes negated)
+    // imaginary part: Ar Bi + Ai Br
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const bf8 arh = as_bf8(a[i][0]), arl = as_bf8(a[i][2]);
+      const bf8 aih = as_bf8(a[i][1]), ail = as_bf8(a[i][3]);
+      const bf8 nih = as_bf8(neg_bf16(a[i][1])), nil = as_bf8(neg_bf16(a[i][3]));
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const bf8 brh = as_bf8(b[j][0]), brl = as_bf8(b[j][2]);
+        const bf8 bih = as_bf8(b[j][1]), bil = as_bf8(b[j][3]);
+        accR[i][j] = mfma16(arh, brh, accR[i][j]);
+        accI[i][j] = mfma16(arh, bih, accI[i][j]);
+        accR[i][j] = mfma16(nih, bih, accR[i][j]);
+        accI[i][j] = mfma16(aih, brh, accI[i][j]);
+        accR[i][j] = mfma16(arh, brl, accR[i][j]);
+        accI[i][j] = mfma16(arh, bil, accI[i][j]);
+        accR[i][j] = mfma16(nih, bil, accR[i][j]);
+        accI[i][j] = mfma16(aih, brl, accI[i][j]);
+        accR[i][j] = mfma16(arl, brh, accR[i][j]);
+        accI[i][j] = mfma16(arl, bih, accI[i][j]);
+        accR[i][j] = mfma16(nil, bih, accR[i][j]);
+        accI[i][j] = mfma16(ail, brh, accI[i][j]);
+      }
+    }
+    if (more) store(cur ^ 1);
+    __syncthreads();
+  }
+  // MFMA output: lane l, register r holds row 4 (l / 16) + r, column l % 16
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int rbase = m0 + wm * 32 + i * 16 + 4 * lg;
+      const int col = n0 + wn * 32 + j * 16 + lr;
+      if (col >= g.N) continue;
+      cf out[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rbase + r;
+        out[r] = cf{0.f, 0.f};
+        if (row >= g.M) continue;
+        const cf ec = g.Ecur[row + (long)col * g.lde];
+        const cf rr = g.R[row + (long)col * g.ldr];
+        const float crj = g.cr[col];
+        cf o = cf{g.sa * (accR[i][j][r] - g.shift * ec.x) + crj * rr.x,
+                  g.sa * (accI[i][j][r] - g.shift * ec.y) + crj * rr.y};
+        if (g.sb != 0.f) {
+          const cf eo = g.Eold[row + (long)col * g.lde];
+          o.x -= g.sb * eo.x;
+          o.y -= g.sb * eo.y;
+        }
+        g.Eout[row + (long)col * g.lde] = o;
+        out[r] = o;
+      }
+      // the split of E_{i+1} for a following BF16 step: 4 consecutive k of
+      // column col, zeros beyond M (inside the padding)
+      if (g.Bnext && rbase < g.Kp) {
+        unsigned rh[4], ih[4], rl[4], il[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          split1(out[r].x, rh[r], rl[r]);
+          split1(out[r].y, ih[r], il[r]);
+        }
+        char* p = g.Bnext + col * g.b_row + (rbase >> 3) * GROUP_B + (rbase & 7) * 2;
+        *(uint2*)(p + 0) = uint2{rh[0] | (rh[1] << 16), rh[2] | (rh[3] << 16)};
+        *(uint2*)(p + 16) = uint2{ih[0] | (ih[1] << 16), ih[2] | (ih[3] << 16)};
+        *(uint2*)(p + 32) = uint2{rl[0] | (rl[1] << 16), rl[2] | (rl[3] << 16)};
+        *(uint2*)(p + 48) = uint2{il[0] | (il[1] << 16), il[2] | (il[3] << 16)};
+      }
+    }
+}
+
+// Split panel of FP32 columns: row j of S = column j of E (K values, zero
+// padded to Kp).  One thread per (column, group of 8).
+__global__ void split_cols(int K, int Kp, int cols, const cf* E, long lde, char* S, long srow) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int groups = Kp / 8;
+  if (idx >= (long)groups * cols) return;
+  const int j = (int)(idx / groups), grp = (int)(idx % groups);
+  cf v[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int k = grp * 8 + i;
+    v[i] = k < K ? E[k + (long)j * lde] : cf{0.f, 0.f};
+  }
+  uint4 pl[4];
+  split8(v, pl);
+  uint4* dst = (uint4*)(S + j * srow + (long)grp * GROUP_B);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) dst[q] = pl[q];
+}
+
+// Split panel of the rows of an FP64 matrix: row m of S = H[m, :] (values
+// rounded to FP32 first, as in the FP32 step), through a 32 x 64 LDS tile.
+constexpr int TM = 32, TK = 64;
+__global__ void split_rows(int n, int Kp, const zc* H, long ldh, char* S, long srow) {
+  __shared__ cf tile[TK][TM + 1];
+  const int m0 = blockIdx.x * TM, k0 = blockIdx.y * TK;
+  const int t = threadIdx.x;
+  // load: m fastest (a column of H is contiguous)
+  for (int e = t; e < TM * TK; e += blockDim.x) {
+    const int mm = e % TM, kk = e / TM;
+    const int m = m0 + mm, k = k0 + kk;
+    cf v = cf{0.f, 0.f};
+    if (m < n && k < n) {
+      const zc h = H[m + (long)k * ldh];
+      v = cf{(float)h.x, (float)h.y};
+    }
+    tile[kk][mm] = v;
+  }
+  __syncthreads();
+  // store: a thread per (row m, group of 8 k)
+  for (int e = t; e < TM * (TK / 8); e += blockDim.x) {
+    const int grp = e % (TK / 8), mm = e / (TK / 8);
+    const int m = m0 + mm;
+    const int kg = k0 + grp * 8;
+    if (m >= n || kg >= Kp) continue;
+    cf v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = tile[grp * 8 + i][mm];
+    uint4 pl[4];
+    split8(v, pl);
+    uint4* dst = (uint4*)(S + m * srow + (long)(kg / 8) * GROUP_B);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = pl[q];
+  }
+}
+
+}  // namespace
+
+int split_kp(int K) { return ((K + SBK - 1) / SBK) * SBK; }
+
+size_t split_panel_bytes(int rows, int K) { return (size_t)rows * (size_t)split_kp(K) * 8; }
+
+int matrix_to_split(hipStream_t s, int n, const zc* H, long ldh, void* Hs) {
+  const int kp = split_kp(n);
+  dim3 grid((unsigned)((n + TM - 1) / TM), (unsigned)((kp + TK - 1) / TK));
+  hipLaunchKernelGGL(split_rows, grid, dim3(256), 0, s, n, kp, H, ldh, (char*)Hs,
+                     (long)kp * 8);
+  return (int)hipGetLastError();
+}
+
+int cols_to_split(hipStream_t s, int K, int cols, const void* E, long lde, void* S) {
+  if (cols <= 0) return 0;
+  const int kp = split_kp(K);
+  const long total = (long)(kp / 8) * cols;
+  hipLaunchKernelGGL(split_cols, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, K, kp,
+                     cols, (const cf*)E, lde, (char*)S, (long)kp * 8);
+  return (int)hipGetLastError();
+}
+
+int defect_step_split(hipStream_t s, int n, int N, const void* Hs, const void* Es,
+                      const void* Ecur, const void* Eold, void* Eout, const void* R32,
+                      const float* cr, float shift, float sa, float sb, void* Es_next) {
+  if (N <= 0) return 0;
+  SplitArgs g = {};
+  g.M = n; g.N = N; g.Kp = split_kp(n);
+  g.As = (const char*)Hs; g.a_row = (long)g.Kp * 8;
+  g.Bs = (const char*)Es; g.b_row = (long)g.Kp * 8;
+  g.Ecur = (const cf*)Ecur; g.Eold = (const cf*)Eold; g.Eout = (cf*)Eout; g.lde = n;
+  g.R = (const cf*)R32; g.ldr = n; g.cr = cr;
+  g.shift = shift; g.sa = sa; g.sb = sb;
+  g.Bnext = (char*)Es_next;
+  g.tiles_m = (n + SBM - 1) / SBM;
+  g.tiles_n = (N + SBN - 1) / SBN;
+  const int grid = ((g.tiles_m + NXCD - 1) / NXCD) * g.tiles_n * NXCD;
+  hipLaunchKernelGGL(defect_gemm_split, dim3(grid), dim3(SNT), 0, s, g);
+  return (int)hipGetLastError();
+}
+
+}  // namespace chfsi

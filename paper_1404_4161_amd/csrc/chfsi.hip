@@ -34,10 +34,27 @@ constexpr int CR_ROWS = 256;
 const zc ONE = {1.0, 0.0}, ZERO = {0.0, 0.0}, MONE = {-1.0, 0.0};
 
 
+// With the environment variable CHFSI_DEBUG set, every failed device call
+// is reported on stderr (call text, source line, HIP or library code).
+bool debug_enabled() {
+  static const bool on = std::getenv("CHFSI_DEBUG") != nullptr;
+  return on;
+}
+
+void report_failure(const char* what, int line, int code) {
+  if (debug_enabled()) {
+    std::fprintf(stderr, "chfsi: %s failed (line %d, code %d)\n", what, line, code);
+    std::fflush(stderr);
+  }
+}
+
 #define CK(expr)                                  \
   do {                                            \
     int _e = (int)(expr);                         \
-    if (_e != 0) return CHFSI_DEVICE_ERROR;       \
+    if (_e != 0) {                                \
+      report_failure(#expr, __LINE__, _e);        \
+      return CHFSI_DEVICE_ERROR;                  \
+    }                                             \
   } while (0)
 
 #define CKS(expr)                                 \
@@ -90,6 +107,7 @@ struct StepBufs {
   zc *T1, *T2, *G, *K2, *invk, *scratch, *gv_part, *V, *w, *h, *fpart;
   size_t fpart_elems;
   void *R32, *E0, *E1;          // mixed-precision filter: complex64 n x k each
+  void *S0, *S1;                // BF16 splits of E_i (k rows of split_kp(n) values)
   float* crtab;                 // CR_ROWS x k coefficients of the residual term
   double* pm;                   // k final scalars p_{m_j}(mu_t)
   float *mlp_p, *mlp_x, *mlp_y;  // degree network: parameters, k x 8 inputs, k outputs
@@ -128,6 +146,8 @@ void carve_step(Carver& c, StepBufs& b, int n, int k, int nev, int lanczos_steps
   b.R32 = c.take<char>(nk * 8);
   b.E0 = c.take<char>(nk * 8);
   b.E1 = c.take<char>(nk * 8);
+  b.S0 = c.take<char>(split_panel_bytes(k, n));
+  b.S1 = c.take<char>(split_panel_bytes(k, n));
   b.crtab = c.take<float>((size_t)CR_ROWS * k);
   b.pm = c.take<double>(k);
   b.mlp_p = c.take<float>(MLP_PARAMS);
@@ -400,11 +420,9 @@ int rayleigh_ritz_dev(hipStream_t s, int n, int k, const zc* H, long ldh, const 
       lk.lock();
       CKS(get_handle(&h));
     }
-    if (rocblas_set_stream(h, s) != rocblas_status_success) return CHFSI_DEVICE_ERROR;
-    if (rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_lower, k,
-                         (rocblas_double_complex*)b.G, k, b.mu, b.E, b.info) !=
-        rocblas_status_success)
-      return CHFSI_DEVICE_ERROR;
+    CK(rocblas_set_stream(h, s));
+    CK(rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_lower, k,
+                        (rocblas_double_complex*)b.G, k, b.mu, b.E, b.info));
   }
   CK(zgemm(s, OP_N, OP_N, n, k, k, ONE, Q, ldq, b.G, k, ZERO, Qout, ldqo, false, nullptr, 0));
   CK(zgemm(s, OP_N, OP_N, n, k, k, ONE, Z, ldz, b.G, k, ZERO, Zout, ldzo, false, nullptr, 0));
@@ -414,7 +432,7 @@ int rayleigh_ritz_dev(hipStream_t s, int n, int k, const zc* H, long ldh, const 
   CK(hipMemcpyAsync(res_h, b.res, sizeof(double) * k, hipMemcpyDeviceToHost, s));
   CK(hipMemcpyAsync(&info, b.info, sizeof(int), hipMemcpyDeviceToHost, s));
   CK(hipStreamSynchronize(s));
-  if (info != 0) return CHFSI_DEVICE_ERROR;
+  CK(info);   // zheevd did not converge
   return CHFSI_OK;
 }
 
@@ -499,10 +517,17 @@ int upload(hipStream_t s, T* dst, const std::vector<T>& v) {
 // Q, Z = H Q (ld) and mu (host) are in the current column order; order[j]
 // is the column filtered j-th (ascending degree m[j]).  The filtered block
 // goes to Y (ld), and Qs (ld) receives the reordered Q.
+//
+// Hs (or null) is the BF16 split panel of H; sched[i] = 1 runs step i (E_i
+// -> E_{i+1}) in the BF16-split form (cfilter16.hip), which needs Hs.
+// flops32 / flops16 receive the algorithmic flops of the FP32 and BF16
+// steps, steps16 the number of BF16 steps.
 int defect_filter_dev(hipStream_t s, int n, int k, const void* H32, const zc* Q, const zc* Z,
                       long ld, const std::vector<double>& mu, const std::vector<int>& order,
                       const std::vector<int>& m, double c, double e, double gamma, zc* Qs, zc* Y,
-                      StepBufs& b, double* flops32, int* launches) {
+                      StepBufs& b, double* flops32, int* launches, const void* Hs = nullptr,
+                      const std::vector<char>* sched = nullptr, double* flops16 = nullptr,
+                      int* steps16 = nullptr) {
   if (k <= 0) return CHFSI_OK;
   const int mmax = m[k - 1];
   if (mmax > CR_ROWS) return CHFSI_INVALID_ARG;
@@ -535,15 +560,36 @@ int defect_filter_dev(hipStream_t s, int n, int k, const void* H32, const zc* Q,
   int first = 0;
   while (first < k && m[first] <= 1) ++first;
   const size_t c64 = 8;   // bytes per complex64
+  const size_t srow = (size_t)split_kp(n) * 8;   // bytes per split-panel row
+  auto bf16_step = [&](int i) {
+    return Hs && sched && i < (int)sched->size() && (*sched)[i] != 0;
+  };
+  bool split_ready = false;   // the split panel of E_i holds the window
   for (int i = 1; i < mmax; ++i) {
     const char* cur = (const char*)((i & 1) ? b.E1 : b.E0);
     char* old = (char*)((i & 1) ? b.E0 : b.E1);
     const size_t off = (size_t)first * n * c64;
     const int cols = k - first;
-    CK(defect_step(s, n, cols, H32, cur + off, old + off, old + off, (const char*)b.R32 + off,
-                   b.crtab + (size_t)i * k + first, (float)c, (float)(2.0 * sig[i + 1] / e),
-                   (float)(sig[i + 1] * sig[i]), b.fpart, b.fpart_elems * 2));
-    *flops32 += 8.0 * (double)n * n * cols;
+    const float shift = (float)c, sa = (float)(2.0 * sig[i + 1] / e);
+    const float sbeta = (float)(sig[i + 1] * sig[i]);
+    const float* cri = b.crtab + (size_t)i * k + first;
+    if (bf16_step(i)) {
+      char* scur = (char*)((i & 1) ? b.S1 : b.S0) + first * srow;
+      char* snext = (char*)((i & 1) ? b.S0 : b.S1) + first * srow;
+      if (!split_ready) CK(cols_to_split(s, n, cols, cur + off, n, scur));
+      const bool next16 = bf16_step(i + 1) && i + 1 < mmax;
+      CK(defect_step_split(s, n, cols, Hs, scur, cur + off, old + off, old + off,
+                           (const char*)b.R32 + off, cri, shift, sa, sbeta,
+                           next16 ? snext : nullptr));
+      split_ready = next16;
+      if (flops16) *flops16 += 8.0 * (double)n * n * cols;
+      if (steps16) *steps16 += 1;
+    } else {
+      CK(defect_step(s, n, cols, H32, cur + off, old + off, old + off, (const char*)b.R32 + off,
+                     cri, shift, sa, sbeta, b.fpart, b.fpart_elems * 2));
+      split_ready = false;
+      *flops32 += 8.0 * (double)n * n * cols;
+    }
     *launches += 1;
     while (first < k && m[first] <= i + 1) ++first;
   }
@@ -620,6 +666,37 @@ bool cap_degrees_fp32(int n_wanted, const std::vector<double>& mu, const std::ve
   return true;
 }
 
+// Per-step precision inside an FP32 defect filter (precision 2).  Step i
+// (E_i -> E_{i+1}) may use the BF16-split product, whose error is about
+// BF16_SPLIT_EPS times the defect, when for every wanted vector j still
+// filtered (m_j > i) that error, damped by the m_j - i - 1 steps after it
+// (eq. resl: by rho_j^-(m_j - i - 1) relative to the column), stays 100x
+// below what the filter aims at (the bound of defect_filter_safe with the
+// step's own damping).  deg is in the current column order; the result has
+// one entry per step index 0 .. max degree - 1 (entry 0 unused).
+constexpr double BF16_SPLIT_EPS = 3.0 / 65536.0;
+
+std::vector<char> bf16_step_schedule(int n_wanted, const std::vector<double>& mu,
+                                     const std::vector<double>& res, const std::vector<int>& deg,
+                                     double c, double e, double tol, double norm_h) {
+  const int ka = (int)deg.size();
+  int mmax = 0;
+  for (int j = 0; j < ka; ++j) mmax = std::max(mmax, deg[j]);
+  std::vector<char> ok(std::max(mmax, 1), 1);
+  ok[0] = 0;
+  for (int j = 0; j < std::min(n_wanted, ka); ++j) {
+    const double t = (mu[j] - c) / e;
+    const double lr = std::fabs(t) > 1.0 ? std::log(std::fabs(t) + std::sqrt(t * t - 1.0)) : 0.0;
+    const double rel = res[j] / norm_h;
+    const double target = std::max(tol, rel * std::exp(-lr * deg[j]));
+    for (int i = 1; i < deg[j]; ++i) {
+      const double floor_ = BF16_SPLIT_EPS * rel * std::exp(-lr * (deg[j] - i - 1));
+      if (!(floor_ <= 0.01 * target)) ok[i] = 0;
+    }
+  }
+  return ok;
+}
+
 int upload_ints(hipStream_t s, int* dst, const std::vector<int>& v) {
   if (v.empty()) return CHFSI_OK;
   CK(hipMemcpyAsync(dst, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, s));
@@ -652,6 +729,7 @@ struct SolveBufs {
   zc *H = nullptr, *L = nullptr, *Linv = nullptr, *W = nullptr, *invd = nullptr;
   zc *QL, *QA, *ZA, *P0, *P1, *TMP;
   void* H32 = nullptr;          // fp32(H), mixed precision only
+  void* Hs = nullptr;           // BF16 split panel of H's rows, precision 2 only
   int* flag;
   StepBufs st;
 };
@@ -676,7 +754,8 @@ size_t carve_solve(Carver& c, SolveBufs& b, int n, int nev, int nex, bool gen, i
   b.P0 = c.take<zc>(nk);
   b.P1 = c.take<zc>(nk);
   b.TMP = c.take<zc>(nk);
-  if (precision == 1) b.H32 = c.take<char>(nn * 8);
+  if (precision >= 1) b.H32 = c.take<char>(nn * 8);
+  if (precision == 2) b.Hs = c.take<char>(split_panel_bytes(n, n));
   b.flag = c.take<int>(8);
   carve_step(c, b.st, n, k, nev, lsteps);
   return c.off + ALIGN;
@@ -941,8 +1020,8 @@ struct Solve {
   double max_locked_res = 0.0;
   int it = 0;
   int status = CHFSI_NO_CONVERGENCE;
-  double filter_flops = 0.0, filter_sec = 0.0, flops32 = 0.0, sec32 = 0.0;
-  int iters32 = 0, launches = 0;
+  double filter_flops = 0.0, filter_sec = 0.0, flops32 = 0.0, sec32 = 0.0, flops16 = 0.0;
+  int iters32 = 0, launches = 0, steps16 = 0;
   bool have_res = false;   // residuals of the current block known
   hipEvent_t fe0 = nullptr, fe1 = nullptr;
   bool done = false;
@@ -1078,7 +1157,8 @@ struct Solve {
     speed.assign(k, NAN);
     if (X0 && o.seq_rates)
       for (int j = 0; j < k; ++j) speed[j] = o.seq_rates[j];
-    if (o.precision == 1) CK(matrix_to_fp32(s, n, H, ldh, b.H32));
+    if (o.precision >= 1) CK(matrix_to_fp32(s, n, H, ldh, b.H32));
+    if (o.precision == 2) CK(matrix_to_split(s, n, H, ldh, b.Hs));
     CK(hipEventCreate(&fe0));
     CK(hipEventCreate(&fe1));
     return CHFSI_OK;
@@ -1109,7 +1189,7 @@ struct Solve {
       CKS(learned_degrees(s, ka_, mu.data(), res.data(), nev - nl, alpha, beta, gamma, norm_h,
                           tol_abs, loop, o.deg_max, o.mlp, sb.mlp_p, sb.mlp_x, sb.mlp_y,
                           deg.data(), nullptr, dsrc.data(), nullptr, -1, &finishing));
-      if (finishing && o.precision == 1) {
+      if (finishing && o.precision >= 1) {
         // a loop whose degrees get capped to the reach of FP32 cannot finish
         const double cc = 0.5 * (alpha + beta), ee = 0.5 * (beta - alpha);
         std::vector<int> d2 = deg;
@@ -1169,7 +1249,7 @@ struct Solve {
     // A warm start with Lambda0 may take its first degrees from the rule
     // once the residuals of X0 are known (first_rule).
     const bool warm_rule = it == 1 && X0 && Lambda0 && o.first_rule && o.degree_mode != 1;
-    if (!have_res && (o.precision == 1 || warm_rule)) {
+    if (!have_res && (o.precision >= 1 || warm_rule)) {
       // one product gives Z = H Q and the residuals of the warm start block
       tm.begin(4);
       CK(zgemm(s, OP_N, OP_N, n, ka, n, ONE, H, ldh, b.QA, ld, ZERO, b.ZA, ld, false, nullptr, 0));
@@ -1191,7 +1271,7 @@ struct Solve {
     // block of the current Ritz pairs and small enough residuals
     use32 = false;
     capped.assign(ka, 0);
-    if (o.precision == 1) {
+    if (o.precision >= 1) {
       use32 = defect_filter_safe(nev - nl, mu, res, deg, c, e, gamma, tol, norm_h);
       if (!use32) {
         std::vector<int> d2 = deg;
@@ -1257,9 +1337,14 @@ struct Solve {
     if (use32) {
       tm.begin(2);
       double f32 = 0.0;
+      std::vector<char> sched;
+      if (o.precision == 2)
+        sched = bf16_step_schedule(nev - nl, mu, res, std::vector<int>(deg.begin(), deg.begin() + ka),
+                                   c, e, tol, norm_h);
       CKS(defect_filter_dev(s, n, ka, b.H32, b.QA, b.ZA, ld,
                             std::vector<double>(mu.begin(), mu.begin() + ka), order, msort, c, e,
-                            gamma, b.P0, b.TMP, sb, &f32, &launches));
+                            gamma, b.P0, b.TMP, sb, &f32, &launches, b.Hs,
+                            o.precision == 2 ? &sched : nullptr, &flops16, &steps16));
       tm.end();
       flops32 += f32;
       iters32 += 1;
@@ -1434,6 +1519,8 @@ struct Solve {
       info->filter_seconds = filter_sec;
       info->filter_iters_fp32 = iters32;
       info->filter_flops_fp32 = flops32;
+      info->filter_flops_bf16 = flops16;
+      info->filter_steps_bf16 = steps16;
       info->filter_seconds_fp32 = sec32;
       info->beta = beta;
       info->norm_h = norm_h;
@@ -1827,7 +1914,7 @@ int validate_solve(int n, int nev, int nex, const void* A, int lda, const void* 
     if (B && (ldb < n || !aligned16(B))) return CHFSI_INVALID_ARG;
     if (X0 && (ldx0 < n || !aligned16(X0))) return CHFSI_INVALID_ARG;
     if (o.deg0 < 1 || o.deg_max < 1 || o.max_iter < 1 || o.lanczos_steps < 1) return CHFSI_INVALID_ARG;
-    if (o.precision < 0 || o.precision > 1) return CHFSI_INVALID_ARG;
+    if (o.precision < 0 || o.precision > 2) return CHFSI_INVALID_ARG;
     if (o.degree_mode < 0 || o.degree_mode > 3 || o.first_rule < 0 || o.first_rule > 1)
       return CHFSI_INVALID_ARG;
     if (o.degree_mode == 3 && !o.seq_rates) return CHFSI_INVALID_ARG;
@@ -1838,7 +1925,7 @@ int validate_solve(int n, int nev, int nex, const void* A, int lda, const void* 
       for (int i = 0; i < MLP_PARAMS; ++i)
         if (!std::isfinite(o.mlp[i])) return CHFSI_NONFINITE;
     }
-    if (o.precision == 1 && (o.deg0 > CR_ROWS || o.deg_max > CR_ROWS)) return CHFSI_INVALID_ARG;
+    if (o.precision >= 1 && (o.deg0 > CR_ROWS || o.deg_max > CR_ROWS)) return CHFSI_INVALID_ARG;
     if (X0 == X && ldx0 != ldx) return CHFSI_INVALID_ARG;
     if (Lambda0) {
       if (!X0) return CHFSI_INVALID_ARG;
@@ -1943,7 +2030,11 @@ int chfsi_solve_batch(int count, const int* n, const int* nev, const int* nex,
     return worst;
   } catch (const std::bad_alloc&) {
     return CHFSI_ALLOC_ERROR;
+  } catch (const std::exception& ex) {
+    report_failure(ex.what(), __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
   } catch (...) {
+    report_failure("unknown exception", __LINE__, -1);
     return CHFSI_DEVICE_ERROR;
   }
 }
@@ -1989,7 +2080,11 @@ int chfsi_solve(int n, int nev, int nex, const void* A, int lda, const void* B, 
                       Lambda0, Lambda, (zc*)X, ldx, work, work_bytes, o, as_stream(stream), info);
   } catch (const std::bad_alloc&) {
     return CHFSI_ALLOC_ERROR;
+  } catch (const std::exception& ex) {
+    report_failure(ex.what(), __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
   } catch (...) {
+    report_failure("unknown exception", __LINE__, -1);
     return CHFSI_DEVICE_ERROR;
   }
 }
@@ -2030,7 +2125,11 @@ int chfsi_filter(int n, int k, const void* H, int ldh, void* Y, int ldy, const i
     if (flops_out) *flops_out = fl;
     if (launches_out) *launches_out = ln;
     return CHFSI_OK;
+  } catch (const std::exception& ex) {
+    report_failure(ex.what(), __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
   } catch (...) {
+    report_failure("unknown exception", __LINE__, -1);
     return CHFSI_DEVICE_ERROR;
   }
 }
@@ -2077,7 +2176,64 @@ int chfsi_filter_defect(int n, int k, const void* H, int ldh, const void* Q, int
     CK(hipStreamSynchronize(s));
     if (flops_out) *flops_out = f32;
     return CHFSI_OK;
+  } catch (const std::exception& ex) {
+    report_failure(ex.what(), __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
   } catch (...) {
+    report_failure("unknown exception", __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
+  }
+}
+
+size_t chfsi_defect_split_workspace_bytes(int n, int k) {
+  if (n < 1 || k < 1) return 0;
+  return chfsi_defect_workspace_bytes(n, k) + split_panel_bytes(n, n) + ALIGN;
+}
+
+int chfsi_filter_defect_split(int n, int k, const void* H, int ldh, const void* Q, int ldq,
+                              const void* Z, int ldz, const double* mu, const int* degrees,
+                              double c, double e, double gamma, int bf16_steps, void* Y, int ldy,
+                              void* work, size_t work_bytes, void* stream,
+                              double* flops_bf16_out, double* flops_fp32_out) {
+  try {
+    if (n < 1 || k < 1 || k > n || ldh < n || ldq != n || ldz != n || ldy < n || !mu ||
+        !degrees || !(e > 0.0) || gamma == c || bf16_steps < 0)
+      return CHFSI_INVALID_ARG;
+    if (check_ptr(H) || check_ptr(Q) || check_ptr(Z) || check_ptr(Y) || check_ptr(work))
+      return CHFSI_INVALID_ARG;
+    for (int j = 0; j < k; ++j) {
+      if (degrees[j] < 1 || degrees[j] > CR_ROWS || (j > 0 && degrees[j] < degrees[j - 1]))
+        return CHFSI_INVALID_ARG;
+    }
+    if (work_bytes < chfsi_defect_split_workspace_bytes(n, k)) return CHFSI_INVALID_ARG;
+    hipStream_t s = as_stream(stream);
+    StepBufs b;
+    Carver cv(work);
+    carve_step(cv, b, n, k, k, 20);
+    void* H32 = cv.take<char>((size_t)n * n * 8);
+    void* Hs = cv.take<char>(split_panel_bytes(n, n));
+    CK(matrix_to_fp32(s, n, (const zc*)H, ldh, H32));
+    CK(matrix_to_split(s, n, (const zc*)H, ldh, Hs));
+    std::vector<int> order(k), m(degrees, degrees + k);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<double> muv(mu, mu + k);
+    const int mmax = m[k - 1];
+    std::vector<char> sched(std::max(mmax, 1), 0);
+    for (int i = 1; i < mmax; ++i) sched[i] = i <= bf16_steps ? 1 : 0;
+    double f32 = 0.0, f16 = 0.0;
+    int launches = 0, steps16 = 0;
+    CKS(defect_filter_dev(s, n, k, H32, (const zc*)Q, (const zc*)Z, n, muv, order, m, c, e, gamma,
+                          b.T1, b.T2, b, &f32, &launches, Hs, &sched, &f16, &steps16));
+    CK(copy2d(s, n, k, b.T2, n, (zc*)Y, ldy));
+    CK(hipStreamSynchronize(s));
+    if (flops_bf16_out) *flops_bf16_out = f16;
+    if (flops_fp32_out) *flops_fp32_out = f32;
+    return CHFSI_OK;
+  } catch (const std::exception& ex) {
+    report_failure(ex.what(), __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
+  } catch (...) {
+    report_failure("unknown exception", __LINE__, -1);
     return CHFSI_DEVICE_ERROR;
   }
 }
@@ -2099,7 +2255,11 @@ int chfsi_orthonormalize(int n, int k, void* Y, int ldy, int nl, const void* QL,
     CK(hipStreamSynchronize(s));
     if (shifted_out) *shifted_out = sh;
     return CHFSI_OK;
+  } catch (const std::exception& ex) {
+    report_failure(ex.what(), __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
   } catch (...) {
+    report_failure("unknown exception", __LINE__, -1);
     return CHFSI_DEVICE_ERROR;
   }
 }
@@ -2121,7 +2281,11 @@ int chfsi_rayleigh_ritz(int n, int k, const void* H, int ldh, void* Q, int ldq, 
     CKS(rayleigh_ritz_dev(s, n, k, (const zc*)H, ldh, b.T1, n, b.T2, n, (zc*)Q, ldq, (zc*)Z, ldz, b,
                           mu, res));
     return CHFSI_OK;
+  } catch (const std::exception& ex) {
+    report_failure(ex.what(), __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
   } catch (...) {
+    report_failure("unknown exception", __LINE__, -1);
     return CHFSI_DEVICE_ERROR;
   }
 }
@@ -2139,7 +2303,11 @@ int chfsi_lanczos_bounds(int n, const void* H, int ldh, int steps, unsigned long
     Carver cv(work);
     carve_step(cv, b, n, 1, 1, 20);
     return lanczos_dev(s, n, (const zc*)H, ldh, steps, seed, b, upper, theta_min, theta_max);
+  } catch (const std::exception& ex) {
+    report_failure(ex.what(), __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
   } catch (...) {
+    report_failure("unknown exception", __LINE__, -1);
     return CHFSI_DEVICE_ERROR;
   }
 }
@@ -2183,7 +2351,11 @@ int chfsi_reduce_standard(int n, const void* A, int lda, const void* B, int ldb,
     CK(copy2d(s, n, n, Hp, n, (zc*)H, ldh));
     CK(hipStreamSynchronize(s));
     return CHFSI_OK;
+  } catch (const std::exception& ex) {
+    report_failure(ex.what(), __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
   } catch (...) {
+    report_failure("unknown exception", __LINE__, -1);
     return CHFSI_DEVICE_ERROR;
   }
 }
@@ -2249,7 +2421,11 @@ int chfsi_degrees_learned(int k, const double* mu, const double* res, int n_want
     return CHFSI_OK;
   } catch (const std::bad_alloc&) {
     return CHFSI_ALLOC_ERROR;
+  } catch (const std::exception& ex) {
+    report_failure(ex.what(), __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
   } catch (...) {
+    report_failure("unknown exception", __LINE__, -1);
     return CHFSI_DEVICE_ERROR;
   }
 }
@@ -2316,7 +2492,11 @@ int chfsi_mlp_train(int n, const float* X, const float* T, float* params, int st
     return CHFSI_OK;
   } catch (const std::bad_alloc&) {
     return CHFSI_ALLOC_ERROR;
+  } catch (const std::exception& ex) {
+    report_failure(ex.what(), __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
   } catch (...) {
+    report_failure("unknown exception", __LINE__, -1);
     return CHFSI_DEVICE_ERROR;
   }
 }
@@ -2357,7 +2537,11 @@ int chfsi_autotune_filter(int count, const int* n, const int* N, void* work, siz
     }
     CK(hipStreamSynchronize(s));
     return CHFSI_OK;
+  } catch (const std::exception& ex) {
+    report_failure(ex.what(), __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
   } catch (...) {
+    report_failure("unknown exception", __LINE__, -1);
     return CHFSI_DEVICE_ERROR;
   }
 }
@@ -2398,7 +2582,11 @@ int chfsi_zgemm(char opa, char opb, int M, int N, int K, const double* alpha, co
              zc{beta[0], beta[1]}, (zc*)C, ldc, false, w, we));
     CK(hipStreamSynchronize(s));
     return CHFSI_OK;
+  } catch (const std::exception& ex) {
+    report_failure(ex.what(), __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
   } catch (...) {
+    report_failure("unknown exception", __LINE__, -1);
     return CHFSI_DEVICE_ERROR;
   }
 }

@@ -156,6 +156,23 @@ int defect_step(hipStream_t s, int n, int N, const void* H32, const void* Ecur, 
 int defect_assemble_launch(hipStream_t s, int n, int k, const zc* Qs, long ld, const void* E0,
                            const void* E1, const int* deg, const double* pm, zc* Y, long ldy);
 
+// ----- BF16-split defect step, cfilter16.hip -----
+// Split panels: rows of a reduction index padded to split_kp(K) (a multiple
+// of 32), 8 bytes per complex value (BF16 hi/lo of the real and imaginary
+// parts, grouped by 8 k).
+int split_kp(int K);
+size_t split_panel_bytes(int rows, int K);
+// Hs row m = split(fp32(H[m, :])).
+int matrix_to_split(hipStream_t s, int n, const zc* H, long ldh, void* Hs);
+// S row j = split(E[:, j]) for j < cols (E complex64, leading dimension lde).
+int cols_to_split(hipStream_t s, int K, int cols, const void* E, long lde, void* S);
+// The defect step of defect_step with H Ecur from the splits Hs and Es (the
+// window's rows of the E_i panel); Es_next (or null) receives the split of
+// Eout for a following BF16 step.  No split-K.
+int defect_step_split(hipStream_t s, int n, int N, const void* Hs, const void* Es,
+                      const void* Ecur, const void* Eold, void* Eout, const void* R32,
+                      const float* cr, float shift, float sa, float sb, void* Es_next);
+
 // ----- degree network (mlp.hip) -----
 // Parameter blob layout (floats); the same layout is documented in chfsi.h.
 constexpr int MLP_IN = 8, MLP_H = 64;

@@ -194,6 +194,75 @@ def test_defect_filter_matches_oracle_with_error_scaling_like_the_residual(delta
     assert f32 == pytest.approx(8.0 * n * n * sum(m - 1 for m in deg))
 
 
+def _ritz_block(n, k, delta, seed):
+    lam, h = _herm_problem(n, seed)
+    q0 = np.linalg.eigh(h)[1][:, :k]
+    q = ochfsi.orthonormalize(q0 + delta * _rand(n, k, seed + 1), np.zeros((n, 0), complex))
+    mu, q, z = ochfsi.rayleigh_ritz(h, q)
+    return lam, h, mu, q, z
+
+
+@pytest.mark.parametrize("n,k", [(333, 70), (1000, 130)])
+def test_bf16_split_step_error_is_within_the_split_precision(n, k):
+    """One BF16-split defect step (every degree 2): E_2 = sa (H E_1 - c E_1)
+    + cr R with H E_1 formed from two-word BF16 splits of H and E_1 (three
+    products).  Each product's dropped split terms are at most 3 * 2^-16
+    |H_ik| |E_kj| (the FP32 accumulation adds far less), so the error of
+    element (i, j) is below 3 * 2^-16 |sa| (|H| |E_1|)_ij; with rounding
+    errors of random sign it is a few 2^-16 |sa| times the root sum of
+    squares of those terms: 2e-4 of it is a 5x margin, which one BF16 word
+    per operand or a dropped cross term (errors about 2^-9 per product)
+    would exceed some 25 times."""
+    lam, h, mu, q, z = _ritz_block(n, k, 1e-3, 41)
+    deg = [2] * k
+    alpha, beta = float(mu[-1]) + 1.0, 41.0
+    c, e, gamma = 0.5 * (alpha + beta), 0.5 * (beta - alpha), float(mu[0])
+    ref = chebyshev.chebyshev_filter(h, q, deg, c, e, gamma)
+    yd, f16, f32 = ch.chfsi_filter_defect_split(dev(h), dev(q), dev(z), mu, deg, c, e, gamma, 1)
+    got = host(yd)
+    sig1 = e / (gamma - c)
+    sig2 = 1.0 / (2.0 / sig1 - sig1)
+    e1 = (sig1 / e) * (z - q * mu)
+    sa = abs(2.0 * sig2 / e)
+    tiny = 1e-12 * np.abs(ref).max()
+    err = np.abs(got - ref)
+    worst = 3.0 * 2.0 ** -16 * sa * (np.abs(h) @ np.abs(e1)) + tiny
+    assert np.all(err <= worst), (err / worst).max()
+    rss = sa * np.sqrt(np.abs(h) ** 2 @ np.abs(e1) ** 2)
+    assert np.all(err <= 2e-4 * rss + tiny), (err / (2e-4 * rss)).max()
+    # the split precision is really coarser than FP32's (the BF16 path ran)
+    assert (err / rss).max() > 2.0 ** -20
+    assert f16 == pytest.approx(8.0 * n * n * k) and f32 == 0.0
+
+
+@pytest.mark.parametrize("delta,n,k,steps", [(1e-3, 700, 40, 99), (1e-6, 700, 40, 99),
+                                             (1e-3, 1000, 200, 4)])
+def test_bf16_split_filter_matches_oracle_with_error_scaling_like_the_residual(delta, n, k,
+                                                                              steps):
+    """The defect filter with its first `steps` steps in BF16-split form
+    (the rest FP32) reproduces the oracle's FP64 filter with the error bound
+    of the FP32 form scaled by the split's precision, 3 * 2^-16 instead of
+    2^-24: it shrinks with the residuals."""
+    lam, h, mu, q, z = _ritz_block(n, k, delta, 23)
+    res = ochfsi.residual_norms(q, z, mu)
+    deg = np.sort(np.random.default_rng(3).integers(2, 20 if k < 100 else 9, k)).tolist()
+    alpha, beta = float(mu[-1]) + 1.0, 41.0
+    c, e, gamma = 0.5 * (alpha + beta), 0.5 * (beta - alpha), float(mu[0])
+    ref = chebyshev.chebyshev_filter(h, q, deg, c, e, gamma)
+    yd, f16, f32 = ch.chfsi_filter_defect_split(dev(h), dev(q), dev(z), mu, deg, c, e, gamma,
+                                                steps)
+    err = rel_col_err(host(yd), ref)
+    norm_h = np.abs(lam).max()
+    growth = (chebyshev.rho(np.array([(gamma - c) / e]))[0]
+              / chebyshev.rho((mu - c) / e)) ** np.array(deg)
+    bound = 1e3 * 3.0 * 2.0 ** -16 * (res / norm_h) * growth + 1e-13
+    assert np.all(err <= bound), (err / bound).max()
+    d = np.array(deg)
+    want16 = sum(int(np.sum(d > i)) for i in range(1, min(steps, d.max() - 1) + 1))
+    assert f16 == pytest.approx(8.0 * n * n * want16)
+    assert f16 + f32 == pytest.approx(8.0 * n * n * sum(m - 1 for m in deg))
+
+
 @pytest.mark.parametrize("variant,k", [(0, 70), (1, 70), (2, 300)])
 def test_filter_tile_variants_match_oracle(variant, k):
     """Every tile variant of the filter step gives the oracle's filter (the

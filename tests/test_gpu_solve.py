@@ -232,16 +232,17 @@ def test_solve_sequence_with_previous_eigenvalues():
         x = xd
 
 
-@pytest.mark.parametrize("with_lambda", [False, True])
-def test_solve_mixed_precision_matches_oracle(with_lambda):
+@pytest.mark.parametrize("with_lambda,precision", [(False, 1), (True, 1), (True, 2)])
+def test_solve_mixed_precision_matches_oracle(with_lambda, precision):
     """precision = 1: filters run in FP32 defect form once residuals allow;
-    the eigenvalues still match the FP64 oracle to 1e-10."""
+    precision = 2 also runs the early steps of those filters with BF16-split
+    products.  The eigenvalues still match the FP64 oracle to 1e-10."""
     conf = gen.CONFIGS["std-n1000"]
     probs = [a.copy() for _, a in gen.Sequence(conf).problems()]
     refs = ochfsi.solve_sequence(probs, conf.nev, conf.nex)
-    o = _opts(precision=1)
+    o = _opts(precision=precision)
     x, lam = None, None
-    used32 = 0
+    used32 = used16 = 0
     for a, ref in zip(probs, refs):
         st, lam, xd, info = ch.chfsi_solve(dev(a), None, conf.nev, conf.nex, conf.tol, X0=x,
                                            Lambda0=lam if (with_lambda and x is not None) else None,
@@ -251,5 +252,7 @@ def test_solve_mixed_precision_matches_oracle(with_lambda):
             RTOL * np.abs(ref.lam[:conf.nev]).min()
         _check_pairs(a, None, lam, host(xd), conf.nev, conf.tol, info["norm_h"])
         used32 += info["filter_iters_fp32"]
+        used16 += info["filter_steps_bf16"]
         x = xd
     assert used32 > 0
+    assert (used16 > 0) == (precision == 2)
