@@ -215,8 +215,9 @@ size_t chfsi_workspace_bytes(int n, int nev, int nex, int generalized, const chf
  *   n, nev, nex  problem size, wanted pairs, extra (guard) vectors; the
  *                block has k = nev + nex columns; 1 <= nev, 1 <= nex,
  *                k <= n.
- *   A, lda       device, n x n Hermitian, read-only (only used as given;
- *                both triangles are read).
+ *   A, lda       device, n x n Hermitian, read-only.  A standard problem
+ *                uses A as given (both triangles); the reduction of a
+ *                generalized problem reads the lower triangle only.
  *   B, ldb       device, n x n Hermitian positive definite, read-only, or
  *                NULL for a standard problem.
  *   tol          residual target (overrides opts->tol); > 0.
@@ -382,7 +383,9 @@ int chfsi_lanczos_bounds(int n, const void* H, int ldh, int steps, unsigned long
                          double* upper, double* theta_min, double* theta_max);
 
 /* Reduction of A x = lambda B x to standard form (Sec. 3.1):
- * B = L L^H (Cholesky), H = L^{-1} A L^{-H} (Hermitian-symmetrised).
+ * B = L L^H (Cholesky), H = L^{-1} A L^{-H}, formed as M + M^H with M =
+ * (L^{-1} T) L^{-H}, T the lower triangle of A with its diagonal halved
+ * (exactly Hermitian; only the lower triangles of A and B are read).
  *   H, ldh  device n x n out.    L, ldl  device n x n out (lower; the
  *   strictly upper part is set to zero).  A and B are read-only.
  * Returns CHFSI_NOT_HPD when the Cholesky factorisation breaks down. */

@@ -118,8 +118,8 @@ __global__ void k_herm_from_lower(int k, zc* G, long ldg) {
   }
 }
 
-// (H + H^H)/2 on 32x32 tile pairs (bi >= bj) through LDS.
-__global__ void k_symmetrize(int n, zc* H, long ldh) {
+// scale (H + H^H) on 32x32 tile pairs (bi >= bj) through LDS.
+__global__ void k_symmetrize(int n, zc* H, long ldh, double scale) {
   __shared__ zc a[32][33], b[32][33];
   const int bi = blockIdx.x, bj = blockIdx.y;
   if (bi < bj) return;
@@ -138,13 +138,27 @@ __global__ void k_symmetrize(int n, zc* H, long ldh) {
     const int row_b = bj * 32 + tx, col_b = bi * 32 + c;
     if (row_a < n && col_a < n) {
       const zc x = a[c][tx], y = b[tx][c];
-      H[row_a + (long)col_a * ldh] = zc{0.5 * (x.x + y.x), 0.5 * (x.y - y.y)};
+      H[row_a + (long)col_a * ldh] = zc{scale * (x.x + y.x), scale * (x.y - y.y)};
     }
     if (row_b < n && col_b < n) {
       const zc x = b[c][tx], y = a[tx][c];
-      H[row_b + (long)col_b * ldh] = zc{0.5 * (x.x + y.x), 0.5 * (x.y - y.y)};
+      H[row_b + (long)col_b * ldh] = zc{scale * (x.x + y.x), scale * (x.y - y.y)};
     }
   }
+}
+
+// D = tril(A) with the diagonal halved (zero above the diagonal).
+__global__ void k_lower_half_diag(int n, const zc* A, long lda, zc* D, long ldd) {
+  const int r = blockIdx.x * NT + threadIdx.x;
+  const int c = blockIdx.y;
+  if (r >= n) return;
+  zc v = zc{0.0, 0.0};
+  if (r > c) v = A[r + (long)c * lda];
+  else if (r == c) {
+    const zc d = A[r + (long)c * lda];
+    v = zc{0.5 * d.x, 0.5 * d.y};
+  }
+  D[r + (long)c * ldd] = v;
 }
 
 __global__ void k_conj_transpose(int n, const zc* src, long lds, zc* dst, long ldd) {
@@ -519,7 +533,20 @@ int herm_from_lower(hipStream_t s, int k, zc* G, long ldg) {
 int symmetrize(hipStream_t s, int n, zc* H, long ldh) {
   if (n <= 0) return 0;
   const unsigned nb = (unsigned)((n + 31) / 32);
-  hipLaunchKernelGGL(k_symmetrize, dim3(nb, nb), dim3(NT), 0, s, n, H, ldh);
+  hipLaunchKernelGGL(k_symmetrize, dim3(nb, nb), dim3(NT), 0, s, n, H, ldh, 0.5);
+  return last();
+}
+
+int add_conj_transpose(hipStream_t s, int n, zc* H, long ldh) {
+  if (n <= 0) return 0;
+  const unsigned nb = (unsigned)((n + 31) / 32);
+  hipLaunchKernelGGL(k_symmetrize, dim3(nb, nb), dim3(NT), 0, s, n, H, ldh, 1.0);
+  return last();
+}
+
+int lower_half_diag(hipStream_t s, int n, const zc* A, long lda, zc* D, long ldd) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(k_lower_half_diag, grid_rows(n, n), dim3(NT), 0, s, n, A, lda, D, ldd);
   return last();
 }
 

@@ -38,11 +38,20 @@ struct GemmArgs {
   int lower_only;    // compute only tiles that meet the lower triangle (incl. diagonal)
   int total_tiles;   // tiles per split (after the lower-only mask)
   int rows_desc;     // visit tile rows in descending order (set by the launcher)
-  int ktri;          // triangular operand: 0 none, 1 op(A) lower (k < m0 + BM),
-                     // 2 op(B) upper (k < n0 + BN), 3 op(A) upper (k >= m0)
+  int ktri;          // triangular operands: 0 none, 1 op(A) lower (k < m0 + BM),
+                     // 2 op(B) upper (k < n0 + BN), 3 op(A) upper (k >= m0),
+                     // 4 op(A) and op(B) lower (n0 <= k < m0 + BM),
+                     // 5 op(A) lower, op(B) upper (k < min(m0 + BM, n0 + BN))
 };
 
-enum KTri { KTRI_NONE = 0, KTRI_A_LOWER = 1, KTRI_B_UPPER = 2, KTRI_A_UPPER = 3 };
+enum KTri {
+  KTRI_NONE = 0,
+  KTRI_A_LOWER = 1,
+  KTRI_B_UPPER = 2,
+  KTRI_A_UPPER = 3,
+  KTRI_AB_LOWER = 4,
+  KTRI_A_LOWER_B_UPPER = 5
+};
 
 // ----- launchers (return hipError_t as int) -------------------------------
 // General complex GEMM C = alpha op(A) op(B) + beta C.  work/work_elems is
@@ -106,6 +115,10 @@ int gather_parity(hipStream_t s, int n, int k, const zc* P0, const zc* P1, long 
 int copy2d(hipStream_t s, int rows, int cols, const zc* src, long lds, zc* dst, long ldd);
 int herm_from_lower(hipStream_t s, int k, zc* G, long ldg);
 int symmetrize(hipStream_t s, int n, zc* H, long ldh);
+// H <- H + H^H in place (exactly Hermitian result).
+int add_conj_transpose(hipStream_t s, int n, zc* H, long ldh);
+// D = lower triangle of A with the diagonal halved, zero above (D != A).
+int lower_half_diag(hipStream_t s, int n, const zc* A, long lda, zc* D, long ldd);
 int conj_transpose(hipStream_t s, int n, const zc* src, long lds, zc* dst, long ldd);
 int zero_upper(hipStream_t s, int n, zc* L, long ldl);
 int set_identity(hipStream_t s, int n, zc* X, long ldx);

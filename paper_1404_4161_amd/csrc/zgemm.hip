@@ -304,6 +304,12 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, 
   if (g.ktri == KTRI_A_LOWER) kend = min(kend, m0 + BM);
   else if (g.ktri == KTRI_B_UPPER) kend = min(kend, n0 + BN);
   else if (g.ktri == KTRI_A_UPPER) kbeg = max(kbeg, m0);
+  else if (g.ktri == KTRI_AB_LOWER) {
+    kbeg = max(kbeg, n0);
+    kend = min(kend, m0 + BM);
+  } else if (g.ktri == KTRI_A_LOWER_B_UPPER) {
+    kend = min(kend, min(m0 + BM, n0 + BN));
+  }
 
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -523,7 +529,7 @@ int launch(hipStream_t s, GemmArgs& g) {
   }
   // rows whose K range is longest first (triangular A with the long rows at
   // the bottom), so the tail of the launch is made of short tiles
-  g.rows_desc = (g.ktri == KTRI_A_LOWER) ? 1 : 0;
+  g.rows_desc = (g.ktri == KTRI_A_LOWER || g.ktri == KTRI_A_LOWER_B_UPPER) ? 1 : 0;
   hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, EPI, KB>), dim3(grid), dim3(NT), 0, s, g);
   return (int)hipGetLastError();
 }
