@@ -441,6 +441,8 @@ def main():
         "filter_share_of_step": round(fsec / elapsed, 3),
         "phase_seconds_per_step": {nm: round(float(v), 4) for nm, v in zip(phase_names, phases)},
         "iters_per_step": [i["iters"] for i in infos],
+        "rr_eigensolves_refined_dense": [sum(i["rr_refined"] for i in infos),
+                                         sum(i["rr_dense"] for i in infos)],
         "b_factor_reused_per_step": [i["b_factor_reused"] for i in infos],
         "roofline": {
             "kernel": "zgemm_kernel<OP_N, OP_N, EPI_CHEB> (Chebyshev filter step)",
@@ -494,6 +496,8 @@ def main():
             "s_per_sequence_step_median": round(statistics.median(lwalls), 4),
             "speedup_vs_fp64_per_step": round(elapsed / lelapsed, 3),
             "iters_per_step": [i["iters"] for i in linfos],
+            "rr_eigensolves_refined_dense": [sum(i["rr_refined"] for i in linfos),
+                                             sum(i["rr_dense"] for i in linfos)],
             "fp32_filter_loops_per_step": [i["filter_iters_fp32"] for i in linfos],
             "filter_matvecs_per_step": [i["filter_matvecs"] for i in linfos],
             "learned_cols": sum(i["learned_cols"] for i in linfos),

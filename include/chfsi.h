@@ -117,7 +117,14 @@ extern "C" {
  *                 where Res_after > 1e3 eps32 Res_before).  On
  *                 input (with X0) the speeds of the previous problem; on
  *                 output this problem's, in the order of Lambda.  Passing
- *                 the array along a sequence carries the calibration. */
+ *                 the array along a sequence carries the calibration.
+ *   rr_refine     1 (default): the k x k eigenproblem of Rayleigh-Ritz is
+ *                 solved by iterative refinement from the identity (the
+ *                 projected matrix is nearly diagonal once the block is
+ *                 close to eigenvectors; close Ritz values are rotated as
+ *                 clusters), with rocSOLVER zheevd as the fallback when it
+ *                 is far from diagonal; 0: zheevd always.  Both give the
+ *                 eigenpairs to rounding (see chfsi_eigh_projected). */
 typedef struct chfsi_opts {
   double tol;
   int deg0;
@@ -135,6 +142,7 @@ typedef struct chfsi_opts {
   double* log;
   const float* mlp;
   double* seq_rates;
+  int rr_refine;
 } chfsi_opts;
 
 /* Per-solve statistics (all optional to read).
@@ -165,6 +173,8 @@ typedef struct chfsi_info {
   int learned_raised;      /* network degrees above the rule's degree            */
   int filter_steps_bf16;   /* defect-filter steps run with BF16-split products   */
   double filter_flops_bf16;/* 8 n^2 per column of those steps                    */
+  int rr_refined;          /* Rayleigh-Ritz eigenproblems solved by refinement   */
+  int rr_dense;            /* ... and by the dense eigensolver (zheevd)          */
 } chfsi_info;
 
 /* Convergence log record (CHFSI_LOG_FIELDS doubles), one per wanted vector
@@ -352,6 +362,25 @@ int chfsi_filter_defect_split(int n, int k, const void* H, int ldh, const void* 
                               double c, double e, double gamma, int bf16_steps, void* Y, int ldy,
                               void* work, size_t work_bytes, void* stream,
                               double* flops_bf16_out, double* flops_fp32_out);
+
+/* The k x k Hermitian eigenproblem of Rayleigh-Ritz, G W = W diag(mu)
+ * with mu ascending and W unitary (Alg. 1, RAYLEIGH-RITZ).
+ *   mode 0: rocSOLVER zheevd.  1: iterative refinement from W = I (each
+ *   step: S = W^H G W, R = I - W^H W, lam_i = s_ii / (1 - r_ii), W <- W (I
+ *   + F) with f_ii = r_ii / 2, f_ij = (s_ij + lam_j r_ij) / (lam_j - lam_i)
+ *   and f_ji = r_ji - conj(f_ij) for i < j when the coupling is below 0.1
+ *   of the gap; pairs coupled more strongly are grouped into clusters whose
+ *   blocks are diagonalised by Jacobi rotations), falling back to zheevd
+ *   when G is far from diagonal (clusters over 32 columns or over half the
+ *   block, or no convergence in 10 steps).  2: refinement only
+ *   (CHFSI_NO_CONVERGENCE instead of the fallback).
+ *   G, ldg      device k x k Hermitian (read-only; both triangles used).
+ *   W, ldw      device k x k out.   mu  HOST, k doubles out.
+ *   refined_out NULL or 1 when the refinement gave the result.
+ *   work        device, >= chfsi_eigh_workspace_bytes(k). */
+size_t chfsi_eigh_workspace_bytes(int k);
+int chfsi_eigh_projected(int k, const void* G, int ldg, void* W, int ldw, double* mu, int mode,
+                         void* work, size_t work_bytes, void* stream, int* refined_out);
 
 /* Orthonormalise the n x k block Y against the n x nl locked block QL
  * (two projection passes, QL^H QL = I assumed) and then by CholeskyQR2,

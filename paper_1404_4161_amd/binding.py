@@ -32,7 +32,7 @@ class ChfsiOpts(Structure):
                 ("reuse_b_factor", c_int), ("precision", c_int), ("seed", c_ulonglong),
                 ("degree_jitter", c_double), ("first_rule", c_int), ("log_capacity", c_int),
                 ("log", POINTER(c_double)), ("mlp", POINTER(c_float)),
-                ("seq_rates", POINTER(c_double))]
+                ("seq_rates", POINTER(c_double)), ("rr_refine", c_int)]
 
 
 class ChfsiInfo(Structure):
@@ -46,7 +46,8 @@ class ChfsiInfo(Structure):
                 ("step_seconds", c_double * 8), ("filter_flops_fp32", c_double),
                 ("filter_seconds_fp32", c_double), ("log_records", c_int),
                 ("learned_cols", c_int), ("fallback_cols", c_int), ("learned_raised", c_int),
-                ("filter_steps_bf16", c_int), ("filter_flops_bf16", c_double)]
+                ("filter_steps_bf16", c_int), ("filter_flops_bf16", c_double),
+                ("rr_refined", c_int), ("rr_dense", c_int)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "step_seconds"}
@@ -84,6 +85,9 @@ _SIGS = {
                                           c_double, c_double, c_double, c_int, c_void_p, c_int,
                                           c_void_p, c_size_t, c_void_p, POINTER(c_double),
                                           POINTER(c_double)]),
+    "chfsi_eigh_workspace_bytes": (c_size_t, [c_int]),
+    "chfsi_eigh_projected": (c_int, [c_int, c_void_p, c_int, c_void_p, c_int, POINTER(c_double),
+                                     c_int, c_void_p, c_size_t, c_void_p, POINTER(c_int)]),
     "chfsi_orthonormalize": (c_int, [c_int, c_int, c_void_p, c_int, c_int, c_void_p, c_int,
                                      c_void_p, c_size_t, c_void_p, POINTER(c_int)]),
     "chfsi_rayleigh_ritz": (c_int, [c_int, c_int, c_void_p, c_int, c_void_p, c_int, c_void_p,
@@ -325,6 +329,25 @@ def chfsi_filter_defect_split(H, Q, Z, mu, degrees, c, e, gamma, bf16_steps, Y=N
                                            ctypes.byref(f16), ctypes.byref(f32)),
            "chfsi_filter_defect_split")
     return Y, f16.value, f32.value
+
+
+def chfsi_eigh_projected(G, mode=1, W=None, work=None, stream=None):
+    """Eigenpairs of the k x k Hermitian device matrix G (Rayleigh-Ritz's
+    projected problem): mode 0 zheevd, 1 refinement with zheevd fallback,
+    2 refinement only.  Returns (mu ascending numpy, W column-major tensor,
+    refined flag)."""
+    torch = _torch()
+    k = G.shape[0]
+    if W is None:
+        W = colmajor(torch.empty((k, k), dtype=torch.complex128, device=G.device))
+    mu = (c_double * k)()
+    wb = int(lib().chfsi_eigh_workspace_bytes(k))
+    w = _work(wb, G.device, work)
+    ref = c_int(0)
+    _check(lib().chfsi_eigh_projected(k, _ptr(G), _ld(G), _ptr(W), _ld(W), mu, int(mode), _ptr(w),
+                                      wb, _stream(stream, G.device), ctypes.byref(ref)),
+           "chfsi_eigh_projected")
+    return np.array(mu[:]), W, ref.value
 
 
 def chfsi_orthonormalize(Y, QL=None, work=None, stream=None):

@@ -111,6 +111,7 @@ struct StepBufs {
   float* crtab;                 // CR_ROWS x k coefficients of the residual term
   double* pm;                   // k final scalars p_{m_j}(mu_t)
   float *mlp_p, *mlp_x, *mlp_y;  // degree network: parameters, k x 8 inputs, k outputs
+  EigRefineBufs ref;            // projected eigenproblem by refinement
   double *mu, *res, *nrm, *E, *alph, *bet, *dummy;
   int *perm, *deg, *info;
   size_t scratch_elems;
@@ -153,6 +154,15 @@ void carve_step(Carver& c, StepBufs& b, int n, int k, int nev, int lanczos_steps
   b.mlp_p = c.take<float>(MLP_PARAMS);
   b.mlp_x = c.take<float>((size_t)MLP_IN * k);
   b.mlp_y = c.take<float>(k);
+  b.ref.mat = c.take<zc>(eig_refine_elems(k));
+  b.ref.lam = c.take<double>(k);
+  b.ref.stats = c.take<unsigned long long>(4);
+  b.ref.pair_cap = 4 * k + 256;
+  b.ref.pairs = c.take<int2>(b.ref.pair_cap);
+  b.ref.entry_cap = 16 * k + 256;
+  b.ref.idx = c.take<int2>(b.ref.entry_cap);
+  b.ref.val = c.take<zc>(b.ref.entry_cap);
+  b.ref.perm = c.take<int>(k);
 }
 
 // ---------------------------------------------------------------------------
@@ -409,17 +419,21 @@ int orthonormalize_dev(hipStream_t s, int n, int k, zc* Y, long ldy, int nl, con
   return CHFSI_NOT_HPD;
 }
 
-// Rayleigh-Ritz on the orthonormal block Q (n x k):
-// Z = H Q, G = Q^H Z, G W = W diag(mu), Qout = Q W, Zout = Z W,
-// res_j = ||Zout_j - mu_j Qout_j||.  mu_h/res_h are host outputs.  Qout and
-// Zout must not overlap Q or Z.
-int rayleigh_ritz_dev(hipStream_t s, int n, int k, const zc* H, long ldh, const zc* Q, long ldq,
-                      zc* Z, long ldz, zc* Qout, long ldqo, zc* Zout, long ldzo, StepBufs& b,
-                      double* mu_h, double* res_h) {
-  CK(zgemm(s, OP_N, OP_N, n, k, n, ONE, H, ldh, Q, ldq, ZERO, Z, ldz, false, nullptr, 0));
-  CK(zgemm(s, OP_C, OP_N, k, k, n, ONE, Q, ldq, Z, ldz, ZERO, b.G, k, true, b.scratch,
-           b.scratch_elems));
-  CK(herm_from_lower(s, k, b.G, k));
+// The k x k Hermitian eigenproblem of Rayleigh-Ritz on b.G (ld k).
+// refine 1: iterative refinement from the identity (eigref.hip), with
+// rocSOLVER zheevd as the fallback; 0: zheevd only; 2: refinement only
+// (CHFSI_NO_CONVERGENCE when it does not converge).  Eigenvalues go to b.mu
+// (ascending); the eigenvectors to b.K2 when refined (*refined = 1), else
+// over b.G.
+int eigh_projected(hipStream_t s, int k, StepBufs& b, int refine, int* refined) {
+  int ok = 0;
+  if (refine != 0) {
+    int iters = 0;
+    CK(eig_refine(s, k, b.G, k, b.K2, k, b.mu, b.ref, &ok, &iters));
+    if (!ok && refine == 2) return CHFSI_NO_CONVERGENCE;
+  }
+  if (refined) *refined = ok;
+  if (ok) return CHFSI_OK;
   {
     std::unique_lock<std::mutex> lk(g_handle_mu, std::defer_lock);
     rocblas_handle h = tl_handle;
@@ -431,17 +445,37 @@ int rayleigh_ritz_dev(hipStream_t s, int n, int k, const zc* H, long ldh, const 
     CK(rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_lower, k,
                         (rocblas_double_complex*)b.G, k, b.mu, b.E, b.info));
   }
-  CK(zgemm(s, OP_N, OP_N, n, k, k, ONE, Q, ldq, b.G, k, ZERO, Qout, ldqo, false, nullptr, 0));
-  CK(zgemm(s, OP_N, OP_N, n, k, k, ONE, Z, ldz, b.G, k, ZERO, Zout, ldzo, false, nullptr, 0));
-  CK(resid_norms(s, n, k, Qout, ldqo, Zout, ldzo, b.mu, b.res));
   int info = 0;
-  CK(hipMemcpyAsync(mu_h, b.mu, sizeof(double) * k, hipMemcpyDeviceToHost, s));
-  CK(hipMemcpyAsync(res_h, b.res, sizeof(double) * k, hipMemcpyDeviceToHost, s));
   CK(hipMemcpyAsync(&info, b.info, sizeof(int), hipMemcpyDeviceToHost, s));
   CK(hipStreamSynchronize(s));
   CK(info);   // zheevd did not converge
   return CHFSI_OK;
 }
+
+// Rayleigh-Ritz on the orthonormal block Q (n x k):
+// Z = H Q, G = Q^H Z, G W = W diag(mu), Qout = Q W, Zout = Z W,
+// res_j = ||Zout_j - mu_j Qout_j||.  mu_h/res_h are host outputs.  Qout and
+// Zout must not overlap Q or Z.
+int rayleigh_ritz_dev(hipStream_t s, int n, int k, const zc* H, long ldh, const zc* Q, long ldq,
+                      zc* Z, long ldz, zc* Qout, long ldqo, zc* Zout, long ldzo, StepBufs& b,
+                      double* mu_h, double* res_h, int refine = 1, int* refined_out = nullptr) {
+  CK(zgemm(s, OP_N, OP_N, n, k, n, ONE, H, ldh, Q, ldq, ZERO, Z, ldz, false, nullptr, 0));
+  CK(zgemm(s, OP_C, OP_N, k, k, n, ONE, Q, ldq, Z, ldz, ZERO, b.G, k, true, b.scratch,
+           b.scratch_elems));
+  CK(herm_from_lower(s, k, b.G, k));
+  int refined = 0;
+  CKS(eigh_projected(s, k, b, refine, &refined));
+  if (refined_out) *refined_out = refined;
+  const zc* Wv = refined ? b.K2 : b.G;
+  CK(zgemm(s, OP_N, OP_N, n, k, k, ONE, Q, ldq, Wv, k, ZERO, Qout, ldqo, false, nullptr, 0));
+  CK(zgemm(s, OP_N, OP_N, n, k, k, ONE, Z, ldz, Wv, k, ZERO, Zout, ldzo, false, nullptr, 0));
+  CK(resid_norms(s, n, k, Qout, ldqo, Zout, ldzo, b.mu, b.res));
+  CK(hipMemcpyAsync(mu_h, b.mu, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  CK(hipMemcpyAsync(res_h, b.res, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+  return CHFSI_OK;
+}
+
 
 // Lanczos with full reorthogonalisation; returns bounds on the host.
 int lanczos_dev(hipStream_t s, int n, const zc* H, long ldh, int steps, unsigned long long seed,
@@ -1028,7 +1062,7 @@ struct Solve {
   int it = 0;
   int status = CHFSI_NO_CONVERGENCE;
   double filter_flops = 0.0, filter_sec = 0.0, flops32 = 0.0, sec32 = 0.0, flops16 = 0.0;
-  int iters32 = 0, launches = 0, steps16 = 0;
+  int iters32 = 0, launches = 0, steps16 = 0, rr_refined = 0, rr_dense = 0;
   bool have_res = false;   // residuals of the current block known
   hipEvent_t fe0 = nullptr, fe1 = nullptr;
   bool done = false;
@@ -1144,8 +1178,10 @@ struct Solve {
       CKS(orthonormalize_dev(s, n, k, b.TMP, ld, 0, nullptr, ld, b.QA, ld, sb, &shifted));
       tm.end();
       tm.begin(4);
+      int refined = 0;
       CKS(rayleigh_ritz_dev(s, n, k, H, ldh, b.QA, ld, b.ZA, ld, b.P0, ld, b.P1, ld, sb,
-                            mu.data(), res.data()));
+                            mu.data(), res.data(), o.rr_refine, &refined));
+      ++(refined ? rr_refined : rr_dense);
       std::swap(b.QA, b.P0);
       std::swap(b.ZA, b.P1);
       tm.end();
@@ -1387,8 +1423,10 @@ struct Solve {
     tm.end();
     // Rayleigh-Ritz (the RAYLEIGH-RITZ steps of Alg. 1) and residuals
     tm.begin(4);
+    int refined = 0;
     CKS(rayleigh_ritz_dev(s, n, ka, H, ldh, b.QA, ld, b.ZA, ld, b.P0, ld, b.P1, ld, sb,
-                          mu.data(), res.data()));
+                          mu.data(), res.data(), o.rr_refine, &refined));
+    ++(refined ? rr_refined : rr_dense);
     std::swap(b.QA, b.P0);
     std::swap(b.ZA, b.P1);
     tm.end();
@@ -1536,6 +1574,8 @@ struct Solve {
       info->learned_cols = learned_cols;
       info->fallback_cols = fallback_cols;
       info->learned_raised = learned_raised;
+      info->rr_refined = rr_refined;
+      info->rr_dense = rr_dense;
       info->total_seconds = elapsed(t_start);
     }
     return status;
@@ -1922,6 +1962,7 @@ int validate_solve(int n, int nev, int nex, const void* A, int lda, const void* 
     if (X0 && (ldx0 < n || !aligned16(X0))) return CHFSI_INVALID_ARG;
     if (o.deg0 < 1 || o.deg_max < 1 || o.max_iter < 1 || o.lanczos_steps < 1) return CHFSI_INVALID_ARG;
     if (o.precision < 0 || o.precision > 2) return CHFSI_INVALID_ARG;
+    if (o.rr_refine < 0 || o.rr_refine > 1) return CHFSI_INVALID_ARG;
     if (o.degree_mode < 0 || o.degree_mode > 3 || o.first_rule < 0 || o.first_rule > 1)
       return CHFSI_INVALID_ARG;
     if (o.degree_mode == 3 && !o.seq_rates) return CHFSI_INVALID_ARG;
@@ -1971,6 +2012,7 @@ int chfsi_default_opts(chfsi_opts* o) {
   o->log = nullptr;
   o->mlp = nullptr;
   o->seq_rates = nullptr;
+  o->rr_refine = 1;
   return CHFSI_OK;
 }
 
@@ -2102,6 +2144,35 @@ size_t chfsi_step_workspace_bytes(int n, int k) {
   Carver c(nullptr);
   carve_step(c, b, n, k, k, 20);
   return c.off + ALIGN;
+}
+
+size_t chfsi_eigh_workspace_bytes(int k) { return chfsi_step_workspace_bytes(k, k); }
+
+int chfsi_eigh_projected(int k, const void* G, int ldg, void* W, int ldw, double* mu, int mode,
+                         void* work, size_t work_bytes, void* stream, int* refined_out) {
+  try {
+    if (k < 1 || ldg < k || ldw < k || !mu || mode < 0 || mode > 2) return CHFSI_INVALID_ARG;
+    if (check_ptr(G) || check_ptr(W) || check_ptr(work)) return CHFSI_INVALID_ARG;
+    if (work_bytes < chfsi_eigh_workspace_bytes(k)) return CHFSI_INVALID_ARG;
+    hipStream_t s = as_stream(stream);
+    StepBufs b;
+    Carver cv(work);
+    carve_step(cv, b, k, k, k, 20);
+    CK(copy2d(s, k, k, (const zc*)G, ldg, b.G, k));
+    int refined = 0;
+    CKS(eigh_projected(s, k, b, mode, &refined));
+    CK(copy2d(s, k, k, refined ? b.K2 : b.G, k, (zc*)W, ldw));
+    CK(hipMemcpyAsync(mu, b.mu, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    if (refined_out) *refined_out = refined;
+    return CHFSI_OK;
+  } catch (const std::exception& ex) {
+    report_failure(ex.what(), __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
+  } catch (...) {
+    report_failure("unknown exception", __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
+  }
 }
 
 int chfsi_filter(int n, int k, const void* H, int ldh, void* Y, int ldy, const int* degrees,

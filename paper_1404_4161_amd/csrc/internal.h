@@ -186,6 +186,27 @@ int defect_step_split(hipStream_t s, int n, int N, const void* Hs, const void* E
                       const void* Ecur, const void* Eold, void* Eout, const void* R32,
                       const float* cr, float shift, float sa, float sb, void* Es_next);
 
+// ----- projected eigenproblem by iterative refinement, eigref.hip -----
+struct EigRefineBufs {
+  zc* mat;                    // 7 k x k work matrices
+  double* lam;                // k
+  unsigned long long* stats;  // 4
+  int2* pairs;                // pair_cap strongly coupled pairs
+  int pair_cap;
+  int2* idx;                  // entry_cap cluster-block entries
+  zc* val;
+  int entry_cap;
+  int* perm;                  // k
+};
+size_t eig_refine_elems(int k);
+// Eigenvectors W (k x k, ld ldw, columns ascending) and eigenvalues mu
+// (device, k, ascending) of the Hermitian G (ld ldg, read-only) by
+// refinement from the identity.  *refined = 0 (and W, mu untouched) when
+// G is too far from diagonal or the refinement does not converge: the
+// caller then uses a dense eigensolver.  Returns a HIP error code.
+int eig_refine(hipStream_t s, int k, const zc* G, long ldg, zc* W, long ldw, double* mu,
+               EigRefineBufs& rb, int* refined, int* iterations);
+
 // ----- degree network (mlp.hip) -----
 // Parameter blob layout (floats); the same layout is documented in chfsi.h.
 constexpr int MLP_IN = 8, MLP_H = 64;

@@ -132,6 +132,12 @@ def test_learned_degree_options_defaults_and_validation():
         return lib.chfsi_solve(10, 2, 2, dummy, 10, None, 0, 1e-10, None, 0, None, lam, dummy, 10,
                                dummy, 1 << 30, ctypes.byref(oo), None, None)
 
+    assert ch.chfsi_default_opts().rr_refine == 1
+    assert solve_with(rr_refine=2) == ch.binding.CHFSI_INVALID_ARG
+    assert lib.chfsi_eigh_projected(4, dummy, 4, dummy, 4, lam, 3, dummy, 1 << 30, None,
+                                    None) == ch.binding.CHFSI_INVALID_ARG
+    assert lib.chfsi_eigh_projected(4, dummy, 3, dummy, 4, lam, 1, dummy, 1 << 30, None,
+                                    None) == ch.binding.CHFSI_INVALID_ARG
     assert solve_with(precision=3) == ch.binding.CHFSI_INVALID_ARG
     assert solve_with(precision=2, deg_max=300) == ch.binding.CHFSI_INVALID_ARG
     assert solve_with(degree_mode=3) == ch.binding.CHFSI_INVALID_ARG

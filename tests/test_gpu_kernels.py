@@ -132,6 +132,72 @@ def test_rayleigh_ritz_and_residuals_match_oracle(n, k):
     assert np.abs(qg.conj().T @ qg - np.eye(k)).max() < 1e-12
 
 
+def _projected(k, kind, seed):
+    """k x k Hermitian test matrices for the projected eigenproblem:
+    'dense' random, 'near' a separated diagonal plus a 1e-6 coupling,
+    'clustered' a spectrum with close (gaps 1e-5, 1e-7, 1e-10) and exactly
+    degenerate pairs and a triple, mixed by rotations inside those groups,
+    plus a 1e-8 coupling (what Rayleigh-Ritz sees in the loops of a
+    warm-started sequence)."""
+    g = np.random.default_rng(seed)
+
+    def herm(scale):
+        a = g.standard_normal((k, k)) + 1j * g.standard_normal((k, k))
+        return scale * 0.5 * (a + a.conj().T)
+
+    if kind == "dense":
+        return herm(1.0)
+    d = np.sort(np.concatenate([g.uniform(-20, -15, k - k // 6), g.uniform(-15, -14, k // 6)]))
+    if kind == "near":
+        m = np.diag(d).astype(complex) + herm(1e-6)
+        return 0.5 * (m + m.conj().T)
+    d[10] = d[9] + 1e-5
+    d[21] = d[20] + 1e-7
+    d[31] = d[30] + 1e-10
+    d[41] = d[40]
+    d[51], d[52] = d[50] + 1e-9, d[50] + 2e-9
+    q = np.eye(k, dtype=complex)
+    for i, j in [(9, 10), (20, 21), (30, 31), (40, 41), (50, 51), (51, 52)]:
+        th, ph = g.uniform(0.2, 1.3), np.exp(1j * g.uniform(0, 6.2))
+        r = np.eye(k, dtype=complex)
+        r[i, i], r[i, j], r[j, i], r[j, j] = (np.cos(th), np.sin(th) * ph,
+                                              -np.sin(th) * np.conj(ph), np.cos(th))
+        q = q @ r
+    m = q @ np.diag(d) @ q.conj().T + herm(1e-8)
+    return 0.5 * (m + m.conj().T)
+
+
+@pytest.mark.parametrize("kind,k", [("dense", 100), ("near", 1), ("near", 70), ("near", 480),
+                                    ("clustered", 130), ("clustered", 480)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_projected_eigenproblem_matches_oracle(kind, k, mode):
+    """Rayleigh-Ritz's k x k eigenproblem: the dense solver (mode 0) and the
+    refinement from the identity with its fallback (mode 1) both give the
+    oracle's eigenvalues to 1e-13 of ||G||, a unitary W to 1e-13 and
+    residuals ||G W - W diag(mu)|| to 1e-13 ||G||; the refinement is the one
+    that answers on the nearly diagonal matrices (with their clusters), the
+    fallback on the dense one."""
+    gm = _projected(k, kind, 5 + k)
+    ref = eigh.eigvalsh(gm)
+    mu, wd, refined = ch.chfsi_eigh_projected(dev(gm), mode=mode)
+    w = host(wd)
+    scale = np.abs(ref).max()
+    assert np.all(np.diff(mu) >= 0)
+    assert np.abs(mu - ref).max() <= 1e-13 * scale
+    assert np.abs(w.conj().T @ w - np.eye(k)).max() <= 1e-13
+    assert np.abs(gm @ w - w * mu).max() <= 1e-13 * scale
+    assert refined == (mode == 1 and kind != "dense")
+
+
+def test_projected_eigenproblem_refinement_only_reports_failure():
+    gm = _projected(64, "dense", 3)
+    with pytest.raises(ch.ChfsiError) as ei:
+        ch.chfsi_eigh_projected(dev(gm), mode=2)
+    assert ei.value.status == ch.binding.CHFSI_NO_CONVERGENCE
+    mu, _, refined = ch.chfsi_eigh_projected(dev(_projected(64, "near", 3)), mode=2)
+    assert refined == 1
+
+
 @pytest.mark.parametrize("n", [5, 300, 1000])
 def test_lanczos_bounds_match_oracle(n):
     lam, h = _herm_problem(n, 13)

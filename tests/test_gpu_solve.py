@@ -62,7 +62,7 @@ def test_solve_std_n1000_sequence_warm_start():
     probs = [a.copy() for _, a in seq.problems()]
     refs = ochfsi.solve_sequence(probs, conf.nev, conf.nex)
     x = None
-    iters = []
+    iters, refined = [], []
     for l, (a, ref) in enumerate(zip(probs, refs)):
         st, lam, xd, info = ch.chfsi_solve(dev(a), None, conf.nev, conf.nex, conf.tol, X0=x)
         assert st == 0
@@ -70,11 +70,16 @@ def test_solve_std_n1000_sequence_warm_start():
             RTOL * np.abs(ref.lam[:conf.nev]).min()
         _check_pairs(a, None, lam, host(xd), conf.nev, conf.tol, info["norm_h"])
         iters.append(info["matvecs"])
+        refined.append((info["rr_refined"], info["rr_dense"]))
         x = xd
     lam1 = seq.lam[:conf.nev]
     assert np.abs(refs[0].lam[:conf.nev] - lam1).max() <= RTOL * np.abs(lam1).min()
     # warm starts need far fewer mat-vecs than the cold first problem (Sec. 4.2)
     assert max(iters[1:]) < 0.5 * iters[0]
+    # the cold start's first Rayleigh-Ritz needs the dense eigensolver; in
+    # the warm-started problems the projected matrices are nearly diagonal
+    assert refined[0][1] >= 1
+    assert all(r > 0 for r, _ in refined[1:]), refined
 
 
 def test_solve_generalized_sequence_against_dense_oracle():
