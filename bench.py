@@ -38,8 +38,8 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 # copy, per tile variant of the step kernel; valid only for the kernel
 # source it was measured on.
 TRAFFIC_MEASURED = {
-    "zgemm_sha256": "b5ca74ccbdf3ae5ba5ccd621dd435a0cc53f8c8144f919e4da1010122d255f7b",
-    "bytes_per_full_width_step": {0: 4.657e9, 1: 2.361e9, 2: 1.697e9},
+    "zgemm_sha256": "4b3bbe5004f1589c71d62e9da39c122766b6a1084a973acd8eda92b51fc758f7",
+    "bytes_per_full_width_step": {0: 4.530e9, 1: 2.393e9, 2: 1.697e9},
     "algorithmic_bytes_per_full_width_step": 1.208e9,
 }
 
@@ -104,10 +104,22 @@ def filter_only(conf, degree):
     t = time.perf_counter()
     flops, launches = ch.chfsi_filter(h, y, [degree] * k, 0.0, nrm, -1.05 * nrm)
     dt = time.perf_counter() - t
+    # then the defect filter at the same shape with every step in BF16-split
+    # form (the Ritz-pair inputs do not change its cost)
+    q = ch.colmajor(torch.linalg.qr(y)[0])
+    z = ch.colmajor(h @ q)
+    mu = np.linspace(-1.2 * nrm, -1.1 * nrm, k)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, f16, _ = ch.chfsi_filter_defect_split(h, q, z, mu, [degree] * k, 0.0, nrm, -1.3 * nrm,
+                                             degree)
+    dt16 = time.perf_counter() - t
     print(json.dumps({"mode": "filter-only", "n": n, "k": k, "degree": degree,
                       "variant": int(v[0]),
                       "launches": launches, "seconds": round(dt, 6),
                       "tflops_wall": round(flops / dt / 1e12, 3),
+                      "bf16_split_defect_seconds": round(dt16, 6),
+                      "bf16_split_defect_tflops_wall": round(f16 / dt16 / 1e12, 3),
                       "copy_bytes": src.numel() * 8}), flush=True)
 
 
