@@ -35,7 +35,8 @@ typedef float2 cf;
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int SBM = 64, SBN = 64, SBK = 32, SNT = 256;
+constexpr int SBK = 32;                        // K per LDS stage
+constexpr int SPLIT_WIDE_MIN_N = 257;          // windows that take the 128 x 128 tile
 constexpr int GROUP_B = 64;                    // bytes per (row, 8 k) group
 constexpr int ROWB = (SBK / 8) * GROUP_B + 16; // LDS bytes per tile row (+16 B pad)
 constexpr int NXCD = 8;
@@ -97,52 +98,69 @@ struct SplitArgs {
   int tiles_m, tiles_n;
 };
 
-// One defect step: 64 x 64 complex output tiles, 4 waves of 32 x 32, K
-// staged 32 deep (two stages of 2 x 64 rows x 272 B of LDS: 68 KB, two
-// workgroups per CU); tile rows interleaved over the 8 XCDs.
-__global__ void __launch_bounds__(SNT, 2) defect_gemm_split(SplitArgs g) {
-  __shared__ __attribute__((aligned(16))) char lds[2][2][SBM * ROWB];
+// One defect step on tiles of BM x BN complex outputs: WGM x WGN waves, each
+// owning TI x TJ sub-tiles of 16 x 16 (BM = 16 WGM TI, BN = 16 WGN TJ), K
+// staged 32 deep through two LDS stages of (BM + BN) rows x 272 B; tile rows
+// interleaved over the 8 XCDs.  Instances: 64 x 64 with 4 waves of 32 x 32
+// (68 KB of LDS, two workgroups per CU) and 128 x 128 with 8 waves of 32 x
+// 64 (136 KB, one per CU: half the operand traffic per output and a third
+// fewer LDS reads per MFMA).
+template <int WGM, int WGN, int TI, int TJ>
+struct SplitTile {
+  static constexpr int BM = 16 * WGM * TI, BN = 16 * WGN * TJ;
+  static constexpr int NTH = 64 * WGM * WGN;
+  static constexpr int LDS_STAGE = (BM + BN) * ROWB;
+  static constexpr int CHUNKS = (BM + BN) * 16 / NTH;   // 16-byte staging loads per thread
+};
+
+template <int WGM, int WGN, int TI, int TJ>
+__device__ __forceinline__ void split_tile_body(const SplitArgs& g, char* lds) {
+  using T = SplitTile<WGM, WGN, TI, TJ>;
+  constexpr int BM = T::BM, BN = T::BN, NTH = T::NTH, CH = T::CHUNKS;
   const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
   const int rows_x = (g.tiles_m - xcd + NXCD - 1) / NXCD;
   const int ri = slot / g.tiles_n;
   const int tn = slot - ri * g.tiles_n;
   if (ri >= rows_x) return;
   const int tm = xcd + NXCD * ri;
-  const int m0 = tm * SBM, n0 = tn * SBN;
+  const int m0 = tm * BM, n0 = tn * BN;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % WGM, wn = wave / WGM;
   const int lr = lane & 15, lg = lane >> 4;
 
-  f4 accR[2][2], accI[2][2];
+  f4 accR[TI][TJ], accI[TI][TJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < TJ; ++j) {
       accR[i][j] = f4{0.f, 0.f, 0.f, 0.f};
       accI[i][j] = f4{0.f, 0.f, 0.f, 0.f};
     }
-  // staging: 16 chunks of 16 B per tile row and stage; 4 chunks of each
-  // operand per thread
-  uint4 ra[4], rb[4];
+  // staging: 16 chunks of 16 B per tile row and stage; chunk c < BM * 16 is
+  // an A row, the rest B rows
+  uint4 rs[CH];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int c = t + SNT * i;
+    for (int i = 0; i < CH; ++i) {
+      const int c = t + NTH * i;
       const int row = c >> 4, ch = c & 15;
       const long koff = (long)k0 * 8 + ch * 16;
-      const int gm = m0 + row, gn = n0 + row;
-      ra[i] = gm < g.M ? *(const uint4*)(g.As + gm * g.a_row + koff) : uint4{0u, 0u, 0u, 0u};
-      rb[i] = gn < g.N ? *(const uint4*)(g.Bs + gn * g.b_row + koff) : uint4{0u, 0u, 0u, 0u};
+      if (row < BM) {
+        const int gm = m0 + row;
+        rs[i] = gm < g.M ? *(const uint4*)(g.As + gm * g.a_row + koff) : uint4{0u, 0u, 0u, 0u};
+      } else {
+        const int gn = n0 + row - BM;
+        rs[i] = gn < g.N ? *(const uint4*)(g.Bs + gn * g.b_row + koff) : uint4{0u, 0u, 0u, 0u};
+      }
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int c = t + SNT * i;
+    for (int i = 0; i < CH; ++i) {
+      const int c = t + NTH * i;
       const int row = c >> 4, ch = c & 15;
-      *(uint4*)(&lds[buf][0][row * ROWB + ch * 16]) = ra[i];
-      *(uint4*)(&lds[buf][1][row * ROWB + ch * 16]) = rb[i];
+      *(uint4*)(lds + buf * T::LDS_STAGE + row * ROWB + ch * 16) = rs[i];
     }
   };
   const int nk = g.Kp / SBK;
@@ -155,16 +173,18 @@ __global__ void __launch_bounds__(SNT, 2) defect_gemm_split(SplitArgs g) {
     const int cur = kt & 1;
     const bool more = kt + 1 < nk;
     if (more) load((kt + 1) * SBK);
-    uint4 a[2][4], b[2][4];
+    const char* la = lds + cur * T::LDS_STAGE;
+    const char* lb = la + BM * ROWB;
+    uint4 a[TI][4], b[TJ][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const char* p = &lds[cur][0][(wm * 32 + i * 16 + lr) * ROWB + lg * GROUP_B];
+    for (int i = 0; i < TI; ++i) {
+      const char* p = la + (wm * 16 * TI + i * 16 + lr) * ROWB + lg * GROUP_B;
 #pragma unroll
       for (int q = 0; q < 4; ++q) a[i][q] = *(const uint4*)(p + 16 * q);
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const char* p = &lds[cur][1][(wn * 32 + j * 16 + lr) * ROWB + lg * GROUP_B];
+    for (int j = 0; j < TJ; ++j) {
+      const char* p = lb + (wn * 16 * TJ + j * 16 + lr) * ROWB + lg * GROUP_B;
 #pragma unroll
       for (int q = 0; q < 4; ++q) b[j][q] = *(const uint4*)(p + 16 * q);
     }
@@ -172,12 +192,12 @@ __global__ void __launch_bounds__(SNT, 2) defect_gemm_split(SplitArgs g) {
     // real part: Ar Br - Ai Bi (the A imaginary planes negated)
     // imaginary part: Ar Bi + Ai Br
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < TI; ++i) {
       const bf8 arh = as_bf8(a[i][0]), arl = as_bf8(a[i][2]);
       const bf8 aih = as_bf8(a[i][1]), ail = as_bf8(a[i][3]);
       const bf8 nih = as_bf8(neg_bf16(a[i][1])), nil = as_bf8(neg_bf16(a[i][3]));
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < TJ; ++j) {
         const bf8 brh = as_bf8(b[j][0]), brl = as_bf8(b[j][2]);
         const bf8 bih = as_bf8(b[j][1]), bil = as_bf8(b[j][3]);
         accR[i][j] = mfma16(arh, brh, accR[i][j]);
@@ -199,11 +219,11 @@ __global__ void __launch_bounds__(SNT, 2) defect_gemm_split(SplitArgs g) {
   }
   // MFMA output: lane l, register r holds row 4 (l / 16) + r, column l % 16
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int rbase = m0 + wm * 32 + i * 16 + 4 * lg;
-      const int col = n0 + wn * 32 + j * 16 + lr;
+    for (int j = 0; j < TJ; ++j) {
+      const int rbase = m0 + wm * 16 * TI + i * 16 + 4 * lg;
+      const int col = n0 + wn * 16 * TJ + j * 16 + lr;
       if (col >= g.N) continue;
       cf out[4];
 #pragma unroll
@@ -240,6 +260,19 @@ __global__ void __launch_bounds__(SNT, 2) defect_gemm_split(SplitArgs g) {
         *(uint2*)(p + 48) = uint2{il[0] | (il[1] << 16), il[2] | (il[3] << 16)};
       }
     }
+}
+
+using TileSmall = SplitTile<2, 2, 2, 2>;   // 64 x 64, 256 threads
+using TileWide = SplitTile<4, 2, 2, 4>;    // 128 x 128, 512 threads
+
+__global__ void __launch_bounds__(TileSmall::NTH, 2) defect_gemm_split(SplitArgs g) {
+  __shared__ __attribute__((aligned(16))) char lds[2 * TileSmall::LDS_STAGE];
+  split_tile_body<2, 2, 2, 2>(g, lds);
+}
+
+__global__ void __launch_bounds__(TileWide::NTH, 1) defect_gemm_split_wide(SplitArgs g) {
+  __shared__ __attribute__((aligned(16))) char lds[2 * TileWide::LDS_STAGE];
+  split_tile_body<4, 2, 2, 4>(g, lds);
 }
 
 // Split panel of FP32 columns: row j of S = column j of E (K values, zero
@@ -333,10 +366,17 @@ int defect_step_split(hipStream_t s, int n, int N, const void* Hs, const void* E
   g.R = (const cf*)R32; g.ldr = n; g.cr = cr;
   g.shift = shift; g.sa = sa; g.sb = sb;
   g.Bnext = (char*)Es_next;
-  g.tiles_m = (n + SBM - 1) / SBM;
-  g.tiles_n = (N + SBN - 1) / SBN;
+  if (N >= SPLIT_WIDE_MIN_N) {
+    g.tiles_m = (n + TileWide::BM - 1) / TileWide::BM;
+    g.tiles_n = (N + TileWide::BN - 1) / TileWide::BN;
+    const int grid = ((g.tiles_m + NXCD - 1) / NXCD) * g.tiles_n * NXCD;
+    hipLaunchKernelGGL(defect_gemm_split_wide, dim3(grid), dim3(TileWide::NTH), 0, s, g);
+    return (int)hipGetLastError();
+  }
+  g.tiles_m = (n + TileSmall::BM - 1) / TileSmall::BM;
+  g.tiles_n = (N + TileSmall::BN - 1) / TileSmall::BN;
   const int grid = ((g.tiles_m + NXCD - 1) / NXCD) * g.tiles_n * NXCD;
-  hipLaunchKernelGGL(defect_gemm_split, dim3(grid), dim3(SNT), 0, s, g);
+  hipLaunchKernelGGL(defect_gemm_split, dim3(grid), dim3(TileSmall::NTH), 0, s, g);
   return (int)hipGetLastError();
 }
 

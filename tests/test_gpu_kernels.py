@@ -268,11 +268,12 @@ def _ritz_block(n, k, delta, seed):
     return lam, h, mu, q, z
 
 
-@pytest.mark.parametrize("n,k", [(333, 70), (1000, 130)])
+@pytest.mark.parametrize("n,k", [(333, 70), (1000, 130), (1000, 400)])
 def test_bf16_split_step_error_is_within_the_split_precision(n, k):
     """One BF16-split defect step (every degree 2): E_2 = sa (H E_1 - c E_1)
     + cr R with H E_1 formed from two-word BF16 splits of H and E_1 (three
-    products).  Each product's dropped split terms are at most 3 * 2^-16
+    products; 400 columns run the 128 x 128 tile).  Each product's dropped
+    split terms are at most 3 * 2^-16
     |H_ik| |E_kj| (the FP32 accumulation adds far less), so the error of
     element (i, j) is below 3 * 2^-16 |sa| (|H| |E_1|)_ij; with rounding
     errors of random sign it is a few 2^-16 |sa| times the root sum of
@@ -302,7 +303,7 @@ def test_bf16_split_step_error_is_within_the_split_precision(n, k):
 
 
 @pytest.mark.parametrize("delta,n,k,steps", [(1e-3, 700, 40, 99), (1e-6, 700, 40, 99),
-                                             (1e-3, 1000, 200, 4)])
+                                             (1e-3, 1000, 200, 4), (1e-3, 1000, 400, 5)])
 def test_bf16_split_filter_matches_oracle_with_error_scaling_like_the_residual(delta, n, k,
                                                                               steps):
     """The defect filter with its first `steps` steps in BF16-split form
