@@ -1,0 +1,58 @@
+"""Full-size checks of the standard n = 20 000 workload (nev 1000, nex 200)
+in the benchmark's launch path, with the mixed-precision filter and its
+BF16-split steps (precision 2):
+
+* the cold first problem against its prescribed spectrum (A = Q diag(lam)
+  Q^H from the generator, so the exact eigenvalues are known without an
+  eigensolver), to 1e-10 relative;
+* the warm-started second problem (A + 1e-3 H) by properties that hold at
+  any size: residuals of sampled pairs, ||A x - lam x|| <= 2 tol N_H, and
+  orthonormality of the sampled vectors; each eigenvalue is then within
+  its residual of an eigenvalue of A.
+
+The inputs are drawn on the GPU (device Gaussian draws, as the benchmark at
+this size); the spectrum comes from the host draw of the recipe."""
+import numpy as np
+import pytest
+
+import paper_1404_4161_amd as ch
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.timeout(900)
+def test_std_n20000_mixed_bf16_first_two_problems():
+    import torch
+    conf = gen.CONFIGS["std-n20000"]
+    seq = gen.Sequence(conf, kind="torch", device="cuda:0", draw="device")
+    problems = seq.problems()
+    opts = ch.chfsi_default_opts()
+    opts.precision = 2
+    nev, nex = conf.nev, conf.nex
+    x, lam = None, None
+    for l in (1, 2):
+        _, a = next(problems)
+        torch.cuda.synchronize()
+        print(f"std-n20000 problem {l}: solving (precision 2)", flush=True)
+        st, lam, xd, info = ch.chfsi_solve(a, None, nev, nex, conf.tol, X0=x,
+                                           Lambda0=lam if x is not None else None, opts=opts)
+        assert st == 0, (l, st)
+        print(f"  iters {info['iters']} fp32 loops {info['filter_iters_fp32']} bf16 steps "
+              f"{info['filter_steps_bf16']} rr refined/dense {info['rr_refined']}/"
+              f"{info['rr_dense']} {info['total_seconds']:.2f}s", flush=True)
+        if l == 1:
+            ref = np.asarray(seq.lam[:nev])
+            err = np.abs(lam[:nev] - ref) / np.abs(ref)
+            assert err.max() <= 1e-10, err.max()
+        else:
+            assert info["filter_steps_bf16"] > 0
+        cols = [0, 1, nev // 3, nev // 2, nev - 2, nev - 1]
+        xs = xd[:, cols]
+        r = torch.linalg.norm(a @ xs - xs * torch.as_tensor(lam[cols], device=xs.device),
+                              dim=0).cpu().numpy()
+        assert r.max() <= 2 * conf.tol * info["norm_h"], (l, r)
+        gram = (xs.conj().transpose(0, 1) @ xs).cpu().numpy()
+        assert np.abs(gram - np.eye(len(cols))).max() <= 1e-12
+        x = xd
+        del a
