@@ -245,7 +245,7 @@ def main():
     ap.add_argument("--steps", type=int, default=9)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="gen-n8000",
-                    choices=["gen-n8000", "std-n1000", "std-n20000", "kpoints"])
+                    choices=["gen-n8000", "std-n1000", "std-n20000", "std-n30000", "kpoints"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-degree", type=int, default=40)
     ap.add_argument("--filter-only", action="store_true",

@@ -212,13 +212,14 @@ def _decay(d0):
 
 
 # Single-GPU workloads: a standard problem at n = 1000 and a generalized one
-# at n = 8000 (5% of the spectrum wanted, 1% guard vectors), and a larger
-# standard problem at n = 20000 (the mixed-precision size; perturbations as
-# at n = 1000).
+# at n = 8000 (5% of the spectrum wanted, 1% guard vectors), larger standard
+# problems at n = 20000 (the mixed-precision size; perturbations as at
+# n = 1000) and at n = 30000 (the learned-degree size, 20 problems).
 CONFIGS = {
     "std-n1000": SequenceConfig("std-n1000", 0, 1000, 50, 20, False, 4, _const(1e-3)),
     "gen-n8000": SequenceConfig("gen-n8000", 1, 8000, 400, 80, True, 10, _decay(1e-2)),
     "std-n20000": SequenceConfig("std-n20000", 2, 20000, 1000, 200, False, 6, _const(1e-3)),
+    "std-n30000": SequenceConfig("std-n30000", 4, 30000, 1500, 300, False, 20, _const(1e-3)),
 }
 
 
