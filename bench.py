@@ -262,6 +262,10 @@ def main():
     ap.add_argument("--no-bf16", action="store_true",
                     help="skip the sequences with BF16-split defect steps (precision 2)")
     ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--variants", default="",
+                    help="comma list of the extra sequences to time (default all): "
+                         "mixed+learned, fp64+learned, mixed+seqcal, fp64+seqcal, mixed-bf16, "
+                         "mixed-bf16+seqcal, mixed-bf16+learned (fp64 and mixed always run)")
     ap.add_argument("--no-lambda0", action="store_true",
                     help="warm-start from the previous Ritz vectors only (one extra QR + "
                          "Rayleigh-Ritz per problem) instead of vectors and values")
@@ -406,6 +410,9 @@ def main():
         plan += [("mixed-bf16", 2, 0, 0), ("mixed-bf16+seqcal", 2, 3, 0)]
         if blob is not None:
             plan.append(("mixed-bf16+learned", 2, 2, 0))
+    if args.variants:
+        keep = set(args.variants.split(","))
+        plan = [p for p in plan if p[0] in keep]
     learned_runs = {}
     variant_modes = {}
     for label, prec, mode, fr in plan:
