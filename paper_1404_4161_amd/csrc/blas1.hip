@@ -147,6 +147,28 @@ __global__ void k_symmetrize(int n, zc* H, long ldh, double scale) {
   }
 }
 
+// ||G - I||_F of a k x k matrix: one workgroup of 1024 threads, partial
+// sums in a fixed order (repeatable).
+__global__ void __launch_bounds__(1024) k_gram_offnorm(int k, const zc* G, long ldg, double* out) {
+  __shared__ double red[1024];
+  const int t = threadIdx.x;
+  double acc = 0.0;
+  const long total = (long)k * k;
+  for (long e = t; e < total; e += 1024) {
+    const int r = (int)(e % k), c = (int)(e / k);
+    zc v = G[r + (long)c * ldg];
+    if (r == c) v.x -= 1.0;
+    acc += v.x * v.x + v.y * v.y;
+  }
+  red[t] = acc;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  if (t == 0) out[0] = sqrt(red[0]);
+}
+
 // D = tril(A) with the diagonal halved (zero above the diagonal).
 __global__ void k_lower_half_diag(int n, const zc* A, long lda, zc* D, long ldd) {
   const int r = blockIdx.x * NT + threadIdx.x;
@@ -541,6 +563,12 @@ int add_conj_transpose(hipStream_t s, int n, zc* H, long ldh) {
   if (n <= 0) return 0;
   const unsigned nb = (unsigned)((n + 31) / 32);
   hipLaunchKernelGGL(k_symmetrize, dim3(nb, nb), dim3(NT), 0, s, n, H, ldh, 1.0);
+  return last();
+}
+
+int gram_offnorm(hipStream_t s, int k, const zc* G, long ldg, double* out) {
+  if (k <= 0) return 0;
+  hipLaunchKernelGGL(k_gram_offnorm, dim3(1), dim3(1024), 0, s, k, G, ldg, out);
   return last();
 }
 

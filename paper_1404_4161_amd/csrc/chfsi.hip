@@ -28,6 +28,9 @@ constexpr size_t ALIGN = 256;
 // A Gram-matrix pivot below this fraction of its (unit) diagonal entry is a
 // CholeskyQR breakdown: kappa(Y) near 1e6 or worse.
 constexpr double GRAM_PIVOT_TOL = 1e-12;
+// ||G - I||_F of the normalised Gram matrix below which one CholeskyQR
+// pass suffices.
+constexpr double CHOLQR_ONE_PASS = 0.1;
 // Largest filter degree the mixed-precision coefficient table holds.
 constexpr int CR_ROWS = 256;
 
@@ -354,18 +357,22 @@ int read_info(hipStream_t s, const int* info_dev, int* out) {
 // One CholeskyQR pass: Yout = Yin R^{-1} with Yin^H Yin = R^H R, after
 // normalising the columns of Yin (in place).  shift > 0 adds shift*I to the
 // Gram matrix.  Returns CHFSI_NOT_HPD on a failed factorisation.
+// offnorm (or null) receives ||G - I||_F of the normalised Gram matrix
+// Yin^H Yin (before any shift).
 int cholqr_pass(hipStream_t s, int n, int k, zc* Yin, long ldy, zc* Yout, long ldo, StepBufs& b,
-                double shift) {
+                double shift, double* offnorm = nullptr) {
   CK(col_norms(s, n, k, Yin, ldy, b.nrm));
   CK(scale_cols_inv(s, n, k, Yin, ldy, b.nrm));
   CK(zgemm(s, OP_C, OP_N, k, k, n, ONE, Yin, ldy, Yin, ldy, ZERO, b.G, k, true, b.scratch,
            b.scratch_elems));
   CK(herm_from_lower(s, k, b.G, k));
+  if (offnorm) CK(gram_offnorm(s, k, b.G, k, b.dummy));
   if (shift > 0.0) CK(add_diag(s, k, b.G, k, shift));
   CK(hipMemsetAsync(b.info, 0, sizeof(int), s));
   zc* invd = b.invk;
   CKS(potrf_blocked(s, k, b.G, k, invd, b.info, GRAM_PIVOT_TOL));
   int info = 0;
+  if (offnorm) CK(hipMemcpyAsync(offnorm, b.dummy, sizeof(double), hipMemcpyDeviceToHost, s));
   CKS(read_info(s, b.info, &info));
   if (info != 0) return CHFSI_NOT_HPD;
   CK(set_identity(s, k, b.K2, k));
@@ -391,7 +398,16 @@ int orthonormalize_dev(hipStream_t s, int n, int k, zc* Y, long ldy, int nl, con
     }
   }
   zc* Q1 = b.T1;
-  int st = cholqr_pass(s, n, k, Y, ldy, Q1, n, b, 0.0);
+  // CholeskyQR2; the second pass only when the first one's Gram matrix is
+  // not close to the identity.  With ||G - I||_F <= 0.1 (kappa(Y) <= 1.11)
+  // one pass already leaves an orthogonality error of the order of the
+  // rounding of G (sqrt(n) eps), as the second pass would.
+  double offn = HUGE_VAL;
+  int st = cholqr_pass(s, n, k, Y, ldy, Q1, n, b, 0.0, &offn);
+  if (st == CHFSI_OK && offn <= CHOLQR_ONE_PASS) {
+    CK(copy2d(s, n, k, Q1, n, Qout, ldq));
+    return CHFSI_OK;
+  }
   if (st == CHFSI_OK) st = cholqr_pass(s, n, k, Q1, n, Qout, ldq, b, 0.0);
   if (st != CHFSI_NOT_HPD) return st;
   // Breakdown: shifted CholeskyQR3 (Fukaya et al., SISC 2020).  The shift is

@@ -117,6 +117,8 @@ int herm_from_lower(hipStream_t s, int k, zc* G, long ldg);
 int symmetrize(hipStream_t s, int n, zc* H, long ldh);
 // H <- H + H^H in place (exactly Hermitian result).
 int add_conj_transpose(hipStream_t s, int n, zc* H, long ldh);
+// out[0] = ||G - I||_F (device double), G k x k.
+int gram_offnorm(hipStream_t s, int k, const zc* G, long ldg, double* out);
 // D = lower triangle of A with the diagonal halved, zero above (D != A).
 int lower_half_diag(hipStream_t s, int n, const zc* A, long lda, zc* D, long ldd);
 int conj_transpose(hipStream_t s, int n, const zc* src, long lds, zc* dst, long ldd);
