@@ -298,22 +298,22 @@ __global__ void k_fill_zero(size_t count, zc* X) {
   if (i < count) X[i] = zc{0.0, 0.0};
 }
 
-// Cholesky of one nb x nb (nb <= 64) diagonal block in LDS, right-looking,
-// plus the inverse of the factor by right-looking forward substitution.
-// Thread t owns row t % 64 and the columns (t / 64) + 4 q, q = 0..15.
-// A pivot d_j <= rel_tol * (original diagonal entry j) counts as a breakdown.
-__global__ void __launch_bounds__(NT) k_potrf_leaf(int nb, zc* G, long ldg, zc* inv, int* info,
-                                                   int col_offset, double rel_tol) {
+// Cholesky of one nb x nb (nb <= 64) diagonal block in LDS, right-looking
+// (1024 threads: thread t owns row t % 64 and the columns (t / 64) + 16 q,
+// q = 0..3; two barriers per column), plus the inverse of the factor by
+// forward substitution, 16 threads per column of the inverse.  A pivot d_j
+// <= rel_tol * (original diagonal entry j) counts as a breakdown.
+__global__ void __launch_bounds__(1024) k_potrf_leaf(int nb, zc* G, long ldg, zc* inv, int* info,
+                                                     int col_offset, double rel_tol) {
   __shared__ zc S[64][65];    // S[col][row]
-  __shared__ zc X[64][65];    // X[col][row] = inv(L)
   __shared__ double D0[64];
   __shared__ int bad;
   const int t = threadIdx.x;
-  const int r = t & 63, cg = t >> 6;
+  const int r = t & 63, cg = t >> 6;   // row, column group (16 groups of 4 columns)
   if (t == 0) bad = 0;
-#pragma unroll 4
-  for (int q = 0; q < 16; ++q) {
-    const int c = cg + 4 * q;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = cg + 16 * q;
     if (r < nb && c < nb) {
       const zc v = (r >= c) ? G[r + (long)c * ldg] : zc{0.0, 0.0};
       S[c][r] = v;
@@ -321,28 +321,41 @@ __global__ void __launch_bounds__(NT) k_potrf_leaf(int nb, zc* G, long ldg, zc* 
     }
   }
   __syncthreads();
+  // right-looking factorisation; per column j every thread first reads what
+  // it needs of column j (scaled in registers), then, after a barrier, the
+  // scaled column is written and the trailing lower triangle updated:
+  // S(r, p) -= L(r, j) conj(L(p, j)), j < p <= r
   for (int j = 0; j < nb; ++j) {
     double d = S[j][j].x;
-    if (!(d > rel_tol * D0[j]) || !(d > 0.0) || !isfinite(d)) {
-      if (t == 0 && bad == 0) bad = j + 1;
-      d = 1.0;
-    }
+    const bool pivot_bad = !(d > rel_tol * D0[j]) || !(d > 0.0) || !isfinite(d);
+    if (pivot_bad) d = 1.0;
     const double ljj = sqrt(d);
     const double inv_l = 1.0 / ljj;
-    __syncthreads();
-    if (cg == 0 && r > j && r < nb) {
-      zc v = S[j][r];
-      S[j][r] = zc{v.x * inv_l, v.y * inv_l};
+    const bool row_active = r > j && r < nb;
+    zc a = zc{0.0, 0.0};
+    zc bp[4];
+    if (row_active) {
+      const zc v = S[j][r];
+      a = zc{v.x * inv_l, v.y * inv_l};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int p = cg + 16 * q;
+        const zc w = (p > j && p <= r) ? S[j][p] : zc{0.0, 0.0};
+        bp[q] = zc{w.x * inv_l, w.y * inv_l};
+      }
     }
-    if (t == 0) S[j][j] = zc{ljj, 0.0};
     __syncthreads();
-    if (r > j && r < nb) {
-      const zc a = S[j][r];      // L(r, j)
-#pragma unroll 4
-      for (int q = 0; q < 16; ++q) {
-        const int p = cg + 4 * q;
-        if (p > j && p <= r) {   // S(r, p) -= L(r, j) conj(L(p, j))
-          const zc b = S[j][p];
+    if (t == 0) {
+      if (pivot_bad && bad == 0) bad = j + 1;
+      S[j][j] = zc{ljj, 0.0};
+    }
+    if (row_active) {
+      if (cg == 0) S[j][r] = a;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int p = cg + 16 * q;
+        if (p > j && p <= r) {
+          const zc b = bp[q];
           zc v = S[p][r];
           v.x -= a.x * b.x + a.y * b.y;
           v.y -= a.y * b.x - a.x * b.y;
@@ -352,42 +365,49 @@ __global__ void __launch_bounds__(NT) k_potrf_leaf(int nb, zc* G, long ldg, zc* 
     }
     __syncthreads();
   }
-  // inverse: L X = I, one row of X finished per step
-#pragma unroll 4
-  for (int q = 0; q < 16; ++q) {
-    const int c = cg + 4 * q;
-    if (r < nb && c < nb) X[c][r] = zc{r == c ? 1.0 : 0.0, 0.0};
-  }
-  __syncthreads();
-  for (int i = 0; i < nb; ++i) {
-    if (cg == 0 && r <= i) {
-      const double f = 1.0 / S[i][i].x;
-      const zc v = X[r][i];
-      X[r][i] = zc{v.x * f, v.y * f};
-    }
-    __syncthreads();
-    if (r > i && r < nb) {
-      const zc l = S[i][r];      // L(r, i)
-#pragma unroll 4
-      for (int q = 0; q < 16; ++q) {
-        const int c = cg + 4 * q;
-        if (c <= i) {            // X(r, c) -= L(r, i) X(i, c)
-          const zc x = X[c][i];
-          zc v = X[c][r];
-          v.x -= l.x * x.x - l.y * x.y;
-          v.y -= l.x * x.y + l.y * x.x;
-          X[c][r] = v;
+  // inverse X = inv(L) by columns, 16 threads per column: x_i = (delta_ic -
+  // sum_{c <= k < i} L(i, k) x_k) / L(i, i), the sum split over the 16
+  // threads (k = sub mod 16, their x_k kept in registers) and reduced by
+  // shuffles; no barriers
+  const int c = t >> 4, sub = t & 15;
+  zc xr[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) xr[m] = zc{0.0, 0.0};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    for (int s = 0; s < 16; ++s) {
+      const int i = 16 * m + s;
+      zc part = zc{0.0, 0.0};
+#pragma unroll
+      for (int m2 = 0; m2 < 4; ++m2) {
+        const int k = sub + 16 * m2;
+        if (k >= c && k < i && i < nb) {
+          const zc l = S[k][i];   // L(i, k)
+          part.x += l.x * xr[m2].x - l.y * xr[m2].y;
+          part.y += l.x * xr[m2].y + l.y * xr[m2].x;
         }
       }
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) {
+        part.x += __shfl_xor(part.x, off, 16);
+        part.y += __shfl_xor(part.y, off, 16);
+      }
+      if (i < nb && i >= c && s == sub) {
+        const double f = 1.0 / S[i][i].x;
+        xr[m] = zc{((i == c ? 1.0 : 0.0) - part.x) * f, -part.y * f};
+      }
     }
-    __syncthreads();
   }
-#pragma unroll 4
-  for (int q = 0; q < 16; ++q) {
-    const int c = cg + 4 * q;
-    if (r < nb && c < nb) {
-      G[r + (long)c * ldg] = S[c][r];
-      inv[r + (long)c * nb] = X[c][r];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int cc = cg + 16 * q;
+    if (r < nb && cc < nb) G[r + (long)cc * ldg] = S[cc][r];
+  }
+  if (c < nb) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int row = sub + 16 * m;
+      if (row < nb) inv[row + (long)c * nb] = row >= c ? xr[m] : zc{0.0, 0.0};
     }
   }
   if (t == 0 && bad != 0 && *info == 0) *info = col_offset + bad;
@@ -638,7 +658,7 @@ int fill_zero(hipStream_t s, size_t count, zc* X) {
 int potrf_leaf(hipStream_t s, int nb, zc* G, long ldg, zc* inv, int* info, int col_offset,
                double rel_tol) {
   if (nb <= 0 || nb > 64) return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_potrf_leaf, dim3(1), dim3(NT), 0, s, nb, G, ldg, inv, info, col_offset,
+  hipLaunchKernelGGL(k_potrf_leaf, dim3(1), dim3(1024), 0, s, nb, G, ldg, inv, info, col_offset,
                      rel_tol);
   return last();
 }
