@@ -87,7 +87,7 @@ extern "C" {
  *                 E, three v_mfma_f32_16x16x32_bf16 products, FP32
  *                 accumulation; error about 3 * 2^-16 of the defect): per
  *                 step i and wanted vector j with m_j > i, the floor
- *                 3 * 2^-16 * rel_j * |rho_j|^-(m_j - i - 1) must be 100x
+ *                 3 * 2^-16 * rel_j * |rho_j|^-(m_j - i - 1) must be 10x
  *                 below max(tol, rel_j |rho_j|^-m_j), rel_j = residual /
  *                 norm_h (eq. resl).  Needs n^2 * 8 more bytes of work.
  *   seed          seed of the SplitMix64 counter-based generator used for

@@ -724,14 +724,19 @@ bool cap_degrees_fp32(int n_wanted, const std::vector<double>& mu, const std::ve
 }
 
 // Per-step precision inside an FP32 defect filter (precision 2).  Step i
-// (E_i -> E_{i+1}) may use the BF16-split product, whose error is about
+// (E_i -> E_{i+1}) may use the BF16-split product, whose error is at most
 // BF16_SPLIT_EPS times the defect, when for every wanted vector j still
 // filtered (m_j > i) that error, damped by the m_j - i - 1 steps after it
-// (eq. resl: by rho_j^-(m_j - i - 1) relative to the column), stays 100x
-// below what the filter aims at (the bound of defect_filter_safe with the
-// step's own damping).  deg is in the current column order; the result has
-// one entry per step index 0 .. max degree - 1 (entry 0 unused).
+// (eq. resl: by rho_j^-(m_j - i - 1) relative to the column), stays
+// BF16_SPLIT_MARGIN times below what the filter aims at (the bound of
+// defect_filter_safe with the step's own damping).  The bound is a worst
+// case: rounding errors of random sign put the measured error near 2^-16,
+// a third of it, so the margin of 10 is about 30 in practice; a step taken
+// too early only costs convergence (the FP64 residuals decide locking).
+// deg is in the current column order; the result has one entry per step
+// index 0 .. max degree - 1 (entry 0 unused).
 constexpr double BF16_SPLIT_EPS = 3.0 / 65536.0;
+constexpr double BF16_SPLIT_MARGIN = 10.0;
 
 std::vector<char> bf16_step_schedule(int n_wanted, const std::vector<double>& mu,
                                      const std::vector<double>& res, const std::vector<int>& deg,
@@ -748,7 +753,7 @@ std::vector<char> bf16_step_schedule(int n_wanted, const std::vector<double>& mu
     const double target = std::max(tol, rel * std::exp(-lr * deg[j]));
     for (int i = 1; i < deg[j]; ++i) {
       const double floor_ = BF16_SPLIT_EPS * rel * std::exp(-lr * (deg[j] - i - 1));
-      if (!(floor_ <= 0.01 * target)) ok[i] = 0;
+      if (!(floor_ * BF16_SPLIT_MARGIN <= target)) ok[i] = 0;
     }
   }
   return ok;
