@@ -113,22 +113,30 @@ def test_solve_x_aliases_x0_and_is_repeatable():
     assert np.abs(lam3[:10] - ref.lam[:10]).max() <= RTOL * np.abs(ref.lam[:10]).min()
 
 
-def test_solve_edge_cases_tiny_and_full_block():
+@pytest.mark.parametrize("precision,rr_refine", [(0, 1), (2, 1), (0, 0)])
+def test_solve_edge_cases_tiny_and_full_block(precision, rr_refine):
+    o = _opts(precision=precision, rr_refine=rr_refine)
     # tiny: n = 6, k = n (the subspace is the whole space)
     lamv = np.array([-3.0, -1.0, 0.5, 2.0, 4.0, 9.0])
     a = gen.prescribed_problem(6, lamv, 3)
-    st, lam, xd, info = ch.chfsi_solve(dev(a), None, 4, 2, 1e-10)
+    st, lam, xd, info = ch.chfsi_solve(dev(a), None, 4, 2, 1e-10, opts=o)
     assert st == 0
     assert np.abs(lam - lamv).max() < 1e-12
     # n not a multiple of the tile, k = n - 1
     lamv = np.linspace(-5, 5, 65)
     a = gen.prescribed_problem(65, lamv, 4)
-    st, lam, xd, info = ch.chfsi_solve(dev(a), None, 60, 4, 1e-10)
+    st, lam, xd, info = ch.chfsi_solve(dev(a), None, 60, 4, 1e-10, opts=o)
     assert st == 0
     assert np.abs(lam[:60] - lamv[:60]).max() < 1e-10 * 5
+    # a warm start of the same problem (nearly diagonal projected matrices)
+    st, lam2, _, info = ch.chfsi_solve(dev(a), None, 60, 4, 1e-10, X0=xd, Lambda0=lam, opts=o)
+    assert st == 0
+    assert np.abs(lam2[:60] - lamv[:60]).max() < 1e-10 * 5
+    if rr_refine == 0:
+        assert info["rr_refined"] == 0
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_solve_degenerate_and_clustered_spectrum(precision):
     """Exactly repeated eigenvalues (multiplicity 4 at the bottom, 3 at the
     edge of the wanted set, a pair split across nev) and a tight cluster:
@@ -156,6 +164,14 @@ def test_solve_degenerate_and_clustered_spectrum(precision):
         np.random.Generator(np.random.PCG64(18)), n, n))
     u4 = q[:, :4]
     assert np.abs(u4 @ (u4.conj().T @ x4) - x4).max() < 1e-8
+    # warm start on the same matrix: the projected matrices are nearly
+    # diagonal with exactly repeated diagonal groups (refinement path)
+    st, lam2, xd2, info2 = ch.chfsi_solve(dev(a), None, nev, nex, 1e-10, X0=xd, Lambda0=lam,
+                                          opts=opts)
+    assert st == 0
+    assert np.abs(lam2[:nev] - lamv[:nev]).max() <= RTOL * np.abs(lamv[:nev]).min()
+    _check_pairs(a, None, lam2, host(xd2), nev, 1e-10, info2["norm_h"])
+    assert info2["rr_refined"] >= 1
 
 
 def test_solve_fixed_degree_and_literal_alpha_modes():
