@@ -411,10 +411,10 @@ int defect_step(hipStream_t s, int n, int N, const void* H32, const void* Ecur, 
   // split-K that fills the resident slots evenly (partials in FP32)
   int splits = 1;
   const int slots = device_slots32();
-  const int max_s = (int)std::min<size_t>(4, part ? part_elems / ((size_t)n * N) : 1);
+  const int max_s = (int)std::min<size_t>(8, part ? part_elems / ((size_t)n * N) : 1);
   double best_u = 0.0;
   for (int sp = 1; sp <= max_s; ++sp) {
-    if (sp > 1 && n / sp < 1024) break;
+    if (sp > 1 && n / sp < 512) break;
     const long wg = (long)tiles * sp;
     const double u = (double)wg / (double)(((wg + slots - 1) / slots) * slots);
     if (u > best_u + 1e-9) { best_u = u; splits = sp; }
