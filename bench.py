@@ -359,6 +359,8 @@ def main():
         train_report["training_sequence"] = f"{conf.name} recipe, seed namespace {tconf.cfg}"
         log(f"degree network: {train_report}")
 
+    cold = {}
+
     def run_sequence(opts, label):
         """Warm-up problem(s), then the timed steps; returns per-step infos,
         wall times, eigenvalues and the elapsed time of the timed region."""
@@ -379,6 +381,11 @@ def main():
             x_prev = X
             log(f"[{label}] warmup problem {w + 1}: iters {info['iters']} total "
                 f"{info['total_seconds']:.3f}s")
+            if w == 0:
+                # the cold first problem (random start block), untimed
+                cold[label] = {"seconds": round(info["total_seconds"], 4),
+                               "iters": info["iters"],
+                               "filter_matvecs": info["filter_matvecs"]}
         torch.cuda.synchronize()
         infos, walls, lams = [], [], []
         t_start = time.perf_counter()
@@ -535,6 +542,7 @@ def main():
             out[label]["filter_effective_tflops"] = round(
                 sum(i["filter_flops"] for i in linfos) / lsec / 1e12, 3)
     out["fp64_filter_matvecs_per_step"] = [i["filter_matvecs"] for i in infos]
+    out["cold_first_problem_untimed"] = cold
     out["filter_autotune"] = autotune
     if train_report is not None:
         out["degree_network"] = train_report
