@@ -204,7 +204,7 @@ struct Timers {
   ~Timers() {
     for (auto& p : pend) { pool.push_back(p.a); pool.push_back(p.b); }
     if (open_ev) pool.push_back(open_ev);
-    for (auto e : pool) hipEventDestroy(e);
+    for (auto e : pool) (void)hipEventDestroy(e);
   }
   hipEvent_t get() {
     if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
@@ -216,13 +216,13 @@ struct Timers {
     if (!acc) return;
     open_ev = get();
     open_phase = phase;
-    if (open_ev) hipEventRecord(open_ev, s);
+    if (open_ev) (void)hipEventRecord(open_ev, s);
   }
   void end() {
     if (!acc || !open_ev) return;
     hipEvent_t e = get();
     if (e) {
-      hipEventRecord(e, s);
+      (void)hipEventRecord(e, s);
       pend.push_back({open_phase, open_ev, e});
     } else {
       pool.push_back(open_ev);
@@ -233,7 +233,7 @@ struct Timers {
   void drain() {
     for (auto& p : pend) {
       float ms = 0.f;
-      hipEventSynchronize(p.b);
+      (void)hipEventSynchronize(p.b);
       if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) acc[p.phase] += 1e-3 * ms;
       pool.push_back(p.a);
       pool.push_back(p.b);
@@ -1103,8 +1103,8 @@ struct Solve {
   std::vector<double> speed_locked;
 
   ~Solve() {
-    if (fe0) hipEventDestroy(fe0);
-    if (fe1) hipEventDestroy(fe1);
+    if (fe0) (void)hipEventDestroy(fe0);
+    if (fe1) (void)hipEventDestroy(fe1);
   }
 
   double alpha_of(int nl_, int ka_) const {
@@ -1643,12 +1643,12 @@ struct FilterGroup {
   bool pending = false;
 
   ~FilterGroup() {
-    if (gexec) hipGraphExecDestroy(gexec);
-    if (graph) hipGraphDestroy(graph);
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
-    if (hlist) hipHostFree(hlist);
-    if (hslots) hipHostFree(hslots);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (hlist) (void)hipHostFree(hlist);
+    if (hslots) (void)hipHostFree(hslots);
   }
 
   int init(GemmArgs* dl, int* ds, size_t ce, size_t cs) {
@@ -1751,11 +1751,11 @@ struct FilterGroup {
     pending = false;
     CK(hipEventSynchronize(e1));
     if (gexec) {
-      hipGraphExecDestroy(gexec);
+      (void)hipGraphExecDestroy(gexec);
       gexec = nullptr;
     }
     if (graph) {
-      hipGraphDestroy(graph);
+      (void)hipGraphDestroy(graph);
       graph = nullptr;
     }
     float ms = 0.f;
@@ -1833,9 +1833,9 @@ int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void
     std::vector<rocblas_handle> h;
     std::vector<hipEvent_t> ev;
     ~Res() {
-      for (auto x : st) if (x) { hipStreamSynchronize(x); hipStreamDestroy(x); }
+      for (auto x : st) if (x) { (void)hipStreamSynchronize(x); (void)hipStreamDestroy(x); }
       for (auto x : h) if (x) rocblas_destroy_handle(x);
-      for (auto x : ev) if (x) hipEventDestroy(x);
+      for (auto x : ev) if (x) (void)hipEventDestroy(x);
     }
   } r;
   r.st.assign(T, nullptr);
@@ -1870,7 +1870,14 @@ int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void
   // run fn(q) for the group's problems, each on its worker's host thread
   auto parallel = [&](int g, auto fn) {
     auto work = [&](int t) {
-      hipSetDevice(dev);
+      if (hipSetDevice(dev) != hipSuccess) {
+        for (int q : members[g])
+          if (thread_of[q] == t) {
+            status[q] = CHFSI_DEVICE_ERROR;
+            failed[q] = 1;
+          }
+        return;
+      }
       tl_handle = r.h[t];
       for (int q : members[g]) {
         if (thread_of[q] != t) continue;

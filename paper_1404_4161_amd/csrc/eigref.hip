@@ -43,7 +43,6 @@ constexpr int MAX_CLUSTER = 32;
 
 const zc ONE = {1.0, 0.0}, ZERO = {0.0, 0.0}, MONE = {-1.0, 0.0};
 
-__device__ __forceinline__ zc zconj(zc a) { return zc{a.x, -a.y}; }
 __device__ __forceinline__ double zabs(zc a) { return sqrt(a.x * a.x + a.y * a.y); }
 
 // non-negative doubles order like their bit patterns
