@@ -303,13 +303,31 @@ __global__ void k_fill_zero(size_t count, zc* X) {
 // q = 0..3; two barriers per column), plus the inverse of the factor by
 // forward substitution, 16 threads per column of the inverse.  A pivot d_j
 // <= rel_tol * (original diagonal entry j) counts as a breakdown.
+//
+// The pivot of column j (its square root and reciprocal) is computed once,
+// by the thread that applies the last update to entry (j, j) -- during the
+// update of column j - 1 -- and published in LDS with that column's
+// barrier; the other threads only read it (FP64 square roots and divisions
+// repeated by all 16 waves would cost more than the factorisation itself).
 __global__ void __launch_bounds__(1024) k_potrf_leaf(int nb, zc* G, long ldg, zc* inv, int* info,
                                                      int col_offset, double rel_tol) {
   __shared__ zc S[64][65];    // S[col][row]
   __shared__ double D0[64];
+  __shared__ double Pi[64];   // 1 / L(j, j)
   __shared__ int bad;
   const int t = threadIdx.x;
   const int r = t & 63, cg = t >> 6;   // row, column group (16 groups of 4 columns)
+  // pivot of column j from its final diagonal value d (one thread per column;
+  // columns are separated by barriers, so `bad` keeps the first breakdown)
+  auto pivot = [&](int j, double d) {
+    if (!(d > rel_tol * D0[j]) || !(d > 0.0) || !isfinite(d)) {
+      if (bad == 0) bad = j + 1;
+      d = 1.0;
+    }
+    const double l = sqrt(d);
+    Pi[j] = 1.0 / l;
+    S[j][j] = zc{l, 0.0};
+  };
   if (t == 0) bad = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -317,7 +335,10 @@ __global__ void __launch_bounds__(1024) k_potrf_leaf(int nb, zc* G, long ldg, zc
     if (r < nb && c < nb) {
       const zc v = (r >= c) ? G[r + (long)c * ldg] : zc{0.0, 0.0};
       S[c][r] = v;
-      if (r == c) D0[r] = fabs(v.x);
+      if (r == c) {
+        D0[r] = fabs(v.x);
+        if (r == 0) pivot(0, v.x);   // thread 0 holds entry (0, 0)
+      }
     }
   }
   __syncthreads();
@@ -326,11 +347,7 @@ __global__ void __launch_bounds__(1024) k_potrf_leaf(int nb, zc* G, long ldg, zc
   // scaled column is written and the trailing lower triangle updated:
   // S(r, p) -= L(r, j) conj(L(p, j)), j < p <= r
   for (int j = 0; j < nb; ++j) {
-    double d = S[j][j].x;
-    const bool pivot_bad = !(d > rel_tol * D0[j]) || !(d > 0.0) || !isfinite(d);
-    if (pivot_bad) d = 1.0;
-    const double ljj = sqrt(d);
-    const double inv_l = 1.0 / ljj;
+    const double inv_l = Pi[j];
     const bool row_active = r > j && r < nb;
     zc a = zc{0.0, 0.0};
     zc bp[4];
@@ -345,10 +362,6 @@ __global__ void __launch_bounds__(1024) k_potrf_leaf(int nb, zc* G, long ldg, zc
       }
     }
     __syncthreads();
-    if (t == 0) {
-      if (pivot_bad && bad == 0) bad = j + 1;
-      S[j][j] = zc{ljj, 0.0};
-    }
     if (row_active) {
       if (cg == 0) S[j][r] = a;
 #pragma unroll
@@ -360,6 +373,8 @@ __global__ void __launch_bounds__(1024) k_potrf_leaf(int nb, zc* G, long ldg, zc
           v.x -= a.x * b.x + a.y * b.y;
           v.y -= a.y * b.x - a.x * b.y;
           S[p][r] = v;
+          // entry (j + 1, j + 1) is final after this update
+          if (p == r && r == j + 1) pivot(r, v.x);
         }
       }
     }
@@ -393,7 +408,7 @@ __global__ void __launch_bounds__(1024) k_potrf_leaf(int nb, zc* G, long ldg, zc
         part.y += __shfl_xor(part.y, off, 16);
       }
       if (i < nb && i >= c && s == sub) {
-        const double f = 1.0 / S[i][i].x;
+        const double f = Pi[i];
         xr[m] = zc{((i == c ? 1.0 : 0.0) - part.x) * f, -part.y * f};
       }
     }
