@@ -114,12 +114,20 @@ def filter_only(conf, degree):
     _, f16, _ = ch.chfsi_filter_defect_split(h, q, z, mu, [degree] * k, 0.0, nrm, -1.3 * nrm,
                                              degree)
     dt16 = time.perf_counter() - t
+    # and with every step in FP16-split form
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, fh, _ = ch.chfsi_filter_defect_split(h, q, z, mu, [degree] * k, 0.0, nrm, -1.3 * nrm,
+                                            degree, fp16=True)
+    dth = time.perf_counter() - t
     print(json.dumps({"mode": "filter-only", "n": n, "k": k, "degree": degree,
                       "variant": int(v[0]),
                       "launches": launches, "seconds": round(dt, 6),
                       "tflops_wall": round(flops / dt / 1e12, 3),
                       "bf16_split_defect_seconds": round(dt16, 6),
                       "bf16_split_defect_tflops_wall": round(f16 / dt16 / 1e12, 3),
+                      "fp16_split_defect_seconds": round(dth, 6),
+                      "fp16_split_defect_tflops_wall": round(fh / dth / 1e12, 3),
                       "copy_bytes": src.numel() * 8}), flush=True)
 
 
@@ -214,6 +222,7 @@ def kpoints(args):
                 "sequential-fp64": ("sequential fp64", 0, False, False),
                 "batched-mixed": ("batched mixed", 1, True, False),
                 "batched-mixed-bf16": ("batched mixed bf16", 2, True, False),
+                "batched-mixed-fp16": ("batched mixed fp16", 3, True, False),
                 "batched-fp64-serial": ("batched fp64 serial", 0, True, False, True)}
     chosen = args.kp_variants.split(",")
     for key in chosen:
@@ -256,16 +265,20 @@ def main():
     ap.add_argument("--kp-count", type=int, default=32,
                     help="k-point workload: number of problems (32 in the full workload)")
     ap.add_argument("--kp-variants", default="batched-fp64,batched-fp64-graph,sequential-fp64,"
-                                             "batched-mixed,batched-mixed-bf16")
+                                             "batched-mixed,batched-mixed-bf16,"
+                                             "batched-mixed-fp16")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training the degree network and the learned-degree sequences")
     ap.add_argument("--no-bf16", action="store_true",
                     help="skip the sequences with BF16-split defect steps (precision 2)")
+    ap.add_argument("--no-fp16", action="store_true",
+                    help="skip the sequences with FP16-split defect steps (precision 3)")
     ap.add_argument("--train-steps", type=int, default=1500)
     ap.add_argument("--variants", default="",
                     help="comma list of the extra sequences to time (default all): "
                          "mixed+learned, fp64+learned, mixed+seqcal, fp64+seqcal, mixed-bf16, "
-                         "mixed-bf16+seqcal, mixed-bf16+learned (fp64 and mixed always run)")
+                         "mixed-bf16+seqcal, mixed-bf16+learned, mixed-fp16, mixed-fp16+seqcal, "
+                         "mixed-fp16+learned (fp64 and mixed always run)")
     ap.add_argument("--no-lambda0", action="store_true",
                     help="warm-start from the previous Ritz vectors only (one extra QR + "
                          "Rayleigh-Ritz per problem) instead of vectors and values")
@@ -316,8 +329,10 @@ def main():
     opts1.precision = 1
     opts2 = ch.chfsi_default_opts()
     opts2.precision = 2
+    opts3 = ch.chfsi_default_opts()
+    opts3.precision = 3
     wb = max(ch.chfsi_workspace_bytes(n, nev, nex, B is not None, o)
-             for o in (opts0, opts1, opts2))
+             for o in (opts0, opts1, opts2, opts3))
     work = torch.empty(wb, dtype=torch.uint8, device=dev)
     X = ch.colmajor(torch.empty((n, k), dtype=torch.complex128, device=dev))
 
@@ -417,6 +432,10 @@ def main():
         plan += [("mixed-bf16", 2, 0, 0), ("mixed-bf16+seqcal", 2, 3, 0)]
         if blob is not None:
             plan.append(("mixed-bf16+learned", 2, 2, 0))
+    if not args.no_fp16:
+        plan += [("mixed-fp16", 3, 0, 0), ("mixed-fp16+seqcal", 3, 3, 0)]
+        if blob is not None:
+            plan.append(("mixed-fp16+learned", 3, 2, 0))
     if args.variants:
         keep = set(args.variants.split(","))
         plan = [p for p in plan if p[0] in keep]
@@ -504,6 +523,9 @@ def main():
         2: ("FP32 defect filter where the residuals allow; its early steps with BF16-split "
             "products (3 BF16 MFMA products, FP32 accumulate) where their rounding is damped "
             "enough"),
+        3: ("FP32 defect filter where the residuals allow; its steps with FP16-split products "
+            "of power-of-two scaled operands (3 FP16 MFMA products, FP32 accumulate) where "
+            "their rounding is damped enough (nearly all)"),
     }
     degree_text = {
         0: "analytic rule (Sec. 3.1.1)",
@@ -533,11 +555,12 @@ def main():
             "max_rel_eig_diff_vs_fp64_per_step": [
                 float(np.max(np.abs(a - b) / np.abs(a))) for a, b in zip(lams64, llams)],
         }
-        if prec == 2:
-            f16 = sum(i["filter_flops_bf16"] for i in linfos)
+        if prec >= 2:
+            w = "bf16" if prec == 2 else "fp16"
+            f16 = sum(i[f"filter_flops_{w}"] for i in linfos)
             f32 = sum(i["filter_flops_fp32"] for i in linfos)
-            out[label]["bf16_steps_per_step"] = [i["filter_steps_bf16"] for i in linfos]
-            out[label]["bf16_share_of_defect_flops"] = round(f16 / max(f16 + f32, 1.0), 3)
+            out[label][f"{w}_steps_per_step"] = [i[f"filter_steps_{w}"] for i in linfos]
+            out[label][f"{w}_share_of_defect_flops"] = round(f16 / max(f16 + f32, 1.0), 3)
             lsec = sum(i["filter_seconds"] for i in linfos)
             out[label]["filter_effective_tflops"] = round(
                 sum(i["filter_flops"] for i in linfos) / lsec / 1e12, 3)

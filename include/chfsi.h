@@ -90,6 +90,16 @@ extern "C" {
  *                 3 * 2^-16 * rel_j * |rho_j|^-(m_j - i - 1) must be 10x
  *                 below max(tol, rel_j |rho_j|^-m_j), rel_j = residual /
  *                 norm_h (eq. resl).  Needs n^2 * 8 more bytes of work.
+ *                 3: as 1, with the FP16-split product instead: two-term
+ *                 FP16 splits of 2^s H (one power of two for H) and of
+ *                 2^s_j E_j (one per column of E, both from the largest
+ *                 magnitude, into [2^14, 2^15)), three
+ *                 v_mfma_f32_16x16x32_f16 products, FP32 accumulation,
+ *                 the scaling undone in the epilogue; error about
+ *                 3 * 2^-22 of the defect, so the rule of precision 2
+ *                 with 3 * 2^-22 in place of 3 * 2^-16 admits nearly
+ *                 every step of an FP32 defect filter.  Needs n^2 * 8
+ *                 more bytes of work.
  *   seed          seed of the SplitMix64 counter-based generator used for
  *                 the Lanczos start vector and a random start block.
  *   degree_jitter 0 (default), or s > 0: every wanted vector's degree m is
@@ -175,6 +185,8 @@ typedef struct chfsi_info {
   double filter_flops_bf16;/* 8 n^2 per column of those steps                    */
   int rr_refined;          /* Rayleigh-Ritz eigenproblems solved by refinement   */
   int rr_dense;            /* ... and by the dense eigensolver (zheevd)          */
+  int filter_steps_fp16;   /* defect-filter steps run with FP16-split products   */
+  double filter_flops_fp16;/* 8 n^2 per column of those steps                    */
 } chfsi_info;
 
 /* Convergence log record (CHFSI_LOG_FIELDS doubles), one per wanted vector
@@ -362,6 +374,22 @@ int chfsi_filter_defect_split(int n, int k, const void* H, int ldh, const void* 
                               double c, double e, double gamma, int bf16_steps, void* Y, int ldy,
                               void* work, size_t work_bytes, void* stream,
                               double* flops_bf16_out, double* flops_fp32_out);
+
+/* chfsi_filter_defect_split with FP16-split steps (precision 3 of
+ * chfsi_opts) in place of the BF16 ones: the first fp16_steps steps take
+ * two-term FP16 splits of 2^s H and of 2^s_j E_i[:, j] (powers of two from
+ * the largest magnitudes; one reduction over H, whose result is read on the
+ * host, so the call synchronises the stream once more), three
+ * v_mfma_f32_16x16x32_f16 products per real product and FP32
+ * accumulation; the later steps run in FP32.  Same arguments, limits and
+ * workspace as chfsi_filter_defect_split.
+ *   flops_fp16_out, flops_fp32_out  NULL or the algorithmic flops of the
+ *               FP16 and of the FP32 steps. */
+int chfsi_filter_defect_fp16(int n, int k, const void* H, int ldh, const void* Q, int ldq,
+                             const void* Z, int ldz, const double* mu, const int* degrees,
+                             double c, double e, double gamma, int fp16_steps, void* Y, int ldy,
+                             void* work, size_t work_bytes, void* stream,
+                             double* flops_fp16_out, double* flops_fp32_out);
 
 /* The k x k Hermitian eigenproblem of Rayleigh-Ritz, G W = W diag(mu)
  * with mu ascending and W unitary (Alg. 1, RAYLEIGH-RITZ).

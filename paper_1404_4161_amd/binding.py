@@ -47,7 +47,8 @@ class ChfsiInfo(Structure):
                 ("filter_seconds_fp32", c_double), ("log_records", c_int),
                 ("learned_cols", c_int), ("fallback_cols", c_int), ("learned_raised", c_int),
                 ("filter_steps_bf16", c_int), ("filter_flops_bf16", c_double),
-                ("rr_refined", c_int), ("rr_dense", c_int)]
+                ("rr_refined", c_int), ("rr_dense", c_int),
+                ("filter_steps_fp16", c_int), ("filter_flops_fp16", c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "step_seconds"}
@@ -85,6 +86,11 @@ _SIGS = {
                                           c_double, c_double, c_double, c_int, c_void_p, c_int,
                                           c_void_p, c_size_t, c_void_p, POINTER(c_double),
                                           POINTER(c_double)]),
+    "chfsi_filter_defect_fp16": (c_int, [c_int, c_int, c_void_p, c_int, c_void_p, c_int,
+                                         c_void_p, c_int, POINTER(c_double), POINTER(c_int),
+                                         c_double, c_double, c_double, c_int, c_void_p, c_int,
+                                         c_void_p, c_size_t, c_void_p, POINTER(c_double),
+                                         POINTER(c_double)]),
     "chfsi_eigh_workspace_bytes": (c_size_t, [c_int]),
     "chfsi_eigh_projected": (c_int, [c_int, c_void_p, c_int, c_void_p, c_int, POINTER(c_double),
                                      c_int, c_void_p, c_size_t, c_void_p, POINTER(c_int)]),
@@ -311,9 +317,10 @@ def chfsi_filter_defect(H, Q, Z, mu, degrees, c, e, gamma, Y=None, work=None, st
 
 
 def chfsi_filter_defect_split(H, Q, Z, mu, degrees, c, e, gamma, bf16_steps, Y=None, work=None,
-                              stream=None):
+                              stream=None, fp16=False):
     """chfsi_filter_defect with its first bf16_steps steps in BF16-split
-    form; returns (Y, BF16-step flops, FP32-step flops)."""
+    form (FP16-split with fp16=True: chfsi_filter_defect_fp16); returns (Y,
+    split-step flops, FP32-step flops)."""
     torch = _torch()
     n, k = Q.shape
     if Y is None:
@@ -323,11 +330,12 @@ def chfsi_filter_defect_split(H, Q, Z, mu, degrees, c, e, gamma, bf16_steps, Y=N
     wb = int(lib().chfsi_defect_split_workspace_bytes(n, k))
     w = _work(wb, Q.device, work)
     f16, f32 = c_double(0.0), c_double(0.0)
-    _check(lib().chfsi_filter_defect_split(n, k, _ptr(H), _ld(H), _ptr(Q), _ld(Q), _ptr(Z),
-                                           _ld(Z), m, deg, c, e, gamma, int(bf16_steps), _ptr(Y),
-                                           _ld(Y), _ptr(w), wb, _stream(stream, Q.device),
-                                           ctypes.byref(f16), ctypes.byref(f32)),
-           "chfsi_filter_defect_split")
+    name = "chfsi_filter_defect_fp16" if fp16 else "chfsi_filter_defect_split"
+    _check(getattr(lib(), name)(n, k, _ptr(H), _ld(H), _ptr(Q), _ld(Q), _ptr(Z), _ld(Z), m, deg,
+                                c, e, gamma, int(bf16_steps), _ptr(Y), _ld(Y), _ptr(w), wb,
+                                _stream(stream, Q.device), ctypes.byref(f16),
+                                ctypes.byref(f32)),
+           name)
     return Y, f16.value, f32.value
 
 

@@ -23,9 +23,22 @@
 // re_lo, im_lo of k = 8g .. 8g + 7, 8 BF16 each.  H is stored by its rows
 // (r = m, k = column of H); E_i by its columns (r = column, k = row).  One
 // 16-byte LDS read then gives an MFMA lane its 8 consecutive k of a plane.
+//
+// FP16 form (v_mfma_f32_16x16x32_f16): the same two-word split with FP16
+// words, x_hi = fp16(x), x_lo = fp16(x - x_hi), 11 significant bits each,
+// so the dropped terms are at most about 3 * 2^-22 |a| |b| -- close to the
+// rounding of the FP32 step itself, at the BF16 step's cost.  FP16 has a
+// narrow exponent range, so the operands are scaled by powers of two first:
+// H by one factor, each column of E_i by its own, both chosen from the
+// largest magnitude so that it lands in [2^14, 2^15); the epilogue undoes
+// the scaling exactly.  Entries more than 2^28 below their matrix's or
+// column's largest one fall into FP16's subnormal range and keep an
+// absolute accuracy of 2^-24 of the scaled unit, far below the bound above
+// relative to |H| |E_i|.
 #include "internal.h"
 
 #include <algorithm>
+#include <cmath>
 
 namespace chfsi {
 
@@ -33,6 +46,7 @@ namespace {
 
 typedef float2 cf;
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 hf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int SBK = 32;                        // K per LDS stage
@@ -55,13 +69,28 @@ __device__ __forceinline__ void split1(float x, unsigned& hi, unsigned& lo) {
   lo = bf16_rne(x - bf16_val(hi));
 }
 
-// the four planes of 8 complex values -> 4 x 16 bytes
-__device__ __forceinline__ void split8(const cf* v, uint4* planes) {
+// hi and lo FP16 words of x (round to nearest even; x - hi is exact in FP32)
+__device__ __forceinline__ void split1h(float x, unsigned& hi, unsigned& lo) {
+  const _Float16 h = (_Float16)x;
+  const _Float16 l = (_Float16)(x - (float)h);
+  hi = __builtin_bit_cast(unsigned short, h);
+  lo = __builtin_bit_cast(unsigned short, l);
+}
+
+// the four planes of 8 complex values -> 4 x 16 bytes (FP16 words when H16,
+// after scaling by sc)
+template <bool H16 = false>
+__device__ __forceinline__ void split8(const cf* v, uint4* planes, float sc = 1.f) {
   unsigned rh[8], ih[8], rl[8], il[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    split1(v[i].x, rh[i], rl[i]);
-    split1(v[i].y, ih[i], il[i]);
+    if constexpr (H16) {
+      split1h(v[i].x * sc, rh[i], rl[i]);
+      split1h(v[i].y * sc, ih[i], il[i]);
+    } else {
+      split1(v[i].x, rh[i], rl[i]);
+      split1(v[i].y, ih[i], il[i]);
+    }
   }
   auto pack = [](const unsigned* w) {
     return uint4{w[0] | (w[1] << 16), w[2] | (w[3] << 16), w[4] | (w[5] << 16),
@@ -73,12 +102,28 @@ __device__ __forceinline__ void split8(const cf* v, uint4* planes) {
   planes[3] = pack(il);
 }
 
-__device__ __forceinline__ f4 mfma16(const bf8& a, const bf8& b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
 
-__device__ __forceinline__ bf8 as_bf8(uint4 v) { return __builtin_bit_cast(bf8, v); }
+// operand words and matrix instruction of the two forms
+template <bool H16>
+struct Words;
+template <>
+struct Words<false> {
+  typedef bf8 V;
+  static __device__ __forceinline__ V cast(uint4 v) { return __builtin_bit_cast(bf8, v); }
+  static __device__ __forceinline__ f4 mma(const V& a, const V& b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Words<true> {
+  typedef hf8 V;
+  static __device__ __forceinline__ V cast(uint4 v) { return __builtin_bit_cast(hf8, v); }
+  static __device__ __forceinline__ f4 mma(const V& a, const V& b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
 
+// sign flip of 8 BF16 or FP16 words (bit 15 of each half)
 __device__ __forceinline__ uint4 neg_bf16(uint4 v) {
   const unsigned s = 0x80008000u;
   return uint4{v.x ^ s, v.y ^ s, v.z ^ s, v.w ^ s};
@@ -95,6 +140,8 @@ struct SplitArgs {
   const float* cr;              // per-column coefficient of R
   float shift, sa, sb;
   char* Bnext;                  // split panel of E_{i+1} (same geometry as Bs) or null
+  float inv_a;                  // FP16 form: 1 / (scale of H)
+  const float* inv_b;           // FP16 form: 1 / (scale of each window column)
   int tiles_m, tiles_n;
 };
 
@@ -113,8 +160,10 @@ struct SplitTile {
   static constexpr int CHUNKS = (BM + BN) * 16 / NTH;   // 16-byte staging loads per thread
 };
 
-template <int WGM, int WGN, int TI, int TJ>
+template <int WGM, int WGN, int TI, int TJ, bool H16>
 __device__ __forceinline__ void split_tile_body(const SplitArgs& g, char* lds) {
+  using W = Words<H16>;
+  typedef typename W::V V;
   using T = SplitTile<WGM, WGN, TI, TJ>;
   constexpr int BM = T::BM, BN = T::BN, NTH = T::NTH, CH = T::CHUNKS;
   const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
@@ -193,25 +242,25 @@ __device__ __forceinline__ void split_tile_body(const SplitArgs& g, char* lds) {
     // imaginary part: Ar Bi + Ai Br
 #pragma unroll
     for (int i = 0; i < TI; ++i) {
-      const bf8 arh = as_bf8(a[i][0]), arl = as_bf8(a[i][2]);
-      const bf8 aih = as_bf8(a[i][1]), ail = as_bf8(a[i][3]);
-      const bf8 nih = as_bf8(neg_bf16(a[i][1])), nil = as_bf8(neg_bf16(a[i][3]));
+      const V arh = W::cast(a[i][0]), arl = W::cast(a[i][2]);
+      const V aih = W::cast(a[i][1]), ail = W::cast(a[i][3]);
+      const V nih = W::cast(neg_bf16(a[i][1])), nil = W::cast(neg_bf16(a[i][3]));
 #pragma unroll
       for (int j = 0; j < TJ; ++j) {
-        const bf8 brh = as_bf8(b[j][0]), brl = as_bf8(b[j][2]);
-        const bf8 bih = as_bf8(b[j][1]), bil = as_bf8(b[j][3]);
-        accR[i][j] = mfma16(arh, brh, accR[i][j]);
-        accI[i][j] = mfma16(arh, bih, accI[i][j]);
-        accR[i][j] = mfma16(nih, bih, accR[i][j]);
-        accI[i][j] = mfma16(aih, brh, accI[i][j]);
-        accR[i][j] = mfma16(arh, brl, accR[i][j]);
-        accI[i][j] = mfma16(arh, bil, accI[i][j]);
-        accR[i][j] = mfma16(nih, bil, accR[i][j]);
-        accI[i][j] = mfma16(aih, brl, accI[i][j]);
-        accR[i][j] = mfma16(arl, brh, accR[i][j]);
-        accI[i][j] = mfma16(arl, bih, accI[i][j]);
-        accR[i][j] = mfma16(nil, bih, accR[i][j]);
-        accI[i][j] = mfma16(ail, brh, accI[i][j]);
+        const V brh = W::cast(b[j][0]), brl = W::cast(b[j][2]);
+        const V bih = W::cast(b[j][1]), bil = W::cast(b[j][3]);
+        accR[i][j] = W::mma(arh, brh, accR[i][j]);
+        accI[i][j] = W::mma(arh, bih, accI[i][j]);
+        accR[i][j] = W::mma(nih, bih, accR[i][j]);
+        accI[i][j] = W::mma(aih, brh, accI[i][j]);
+        accR[i][j] = W::mma(arh, brl, accR[i][j]);
+        accI[i][j] = W::mma(arh, bil, accI[i][j]);
+        accR[i][j] = W::mma(nih, bil, accR[i][j]);
+        accI[i][j] = W::mma(aih, brl, accI[i][j]);
+        accR[i][j] = W::mma(arl, brh, accR[i][j]);
+        accI[i][j] = W::mma(arl, bih, accI[i][j]);
+        accR[i][j] = W::mma(nil, bih, accR[i][j]);
+        accI[i][j] = W::mma(ail, brh, accI[i][j]);
       }
     }
     if (more) store(cur ^ 1);
@@ -225,6 +274,8 @@ __device__ __forceinline__ void split_tile_body(const SplitArgs& g, char* lds) {
       const int rbase = m0 + wm * 16 * TI + i * 16 + 4 * lg;
       const int col = n0 + wn * 16 * TJ + j * 16 + lr;
       if (col >= g.N) continue;
+      float unscale = 1.f;   // FP16 form: undo the operand scaling (powers of two)
+      if constexpr (H16) unscale = g.inv_a * g.inv_b[col];
       cf out[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -234,8 +285,13 @@ __device__ __forceinline__ void split_tile_body(const SplitArgs& g, char* lds) {
         const cf ec = g.Ecur[row + (long)col * g.lde];
         const cf rr = g.R[row + (long)col * g.ldr];
         const float crj = g.cr[col];
-        cf o = cf{g.sa * (accR[i][j][r] - g.shift * ec.x) + crj * rr.x,
-                  g.sa * (accI[i][j][r] - g.shift * ec.y) + crj * rr.y};
+        float pr = accR[i][j][r], pi = accI[i][j][r];
+        if constexpr (H16) {
+          pr *= unscale;
+          pi *= unscale;
+        }
+        cf o = cf{g.sa * (pr - g.shift * ec.x) + crj * rr.x,
+                  g.sa * (pi - g.shift * ec.y) + crj * rr.y};
         if (g.sb != 0.f) {
           const cf eo = g.Eold[row + (long)col * g.lde];
           o.x -= g.sb * eo.x;
@@ -245,8 +301,9 @@ __device__ __forceinline__ void split_tile_body(const SplitArgs& g, char* lds) {
         out[r] = o;
       }
       // the split of E_{i+1} for a following BF16 step: 4 consecutive k of
-      // column col, zeros beyond M (inside the padding)
-      if (g.Bnext && rbase < g.Kp) {
+      // column col, zeros beyond M (inside the padding); the FP16 form
+      // needs the column's scale first and splits in a pass of its own
+      if (!H16 && g.Bnext && rbase < g.Kp) {
         unsigned rh[4], ih[4], rl[4], il[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -267,12 +324,84 @@ using TileWide = SplitTile<4, 2, 2, 4>;    // 128 x 128, 512 threads
 
 __global__ void __launch_bounds__(TileSmall::NTH, 2) defect_gemm_split(SplitArgs g) {
   __shared__ __attribute__((aligned(16))) char lds[2 * TileSmall::LDS_STAGE];
-  split_tile_body<2, 2, 2, 2>(g, lds);
+  split_tile_body<2, 2, 2, 2, false>(g, lds);
 }
 
 __global__ void __launch_bounds__(TileWide::NTH, 1) defect_gemm_split_wide(SplitArgs g) {
   __shared__ __attribute__((aligned(16))) char lds[2 * TileWide::LDS_STAGE];
-  split_tile_body<4, 2, 2, 4>(g, lds);
+  split_tile_body<4, 2, 2, 4, false>(g, lds);
+}
+
+__global__ void __launch_bounds__(TileSmall::NTH, 2) defect_gemm_h16(SplitArgs g) {
+  __shared__ __attribute__((aligned(16))) char lds[2 * TileSmall::LDS_STAGE];
+  split_tile_body<2, 2, 2, 2, true>(g, lds);
+}
+
+__global__ void __launch_bounds__(TileWide::NTH, 1) defect_gemm_h16_wide(SplitArgs g) {
+  __shared__ __attribute__((aligned(16))) char lds[2 * TileWide::LDS_STAGE];
+  split_tile_body<4, 2, 2, 4, true>(g, lds);
+}
+
+// Power-of-two scale that brings the largest magnitude m into [2^14, 2^15)
+// (1 for m = 0; capped at 2^100 so that its inverse stays a normal number).
+__device__ __forceinline__ int h16_scale_exp(float m) {
+  if (!(m > 0.f) || !isfinite(m)) return 0;
+  return min(14 - ilogbf(m), 100);
+}
+
+// FP16 split panel of FP32 columns, each scaled by its own power of two:
+// one workgroup (256 threads) per column; inv[j] receives 1 / scale.
+__global__ void __launch_bounds__(256) split_cols_h16(int K, int Kp, const cf* E, long lde,
+                                                      char* S, long srow, float* inv) {
+  __shared__ float red[256];
+  const int j = blockIdx.x, t = threadIdx.x;
+  const cf* col = E + (long)j * lde;
+  float m = 0.f;
+  for (int r = t; r < K; r += 256) {
+    const cf v = col[r];
+    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+  red[t] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] = fmaxf(red[t], red[t + w]);
+    __syncthreads();
+  }
+  const int ex = h16_scale_exp(red[0]);
+  const float sc = ldexpf(1.f, ex);
+  const int groups = Kp / 8;
+  for (int grp = t; grp < groups; grp += 256) {
+    cf v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int k = grp * 8 + i;
+      v[i] = k < K ? col[k] : cf{0.f, 0.f};
+    }
+    uint4 pl[4];
+    split8<true>(v, pl, sc);
+    uint4* dst = (uint4*)(S + j * srow + (long)grp * GROUP_B);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = pl[q];
+  }
+  if (t == 0) inv[j] = ldexpf(1.f, -ex);
+}
+
+// Largest |re|, |im| of count complex64 values: one partial per workgroup.
+__global__ void __launch_bounds__(256) absmax_part(long count, const cf* X, float* part) {
+  __shared__ float red[256];
+  const int t = threadIdx.x;
+  float m = 0.f;
+  for (long i = (long)blockIdx.x * 256 + t; i < count; i += (long)gridDim.x * 256) {
+    const cf v = X[i];
+    m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+  red[t] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] = fmaxf(red[t], red[t + w]);
+    __syncthreads();
+  }
+  if (t == 0) part[blockIdx.x] = red[0];
 }
 
 // Split panel of FP32 columns: row j of S = column j of E (K values, zero
@@ -298,7 +427,8 @@ __global__ void split_cols(int K, int Kp, int cols, const cf* E, long lde, char*
 // Split panel of the rows of an FP64 matrix: row m of S = H[m, :] (values
 // rounded to FP32 first, as in the FP32 step), through a 32 x 64 LDS tile.
 constexpr int TM = 32, TK = 64;
-__global__ void split_rows(int n, int Kp, const zc* H, long ldh, char* S, long srow) {
+template <bool H16>
+__global__ void split_rows(int n, int Kp, const zc* H, long ldh, char* S, long srow, float sc) {
   __shared__ cf tile[TK][TM + 1];
   const int m0 = blockIdx.x * TM, k0 = blockIdx.y * TK;
   const int t = threadIdx.x;
@@ -324,7 +454,7 @@ __global__ void split_rows(int n, int Kp, const zc* H, long ldh, char* S, long s
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = tile[grp * 8 + i][mm];
     uint4 pl[4];
-    split8(v, pl);
+    split8<H16>(v, pl, sc);
     uint4* dst = (uint4*)(S + m * srow + (long)(kg / 8) * GROUP_B);
 #pragma unroll
     for (int q = 0; q < 4; ++q) dst[q] = pl[q];
@@ -340,8 +470,42 @@ size_t split_panel_bytes(int rows, int K) { return (size_t)rows * (size_t)split_
 int matrix_to_split(hipStream_t s, int n, const zc* H, long ldh, void* Hs) {
   const int kp = split_kp(n);
   dim3 grid((unsigned)((n + TM - 1) / TM), (unsigned)((kp + TK - 1) / TK));
-  hipLaunchKernelGGL(split_rows, grid, dim3(256), 0, s, n, kp, H, ldh, (char*)Hs,
-                     (long)kp * 8);
+  hipLaunchKernelGGL(split_rows<false>, grid, dim3(256), 0, s, n, kp, H, ldh, (char*)Hs,
+                     (long)kp * 8, 1.f);
+  return (int)hipGetLastError();
+}
+
+int matrix_to_split_h16(hipStream_t s, int n, const zc* H, long ldh, const void* H32,
+                        void* Hs, float* part, float* inv_out) {
+  constexpr int PARTS = 1024;
+  const long count = (long)n * n;
+  const int blocks = (int)std::min<long>(PARTS, (count + 255) / 256);
+  hipLaunchKernelGGL(absmax_part, dim3(blocks), dim3(256), 0, s, count, (const cf*)H32, part);
+  int e = (int)hipGetLastError();
+  if (e) return e;
+  float hp[PARTS];
+  e = (int)hipMemcpyAsync(hp, part, sizeof(float) * blocks, hipMemcpyDeviceToHost, s);
+  if (e) return e;
+  e = (int)hipStreamSynchronize(s);
+  if (e) return e;
+  float m = 0.f;
+  for (int i = 0; i < blocks; ++i) m = std::max(m, hp[i]);
+  int ex = 0;
+  if (m > 0.f && std::isfinite(m)) ex = std::min(14 - std::ilogb(m), 100);
+  const int kp = split_kp(n);
+  dim3 grid((unsigned)((n + TM - 1) / TM), (unsigned)((kp + TK - 1) / TK));
+  hipLaunchKernelGGL(split_rows<true>, grid, dim3(256), 0, s, n, kp, H, ldh, (char*)Hs,
+                     (long)kp * 8, std::ldexp(1.f, ex));
+  *inv_out = std::ldexp(1.f, -ex);
+  return (int)hipGetLastError();
+}
+
+int cols_to_split_h16(hipStream_t s, int K, int cols, const void* E, long lde, void* S,
+                      float* inv) {
+  if (cols <= 0) return 0;
+  const int kp = split_kp(K);
+  hipLaunchKernelGGL(split_cols_h16, dim3((unsigned)cols), dim3(256), 0, s, K, kp, (const cf*)E,
+                     lde, (char*)S, (long)kp * 8, inv);
   return (int)hipGetLastError();
 }
 
@@ -377,6 +541,33 @@ int defect_step_split(hipStream_t s, int n, int N, const void* Hs, const void* E
   g.tiles_n = (N + TileSmall::BN - 1) / TileSmall::BN;
   const int grid = ((g.tiles_m + NXCD - 1) / NXCD) * g.tiles_n * NXCD;
   hipLaunchKernelGGL(defect_gemm_split, dim3(grid), dim3(TileSmall::NTH), 0, s, g);
+  return (int)hipGetLastError();
+}
+
+int defect_step_h16(hipStream_t s, int n, int N, const void* Hs, float inv_h, const void* Es,
+                    const float* inv_e, const void* Ecur, const void* Eold, void* Eout,
+                    const void* R32, const float* cr, float shift, float sa, float sb) {
+  if (N <= 0) return 0;
+  SplitArgs g = {};
+  g.M = n; g.N = N; g.Kp = split_kp(n);
+  g.As = (const char*)Hs; g.a_row = (long)g.Kp * 8;
+  g.Bs = (const char*)Es; g.b_row = (long)g.Kp * 8;
+  g.Ecur = (const cf*)Ecur; g.Eold = (const cf*)Eold; g.Eout = (cf*)Eout; g.lde = n;
+  g.R = (const cf*)R32; g.ldr = n; g.cr = cr;
+  g.shift = shift; g.sa = sa; g.sb = sb;
+  g.Bnext = nullptr;
+  g.inv_a = inv_h; g.inv_b = inv_e;
+  if (N >= SPLIT_WIDE_MIN_N) {
+    g.tiles_m = (n + TileWide::BM - 1) / TileWide::BM;
+    g.tiles_n = (N + TileWide::BN - 1) / TileWide::BN;
+    const int grid = ((g.tiles_m + NXCD - 1) / NXCD) * g.tiles_n * NXCD;
+    hipLaunchKernelGGL(defect_gemm_h16_wide, dim3(grid), dim3(TileWide::NTH), 0, s, g);
+    return (int)hipGetLastError();
+  }
+  g.tiles_m = (n + TileSmall::BM - 1) / TileSmall::BM;
+  g.tiles_n = (N + TileSmall::BN - 1) / TileSmall::BN;
+  const int grid = ((g.tiles_m + NXCD - 1) / NXCD) * g.tiles_n * NXCD;
+  hipLaunchKernelGGL(defect_gemm_h16, dim3(grid), dim3(TileSmall::NTH), 0, s, g);
   return (int)hipGetLastError();
 }
 

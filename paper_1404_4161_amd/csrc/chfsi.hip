@@ -110,7 +110,9 @@ struct StepBufs {
   zc *T1, *T2, *G, *K2, *invk, *scratch, *gv_part, *V, *w, *h, *fpart;
   size_t fpart_elems;
   void *R32, *E0, *E1;          // mixed-precision filter: complex64 n x k each
-  void *S0, *S1;                // BF16 splits of E_i (k rows of split_kp(n) values)
+  void *S0, *S1;                // BF16 / FP16 splits of E_i (k rows of split_kp(n) values)
+  float* colscale;              // FP16 splits: 1 / scale of each column of E_i (k)
+  float* h16part;               // FP16 splits: partial maxima of |H| (1024)
   float* crtab;                 // CR_ROWS x k coefficients of the residual term
   double* pm;                   // k final scalars p_{m_j}(mu_t)
   float *mlp_p, *mlp_x, *mlp_y;  // degree network: parameters, k x 8 inputs, k outputs
@@ -152,6 +154,8 @@ void carve_step(Carver& c, StepBufs& b, int n, int k, int nev, int lanczos_steps
   b.E1 = c.take<char>(nk * 8);
   b.S0 = c.take<char>(split_panel_bytes(k, n));
   b.S1 = c.take<char>(split_panel_bytes(k, n));
+  b.colscale = c.take<float>(k);
+  b.h16part = c.take<float>(1024);
   b.crtab = c.take<float>((size_t)CR_ROWS * k);
   b.pm = c.take<double>(k);
   b.mlp_p = c.take<float>(MLP_PARAMS);
@@ -575,16 +579,26 @@ int upload(hipStream_t s, T* dst, const std::vector<T>& v) {
 // is the column filtered j-th (ascending degree m[j]).  The filtered block
 // goes to Y (ld), and Qs (ld) receives the reordered Q.
 //
-// Hs (or null) is the BF16 split panel of H; sched[i] = 1 runs step i (E_i
-// -> E_{i+1}) in the BF16-split form (cfilter16.hip), which needs Hs.
-// flops32 / flops16 receive the algorithmic flops of the FP32 and BF16
-// steps, steps16 the number of BF16 steps.
+// Per-step forms of the defect filter besides FP32 (cfilter16.hip):
+// sched[i] = 1 runs step i (E_i -> E_{i+1}) in the BF16-split form (needs
+// Hs, the BF16 split panel of H), 2 in the FP16-split form (needs Hh, the
+// FP16 split panel of 2^s H, and inv_h = 2^-s).  The counters receive the
+// algorithmic flops and the number of steps of each split form.
+struct SplitSteps {
+  const void* Hs = nullptr;
+  const void* Hh = nullptr;
+  float inv_h = 1.f;
+  const std::vector<char>* sched = nullptr;
+  double flops_bf16 = 0.0, flops_fp16 = 0.0;
+  int steps_bf16 = 0, steps_fp16 = 0;
+};
+
+// flops32 receives the algorithmic flops of the FP32 steps; sp (or null)
+// selects split forms for some steps and counts them.
 int defect_filter_dev(hipStream_t s, int n, int k, const void* H32, const zc* Q, const zc* Z,
                       long ld, const std::vector<double>& mu, const std::vector<int>& order,
                       const std::vector<int>& m, double c, double e, double gamma, zc* Qs, zc* Y,
-                      StepBufs& b, double* flops32, int* launches, const void* Hs = nullptr,
-                      const std::vector<char>* sched = nullptr, double* flops16 = nullptr,
-                      int* steps16 = nullptr) {
+                      StepBufs& b, double* flops32, int* launches, SplitSteps* sp = nullptr) {
   if (k <= 0) return CHFSI_OK;
   const int mmax = m[k - 1];
   if (mmax > CR_ROWS) return CHFSI_INVALID_ARG;
@@ -618,8 +632,12 @@ int defect_filter_dev(hipStream_t s, int n, int k, const void* H32, const zc* Q,
   while (first < k && m[first] <= 1) ++first;
   const size_t c64 = 8;   // bytes per complex64
   const size_t srow = (size_t)split_kp(n) * 8;   // bytes per split-panel row
-  auto bf16_step = [&](int i) {
-    return Hs && sched && i < (int)sched->size() && (*sched)[i] != 0;
+  auto kind = [&](int i) -> int {
+    if (!sp || !sp->sched || i >= (int)sp->sched->size()) return 0;
+    const int v = (*sp->sched)[i];
+    if (v == 1 && sp->Hs) return 1;
+    if (v == 2 && sp->Hh) return 2;
+    return 0;
   };
   bool split_ready = false;   // the split panel of E_i holds the window
   for (int i = 1; i < mmax; ++i) {
@@ -630,17 +648,26 @@ int defect_filter_dev(hipStream_t s, int n, int k, const void* H32, const zc* Q,
     const float shift = (float)c, sa = (float)(2.0 * sig[i + 1] / e);
     const float sbeta = (float)(sig[i + 1] * sig[i]);
     const float* cri = b.crtab + (size_t)i * k + first;
-    if (bf16_step(i)) {
+    const int kd = kind(i);
+    if (kd == 1) {
       char* scur = (char*)((i & 1) ? b.S1 : b.S0) + first * srow;
       char* snext = (char*)((i & 1) ? b.S0 : b.S1) + first * srow;
       if (!split_ready) CK(cols_to_split(s, n, cols, cur + off, n, scur));
-      const bool next16 = bf16_step(i + 1) && i + 1 < mmax;
-      CK(defect_step_split(s, n, cols, Hs, scur, cur + off, old + off, old + off,
+      const bool next16 = kind(i + 1) == 1 && i + 1 < mmax;
+      CK(defect_step_split(s, n, cols, sp->Hs, scur, cur + off, old + off, old + off,
                            (const char*)b.R32 + off, cri, shift, sa, sbeta,
                            next16 ? snext : nullptr));
       split_ready = next16;
-      if (flops16) *flops16 += 8.0 * (double)n * n * cols;
-      if (steps16) *steps16 += 1;
+      sp->flops_bf16 += 8.0 * (double)n * n * cols;
+      sp->steps_bf16 += 1;
+    } else if (kd == 2) {
+      char* scur = (char*)b.S0 + first * srow;
+      CK(cols_to_split_h16(s, n, cols, cur + off, n, scur, b.colscale + first));
+      CK(defect_step_h16(s, n, cols, sp->Hh, sp->inv_h, scur, b.colscale + first, cur + off,
+                         old + off, old + off, (const char*)b.R32 + off, cri, shift, sa, sbeta));
+      split_ready = false;
+      sp->flops_fp16 += 8.0 * (double)n * n * cols;
+      sp->steps_fp16 += 1;
     } else {
       CK(defect_step(s, n, cols, H32, cur + off, old + off, old + off, (const char*)b.R32 + off,
                      cri, shift, sa, sbeta, b.fpart, b.fpart_elems * 2));
@@ -735,16 +762,20 @@ bool cap_degrees_fp32(int n_wanted, const std::vector<double>& mu, const std::ve
 // too early only costs convergence (the FP64 residuals decide locking).
 // deg is in the current column order; the result has one entry per step
 // index 0 .. max degree - 1 (entry 0 unused).
+// The FP16-split form (precision 3) takes the same rule with its own
+// bound, FP16_SPLIT_EPS = 3 * 2^-22, and marks its steps 2.
 constexpr double BF16_SPLIT_EPS = 3.0 / 65536.0;
+constexpr double FP16_SPLIT_EPS = 3.0 / 4194304.0;
 constexpr double BF16_SPLIT_MARGIN = 10.0;
 
-std::vector<char> bf16_step_schedule(int n_wanted, const std::vector<double>& mu,
-                                     const std::vector<double>& res, const std::vector<int>& deg,
-                                     double c, double e, double tol, double norm_h) {
+std::vector<char> split_step_schedule(int n_wanted, const std::vector<double>& mu,
+                                      const std::vector<double>& res, const std::vector<int>& deg,
+                                      double c, double e, double tol, double norm_h,
+                                      double eps, char mark) {
   const int ka = (int)deg.size();
   int mmax = 0;
   for (int j = 0; j < ka; ++j) mmax = std::max(mmax, deg[j]);
-  std::vector<char> ok(std::max(mmax, 1), 1);
+  std::vector<char> ok(std::max(mmax, 1), mark);
   ok[0] = 0;
   for (int j = 0; j < std::min(n_wanted, ka); ++j) {
     const double t = (mu[j] - c) / e;
@@ -752,7 +783,7 @@ std::vector<char> bf16_step_schedule(int n_wanted, const std::vector<double>& mu
     const double rel = res[j] / norm_h;
     const double target = std::max(tol, rel * std::exp(-lr * deg[j]));
     for (int i = 1; i < deg[j]; ++i) {
-      const double floor_ = BF16_SPLIT_EPS * rel * std::exp(-lr * (deg[j] - i - 1));
+      const double floor_ = eps * rel * std::exp(-lr * (deg[j] - i - 1));
       if (!(floor_ * BF16_SPLIT_MARGIN <= target)) ok[i] = 0;
     }
   }
@@ -792,6 +823,8 @@ struct SolveBufs {
   zc *QL, *QA, *ZA, *P0, *P1, *TMP;
   void* H32 = nullptr;          // fp32(H), mixed precision only
   void* Hs = nullptr;           // BF16 split panel of H's rows, precision 2 only
+  void* Hh = nullptr;           // FP16 split panel of 2^s H's rows, precision 3 only
+  float inv_hh = 1.f;           // 2^-s
   int* flag;
   StepBufs st;
 };
@@ -818,6 +851,7 @@ size_t carve_solve(Carver& c, SolveBufs& b, int n, int nev, int nex, bool gen, i
   b.TMP = c.take<zc>(nk);
   if (precision >= 1) b.H32 = c.take<char>(nn * 8);
   if (precision == 2) b.Hs = c.take<char>(split_panel_bytes(n, n));
+  if (precision == 3) b.Hh = c.take<char>(split_panel_bytes(n, n));
   b.flag = c.take<int>(8);
   carve_step(c, b.st, n, k, nev, lsteps);
   return c.off + ALIGN;
@@ -1083,7 +1117,8 @@ struct Solve {
   int it = 0;
   int status = CHFSI_NO_CONVERGENCE;
   double filter_flops = 0.0, filter_sec = 0.0, flops32 = 0.0, sec32 = 0.0, flops16 = 0.0;
-  int iters32 = 0, launches = 0, steps16 = 0, rr_refined = 0, rr_dense = 0;
+  double flopsh = 0.0;
+  int iters32 = 0, launches = 0, steps16 = 0, stepsh = 0, rr_refined = 0, rr_dense = 0;
   bool have_res = false;   // residuals of the current block known
   hipEvent_t fe0 = nullptr, fe1 = nullptr;
   bool done = false;
@@ -1223,6 +1258,8 @@ struct Solve {
       for (int j = 0; j < k; ++j) speed[j] = o.seq_rates[j];
     if (o.precision >= 1) CK(matrix_to_fp32(s, n, H, ldh, b.H32));
     if (o.precision == 2) CK(matrix_to_split(s, n, H, ldh, b.Hs));
+    if (o.precision == 3)
+      CK(matrix_to_split_h16(s, n, H, ldh, b.H32, b.Hh, b.st.h16part, &b.inv_hh));
     CK(hipEventCreate(&fe0));
     CK(hipEventCreate(&fe1));
     return CHFSI_OK;
@@ -1402,13 +1439,24 @@ struct Solve {
       tm.begin(2);
       double f32 = 0.0;
       std::vector<char> sched;
-      if (o.precision == 2)
-        sched = bf16_step_schedule(nev - nl, mu, res, std::vector<int>(deg.begin(), deg.begin() + ka),
-                                   c, e, tol, norm_h);
+      SplitSteps sp;
+      if (o.precision >= 2) {
+        const bool h16 = o.precision == 3;
+        sched = split_step_schedule(nev - nl, mu, res,
+                                    std::vector<int>(deg.begin(), deg.begin() + ka), c, e, tol,
+                                    norm_h, h16 ? FP16_SPLIT_EPS : BF16_SPLIT_EPS, h16 ? 2 : 1);
+        sp.Hs = b.Hs;
+        sp.Hh = b.Hh;
+        sp.inv_h = b.inv_hh;
+        sp.sched = &sched;
+      }
       CKS(defect_filter_dev(s, n, ka, b.H32, b.QA, b.ZA, ld,
                             std::vector<double>(mu.begin(), mu.begin() + ka), order, msort, c, e,
-                            gamma, b.P0, b.TMP, sb, &f32, &launches, b.Hs,
-                            o.precision == 2 ? &sched : nullptr, &flops16, &steps16));
+                            gamma, b.P0, b.TMP, sb, &f32, &launches, &sp));
+      flops16 += sp.flops_bf16;
+      steps16 += sp.steps_bf16;
+      flopsh += sp.flops_fp16;
+      stepsh += sp.steps_fp16;
       tm.end();
       flops32 += f32;
       iters32 += 1;
@@ -1587,6 +1635,8 @@ struct Solve {
       info->filter_flops_fp32 = flops32;
       info->filter_flops_bf16 = flops16;
       info->filter_steps_bf16 = steps16;
+      info->filter_flops_fp16 = flopsh;
+      info->filter_steps_fp16 = stepsh;
       info->filter_seconds_fp32 = sec32;
       info->beta = beta;
       info->norm_h = norm_h;
@@ -1989,7 +2039,7 @@ int validate_solve(int n, int nev, int nex, const void* A, int lda, const void* 
     if (B && (ldb < n || !aligned16(B))) return CHFSI_INVALID_ARG;
     if (X0 && (ldx0 < n || !aligned16(X0))) return CHFSI_INVALID_ARG;
     if (o.deg0 < 1 || o.deg_max < 1 || o.max_iter < 1 || o.lanczos_steps < 1) return CHFSI_INVALID_ARG;
-    if (o.precision < 0 || o.precision > 2) return CHFSI_INVALID_ARG;
+    if (o.precision < 0 || o.precision > 3) return CHFSI_INVALID_ARG;
     if (o.rr_refine < 0 || o.rr_refine > 1) return CHFSI_INVALID_ARG;
     if (o.degree_mode < 0 || o.degree_mode > 3 || o.first_rule < 0 || o.first_rule > 1)
       return CHFSI_INVALID_ARG;
@@ -2296,45 +2346,87 @@ size_t chfsi_defect_split_workspace_bytes(int n, int k) {
   return chfsi_defect_workspace_bytes(n, k) + split_panel_bytes(n, n) + ALIGN;
 }
 
+namespace {
+
+// The defect filter with its first split_steps steps in a split form (mark
+// 1: BF16, 2: FP16), the rest FP32 (the workspace of both entry points).
+int filter_defect_split_impl(int n, int k, const void* H, int ldh, const void* Q, int ldq,
+                             const void* Z, int ldz, const double* mu, const int* degrees,
+                             double c, double e, double gamma, int split_steps, char mark,
+                             void* Y, int ldy, void* work, size_t work_bytes, void* stream,
+                             double* flops_split_out, double* flops_fp32_out) {
+  if (n < 1 || k < 1 || k > n || ldh < n || ldq != n || ldz != n || ldy < n || !mu ||
+      !degrees || !(e > 0.0) || gamma == c || split_steps < 0)
+    return CHFSI_INVALID_ARG;
+  if (check_ptr(H) || check_ptr(Q) || check_ptr(Z) || check_ptr(Y) || check_ptr(work))
+    return CHFSI_INVALID_ARG;
+  for (int j = 0; j < k; ++j) {
+    if (degrees[j] < 1 || degrees[j] > CR_ROWS || (j > 0 && degrees[j] < degrees[j - 1]))
+      return CHFSI_INVALID_ARG;
+  }
+  if (work_bytes < chfsi_defect_split_workspace_bytes(n, k)) return CHFSI_INVALID_ARG;
+  hipStream_t s = as_stream(stream);
+  StepBufs b;
+  Carver cv(work);
+  carve_step(cv, b, n, k, k, 20);
+  void* H32 = cv.take<char>((size_t)n * n * 8);
+  void* Hsp = cv.take<char>(split_panel_bytes(n, n));
+  CK(matrix_to_fp32(s, n, (const zc*)H, ldh, H32));
+  SplitSteps sp;
+  if (mark == 1) {
+    CK(matrix_to_split(s, n, (const zc*)H, ldh, Hsp));
+    sp.Hs = Hsp;
+  } else {
+    CK(matrix_to_split_h16(s, n, (const zc*)H, ldh, H32, Hsp, b.h16part, &sp.inv_h));
+    sp.Hh = Hsp;
+  }
+  std::vector<int> order(k), m(degrees, degrees + k);
+  std::iota(order.begin(), order.end(), 0);
+  std::vector<double> muv(mu, mu + k);
+  const int mmax = m[k - 1];
+  std::vector<char> sched(std::max(mmax, 1), 0);
+  for (int i = 1; i < mmax; ++i) sched[i] = i <= split_steps ? mark : 0;
+  sp.sched = &sched;
+  double f32 = 0.0;
+  int launches = 0;
+  CKS(defect_filter_dev(s, n, k, H32, (const zc*)Q, (const zc*)Z, n, muv, order, m, c, e, gamma,
+                        b.T1, b.T2, b, &f32, &launches, &sp));
+  CK(copy2d(s, n, k, b.T2, n, (zc*)Y, ldy));
+  CK(hipStreamSynchronize(s));
+  if (flops_split_out) *flops_split_out = mark == 1 ? sp.flops_bf16 : sp.flops_fp16;
+  if (flops_fp32_out) *flops_fp32_out = f32;
+  return CHFSI_OK;
+}
+
+}  // namespace
+
 int chfsi_filter_defect_split(int n, int k, const void* H, int ldh, const void* Q, int ldq,
                               const void* Z, int ldz, const double* mu, const int* degrees,
                               double c, double e, double gamma, int bf16_steps, void* Y, int ldy,
                               void* work, size_t work_bytes, void* stream,
                               double* flops_bf16_out, double* flops_fp32_out) {
   try {
-    if (n < 1 || k < 1 || k > n || ldh < n || ldq != n || ldz != n || ldy < n || !mu ||
-        !degrees || !(e > 0.0) || gamma == c || bf16_steps < 0)
-      return CHFSI_INVALID_ARG;
-    if (check_ptr(H) || check_ptr(Q) || check_ptr(Z) || check_ptr(Y) || check_ptr(work))
-      return CHFSI_INVALID_ARG;
-    for (int j = 0; j < k; ++j) {
-      if (degrees[j] < 1 || degrees[j] > CR_ROWS || (j > 0 && degrees[j] < degrees[j - 1]))
-        return CHFSI_INVALID_ARG;
-    }
-    if (work_bytes < chfsi_defect_split_workspace_bytes(n, k)) return CHFSI_INVALID_ARG;
-    hipStream_t s = as_stream(stream);
-    StepBufs b;
-    Carver cv(work);
-    carve_step(cv, b, n, k, k, 20);
-    void* H32 = cv.take<char>((size_t)n * n * 8);
-    void* Hs = cv.take<char>(split_panel_bytes(n, n));
-    CK(matrix_to_fp32(s, n, (const zc*)H, ldh, H32));
-    CK(matrix_to_split(s, n, (const zc*)H, ldh, Hs));
-    std::vector<int> order(k), m(degrees, degrees + k);
-    std::iota(order.begin(), order.end(), 0);
-    std::vector<double> muv(mu, mu + k);
-    const int mmax = m[k - 1];
-    std::vector<char> sched(std::max(mmax, 1), 0);
-    for (int i = 1; i < mmax; ++i) sched[i] = i <= bf16_steps ? 1 : 0;
-    double f32 = 0.0, f16 = 0.0;
-    int launches = 0, steps16 = 0;
-    CKS(defect_filter_dev(s, n, k, H32, (const zc*)Q, (const zc*)Z, n, muv, order, m, c, e, gamma,
-                          b.T1, b.T2, b, &f32, &launches, Hs, &sched, &f16, &steps16));
-    CK(copy2d(s, n, k, b.T2, n, (zc*)Y, ldy));
-    CK(hipStreamSynchronize(s));
-    if (flops_bf16_out) *flops_bf16_out = f16;
-    if (flops_fp32_out) *flops_fp32_out = f32;
-    return CHFSI_OK;
+    return filter_defect_split_impl(n, k, H, ldh, Q, ldq, Z, ldz, mu, degrees, c, e, gamma,
+                                    bf16_steps, 1, Y, ldy, work, work_bytes, stream,
+                                    flops_bf16_out, flops_fp32_out);
+  } catch (const std::exception& ex) {
+    report_failure(ex.what(), __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
+  } catch (...) {
+    report_failure("unknown exception", __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
+  }
+}
+
+int chfsi_filter_defect_fp16(int n, int k, const void* H, int ldh, const void* Q, int ldq,
+                             const void* Z, int ldz, const double* mu, const int* degrees,
+                             double c, double e, double gamma, int fp16_steps, void* Y, int ldy,
+                             void* work, size_t work_bytes, void* stream,
+                             double* flops_fp16_out, double* flops_fp32_out) {
+  try {
+    return filter_defect_split_impl(n, k, H, ldh, Q, ldq, Z, ldz, mu, degrees, c, e, gamma,
+                                    fp16_steps, 2, Y, ldy, work, work_bytes, stream,
+                                    flops_fp16_out, flops_fp32_out);
   } catch (const std::exception& ex) {
     report_failure(ex.what(), __LINE__, -1);
     return CHFSI_DEVICE_ERROR;

@@ -171,7 +171,7 @@ int defect_step(hipStream_t s, int n, int N, const void* H32, const void* Ecur, 
 int defect_assemble_launch(hipStream_t s, int n, int k, const zc* Qs, long ld, const void* E0,
                            const void* E1, const int* deg, const double* pm, zc* Y, long ldy);
 
-// ----- BF16-split defect step, cfilter16.hip -----
+// ----- BF16- and FP16-split defect steps, cfilter16.hip -----
 // Split panels: rows of a reduction index padded to split_kp(K) (a multiple
 // of 32), 8 bytes per complex value (BF16 hi/lo of the real and imaginary
 // parts, grouped by 8 k).
@@ -187,6 +187,21 @@ int cols_to_split(hipStream_t s, int K, int cols, const void* E, long lde, void*
 int defect_step_split(hipStream_t s, int n, int N, const void* Hs, const void* Es,
                       const void* Ecur, const void* Eold, void* Eout, const void* R32,
                       const float* cr, float shift, float sa, float sb, void* Es_next);
+// FP16 form (same panel geometry, FP16 words of scaled values).  Hs row m =
+// split(2^s fp32(H[m, :])) with one power of two s from the largest
+// magnitude of H32 (= fp32(H), n x n contiguous; part: 1024 floats of
+// device scratch; synchronises the stream); *inv_out = 2^-s.
+int matrix_to_split_h16(hipStream_t s, int n, const zc* H, long ldh, const void* H32,
+                        void* Hs, float* part, float* inv_out);
+// S row j = split(2^s_j E[:, j]) with s_j from column j's largest magnitude;
+// inv[j] = 2^-s_j (device).
+int cols_to_split_h16(hipStream_t s, int K, int cols, const void* E, long lde, void* S,
+                      float* inv);
+// The defect step with H Ecur from the FP16 splits (inv_h, inv_e undo the
+// scaling).  No split-K.
+int defect_step_h16(hipStream_t s, int n, int N, const void* Hs, float inv_h, const void* Es,
+                    const float* inv_e, const void* Ecur, const void* Eold, void* Eout,
+                    const void* R32, const float* cr, float shift, float sa, float sb);
 
 // ----- projected eigenproblem by iterative refinement, eigref.hip -----
 struct EigRefineBufs {

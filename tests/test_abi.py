@@ -35,14 +35,16 @@ def test_workspace_query():
     assert gen - small >= 3 * 1000 * 1000 * 16                      # H, L, W for the reduction
     assert ch.chfsi_step_workspace_bytes(1000, 70) > 2 * 1000 * 70 * 16
     assert ch.chfsi_reduce_workspace_bytes(300) >= 300 * 300 * 16
-    # mixed precision adds fp32(H); the BF16-split form also its split panel
+    # mixed precision adds fp32(H); the BF16- and FP16-split forms also their
+    # split panel
     o = ch.chfsi_default_opts()
     sizes = []
-    for p in (0, 1, 2):
+    for p in (0, 1, 2, 3):
         o.precision = p
         sizes.append(ch.chfsi_workspace_bytes(1000, 50, 20, False, o))
     assert sizes[1] - sizes[0] >= 1000 * 1000 * 8
     assert sizes[2] - sizes[1] >= 1000 * 1024 * 8
+    assert sizes[3] == sizes[2]
     lib = ch.lib()
     assert lib.chfsi_defect_split_workspace_bytes(1000, 70) >= \
         lib.chfsi_defect_workspace_bytes(1000, 70) + 1000 * 1024 * 8
@@ -88,10 +90,10 @@ def test_invalid_arguments_are_rejected_before_any_device_call():
     # BF16-split defect filter: negative step count, unsorted degrees, small workspace
     mu = (ctypes.c_double * 2)(1.0, 2.0)
     ok = (ctypes.c_int * 2)(2, 3)
-    for steps, dg, wb in ((-1, ok, 1 << 40), (1, deg, 1 << 40), (1, ok, 64)):
-        assert lib.chfsi_filter_defect_split(10, 2, dummy, 10, dummy, 10, dummy, 10, mu, dg, 5.0,
-                                             1.0, -2.0, steps, dummy, 10, dummy, wb, None, None,
-                                             None) == ch.binding.CHFSI_INVALID_ARG
+    for fn in (lib.chfsi_filter_defect_split, lib.chfsi_filter_defect_fp16):
+        for steps, dg, wb in ((-1, ok, 1 << 40), (1, deg, 1 << 40), (1, ok, 64)):
+            assert fn(10, 2, dummy, 10, dummy, 10, dummy, 10, mu, dg, 5.0, 1.0, -2.0, steps,
+                      dummy, 10, dummy, wb, None, None, None) == ch.binding.CHFSI_INVALID_ARG
 
 
 def test_degree_rule_bit_exact_with_oracle():
@@ -138,8 +140,10 @@ def test_learned_degree_options_defaults_and_validation():
                                     None) == ch.binding.CHFSI_INVALID_ARG
     assert lib.chfsi_eigh_projected(4, dummy, 3, dummy, 4, lam, 1, dummy, 1 << 30, None,
                                     None) == ch.binding.CHFSI_INVALID_ARG
-    assert solve_with(precision=3) == ch.binding.CHFSI_INVALID_ARG
+    assert solve_with(precision=4) == ch.binding.CHFSI_INVALID_ARG
+    assert solve_with(precision=-1) == ch.binding.CHFSI_INVALID_ARG
     assert solve_with(precision=2, deg_max=300) == ch.binding.CHFSI_INVALID_ARG
+    assert solve_with(precision=3, deg_max=300) == ch.binding.CHFSI_INVALID_ARG
     assert solve_with(degree_mode=3) == ch.binding.CHFSI_INVALID_ARG
     assert solve_with(degree_mode=2) == ch.binding.CHFSI_INVALID_ARG        # no network
     assert solve_with(degree_jitter=-0.1) == ch.binding.CHFSI_INVALID_ARG

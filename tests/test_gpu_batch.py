@@ -41,7 +41,7 @@ def _opts(**kw):
     return o
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 3])
 def test_batch_sequence_matches_oracle_and_single_solves(precision):
     import torch
     seqs, probs = _batch(length=3)

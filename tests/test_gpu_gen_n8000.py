@@ -47,7 +47,7 @@ def sequence():
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("precision", [0, 1, 2, 3])
 def test_gen_n8000_sequence_matches_golden(sequence, precision):
     import torch
     conf, seq, probs = sequence

@@ -330,6 +330,90 @@ def test_bf16_split_filter_matches_oracle_with_error_scaling_like_the_residual(d
     assert f16 + f32 == pytest.approx(8.0 * n * n * sum(m - 1 for m in deg))
 
 
+def _ritz_block_spread(n, k, seed, hscale):
+    """Ritz block of (hscale * H) whose columns' perturbations span seven
+    orders of magnitude (1e-9 .. 1e-2), so that the defect columns differ in
+    scale by as much (each FP16 column scale is then exercised)."""
+    lam, h = _herm_problem(n, seed)
+    lam, h = lam * hscale, h * hscale
+    q0 = np.linalg.eigh(h)[1][:, :k]
+    d = 10.0 ** np.random.default_rng(seed + 2).uniform(-9, -2, k)
+    q = ochfsi.orthonormalize(q0 + _rand(n, k, seed + 1) * d, np.zeros((n, 0), complex))
+    mu, q, z = ochfsi.rayleigh_ritz(h, q)
+    return lam, h, mu, q, z
+
+
+@pytest.mark.parametrize("n,k,hscale", [(333, 70, 1.0), (1000, 130, 1e6), (1000, 400, 1e-5),
+                                        (100, 3, 1.0)])
+def test_fp16_split_step_error_is_within_the_split_precision(n, k, hscale):
+    """One FP16-split defect step (every degree 2): H E_1 formed from
+    two-word FP16 splits of 2^s H and of 2^s_j E_1[:, j] (three products,
+    FP32 accumulation; 400 columns run the 128 x 128 tile).  The dropped
+    split terms are at most 3 * 2^-22 |H_ik| |E_kj|; with FP32 accumulation
+    over 1500 partial sums (about 2^-20 of the root sum of squares of the
+    terms, at most a few times that over all elements) the error stays below
+    2^-16 of that root sum of squares, which the BF16 words (errors of a few
+    2^-16 typical) exceed.  The spectra are scaled by 1e6 and 1e-5 and the
+    defect columns span seven orders of magnitude, so both the scale of H
+    and the per-column scales of E_1 are exercised (unscaled FP16 would
+    overflow or flush them)."""
+    lam, h, mu, q, z = _ritz_block_spread(n, k, 41, hscale)
+    deg = [2] * k
+    alpha, beta = float(mu[-1]) + 1.0 * hscale, 41.0 * hscale
+    c, e, gamma = 0.5 * (alpha + beta), 0.5 * (beta - alpha), float(mu[0])
+    ref = chebyshev.chebyshev_filter(h, q, deg, c, e, gamma)
+    yd, fh, f32 = ch.chfsi_filter_defect_split(dev(h), dev(q), dev(z), mu, deg, c, e, gamma, 1,
+                                               fp16=True)
+    got = host(yd)
+    sig1 = e / (gamma - c)
+    sig2 = 1.0 / (2.0 / sig1 - sig1)
+    e1 = (sig1 / e) * (z - q * mu)
+    sa = abs(2.0 * sig2 / e)
+    rss = sa * np.sqrt(np.abs(h) ** 2 @ np.abs(e1) ** 2)
+    # FP32 rounding of the epilogue's other terms (sa c E_1, cr R) and of the
+    # stored E_2 = Y_2 - Q p_2(mu), with p_1 = sig1 t, p_2 = 2 sig2 t p_1 -
+    # sig2 sig1 (t = (mu - c) / e, the scalar recurrence)
+    t = (mu - c) / e
+    p1 = sig1 * t
+    p2 = 2.0 * sig2 * t * p1 - sig2 * sig1
+    cr = 2.0 * sig2 * p1 / e
+    e2 = ref - q * p2
+    floor = (2.0 ** -21 * (sa * abs(c) * np.abs(e1) + np.abs(cr * (z - q * mu)) + np.abs(e2))
+             + 1e-15 * np.abs(ref).max())
+    err = np.abs(got - ref)
+    print(f"max err / rss {np.max(err / (rss + 1e-300)):.3e} (2^{np.log2(np.max(err / (rss + 1e-300))):.1f})")
+    assert np.all(err <= 2.0 ** -16 * rss + floor), (err / (2.0 ** -16 * rss + floor)).max()
+    assert fh == pytest.approx(8.0 * n * n * k) and f32 == 0.0
+
+
+@pytest.mark.parametrize("delta,n,k,steps", [(1e-3, 700, 40, 99), (1e-6, 700, 40, 99),
+                                             (1e-3, 1000, 200, 4), (1e-3, 1000, 400, 99)])
+def test_fp16_split_filter_matches_oracle_with_error_scaling_like_the_residual(delta, n, k,
+                                                                              steps):
+    """The defect filter with its first `steps` steps in FP16-split form
+    (the rest FP32) reproduces the oracle's FP64 filter with the error bound
+    of the FP32 form scaled by the split's precision, 3 * 2^-22 instead of
+    2^-24: it shrinks with the residuals."""
+    lam, h, mu, q, z = _ritz_block(n, k, delta, 23)
+    res = ochfsi.residual_norms(q, z, mu)
+    deg = np.sort(np.random.default_rng(3).integers(2, 20 if k < 100 else 9, k)).tolist()
+    alpha, beta = float(mu[-1]) + 1.0, 41.0
+    c, e, gamma = 0.5 * (alpha + beta), 0.5 * (beta - alpha), float(mu[0])
+    ref = chebyshev.chebyshev_filter(h, q, deg, c, e, gamma)
+    yd, fh, f32 = ch.chfsi_filter_defect_split(dev(h), dev(q), dev(z), mu, deg, c, e, gamma,
+                                               steps, fp16=True)
+    err = rel_col_err(host(yd), ref)
+    norm_h = np.abs(lam).max()
+    growth = (chebyshev.rho(np.array([(gamma - c) / e]))[0]
+              / chebyshev.rho((mu - c) / e)) ** np.array(deg)
+    bound = 1e3 * 3.0 * 2.0 ** -22 * (res / norm_h) * growth + 1e-13
+    assert np.all(err <= bound), (err / bound).max()
+    d = np.array(deg)
+    wanth = sum(int(np.sum(d > i)) for i in range(1, min(steps, d.max() - 1) + 1))
+    assert fh == pytest.approx(8.0 * n * n * wanth)
+    assert fh + f32 == pytest.approx(8.0 * n * n * sum(m - 1 for m in deg))
+
+
 @pytest.mark.parametrize("variant,k", [(0, 70), (1, 70), (2, 300)])
 def test_filter_tile_variants_match_oracle(variant, k):
     """Every tile variant of the filter step gives the oracle's filter (the

@@ -113,7 +113,7 @@ def test_solve_x_aliases_x0_and_is_repeatable():
     assert np.abs(lam3[:10] - ref.lam[:10]).max() <= RTOL * np.abs(ref.lam[:10]).min()
 
 
-@pytest.mark.parametrize("precision,rr_refine", [(0, 1), (2, 1), (0, 0)])
+@pytest.mark.parametrize("precision,rr_refine", [(0, 1), (2, 1), (3, 1), (0, 0)])
 def test_solve_edge_cases_tiny_and_full_block(precision, rr_refine):
     o = _opts(precision=precision, rr_refine=rr_refine)
     # tiny: n = 6, k = n (the subspace is the whole space)
@@ -136,7 +136,7 @@ def test_solve_edge_cases_tiny_and_full_block(precision, rr_refine):
         assert info["rr_refined"] == 0
 
 
-@pytest.mark.parametrize("precision", [0, 1, 2])
+@pytest.mark.parametrize("precision", [0, 1, 2, 3])
 def test_solve_degenerate_and_clustered_spectrum(precision):
     """Exactly repeated eigenvalues (multiplicity 4 at the bottom, 3 at the
     edge of the wanted set, a pair split across nev) and a tight cluster:
@@ -253,17 +253,18 @@ def test_solve_sequence_with_previous_eigenvalues():
         x = xd
 
 
-@pytest.mark.parametrize("with_lambda,precision", [(False, 1), (True, 1), (True, 2)])
+@pytest.mark.parametrize("with_lambda,precision", [(False, 1), (True, 1), (True, 2), (True, 3)])
 def test_solve_mixed_precision_matches_oracle(with_lambda, precision):
     """precision = 1: filters run in FP32 defect form once residuals allow;
     precision = 2 also runs the early steps of those filters with BF16-split
-    products.  The eigenvalues still match the FP64 oracle to 1e-10."""
+    products, precision = 3 most of their steps with FP16-split products.
+    The eigenvalues still match the FP64 oracle to 1e-10."""
     conf = gen.CONFIGS["std-n1000"]
     probs = [a.copy() for _, a in gen.Sequence(conf).problems()]
     refs = ochfsi.solve_sequence(probs, conf.nev, conf.nex)
     o = _opts(precision=precision)
     x, lam = None, None
-    used32 = used16 = 0
+    used32 = used16 = usedh = 0
     for a, ref in zip(probs, refs):
         st, lam, xd, info = ch.chfsi_solve(dev(a), None, conf.nev, conf.nex, conf.tol, X0=x,
                                            Lambda0=lam if (with_lambda and x is not None) else None,
@@ -274,6 +275,8 @@ def test_solve_mixed_precision_matches_oracle(with_lambda, precision):
         _check_pairs(a, None, lam, host(xd), conf.nev, conf.tol, info["norm_h"])
         used32 += info["filter_iters_fp32"]
         used16 += info["filter_steps_bf16"]
+        usedh += info["filter_steps_fp16"]
         x = xd
     assert used32 > 0
     assert (used16 > 0) == (precision == 2)
+    assert (usedh > 0) == (precision == 3)
