@@ -1,8 +1,8 @@
 """Full-size check of the batched k-point workload: 32 generalized problems
 with n uniform in [2000, 9000] (nev 5 %, nex 1 % of n), solved in one
 lockstep batch with the mixed-precision filter and its BF16-split steps
-(precision 2), the cold first step and one warm-started step, as the
-benchmark runs them.  Checked by properties that hold at any size: every
+(precision 2) or FP16-split steps (precision 3), the cold first step and
+one warm-started step, as the benchmark runs them.  Checked by properties that hold at any size: every
 problem converges; sampled pairs have residuals ||A x - lam B x|| <= 2 tol
 N_H ||B|| (||B|| <= 1.05 for B = I + 0.05 G) and B-orthonormal vectors.
 (The small-size batch tests compare the same path element by element with
@@ -17,14 +17,15 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.timeout(900)
-def test_kpoints_full_size_batched_precision2():
+@pytest.mark.parametrize("precision", [2, 3])
+def test_kpoints_full_size_batched_split_steps(precision):
     import torch
     confs = gen.kpoint_configs()
     seqs = [gen.Sequence(c, kind="torch", device="cuda:0", draw="device") for c in confs]
     gens = [s.problems() for s in seqs]
     Bs = [s.B for s in seqs]
     opts = ch.chfsi_default_opts()
-    opts.precision = 2
+    opts.precision = precision
     x0s = lam0s = None
     for step in (1, 2):
         As = [next(g)[1] for g in gens]
@@ -35,7 +36,8 @@ def test_kpoints_full_size_batched_precision2():
             Lambda0s=lam0s, opts=opts)
         assert st == 0 and all(s == 0 for s in sts), sts
         if step == 2:
-            assert sum(i["filter_steps_bf16"] for i in infos) > 0
+            w = "filter_steps_bf16" if precision == 2 else "filter_steps_fp16"
+            assert sum(i[w] for i in infos) > 0
         worst_r = worst_o = 0.0
         for q, c in enumerate(confs):
             cols = [0, c.nev // 2, c.nev - 1]

@@ -1,6 +1,6 @@
 """Full-size checks of the standard n = 20 000 workload (nev 1000, nex 200)
 in the benchmark's launch path, with the mixed-precision filter and its
-BF16-split steps (precision 2):
+BF16-split steps (precision 2) or FP16-split steps (precision 3):
 
 * the cold first problem against its prescribed spectrum (A = Q diag(lam)
   Q^H from the generator, so the exact eigenvalues are known without an
@@ -22,31 +22,33 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.timeout(900)
-def test_std_n20000_mixed_bf16_first_two_problems():
+@pytest.mark.parametrize("precision", [2, 3])
+def test_std_n20000_mixed_split_first_two_problems(precision):
     import torch
     conf = gen.CONFIGS["std-n20000"]
     seq = gen.Sequence(conf, kind="torch", device="cuda:0", draw="device")
     problems = seq.problems()
     opts = ch.chfsi_default_opts()
-    opts.precision = 2
+    opts.precision = precision
     nev, nex = conf.nev, conf.nex
     x, lam = None, None
     for l in (1, 2):
         _, a = next(problems)
         torch.cuda.synchronize()
-        print(f"std-n20000 problem {l}: solving (precision 2)", flush=True)
+        print(f"std-n20000 problem {l}: solving (precision {precision})", flush=True)
         st, lam, xd, info = ch.chfsi_solve(a, None, nev, nex, conf.tol, X0=x,
                                            Lambda0=lam if x is not None else None, opts=opts)
         assert st == 0, (l, st)
-        print(f"  iters {info['iters']} fp32 loops {info['filter_iters_fp32']} bf16 steps "
-              f"{info['filter_steps_bf16']} rr refined/dense {info['rr_refined']}/"
+        print(f"  iters {info['iters']} fp32 loops {info['filter_iters_fp32']} bf16/fp16 steps "
+              f"{info['filter_steps_bf16']}/{info['filter_steps_fp16']} rr refined/dense "
+              f"{info['rr_refined']}/"
               f"{info['rr_dense']} {info['total_seconds']:.2f}s", flush=True)
         if l == 1:
             ref = np.asarray(seq.lam[:nev])
             err = np.abs(lam[:nev] - ref) / np.abs(ref)
             assert err.max() <= 1e-10, err.max()
         else:
-            assert info["filter_steps_bf16"] > 0
+            assert info["filter_steps_bf16" if precision == 2 else "filter_steps_fp16"] > 0
         cols = [0, 1, nev // 3, nev // 2, nev - 2, nev - 1]
         xs = xd[:, cols]
         r = torch.linalg.norm(a @ xs - xs * torch.as_tensor(lam[cols], device=xs.device),
