@@ -564,6 +564,18 @@ def main():
             lsec = sum(i["filter_seconds"] for i in linfos)
             out[label]["filter_effective_tflops"] = round(
                 sum(i["filter_flops"] for i in linfos) / lsec / 1e12, 3)
+    # the metric's comparison: FP64 against the fastest mixed-precision
+    # variant with learned degrees
+    ml = [lab for lab in learned_runs if lab.startswith("mixed") and lab.endswith("+learned")]
+    if ml:
+        best = min(ml, key=lambda lab: out[lab]["ms_per_step"])
+        out["fp64_vs_mixed_learned"] = {
+            "fp64_ms_per_step": out["ms_per_step"],
+            "variant": best,
+            "ms_per_step": out[best]["ms_per_step"],
+            "speedup": out[best]["speedup_vs_fp64_per_step"],
+            "max_rel_eig_diff_vs_fp64": max(out[best]["max_rel_eig_diff_vs_fp64_per_step"]),
+        }
     out["fp64_filter_matvecs_per_step"] = [i["filter_matvecs"] for i in infos]
     out["cold_first_problem_untimed"] = cold
     out["filter_autotune"] = autotune
