@@ -80,7 +80,10 @@ extern "C" {
  *                 residual the filter aims at), the
  *                 filter runs in complex FP32 on the defect
  *                 E = p(Ht) Q - Q p(mu_t) of the Ritz vectors Q; QR,
- *                 Rayleigh-Ritz, residuals and locking stay FP64.
+ *                 Rayleigh-Ritz, residuals and locking stay FP64.  The
+ *                 Lanczos mat-vecs of precisions 1-3 read fp32(H) (FP64
+ *                 sums), and the upper bound is raised by 2^-24 sqrt(n)
+ *                 max(|bound|, |theta_min|), a bound of ||H - fp32(H)||_2.
  *                 2: as 1, and inside such a filter each recurrence step
  *                 whose rounding is damped enough by the steps after it
  *                 runs its product in BF16 (two-term BF16 splits of H and

@@ -429,7 +429,9 @@ __global__ void __launch_bounds__(1024) k_potrf_leaf(int nb, zc* G, long ldg, zc
 }
 
 // y_part[s][r] = sum over the s-th column chunk of H[r, k] x[k]
-__global__ void k_gemv_part(int n, const zc* H, long ldh, const zc* x, zc* part, int chunk) {
+// T = zc (FP64 H) or cf (FP32 H, products and sums in FP64)
+template <typename T>
+__global__ void k_gemv_part(int n, const T* H, long ldh, const zc* x, zc* part, int chunk) {
   __shared__ zc xs[NT];
   const int r = blockIdx.x * NT + threadIdx.x;
   const int c0 = blockIdx.y * chunk;
@@ -442,7 +444,8 @@ __global__ void k_gemv_part(int n, const zc* H, long ldh, const zc* x, zc* part,
     const int cnt = min(NT, c1 - cb);
     if (r < n) {
       for (int q = 0; q < cnt; ++q) {
-        const zc h = H[r + (long)(cb + q) * ldh], v = xs[q];
+        const T hv = H[r + (long)(cb + q) * ldh];
+        const zc h = zc{(double)hv.x, (double)hv.y}, v = xs[q];
         acc.x += h.x * v.x - h.y * v.y;
         acc.y += h.x * v.y + h.y * v.x;
       }
@@ -687,13 +690,17 @@ int add_random(hipStream_t s, int n, int k, zc* X, long ldx, unsigned long long 
 }
 
 int gemv_n(hipStream_t s, int n, const zc* H, long ldh, const zc* x, zc* y, zc* part,
-           int splits) {
+           int splits, const void* H32) {
   if (n <= 0) return 0;
   if (splits < 1) splits = 1;
   const int chunk = (n + splits - 1) / splits;
   splits = (n + chunk - 1) / chunk;
-  hipLaunchKernelGGL(k_gemv_part, grid_rows(n, splits), dim3(NT), 0, s, n, H, ldh, x, part,
-                     chunk);
+  if (H32)
+    hipLaunchKernelGGL(k_gemv_part<float2>, grid_rows(n, splits), dim3(NT), 0, s, n,
+                       (const float2*)H32, (long)n, x, part, chunk);
+  else
+    hipLaunchKernelGGL(k_gemv_part<zc>, grid_rows(n, splits), dim3(NT), 0, s, n, H, ldh, x,
+                       part, chunk);
   int e = last();
   if (e) return e;
   hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), 0, s, n, splits,

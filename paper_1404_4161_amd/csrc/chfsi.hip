@@ -498,15 +498,20 @@ int rayleigh_ritz_dev(hipStream_t s, int n, int k, const zc* H, long ldh, const 
 
 
 // Lanczos with full reorthogonalisation; returns bounds on the host.
+// With H32 (fp32(H), n x n contiguous) the mat-vecs read it instead of H
+// (half the bytes; products and sums stay FP64): the recurrence then runs
+// on fp32(H), and the upper bound is raised by a bound of ||H - fp32(H)||_2
+// <= 2^-24 ||H||_F <= 2^-24 sqrt(n) ||H||_2 so that it still bounds H.
 int lanczos_dev(hipStream_t s, int n, const zc* H, long ldh, int steps, unsigned long long seed,
-                StepBufs& b, double* upper, double* tmin, double* tmax) {
+                StepBufs& b, double* upper, double* tmin, double* tmax,
+                const void* H32 = nullptr) {
   const int m = std::max(1, std::min(steps, std::min(n, b.lanczos_cap)));
   const int gs = gemv_splits(n);
   CK(fill_counter_random(s, n, 1, b.V, n, seed, 0));
   CK(normalize_into(s, n, b.V, b.V, b.dummy));
   for (int j = 0; j < m; ++j) {
     const zc* vj = b.V + (size_t)j * n;
-    CK(gemv_n(s, n, H, ldh, vj, b.w, b.gv_part, gs));
+    CK(gemv_n(s, n, H, ldh, vj, b.w, b.gv_part, gs, H32));
     CK(dots_c(s, n, j + 1, b.V, n, b.w, b.h));
     CK(lanczos_axpy(s, n, j, b.V, n, b.h, b.bet, b.w, b.alph));
     for (int pass = 0; pass < 2; ++pass) {
@@ -532,6 +537,10 @@ int lanczos_dev(hipStream_t s, int n, const zc* H, long ldh, int steps, unsigned
   *tmin = lo;
   *tmax = hi;
   *upper = hi + std::fabs(bb[meff - 1]);
+  if (H32) {
+    const double scale = std::max(std::fabs(*upper), std::fabs(lo));
+    *upper += std::ldexp(1.0, -24) * std::sqrt((double)n) * scale;
+  }
   return CHFSI_OK;
 }
 
@@ -1213,9 +1222,12 @@ struct Solve {
     }
     if (!X0) CK(fill_counter_random(s, n, k, b.QA, ld, o.seed, 1));
 
-    // Lanczos bound (the LANCZOS step of Alg. 1)
+    // Lanczos bound (the LANCZOS step of Alg. 1); the mixed-precision modes
+    // need fp32(H) anyway and run its mat-vecs on that copy
+    if (o.precision >= 1) CK(matrix_to_fp32(s, n, H, ldh, b.H32));
     tm.begin(1);
-    CKS(lanczos_dev(s, n, H, ldh, o.lanczos_steps, o.seed, sb, &beta, &tmin, &tmax));
+    CKS(lanczos_dev(s, n, H, ldh, o.lanczos_steps, o.seed, sb, &beta, &tmin, &tmax,
+                    o.precision >= 1 ? b.H32 : nullptr));
     tm.end();
     norm_h = std::max(std::fabs(beta), std::fabs(tmin));
     tol_abs = tol * norm_h;
@@ -1256,7 +1268,6 @@ struct Solve {
     speed.assign(k, NAN);
     if (X0 && o.seq_rates)
       for (int j = 0; j < k; ++j) speed[j] = o.seq_rates[j];
-    if (o.precision >= 1) CK(matrix_to_fp32(s, n, H, ldh, b.H32));
     if (o.precision == 2) CK(matrix_to_split(s, n, H, ldh, b.Hs));
     if (o.precision == 3)
       CK(matrix_to_split_h16(s, n, H, ldh, b.H32, b.Hh, b.st.h16part, &b.inv_hh));

@@ -146,7 +146,9 @@ int add_random(hipStream_t s, int n, int k, zc* X, long ldx, unsigned long long 
                int stream_id, double eps);
 
 // Lanczos helpers
-int gemv_n(hipStream_t s, int n, const zc* H, long ldh, const zc* x, zc* y, zc* part, int splits);
+// H32 (or null): fp32(H), n x n contiguous, read instead of H (FP64 sums).
+int gemv_n(hipStream_t s, int n, const zc* H, long ldh, const zc* x, zc* y, zc* part, int splits,
+           const void* H32 = nullptr);
 int dots_c(hipStream_t s, int n, int cnt, const zc* V, long ldv, const zc* w, zc* h);
 int sub_vh(hipStream_t s, int n, int cnt, const zc* V, long ldv, const zc* h, zc* w);
 int lanczos_axpy(hipStream_t s, int n, int j, const zc* V, long ldv, const zc* h,
