@@ -38,6 +38,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 
 namespace chfsi {
@@ -143,6 +144,8 @@ struct SplitArgs {
   float inv_a;                  // FP16 form: 1 / (scale of H)
   const float* inv_b;           // FP16 form: 1 / (scale of each window column)
   int tiles_m, tiles_n;
+  int splits, kstages;          // split-K: K stages per split (splits = 1: none)
+  cf* part;                     // split-K partials: part[s * M * N + i + j * M]
 };
 
 // One defect step on tiles of BM x BN complex outputs: WGM x WGN waves, each
@@ -166,12 +169,15 @@ __device__ __forceinline__ void split_tile_body(const SplitArgs& g, char* lds) {
   typedef typename W::V V;
   using T = SplitTile<WGM, WGN, TI, TJ>;
   constexpr int BM = T::BM, BN = T::BN, NTH = T::NTH, CH = T::CHUNKS;
+  // virtual tile rows (split, tile row) interleaved over the XCDs
   const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
-  const int rows_x = (g.tiles_m - xcd + NXCD - 1) / NXCD;
+  const int vrows = g.splits * g.tiles_m;
+  const int rows_x = (vrows - xcd + NXCD - 1) / NXCD;
   const int ri = slot / g.tiles_n;
   const int tn = slot - ri * g.tiles_n;
   if (ri >= rows_x) return;
-  const int tm = xcd + NXCD * ri;
+  const int v = xcd + NXCD * ri;
+  const int split = v / g.tiles_m, tm = v - split * g.tiles_m;
   const int m0 = tm * BM, n0 = tn * BN;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -212,16 +218,17 @@ __device__ __forceinline__ void split_tile_body(const SplitArgs& g, char* lds) {
       *(uint4*)(lds + buf * T::LDS_STAGE + row * ROWB + ch * 16) = rs[i];
     }
   };
-  const int nk = g.Kp / SBK;
+  const int kt0 = split * g.kstages;
+  const int nk = min(g.Kp / SBK, kt0 + g.kstages) - kt0;
   if (nk > 0) {
-    load(0);
+    load(kt0 * SBK);
     store(0);
   }
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     const bool more = kt + 1 < nk;
-    if (more) load((kt + 1) * SBK);
+    if (more) load((kt0 + kt + 1) * SBK);
     const char* la = lds + cur * T::LDS_STAGE;
     const char* lb = la + BM * ROWB;
     uint4 a[TI][4], b[TJ][4];
@@ -276,6 +283,16 @@ __device__ __forceinline__ void split_tile_body(const SplitArgs& g, char* lds) {
       if (col >= g.N) continue;
       float unscale = 1.f;   // FP16 form: undo the operand scaling (powers of two)
       if constexpr (H16) unscale = g.inv_a * g.inv_b[col];
+      if (g.splits > 1) {    // split-K: unscaled partial sums, epilogue in the reduction
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = rbase + r;
+          if (row < g.M)
+            g.part[(long)split * g.M * g.N + row + (long)col * g.M] =
+                cf{accR[i][j][r] * unscale, accI[i][j][r] * unscale};
+        }
+        continue;
+      }
       cf out[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -461,6 +478,21 @@ __global__ void split_rows(int n, int Kp, const zc* H, long ldh, char* S, long s
   }
 }
 
+// Compute units of the current device (cached per device).
+int split_device_cus() {
+  static std::atomic<int> cache[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cache[dev] == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    cache[dev] = cus;
+  }
+  return cache[dev];
+}
+
 }  // namespace
 
 int split_kp(int K) { return ((K + SBK - 1) / SBK) * SBK; }
@@ -530,6 +562,8 @@ int defect_step_split(hipStream_t s, int n, int N, const void* Hs, const void* E
   g.R = (const cf*)R32; g.ldr = n; g.cr = cr;
   g.shift = shift; g.sa = sa; g.sb = sb;
   g.Bnext = (char*)Es_next;
+  g.splits = 1;
+  g.kstages = g.Kp / SBK;
   if (N >= SPLIT_WIDE_MIN_N) {
     g.tiles_m = (n + TileWide::BM - 1) / TileWide::BM;
     g.tiles_n = (N + TileWide::BN - 1) / TileWide::BN;
@@ -546,7 +580,8 @@ int defect_step_split(hipStream_t s, int n, int N, const void* Hs, const void* E
 
 int defect_step_h16(hipStream_t s, int n, int N, const void* Hs, float inv_h, const void* Es,
                     const float* inv_e, const void* Ecur, const void* Eold, void* Eout,
-                    const void* R32, const float* cr, float shift, float sa, float sb) {
+                    const void* R32, const float* cr, float shift, float sa, float sb,
+                    void* part, size_t part_elems) {
   if (N <= 0) return 0;
   SplitArgs g = {};
   g.M = n; g.N = N; g.Kp = split_kp(n);
@@ -557,6 +592,8 @@ int defect_step_h16(hipStream_t s, int n, int N, const void* Hs, float inv_h, co
   g.shift = shift; g.sa = sa; g.sb = sb;
   g.Bnext = nullptr;
   g.inv_a = inv_h; g.inv_b = inv_e;
+  g.splits = 1;
+  g.kstages = g.Kp / SBK;
   if (N >= SPLIT_WIDE_MIN_N) {
     g.tiles_m = (n + TileWide::BM - 1) / TileWide::BM;
     g.tiles_n = (N + TileWide::BN - 1) / TileWide::BN;
@@ -566,9 +603,29 @@ int defect_step_h16(hipStream_t s, int n, int N, const void* Hs, float inv_h, co
   }
   g.tiles_m = (n + TileSmall::BM - 1) / TileSmall::BM;
   g.tiles_n = (N + TileSmall::BN - 1) / TileSmall::BN;
-  const int grid = ((g.tiles_m + NXCD - 1) / NXCD) * g.tiles_n * NXCD;
+  // split-K that fills the resident slots (two workgroups per CU) evenly
+  const int stages = g.Kp / SBK;
+  const int slots = 2 * split_device_cus();
+  const long tiles = (long)g.tiles_m * g.tiles_n;
+  const int max_s = (int)std::min<size_t>(8, part ? part_elems / ((size_t)n * N) : 1);
+  double best_u = 0.0;
+  int sp_best = 1;
+  for (int sp = 1; sp <= max_s; ++sp) {
+    if (sp > 1 && n / sp < 512) break;
+    const long wg = tiles * sp;
+    const double u = (double)wg / (double)(((wg + slots - 1) / slots) * slots);
+    if (u > best_u + 1e-9) { best_u = u; sp_best = sp; }
+    if (u >= 0.9) break;
+  }
+  g.kstages = (stages + sp_best - 1) / sp_best;
+  g.splits = (stages + g.kstages - 1) / g.kstages;
+  g.part = (cf*)part;
+  const int grid = ((g.splits * g.tiles_m + NXCD - 1) / NXCD) * g.tiles_n * NXCD;
   hipLaunchKernelGGL(defect_gemm_h16, dim3(grid), dim3(TileSmall::NTH), 0, s, g);
-  return (int)hipGetLastError();
+  int e = (int)hipGetLastError();
+  if (e || g.splits == 1) return e;
+  return defect_reduce_launch(s, n, N, g.splits, part, Ecur, Eold, Eout, n, R32, n, cr, shift,
+                              sa, sb);
 }
 
 }  // namespace chfsi

@@ -395,6 +395,17 @@ int defect_assemble_launch(hipStream_t s, int n, int k, const zc* Qs, long ld, c
   return (int)hipGetLastError();
 }
 
+int defect_reduce_launch(hipStream_t s, int M, int N, int splits, const void* part,
+                         const void* Ecur, const void* Eold, void* Eout, long lde, const void* R,
+                         long ldr, const float* cr, float shift, float sa, float sb) {
+  const long total = (long)M * N;
+  if (total <= 0) return 0;
+  hipLaunchKernelGGL(defect_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, M, N,
+                     splits, (const cf*)part, (const cf*)Ecur, (const cf*)Eold, (cf*)Eout, lde,
+                     (const cf*)R, ldr, cr, shift, sa, sb);
+  return (int)hipGetLastError();
+}
+
 int defect_step(hipStream_t s, int n, int N, const void* H32, const void* Ecur, const void* Eold,
                 void* Eout, const void* R32, const float* cr, float shift, float sa, float sb,
                 void* part, size_t part_elems) {

@@ -673,7 +673,8 @@ int defect_filter_dev(hipStream_t s, int n, int k, const void* H32, const zc* Q,
       char* scur = (char*)b.S0 + first * srow;
       CK(cols_to_split_h16(s, n, cols, cur + off, n, scur, b.colscale + first));
       CK(defect_step_h16(s, n, cols, sp->Hh, sp->inv_h, scur, b.colscale + first, cur + off,
-                         old + off, old + off, (const char*)b.R32 + off, cri, shift, sa, sbeta));
+                         old + off, old + off, (const char*)b.R32 + off, cri, shift, sa, sbeta,
+                         b.fpart, b.fpart_elems * 2));
       split_ready = false;
       sp->flops_fp16 += 8.0 * (double)n * n * cols;
       sp->steps_fp16 += 1;

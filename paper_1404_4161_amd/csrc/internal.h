@@ -173,6 +173,12 @@ int defect_step(hipStream_t s, int n, int N, const void* H32, const void* Ecur, 
 int defect_assemble_launch(hipStream_t s, int n, int k, const zc* Qs, long ld, const void* E0,
                            const void* E1, const int* deg, const double* pm, zc* Y, long ldy);
 
+// Sum of split-K partials part[p * M * N + i + j * M] (p < splits) followed
+// by the defect step's epilogue (the form of defect_step), into Eout.
+int defect_reduce_launch(hipStream_t s, int M, int N, int splits, const void* part,
+                         const void* Ecur, const void* Eold, void* Eout, long lde, const void* R,
+                         long ldr, const float* cr, float shift, float sa, float sb);
+
 // ----- BF16- and FP16-split defect steps, cfilter16.hip -----
 // Split panels: rows of a reduction index padded to split_kp(K) (a multiple
 // of 32), 8 bytes per complex value (BF16 hi/lo of the real and imaginary
@@ -200,10 +206,13 @@ int matrix_to_split_h16(hipStream_t s, int n, const zc* H, long ldh, const void*
 int cols_to_split_h16(hipStream_t s, int K, int cols, const void* E, long lde, void* S,
                       float* inv);
 // The defect step with H Ecur from the FP16 splits (inv_h, inv_e undo the
-// scaling).  No split-K.
+// scaling).  Windows narrower than 257 columns split K (up to 8 ways,
+// chunks of at least 512) when that fills the GPU better, with partials in
+// part (part_elems complex64 values; no split-K when it is too small).
 int defect_step_h16(hipStream_t s, int n, int N, const void* Hs, float inv_h, const void* Es,
                     const float* inv_e, const void* Ecur, const void* Eold, void* Eout,
-                    const void* R32, const float* cr, float shift, float sa, float sb);
+                    const void* R32, const float* cr, float shift, float sa, float sb,
+                    void* part, size_t part_elems);
 
 // ----- projected eigenproblem by iterative refinement, eigref.hip -----
 struct EigRefineBufs {

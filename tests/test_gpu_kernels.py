@@ -344,7 +344,7 @@ def _ritz_block_spread(n, k, seed, hscale):
 
 
 @pytest.mark.parametrize("n,k,hscale", [(333, 70, 1.0), (1000, 130, 1e6), (1000, 400, 1e-5),
-                                        (100, 3, 1.0)])
+                                        (100, 3, 1.0), (2100, 70, 1.0)])
 def test_fp16_split_step_error_is_within_the_split_precision(n, k, hscale):
     """One FP16-split defect step (every degree 2): H E_1 formed from
     two-word FP16 splits of 2^s H and of 2^s_j E_1[:, j] (three products,
@@ -356,7 +356,8 @@ def test_fp16_split_step_error_is_within_the_split_precision(n, k, hscale):
     2^-16 typical) exceed.  The spectra are scaled by 1e6 and 1e-5 and the
     defect columns span seven orders of magnitude, so both the scale of H
     and the per-column scales of E_1 are exercised (unscaled FP16 would
-    overflow or flush them)."""
+    overflow or flush them).  n = 2100 with 70 columns splits K four ways
+    (partial sums reduced by a second kernel)."""
     lam, h, mu, q, z = _ritz_block_spread(n, k, 41, hscale)
     deg = [2] * k
     alpha, beta = float(mu[-1]) + 1.0 * hscale, 41.0 * hscale
@@ -386,8 +387,39 @@ def test_fp16_split_step_error_is_within_the_split_precision(n, k, hscale):
     assert fh == pytest.approx(8.0 * n * n * k) and f32 == 0.0
 
 
+@pytest.mark.parametrize("fp16", [True, False])
+def test_split_filter_with_exact_eigenvectors_has_zero_defect_columns(fp16):
+    """Columns that are exact eigenvectors (of a diagonal H, unit vectors)
+    have residual, and so defect, exactly zero: the split forms must give
+    exactly Q p(mu) there (an all-zero column takes scale 1 in the FP16
+    form), while the perturbed columns beside them follow the oracle."""
+    n, k = 300, 24
+    lam = np.sort(np.random.default_rng(5).uniform(-20, 40, n))
+    h = np.diag(lam).astype(complex)
+    q = np.zeros((n, k), complex)
+    q[np.arange(k), np.arange(k)] = 1.0
+    # columns 12 .. 23 perturbed (a Ritz block of their own span)
+    q[:, 12:] = ochfsi.orthonormalize(q[:, 12:] + 1e-4 * _rand(n, 12, 6), q[:, :12])
+    mu = np.real(np.einsum("ij,ij->j", q.conj(), h @ q))
+    z = h @ q
+    deg = [6] * k
+    alpha, beta = float(lam[k]) + 0.5, 41.0
+    c, e, gamma = 0.5 * (alpha + beta), 0.5 * (beta - alpha), float(lam[0])
+    ref = chebyshev.chebyshev_filter(h, q, deg, c, e, gamma)
+    yd, fs, f32 = ch.chfsi_filter_defect_split(dev(h), dev(q), dev(z), mu, deg, c, e, gamma, 99,
+                                               fp16=fp16)
+    got = host(yd)
+    # exact columns: Y = p(mu) q with p(mu) from the FP64 scalar recurrence
+    assert np.array_equal(got[:, :12] == 0, ref[:, :12] == 0)
+    err = rel_col_err(got, ref)
+    assert err[:12].max() <= 1e-14, err[:12].max()
+    assert err[12:].max() <= 1e-6, err[12:].max()
+    assert f32 == 0.0 and fs == pytest.approx(8.0 * n * n * k * 5)
+
+
 @pytest.mark.parametrize("delta,n,k,steps", [(1e-3, 700, 40, 99), (1e-6, 700, 40, 99),
-                                             (1e-3, 1000, 200, 4), (1e-3, 1000, 400, 99)])
+                                             (1e-3, 1000, 200, 4), (1e-3, 1000, 400, 99),
+                                             (1e-3, 1500, 40, 99)])
 def test_fp16_split_filter_matches_oracle_with_error_scaling_like_the_residual(delta, n, k,
                                                                               steps):
     """The defect filter with its first `steps` steps in FP16-split form
