@@ -1,7 +1,7 @@
 """Full-size check of the learned-degree workload: the standard n = 30 000
-problem (nev 1500, nex 300) with the mixed-precision filter (precision 2)
-and the degree network (degree_mode 2), cold first problem and one
-warm-started problem.  The network is trained on the GPU from the logs of
+problem (nev 1500, nex 300) with the mixed-precision filter and its
+FP16-split steps (precision 3) and the degree network (degree_mode 2),
+cold first problem and one warm-started problem.  The network is trained on the GPU from the logs of
 two small sequences of the same recipe; at this size most of its inputs
 are outside that training range, so the analytic rule (the floor and
 fallback of every learned degree) decides most degrees -- which is what
@@ -46,19 +46,19 @@ def test_std_n30000_mixed_learned_first_two_problems():
     seq = gen.Sequence(conf, kind="torch", device="cuda:0", draw="device")
     problems = seq.problems()
     opts = ch.chfsi_default_opts()
-    opts.precision, opts.degree_mode = 2, 2
+    opts.precision, opts.degree_mode = 3, 2
     nev, nex = conf.nev, conf.nex
     x, lam = None, None
     for l in (1, 2):
         _, a = next(problems)
         torch.cuda.synchronize()
-        print(f"std-n30000 problem {l}: solving (precision 2, learned degrees)", flush=True)
+        print(f"std-n30000 problem {l}: solving (precision 3, learned degrees)", flush=True)
         st, lam, xd, info = ch.chfsi_solve(a, None, nev, nex, conf.tol, X0=x,
                                            Lambda0=lam if x is not None else None, opts=opts,
                                            mlp=blob)
         assert st == 0, (l, st)
-        print(f"  iters {info['iters']} fp32 loops {info['filter_iters_fp32']} bf16 steps "
-              f"{info['filter_steps_bf16']} learned/fallback cols {info['learned_cols']}/"
+        print(f"  iters {info['iters']} fp32 loops {info['filter_iters_fp32']} fp16 steps "
+              f"{info['filter_steps_fp16']} learned/fallback cols {info['learned_cols']}/"
               f"{info['fallback_cols']} {info['total_seconds']:.2f}s", flush=True)
         if l == 1:
             ref = np.asarray(seq.lam[:nev])
