@@ -31,10 +31,11 @@
 // narrow exponent range, so the operands are scaled by powers of two first:
 // H by one factor, each column of E_i by its own, both chosen from the
 // largest magnitude so that it lands in [2^14, 2^15); the epilogue undoes
-// the scaling exactly.  Entries more than 2^28 below their matrix's or
-// column's largest one fall into FP16's subnormal range and keep an
-// absolute accuracy of 2^-24 of the scaled unit, far below the bound above
-// relative to |H| |E_i|.
+// the scaling exactly.  Words that fall into FP16's subnormal range (hi
+// words of entries 2^28, lo words of entries 2^17 below the largest one)
+// keep an absolute error of at most 2^-25 of the scaled unit, 2^-39 of the
+// largest magnitude, which adds at most n 2^-39 max|H| max|E_i[:, j]| to an
+// element of column j of the product.
 #include "internal.h"
 
 #include <algorithm>
