@@ -39,7 +39,7 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 # source it was measured on.
 TRAFFIC_MEASURED = {
     "zgemm_sha256": "4b3bbe5004f1589c71d62e9da39c122766b6a1084a973acd8eda92b51fc758f7",
-    "bytes_per_full_width_step": {0: 4.499e9, 1: 2.381e9, 2: 1.697e9},
+    "bytes_per_full_width_step": {0: 4.570e9, 1: 2.384e9, 2: 1.697e9},
     "algorithmic_bytes_per_full_width_step": 1.208e9,
 }
 
