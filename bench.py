@@ -38,8 +38,8 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 # copy, per tile variant of the step kernel; valid only for the kernel
 # source it was measured on.
 TRAFFIC_MEASURED = {
-    "zgemm_sha256": "4b3bbe5004f1589c71d62e9da39c122766b6a1084a973acd8eda92b51fc758f7",
-    "bytes_per_full_width_step": {0: 4.570e9, 1: 2.384e9, 2: 1.697e9},
+    "zgemm_sha256": "8df37dde5efc6e7bda01d1ea51ab5cea363e65cd6970b6f321f9b3caf55a364e",
+    "bytes_per_full_width_step": {0: 4.564e9, 1: 2.371e9, 2: 1.697e9},
     "algorithmic_bytes_per_full_width_step": 1.208e9,
 }
 

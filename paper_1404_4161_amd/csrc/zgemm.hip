@@ -131,6 +131,40 @@ template <int OPA, int OPB, int EPI, int KB>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, int tn,
                                           zc (*As)[KB][PA], zc (*Bs)[KB][PB]);
 
+// Lower-triangle tile set without split-K, XCD-aware: XCD x (workgroup w
+// runs on XCD w % 8) takes the tile rows tm = x (mod 8) from the bottom row
+// up, each row's tiles tn = 0 .. tm in order, so a row's A strip stays in
+// one XCD's L2 and the rows with the most tiles (and, for triangular K
+// ranges, the longest ones) start first.  Row i of XCD x (tm = top - 8 i)
+// holds top + 1 - 8 i tiles, S(i) = i (top + 5) - 4 i^2 precede it.
+// Returns false when workgroup b has no tile.
+__device__ __forceinline__ bool lower_tile_xcd(const GemmArgs& g, int b, int& tm, int& tn) {
+  const int x = b % NXCD, slot = b / NXCD;
+  if (x >= g.tiles_m) return false;
+  const int top = x + NXCD * ((g.tiles_m - 1 - x) / NXCD);
+  const int rows = (top - x) / NXCD + 1;
+  auto S = [&](int i) { return (long)i * (top + 5) - 4L * i * i; };
+  const double a = top + 5.0;
+  int i = (int)((a - sqrt(fmax(a * a - 16.0 * slot, 0.0))) / 8.0);
+  while (i > 0 && S(i) > slot) --i;
+  while (i + 1 <= rows && S(i + 1) <= slot) ++i;
+  if (i >= rows) return false;
+  tm = top - NXCD * i;
+  tn = slot - (int)S(i);
+  return true;
+}
+
+// Workgroups of the lower_tile_xcd schedule: 8 x the largest per-XCD count.
+int lower_xcd_grid(int tiles_m) {
+  long best = 0;
+  for (int x = 0; x < NXCD && x < tiles_m; ++x) {
+    const long top = x + NXCD * ((tiles_m - 1 - x) / NXCD);
+    const long rows = (top - x) / NXCD + 1;
+    best = std::max(best, rows * (top + 5) - 4 * rows * rows);
+  }
+  return (int)(best * NXCD);
+}
+
 // Virtual-row scheduling of a rectangular tile set (see zgemm_kernel):
 // returns false when workgroup `local` has no tile.
 __device__ __forceinline__ bool rect_tile(const GemmArgs& g, int local, int& split, int& tm,
@@ -162,7 +196,10 @@ __global__ void __launch_bounds__(NT, KB == 8 ? 4 : 2) zgemm_kernel(GemmArgs g) 
   // rows, which balances triangular K ranges.  A virtual row is a (split,
   // tile row) pair.
   int split, tm, tn;
-  if (g.lower_only) {
+  if (g.lower_only && g.splits == 1) {
+    split = 0;
+    if (!lower_tile_xcd(g, blockIdx.x, tm, tn)) return;
+  } else if (g.lower_only) {
     const int logical = blockIdx.x;
     if (logical >= g.total_tiles * g.splits) return;
     split = logical / g.total_tiles;
@@ -521,7 +558,9 @@ Plan make_plan(int M, int N, int K, bool lower_only, bool allow_split) {
 template <int OPA, int OPB, int EPI, int KB = BK>
 int launch(hipStream_t s, GemmArgs& g) {
   int grid;
-  if (g.lower_only) {
+  if (g.lower_only && g.splits == 1) {
+    grid = lower_xcd_grid(g.tiles_m);
+  } else if (g.lower_only) {
     grid = g.total_tiles * g.splits;
   } else {
     const int vrows = g.splits * g.tiles_m;

@@ -210,7 +210,7 @@ def test_lanczos_bounds_match_oracle(n):
     assert got[0] >= lam[-1] - 1e-9
 
 
-@pytest.mark.parametrize("n", [64, 300, 700])
+@pytest.mark.parametrize("n", [64, 300, 700, 1100])
 def test_reduce_standard_matches_oracle(n):
     a = gen.prescribed_problem(n, np.linspace(-20, 40, n), 2)
     b = gen.random_hpd(n, 3)
