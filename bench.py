@@ -39,7 +39,7 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 # source it was measured on.
 TRAFFIC_MEASURED = {
     "zgemm_sha256": "8df37dde5efc6e7bda01d1ea51ab5cea363e65cd6970b6f321f9b3caf55a364e",
-    "bytes_per_full_width_step": {0: 4.564e9, 1: 2.371e9, 2: 1.697e9},
+    "bytes_per_full_width_step": {0: 4.571e9, 1: 2.370e9, 2: 1.697e9},
     "algorithmic_bytes_per_full_width_step": 1.208e9,
 }
 
