@@ -2,7 +2,7 @@
 the float64 oracle (oracle/mlp.py): forward pass, mean-squared-error
 gradient (several reduction chunks and a ragged tail), Adam, the training
 loop, and the learned degree rule; plus the solver's convergence log and
-its learned mode (fallback, judge)."""
+its learned mode (the rule as floor and fallback)."""
 import math
 
 import numpy as np
