@@ -284,8 +284,9 @@ def main():
                          "Rayleigh-Ritz per problem) instead of vectors and values")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
-                                   "part of this build", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the library solves "
+                                   "each problem (or batch) on one device and has no multi-GPU "
+                                   "path", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
