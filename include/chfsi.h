@@ -463,6 +463,21 @@ int chfsi_reduce_standard(int n, const void* A, int lda, const void* B, int ldb,
 int chfsi_degrees(int k, const double* mu, const double* res, int n_wanted,
                   double alpha, double beta, double tol_abs, int deg_max, int* deg);
 
+/* Which recurrence steps of an FP32 defect filter the solver runs in a
+ * split form (host only; precision 2: form 1, BF16 words, eps = 3 * 2^-16;
+ * precision 3: form 2, FP16 words of scaled operands, eps = 3 * 2^-22).
+ * Step i (E_i -> E_{i+1}, 1 <= i < max deg) is split when for every wanted
+ * vector j < n_wanted with deg_j > i:
+ *   10 eps rel_j |rho_j|^-(deg_j - i - 1) <= max(tol, rel_j |rho_j|^-deg_j),
+ * rel_j = res_j / norm_h, |rho_j| from t_j = (mu_j - c)/e (1 for |t_j| <= 1).
+ *   mu, res  HOST, ka doubles.   deg  HOST, ka ints >= 1.
+ *   steps    HOST, max(deg) signed chars out: 0 (FP32) or form; steps[0] = 0.
+ * Returns CHFSI_INVALID_ARG for ka < 1, form not 1 or 2, e <= 0, tol <= 0,
+ * norm_h <= 0, a degree < 1 or a NULL pointer. */
+int chfsi_split_schedule(int n_wanted, int ka, const double* mu, const double* res,
+                         const int* deg, double c, double e, double tol, double norm_h, int form,
+                         signed char* steps);
+
 /* Input features of the degree network for wanted vector j (host only),
  * with t = (mu_j - c)/e, c, e from alpha and beta, |rho| = |t| + sqrt(t^2-1):
  *   f0 = ln(max(res_j, tol_abs) / tol_abs)   f1 = ln(ln|rho|)

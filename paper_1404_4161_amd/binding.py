@@ -105,6 +105,9 @@ _SIGS = {
     "chfsi_reduce_workspace_bytes": (c_size_t, [c_int]),
     "chfsi_reduce_standard": (c_int, [c_int, c_void_p, c_int, c_void_p, c_int, c_void_p, c_int,
                                       c_void_p, c_int, c_void_p, c_size_t, c_void_p]),
+    "chfsi_split_schedule": (c_int, [c_int, c_int, POINTER(c_double), POINTER(c_double),
+                                     POINTER(c_int), c_double, c_double, c_double, c_double,
+                                     c_int, POINTER(ctypes.c_byte)]),
     "chfsi_degrees": (c_int, [c_int, POINTER(c_double), POINTER(c_double), c_int, c_double,
                               c_double, c_double, c_int, POINTER(c_int)]),
     "chfsi_degree_features": (c_int, [c_double, c_double, c_double, c_double, c_double, c_double,
@@ -422,6 +425,19 @@ def chfsi_degrees(mu, res, n_wanted, alpha, beta, tol_abs, deg_max=40):
     _check(lib().chfsi_degrees(k, m, r, int(n_wanted), float(alpha), float(beta), float(tol_abs),
                                int(deg_max), d), "chfsi_degrees")
     return np.array(d[:], dtype=np.int64)
+
+
+def chfsi_split_schedule(mu, res, deg, n_wanted, c, e, tol, norm_h, form):
+    """Per-step split forms of an FP32 defect filter (host only): array of
+    max(deg) entries, 0 = FP32 step, form (1 BF16, 2 FP16) = split step."""
+    k = len(deg)
+    m = (c_double * k)(*[float(x) for x in mu])
+    r = (c_double * k)(*[float(x) for x in res])
+    d = (c_int * k)(*[int(x) for x in deg])
+    out = (ctypes.c_byte * max(max(int(x) for x in deg), 1))()
+    _check(lib().chfsi_split_schedule(int(n_wanted), k, m, r, d, float(c), float(e), float(tol),
+                                      float(norm_h), int(form), out), "chfsi_split_schedule")
+    return np.array(out[:], dtype=np.int64)
 
 
 def chfsi_zgemm(opa, opb, alpha, A, B, beta, C, work=None, stream=None):

@@ -2577,6 +2577,22 @@ int chfsi_degrees(int k, const double* mu, const double* res, int n_wanted, doub
   return degrees_host(k, mu, res, n_wanted, alpha, beta, tol_abs, deg_max, deg);
 }
 
+int chfsi_split_schedule(int n_wanted, int ka, const double* mu, const double* res,
+                         const int* deg, double c, double e, double tol, double norm_h, int form,
+                         signed char* steps) {
+  if (ka < 1 || !mu || !res || !deg || !steps || (form != 1 && form != 2) || !(e > 0.0) ||
+      !(tol > 0.0) || !(norm_h > 0.0))
+    return CHFSI_INVALID_ARG;
+  for (int j = 0; j < ka; ++j)
+    if (deg[j] < 1) return CHFSI_INVALID_ARG;
+  const std::vector<char> sched = split_step_schedule(
+      n_wanted, std::vector<double>(mu, mu + ka), std::vector<double>(res, res + ka),
+      std::vector<int>(deg, deg + ka), c, e, tol, norm_h,
+      form == 2 ? FP16_SPLIT_EPS : BF16_SPLIT_EPS, (char)form);
+  for (size_t i = 0; i < sched.size(); ++i) steps[i] = (signed char)sched[i];
+  return CHFSI_OK;
+}
+
 int chfsi_degree_features(double mu, double res, double gap, double alpha, double beta,
                           double gamma, double norm_h, double tol_abs, int loop, double* f) {
   if (!f || !(beta > alpha) || !(tol_abs > 0.0) || !(norm_h > 0.0)) return CHFSI_INVALID_ARG;
