@@ -1,12 +1,14 @@
-"""The error bound of the FP16-split product used by the mixed-precision
-filter's FP16 steps, checked on the host with IEEE binary16 (numpy float16,
-round to nearest even): an FP32 value x, scaled by a power of two so that
+"""The error bounds of the split products used by the mixed-precision
+filter's FP16 and BF16 steps, checked on the host.  FP16 (IEEE binary16,
+numpy float16, round to nearest even): an FP32 value x, scaled by a power
+of two so that
 its vector's largest magnitude lies in [2^14, 2^15), splits into
 hi = fp16(x), lo = fp16(x - hi); hi_a hi_b + hi_a lo_b + lo_a hi_b then
 differs from a b by at most 3 * 2^-22 |a| |b| for normal words, and a dot
 product of such terms by at most that fraction of sum |a_k| |b_k| plus
 n 2^-39 max|a| max|b| (words in FP16's subnormal range).  The sums here
-are exact (float64 of binary16 products), so only the split is measured."""
+are exact (float64 of binary16 products), so only the split is measured.
+BF16 (rounded from FP32 bits, nearest even): 3 * 2^-16 |a| |b|."""
 import numpy as np
 
 
@@ -65,3 +67,29 @@ def test_dot_products_within_the_bound_with_the_subnormal_floor():
                  + n * 2.0 ** -39 * float(np.max(np.abs(a64)) * np.max(np.abs(b64)))
                  + 1e-15 * float(np.sum(np.abs(a64 * b64))))
         assert abs(approx - exact) <= bound, (trial, abs(approx - exact) / bound)
+
+
+def _bf16(x):
+    """Round float32 values to bfloat16 (nearest even), returned as float32."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (r.astype(np.uint32) << 16).view(np.float32)
+
+
+def test_bf16_split_product_error_within_three_times_two_to_minus_16():
+    """The BF16 form (precision 2) needs no scaling (BF16 has FP32's
+    exponent range); its dropped terms are at most 3 * 2^-16 |a| |b|."""
+    g = np.random.default_rng(4)
+    a = (g.standard_normal(20000) * 10.0 ** g.uniform(-20, 20, 20000)).astype(np.float32)
+    b = (g.standard_normal(20000) * 10.0 ** g.uniform(-20, 20, 20000)).astype(np.float32)
+    ha = _bf16(a)
+    la = _bf16(a - ha)
+    hb = _bf16(b)
+    lb = _bf16(b - hb)
+    h = [x.astype(np.float64) for x in (ha, la, hb, lb)]
+    approx = h[0] * h[2] + h[0] * h[3] + h[1] * h[2]
+    exact = a.astype(np.float64) * b.astype(np.float64)
+    err = np.abs(approx - exact)
+    bound = 3.0 * 2.0 ** -16 * np.abs(exact)
+    assert np.all(err <= bound), (err / bound).max()
+    assert (err / bound).max() > 0.05
