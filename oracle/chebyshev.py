@@ -9,16 +9,12 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   1 inside [-1, 1].  The convergence ratio of eq. (ratio) is 1/|rho|.
 * ``sigmas``: the scalars of Alg. 2, sigma_1 = e / (gamma - c) and
   sigma_{i+1} = 1 / (2/sigma_1 - sigma_i).
-* ``chebyshev_filter``: Alg. 2 -- the scaled three-term recurrence
-  Y_{i+1} = 2 sigma_{i+1} Ht Y_i - sigma_{i+1} sigma_i Y_{i-1} with
-  Ht = (H - cI)/e, over columns sorted by ascending degree; a column whose
-  degree is reached is carried forward unchanged.
-
-Readings of Alg. 2 (the printed listing has typos):
-  * the subtracted term of the recurrence is Y_{i-1} (as in eq. 3term and
-    as the sigma recursion requires), not Y_i;
-  * the column range is s..k (columns), not s..n;
-  * s is the first column whose degree exceeds the current step.
+* ``chebyshev_filter``: the filter of Sec. 3.1.1 with a degree per
+  column: column j becomes p_{m_j}(H) y_j, p_m(x) = C_m((x - c)/e) /
+  C_m((gamma - c)/e), evaluated by the scaled three-term recurrence of
+  eq. (3term) (each iterate is built from the two before it).  Alg. 2 is
+  the blocked, degree-sorted schedule of the same computation; the oracle
+  keeps only the per-column definition.
 """
 from __future__ import annotations
 
@@ -61,43 +57,47 @@ def sigmas(m_max: int, c: float, e: float, gamma: float):
 
 def chebyshev_filter(h: np.ndarray, y0: np.ndarray, degrees, c: float, e: float,
                      gamma: float) -> np.ndarray:
-    """Alg. 2.  ``degrees`` must be ascending and >= 1; column j of the
-    result is p_{m_j}(Ht) y0_j with p_m(t) = C_m(t) / C_m((gamma - c)/e)."""
-    m = [int(x) for x in degrees]
-    k = len(m)
+    """Column j of the result is p_{m_j}(H) y0_j, the filter polynomial of
+    Sec. 3.1.1 of degree m_j:
+
+        p_m(x) = C_m((x - c)/e) / C_m((gamma - c)/e),
+
+    evaluated by the scaled three-term recurrence of eq. (3term):
+
+        Y_1     = (sigma_1 / e) (H - cI) Y_0
+        Y_{i+1} = (2 sigma_{i+1} / e) (H - cI) Y_i - sigma_{i+1} sigma_i Y_{i-1}
+
+    with the sigmas of ``sigmas``.  Every column runs the recurrence on its
+    own for m_j steps; the columns still below their degree at a given step
+    are simply advanced together.  Degrees may come in any order (Alg. 2
+    sorts them only so that the still-active columns form a contiguous
+    window, which changes nothing in the result)."""
+    m = np.asarray([int(x) for x in degrees], dtype=np.int64)
+    k = m.size
+    out = np.array(y0, dtype=np.complex128, copy=True)
     if k == 0:
-        return y0.copy()
-    if any(x < 1 for x in m) or any(m[j] > m[j + 1] for j in range(k - 1)):
-        raise ValueError("degrees must be >= 1 and sorted ascending")
-    n = h.shape[0]
-    ht = (h - c * np.eye(n)) / e                       # shifted, scaled matrix
-    sig1 = e / (gamma - c)
-    y_prev = y0.astype(np.complex128, copy=True)
-    y_cur = sig1 * (ht @ y_prev)                       # degree-1 iterate
-    s = next((j for j in range(k) if m[j] != 1), k)    # first column still active
-    sig = sig1
-    for i in range(1, m[-1]):
-        sig_next = 1.0 / (2.0 / sig1 - sig)
-        y_next = np.empty_like(y_cur)
-        y_next[:, :s] = y_cur[:, :s]                   # finished columns carried forward
-        y_next[:, s:] = (2.0 * sig_next) * (ht @ y_cur[:, s:]) \
-            - (sig_next * sig) * y_prev[:, s:]         # three-term recurrence
-        s = next((j for j in range(s, k) if m[j] != i + 1), k)
+        return out
+    if np.any(m < 1):
+        raise ValueError("degrees must be >= 1")
+    sig = sigmas(int(m.max()), c, e, gamma)
+
+    def shifted(y):                                 # (H - cI) y
+        return h @ y - c * y
+
+    cols = np.arange(k)                             # columns still below their degree
+    y_prev = out.copy()
+    y_cur = (sig[0] / e) * shifted(y_prev)          # degree-1 iterate of every column
+    for i in range(1, int(m.max()) + 1):
+        # the columns whose degree is i are finished: their iterate is Y_i
+        fin = m[cols] == i
+        out[:, cols[fin]] = y_cur[:, fin]
+        keep = ~fin
+        cols, y_prev, y_cur = cols[keep], y_prev[:, keep], y_cur[:, keep]
+        if cols.size == 0:
+            break
+        # Y_{i+1} from Y_i and Y_{i-1} (sig[i] is sigma_{i+1})
+        y_next = (2.0 * sig[i] / e) * shifted(y_cur) - (sig[i] * sig[i - 1]) * y_prev
         y_prev, y_cur = y_cur, y_next
-        sig = sig_next
-    return y_cur
-
-
-def filter_closed_form(lam, q, y0, degrees, c, e, gamma):
-    """Reference value of the filter for H = Q diag(lam) Q^H:
-    column j -> Q diag(C_{m_j}(t) / C_{m_j}(tg)) Q^H y0_j, t = (lam - c)/e."""
-    t = (np.asarray(lam) - c) / e
-    tg = (gamma - c) / e
-    coef = q.conj().T @ y0
-    out = np.empty_like(y0, dtype=np.complex128)
-    for j, mj in enumerate(degrees):
-        scale = cheb(mj, t) / cheb(mj, np.array([tg]))[0]
-        out[:, j] = q @ (scale * coef[:, j])
     return out
 
 

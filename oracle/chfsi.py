@@ -228,8 +228,7 @@ def chfsi(a: np.ndarray, nev: int, nex: int, b: Optional[np.ndarray] = None,
     while it < o.max_iter:
         it += 1
         c, e = 0.5 * (alpha + beta), 0.5 * (beta - alpha)
-        order = np.argsort(deg, kind="stable")
-        yf = chebyshev.chebyshev_filter(h, qa[:, order], deg[order], c, e, gamma)
+        yf = chebyshev.chebyshev_filter(h, qa, deg, c, e, gamma)
         filter_mv += chebyshev.filter_matvecs(deg)
         qa = orthonormalize(yf, q_locked)
         mu, qa, za = rayleigh_ritz(h, qa)
@@ -240,7 +239,7 @@ def chfsi(a: np.ndarray, nev: int, nex: int, b: Optional[np.ndarray] = None,
         lock = np.zeros(qa.shape[1], dtype=bool)
         lock[:n_cand] = res[:n_cand] <= tol_abs
         log.append(dict(it=it, alpha=alpha, beta=beta, gamma=gamma, c=c, e=e,
-                        degrees=deg[order].tolist(), mu=mu.tolist(), res=res.tolist(),
+                        degrees=deg.tolist(), mu=mu.tolist(), res=res.tolist(),
                         locked_before=n_locked, newly_locked=int(lock.sum())))
         if lock.any():
             q_locked = np.concatenate([q_locked, qa[:, lock]], axis=1)

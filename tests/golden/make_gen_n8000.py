@@ -30,7 +30,13 @@ from workloads import gen  # noqa: E402
 
 def inertia_below(a, b, sigma):
     import scipy.linalg
-    _, d, _ = scipy.linalg.ldl(a - sigma * b, lower=True, hermitian=True)
+    if b is None:                      # standard problem: A - sigma I
+        m = np.array(a, dtype=np.complex128, copy=True)
+        m[np.diag_indices_from(m)] -= sigma
+    else:
+        m = a - sigma * b
+    _, d, _ = scipy.linalg.ldl(m, lower=True, hermitian=True)
+    del m
     # d is block diagonal with 1x1 and 2x2 blocks: a Hermitian tridiagonal
     w = scipy.linalg.eigvalsh_tridiagonal(np.diag(d).real, np.abs(np.diag(d, -1)))
     return int((w < 0).sum())

@@ -102,13 +102,34 @@ def test_gamma_only_rescales_columns():
         assert np.allclose(y2[:, j], y1[:, j] * f, rtol=1e-12, atol=1e-14)
 
 
-def test_filter_rejects_unsorted_or_zero_degrees():
+def test_filter_rejects_zero_degrees():
     h = np.eye(4, dtype=complex)
     y = np.ones((4, 2), dtype=complex)
     with pytest.raises(ValueError):
-        chebyshev.chebyshev_filter(h, y, [3, 2], 0.0, 1.0, -2.0)
-    with pytest.raises(ValueError):
         chebyshev.chebyshev_filter(h, y, [0, 2], 0.0, 1.0, -2.0)
+
+
+def test_filter_is_independent_of_column_order():
+    # the definition is per column: any order of the degrees gives the same
+    # columns (Alg. 2 sorts them only to keep the active ones contiguous)
+    lam, q, h = _herm(36, 4)
+    deg = [7, 1, 4, 4, 2, 9]
+    y0 = gen.random_block(36, len(deg), 13)
+    c, e, gamma = 1.5, 2.5, -3.4
+    got = chebyshev.chebyshev_filter(h, y0, deg, c, e, gamma)
+    perm = np.argsort(deg, kind="stable")
+    srt = chebyshev.chebyshev_filter(h, y0[:, perm], [deg[p] for p in perm], c, e, gamma)
+    assert np.allclose(got[:, perm], srt, rtol=1e-13, atol=1e-13 * np.abs(srt).max())
+    t, tg = (lam - c) / e, (gamma - c) / e
+    for j, m in enumerate(deg):
+        col = q @ ((_cheb_np(m, t) / _cheb_np(m, tg)) * (q.conj().T @ y0[:, j]))
+        assert np.linalg.norm(got[:, j] - col) <= 1e-12 * np.linalg.norm(col)
+
+
+def test_filter_of_an_empty_block():
+    h = np.eye(5, dtype=complex)
+    assert chebyshev.chebyshev_filter(h, np.zeros((5, 0), complex), [], 0.0, 1.0, -2.0).shape \
+        == (5, 0)
 
 
 def test_filter_damps_interval_and_amplifies_below():

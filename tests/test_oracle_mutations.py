@@ -31,22 +31,24 @@ def _filter_pin_holds(filt):
     return True
 
 
-def _filter_variant(y_old_is_current=False, shift_sign=1.0):
+def _filter_variant(y_old_is_current=False, shift_sign=1.0, sigma_index_shift=0):
+    """A copy of the oracle's per-column recurrence with one planted
+    mistake: the subtracted term taken from Y_i instead of Y_{i-1}, the
+    shift added instead of subtracted, or the sigmas used one step late."""
     def filt(h, y0, m, c, e, gamma):
-        k = len(m)
-        ht = (h - shift_sign * c * np.eye(h.shape[0])) / e
-        sig1 = e / (gamma - c)
-        y_prev, y_cur = y0.copy(), sig1 * (ht @ y0)
-        s = next((j for j in range(k) if m[j] != 1), k)
-        sig = sig1
-        for i in range(1, m[-1]):
-            sn = 1.0 / (2.0 / sig1 - sig)
-            y_next = y_cur.copy()
-            old = y_cur if y_old_is_current else y_prev
-            y_next[:, s:] = 2 * sn * (ht @ y_cur[:, s:]) - sn * sig * old[:, s:]
-            s = next((j for j in range(s, k) if m[j] != i + 1), k)
-            y_prev, y_cur, sig = y_cur, y_next, sn
-        return y_cur
+        sig = chebyshev.sigmas(max(m) + 1, c, e, gamma)
+        out = np.empty_like(y0)
+        for j, mj in enumerate(m):
+            prev = y0[:, j].copy()
+            cur = (sig[0] / e) * (h @ prev - shift_sign * c * prev)
+            for i in range(1, mj):
+                s_new = sig[i + sigma_index_shift]
+                s_old = sig[i - 1 + sigma_index_shift]
+                old = cur if y_old_is_current else prev
+                nxt = (2 * s_new / e) * (h @ cur - shift_sign * c * cur) - s_new * s_old * old
+                prev, cur = cur, nxt
+            out[:, j] = cur
+        return out
     return filt
 
 
@@ -55,9 +57,10 @@ def test_filter_pin_accepts_oracle_and_a_faithful_copy():
     assert _filter_pin_holds(_filter_variant())
 
 
-def test_filter_pin_catches_listing_typo_and_sign_error():
+def test_filter_pin_catches_wrong_term_sign_and_sigma_index():
     assert not _filter_pin_holds(_filter_variant(y_old_is_current=True))
     assert not _filter_pin_holds(_filter_variant(shift_sign=-1.0))
+    assert not _filter_pin_holds(_filter_variant(sigma_index_shift=1))
 
 
 def test_reduction_pin_catches_plain_transpose():
