@@ -19,7 +19,8 @@ that can finish every wanted vector (all predicted degrees within the cap);
 in the other loops some vectors continue anyway and margin 0 is used.  Everything here is
 float64 numpy written from those definitions: the network (8 -> 64 -> 64 ->
 1, tanh), the mean-squared-error gradient by backpropagation, Adam (Kingma
-and Ba, ICLR 2015, with bias correction), the input features and the
+and Ba, ICLR 2015, with bias correction), the input features, the training
+target y of one logged loop, the safety margin from held-out errors and the
 learned degree rule.
 
 Parameter blob layout (floats), the interface shared with the library:
@@ -110,6 +111,53 @@ def adam_step(blob, grad, m, v, lr, t, b1=0.9, b2=0.999, eps=1e-8):
     vhat = v[sl] / (1 - b2 ** t)
     p[sl] -= lr * mhat / (np.sqrt(vhat) + eps)
     return p, m, v
+
+
+# ---------------------------------------------------------------------------
+# training data: the target of one logged loop and the safety margin
+
+# an observed residual below this fraction of the target is not trusted
+# (it may sit on a rounding floor): it is raised to the fraction first
+AFTER_FLOOR = 1e-2
+# the observed speed relative to the model is clipped to [0.05, 8]
+EFF_MIN, EFF_MAX = 0.05, 8.0
+
+
+def training_target(res_before, res_after, degree, ln_rho, tol_abs, fp32_loop=False):
+    """Target y of one vector in one loop, or None when the record is unusable.
+
+    Eq. (resl) models the residual after a degree-m filter as
+    res_before |rho|^-m, so the observed speed relative to the model is
+        eff = ln(res_before / res_after') / (m ln|rho|),
+    res_after' = max(res_after, AFTER_FLOOR tol_abs); y = ln(clip(eff,
+    EFF_MIN, EFF_MAX)).  Loops filtered in FP32 are unusable (the residual
+    can stop at FP32's rounding floor, which measures the precision, not the
+    polynomial), and so are records without positive finite residuals, a
+    degree of at least 1 and a positive ln|rho|.  A residual that grew gives
+    a negative eff, which the clip raises to EFF_MIN."""
+    if fp32_loop:
+        return None
+    vals = (res_before, res_after, ln_rho, tol_abs)
+    if not all(math.isfinite(v) for v in vals) or degree < 1:
+        return None
+    if res_after <= 0.0 or res_before <= 0.0 or ln_rho <= 0.0:
+        return None
+    after = max(res_after, AFTER_FLOOR * tol_abs)
+    eff = math.log(res_before / after) / (degree * ln_rho)
+    if not math.isfinite(eff):
+        return None
+    return math.log(min(max(eff, EFF_MIN), EFF_MAX))
+
+
+def holdout_margin(pred, target, z=3.0):
+    """Safety margin of the learned degrees: mean + z * std (population) of
+    the held-out prediction errors pred - target, floored at 0.  A larger
+    prediction means a faster vector and a lower degree, so the margin
+    lowers every prediction by an amount far into the tail of the errors."""
+    d = np.asarray(pred, dtype=np.float64) - np.asarray(target, dtype=np.float64)
+    if d.size == 0:
+        return 0.0
+    return max(0.0, float(d.mean() + z * d.std()))
 
 
 # ---------------------------------------------------------------------------

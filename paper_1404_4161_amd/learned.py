@@ -98,6 +98,16 @@ def targets(rec, fp64_only=True):
     return feats[ok].astype(np.float32), y[ok].astype(np.float32), ok
 
 
+def holdout_margin(pred, y, z=3.0):
+    """mean + z std of the held-out errors pred - y, at least 0 (the margin
+    the solver subtracts from the network's output where a loop can finish
+    every wanted vector)."""
+    d = np.asarray(pred, dtype=np.float64) - np.asarray(y, dtype=np.float64)
+    if d.size == 0:
+        return 0.0
+    return max(0.0, float(np.mean(d) + z * np.std(d)))
+
+
 def init_blob(X, seed=0):
     """Feature statistics from X and seeded Glorot-uniform weights."""
     g = np.random.default_rng(seed)
@@ -145,7 +155,7 @@ def fit(rec, steps=1500, lr=3e-3, seed=0, holdout=0.2, z=3.0, device="cuda"):
         d = pred - y[te]
         report["holdout_mse"] = float(np.mean(d ** 2))
         report["holdout_var"] = float(np.var(y[te]))
-        margin = max(0.0, float(np.mean(d) + z * np.std(d)))
+        margin = holdout_margin(pred, y[te], z)
     else:
         margin = 0.0
     out = pt.cpu().numpy().astype(np.float32)

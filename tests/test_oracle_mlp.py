@@ -246,3 +246,61 @@ def test_margin_only_in_loops_that_can_finish():
     deg, _, src, _ = mlp.learned_degrees(p, mu, res, nw, alpha, beta, gamma, norm_h, tol_abs, 1,
                                          cap, rule=rule)
     assert np.array_equal(deg, rule)
+
+
+# ---------------------------------------------------------------------------
+# the gap feature, the training target and the margin
+
+def test_ritz_gap_closed_form():
+    mu = [0.0, 1.0, 3.0, 7.0]
+    assert [mlp.ritz_gap(mu, j, 5.0) for j in range(4)] == [1.0, 1.0, 2.0, 4.0]
+    assert mlp.ritz_gap([2.5], 0, 0.75) == 0.75           # one value: the half-width e
+
+
+def test_ritz_gap_pin_catches_one_sided_gap():
+    def right_only(mu, j, e):
+        return mu[j + 1] - mu[j] if j + 1 < len(mu) else e
+
+    def left_only(mu, j, e):
+        return mu[j] - mu[j - 1] if j > 0 else e
+
+    mu = [0.0, 1.0, 3.0, 7.0]
+    want = [1.0, 1.0, 2.0, 4.0]
+    assert [right_only(mu, j, 5.0) for j in range(4)] != want
+    assert [left_only(mu, j, 5.0) for j in range(4)] != want
+
+
+@pytest.mark.parametrize("eff", [0.25, 0.5, 1.0, 2.0, 5.0])
+def test_training_target_recovers_a_known_rate(eff):
+    # a vector that converged eff times as fast as eq. (resl)'s model:
+    # res_after = res_before |rho|^(-eff m)
+    res, m, ln_rho, tol = 3e-4, 6, 0.35, 1e-9
+    after = res * math.exp(-eff * m * ln_rho)
+    y = mlp.training_target(res, after, m, ln_rho, tol)
+    assert abs(y - math.log(eff)) < 1e-12
+
+
+def test_training_target_floor_clip_and_exclusions():
+    res, m, ln_rho, tol = 1e-3, 6, 0.25, 1e-9
+    # below 1e-2 tol the residual is raised to it: eff = ln(1e-3/1e-11)/1.5 = 12.3, clipped to 8
+    assert abs(mlp.training_target(res, 1e-30, m, ln_rho, tol) - math.log(8.0)) < 1e-15
+    # just above the floor: not raised
+    after = 2e-11
+    want = math.log(math.log(res / after) / (m * ln_rho))
+    assert abs(mlp.training_target(res, after, m, ln_rho, tol) - min(want, math.log(8.0))) < 1e-12
+    # a residual that grew: eff < 0, clipped to 0.05
+    assert abs(mlp.training_target(res, 2 * res, m, ln_rho, tol) - math.log(0.05)) < 1e-15
+    # unusable records
+    assert mlp.training_target(res, 1e-5, m, ln_rho, tol, fp32_loop=True) is None
+    assert mlp.training_target(res, 1e-5, 0, ln_rho, tol) is None
+    assert mlp.training_target(res, 0.0, m, ln_rho, tol) is None
+    assert mlp.training_target(res, float("nan"), m, ln_rho, tol) is None
+    assert mlp.training_target(res, 1e-5, m, 0.0, tol) is None
+
+
+def test_holdout_margin_closed_forms():
+    assert mlp.holdout_margin([1.0, -1.0, 1.0, -1.0], [0.0] * 4) == pytest.approx(3.0, abs=1e-15)
+    assert mlp.holdout_margin([1.0, 2.0], [3.0, 4.0]) == 0.0          # all errors -2
+    assert mlp.holdout_margin([0.5] * 4, [0.0] * 4) == pytest.approx(0.5, abs=1e-15)
+    assert mlp.holdout_margin([2.0, 0.0], [0.0, 0.0], z=1.0) == pytest.approx(2.0, abs=1e-15)
+    assert mlp.holdout_margin([], []) == 0.0

@@ -8,7 +8,13 @@ differs from a b by at most 3 * 2^-22 |a| |b| for normal words, and a dot
 product of such terms by at most that fraction of sum |a_k| |b_k| plus
 n 2^-39 max|a| max|b| (words in FP16's subnormal range).  The sums here
 are exact (float64 of binary16 products), so only the split is measured.
-BF16 (rounded from FP32 bits, nearest even): 3 * 2^-16 |a| |b|."""
+BF16 (rounded from FP32 bits, nearest even): 3 * 2^-16 |a| |b|.
+
+These tests pin the derivation of the bounds with numpy's own binary16
+arithmetic; they do not call the library.  The kernels' splits (and their
+NaN, infinity, scale-cap and subnormal branches) are covered on the GPU by
+the split-step tests of test_gpu_kernels.py, which hold the product of a
+kernel step to the same bounds."""
 import numpy as np
 
 
