@@ -11,10 +11,11 @@ are exact (float64 of binary16 products), so only the split is measured.
 BF16 (rounded from FP32 bits, nearest even): 3 * 2^-16 |a| |b|.
 
 These tests pin the derivation of the bounds with numpy's own binary16
-arithmetic; they do not call the library.  The kernels' splits (and their
-NaN, infinity, scale-cap and subnormal branches) are covered on the GPU by
-the split-step tests of test_gpu_kernels.py, which hold the product of a
-kernel step to the same bounds."""
+arithmetic; they do not call the library.  The kernels' splits are
+covered on the GPU by the split-step tests of test_gpu_kernels.py, which
+hold one kernel step to the same bounds (H scaled by 1e6 and 1e-5, defect
+columns spanning seven decades, exactly zero defect columns); their NaN
+and infinity branches are not exercised by any test."""
 import numpy as np
 
 
