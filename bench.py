@@ -1,21 +1,32 @@
-"""Benchmark: ChFSI on a sequence of dense generalized Hermitian eigenproblems.
+"""Benchmark: ChFSI on a sequence of correlated dense Hermitian eigenproblems.
 
-One step = one call of chfsi_solve on the next problem of the sequence
-(reduction to standard form, Lanczos bound, filter/QR/Rayleigh-Ritz/
-residual/locking loops until nev pairs reach residual 1e-10, back-
-transform), warm-started from the previous problem's Ritz vectors.
+One step = one chfsi_solve call on the next problem of the sequence
+(Lanczos bound, filter / QR / Rayleigh-Ritz / residual / locking loops
+until nev pairs reach residual 1e-10, plus the reduction to standard form
+and the back-transform for generalized problems), warm-started from the
+previous problem's Ritz vectors and values.
 
-Default workload: generalized complex Hermitian A x = lambda B x,
-n = 8000, nev = 400, nex = 80, B = I + 0.05 G (G random HPD of unit norm),
-a 10-problem sequence with perturbations 1e-2 * 0.5^l.  The first problem
-(random start) is the warm-up; the timed steps are warm-started problems.
-All matrices are generated on the GPU from seeded host draws and are
-resident in HBM before timing starts.
+Default workload (the learned-degree configuration): the standard complex
+Hermitian sequence at n = 30000, nev = 1500, nex = 300, 20 problems,
+A(l+1) = A(l) + 1e-3 H_l.  Problem 1 (random start block) is solved once,
+untimed, with the mixed-precision filter; every timed variant then solves
+problems 2..20 in order from that solution (19 timed steps).  Inputs are
+generated on the GPU from seeded draws and are resident in HBM before each
+timed solve; generating a problem is outside the timed region.
 
-Printed (one JSON line): filter TFLOP/s (algorithmic 8 n^2 flops per
-column mat-vec / device time of the filter-step kernels) as `value`, the
-wall time per sequence step as `ms_per_step`, the roofline of the
-filter-step kernel and the CPU oracle's filter rate on a bounded sample.
+Timed variants: `fp64` (the paper's method: FP64 filter, analytic
+degrees), `mixed-fp16+learned` (FP16-split / FP32 defect filter with the
+degree network, trained in this run on convergence logs of the n = 8000
+generalized, n = 20000 standard and k-point recipes under other seeds) and
+`mixed-fp16` (the same filter with the analytic degrees), plus any
+`--variants`.
+
+Printed: one JSON line under 4 KB -- FP64 filter TFLOP/s (algorithmic
+8 n^2 flops per column mat-vec / device time of the filter launches) as
+`value`, the FP64 wall time per step as `ms_per_step`, the filter kernel's
+roofline, the CPU oracle's filter rate on a bounded sample and the
+FP64-against-mixed+learned comparison.  Per-step detail goes to stderr
+(and to --detail-out).
 """
 from __future__ import annotations
 
@@ -33,24 +44,27 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 
-# HBM bytes of one full-width filter step (n = 8000, N = 480), from the two
-# rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) calibrated on a 1 GiB
-# copy, per tile variant of the step kernel; valid only for the kernel
-# source it was measured on.
+# HBM bytes of one full-width launch of the FP64 filter step kernel, from
+# the two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) of
+# `bench.py --filter-only`, calibrated on a 1 GiB device copy; keyed by
+# (n, N, tile variant).  Valid only for the kernel source they were
+# measured on (the hash); otherwise the roofline reports traffic null.
 TRAFFIC_MEASURED = {
     "zgemm_sha256": "8df37dde5efc6e7bda01d1ea51ab5cea363e65cd6970b6f321f9b3caf55a364e",
-    "bytes_per_full_width_step": {0: 4.571e9, 1: 2.370e9, 2: 1.697e9},
-    "algorithmic_bytes_per_full_width_step": 1.208e9,
+    "bytes_per_full_width_launch": {(8000, 480, 0): 4.571e9, (8000, 480, 1): 2.370e9,
+                                    (8000, 480, 2): 1.697e9},
 }
 
 
-def traffic_entry(variant):
+def traffic_entry(n, N, variant):
+    """Measured HBM GB of one full-width step launch at (n, N), or None."""
     import hashlib
     src = os.path.join(ROOT, "paper_1404_4161_amd", "csrc", "zgemm.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if sha != TRAFFIC_MEASURED["zgemm_sha256"]:
+    b = TRAFFIC_MEASURED["bytes_per_full_width_launch"].get((int(n), int(N), int(variant)))
+    if sha != TRAFFIC_MEASURED["zgemm_sha256"] or b is None:
         return None
-    return round(TRAFFIC_MEASURED["bytes_per_full_width_step"][int(variant)] / 1e9, 3)
+    return round(b / 1e9, 3)
 
 
 def log(msg):
@@ -58,8 +72,9 @@ def log(msg):
 
 
 def cpu_baseline(a_host: np.ndarray, k: int, degree: int, seed: int = 0):
-    """Time the CPU oracle's Chebyshev filter (Alg. 2) on a bounded sample:
-    the n x n matrix of the workload and k columns at one degree."""
+    """Time the CPU oracle's Chebyshev filter on a bounded sample: the
+    workload's n x n matrix and `k` random columns, each filtered to one
+    degree (the oracle as it stands, numpy BLAS on the host's threads)."""
     from oracle import chebyshev
     try:
         import threadpoolctl
@@ -74,9 +89,10 @@ def cpu_baseline(a_host: np.ndarray, k: int, degree: int, seed: int = 0):
     chebyshev.chebyshev_filter(a_host, y0, [degree] * k, 12.5, 27.5, -20.0)
     dt = time.perf_counter() - t
     flops = 8.0 * n * n * k * degree
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"oracle Chebyshev filter (Alg. 2), n={n}, {k} columns, degree {degree}, "
-                      f"{dt:.1f} s on the host"}
+    return {"value": round(flops / dt / 1e12, 4), "unit": "TFLOP/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"oracle filter on problem 1's matrix (n={n}), {k} columns at degree "
+                      f"{degree}, {dt:.1f} s on the host"}
 
 
 def filter_only(conf, degree):
@@ -248,15 +264,145 @@ def kpoints(args):
     print(json.dumps(out), flush=True)
 
 
+# (precision, degree_mode, first_rule) of each solver variant.  precision:
+# 0 FP64 filter, 1 FP32 defect filter, 2 with BF16-split steps, 3 with
+# FP16-split steps; degree_mode: 0 analytic rule, 2 degree network,
+# 3 sequence-calibrated speeds.  FP64 takes the first loop's degrees from
+# the residuals of X0 only with the network (first_rule 1).
+VARIANTS = {
+    "fp64": (0, 0, 0),
+    "mixed": (1, 0, 0),
+    "mixed-bf16": (2, 0, 0),
+    "mixed-fp16": (3, 0, 0),
+    "mixed-fp16+learned": (3, 2, 0),
+    "mixed+learned": (1, 2, 0),
+    "mixed-bf16+learned": (2, 2, 0),
+    "fp64+learned": (0, 2, 1),
+    "mixed-fp16+seqcal": (3, 3, 0),
+    "fp64+seqcal": (0, 3, 1),
+}
+HEADLINE = "mixed-fp16+learned"      # the metric's mixed+learned form
+RULE_TWIN = "mixed-fp16"             # the same filter with the analytic degrees
+PHASES = ["reduction", "lanczos", "filter", "orthonormalize", "rayleigh_ritz", "residuals",
+          "locking", "back_transform"]
+
+
+def training_logs(dev, quick=False):
+    """Convergence records for the degree network: FP64 solves (first loop
+    degrees from X0's residuals, and a second pass with degree jitter 0.3
+    for spread) of three recipes under seed namespaces the benchmark does
+    not time -- the generalized n = 8000 sequence (10 problems), the
+    standard n = 20000 sequence (first 3 problems) and 6 k-point
+    sequences (n in [2000, 9000], 5 problems each)."""
+    import torch
+    import paper_1404_4161_amd as ch
+    from paper_1404_4161_amd import learned
+    from workloads import gen
+    buf = learned.LogBuffer(600_000)
+    report = []
+    c1 = gen.variant(gen.CONFIGS["gen-n8000"], 101)
+    c2 = gen.variant(gen.CONFIGS["std-n20000"], 102)
+    kp = gen.kpoint_configs(count=6, cfg_base=500, seed=5)
+    plan = [(c1, c1.length, (0.0, 0.3)), (c2, 2 if quick else 3, (0.0,))]
+    plan += [(c, c.length, (0.0,)) for c in kp[:2 if quick else 6]]
+    for conf, count, jitters in plan:
+        t0 = time.perf_counter()
+        draw = "device" if conf.n > 10000 else "host"
+        seq = gen.Sequence(conf, kind="torch", device=dev, draw=draw)
+        probs = [a.clone() for _, a in seq.problems(count)]
+        torch.cuda.synchronize()
+        before = buf.count
+        iters = []
+        for jit in jitters:
+            o = ch.chfsi_default_opts()
+            o.precision, o.first_rule, o.degree_jitter, o.seed = 0, 1, jit, 7
+            iters.append([i["iters"] for i in learned.solve_sequence_logged(
+                probs, seq.B, conf.nev, conf.nex, conf.tol, o, buf)])
+        report.append({"recipe": conf.name, "problems": count, "records": buf.count - before,
+                       "seconds": round(time.perf_counter() - t0, 1)})
+        log(f"training logs {conf.name}: {count} problems, loops {iters}, "
+            f"{buf.count - before} records, {time.perf_counter() - t0:.1f}s")
+        del probs, seq
+        torch.cuda.empty_cache()
+    return buf.records(), report
+
+
+def run_variant(label, seq, conf, B, x1, lam1, steps, work, X, blob, dev):
+    """Solve problems 2..steps+1 of the sequence in order, starting from
+    problem 1's solution (x1, lam1).  Each problem is generated (untimed)
+    before its solve; the wall time of every chfsi_solve call is kept."""
+    import torch
+    import paper_1404_4161_amd as ch
+    prec, mode, first = VARIANTS[label]
+    o = ch.chfsi_default_opts()
+    o.precision, o.degree_mode, o.first_rule = prec, mode, first
+    rates = np.full(conf.k, np.nan) if mode == 3 else None
+    x_prev, lam_prev = x1, lam1
+    stream = torch.cuda.current_stream(dev)
+    infos, walls, lams = [], [], []
+    for l, a in seq.problems(steps + 1):
+        if l == 1:
+            continue
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        st, lam, _, info = ch.chfsi_solve(a, B, conf.nev, conf.nex, conf.tol, X0=x_prev,
+                                          Lambda0=lam_prev, opts=o, X=X, work=work,
+                                          stream=stream, mlp=blob if mode == 2 else None,
+                                          seq_rates=rates)
+        walls.append(time.perf_counter() - ts)
+        if st != 0:
+            raise RuntimeError(f"[{label}] chfsi_solve status {st} on problem {l}")
+        x_prev, lam_prev = X, lam
+        infos.append(info)
+        lams.append(lam[:conf.nev].copy())
+        log(f"[{label}] problem {l}: loops {info['iters']} (fp32 {info['filter_iters_fp32']}) "
+            f"matvecs {info['filter_matvecs']} filter {info['filter_seconds'] * 1e3:.1f} ms "
+            f"step {walls[-1] * 1e3:.1f} ms")
+        del a
+    return {"infos": infos, "walls": walls, "lams": lams}
+
+
+def summarize(label, r, ref_lams=None):
+    infos, walls = r["infos"], r["walls"]
+    steps = len(walls)
+    fl = sum(i["filter_flops"] for i in infos)
+    fs = sum(i["filter_seconds"] for i in infos)
+    d = {"ms_per_step": round(1e3 * sum(walls) / steps, 2),
+         "s_per_step_median": round(statistics.median(walls), 4),
+         "loops": sum(i["iters"] for i in infos),
+         "filter_matvecs": sum(i["filter_matvecs"] for i in infos),
+         "filter_ms_per_step": round(1e3 * fs / steps, 2),
+         "filter_effective_tflops": round(fl / fs / 1e12, 2) if fs > 0 else None}
+    if ref_lams is not None:
+        d["max_rel_eig_diff_vs_fp64"] = float(f"{max(float(np.max(np.abs(a - b) / np.abs(b))) for a, b in zip(r['lams'], ref_lams)):.2e}")
+    return d
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=9)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gen-n8000",
+    ap.add_argument("--steps", type=int, default=19,
+                    help="timed problems (at most the sequence length minus the untimed first)")
+    ap.add_argument("--warmup", type=int, default=1,
+                    help="accepted for the harness; the one untimed problem is the sequence's "
+                         "cold first problem")
+    ap.add_argument("--workload", default="std-n30000",
                     choices=["gen-n8000", "std-n1000", "std-n20000", "std-n30000", "kpoints"])
+    ap.add_argument("--variants", default="",
+                    help="comma list of extra variants to time after fp64, mixed-fp16+learned "
+                         "and mixed-fp16: " + ", ".join(VARIANTS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-degree", type=int, default=40)
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the degree network (and the learned variant)")
+    ap.add_argument("--quick-logs", action="store_true",
+                    help="fewer training-log problems (for short runs)")
+    ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--budget-s", type=float, default=520.0,
+                    help="wall-clock budget: optional phases that would not finish within it "
+                         "are skipped (and reported as skipped)")
+    ap.add_argument("--detail-out", default="",
+                    help="write the per-step detail JSON to this file")
     ap.add_argument("--filter-only", action="store_true",
                     help="time only the Chebyshev filter at the workload shape (n x k block, "
                          "uniform degree) after a 1 GiB device copy used to calibrate "
@@ -267,22 +413,8 @@ def main():
     ap.add_argument("--kp-variants", default="batched-fp64,batched-fp64-graph,sequential-fp64,"
                                              "batched-mixed,batched-mixed-bf16,"
                                              "batched-mixed-fp16")
-    ap.add_argument("--no-learned", action="store_true",
-                    help="skip training the degree network and the learned-degree sequences")
-    ap.add_argument("--no-bf16", action="store_true",
-                    help="skip the sequences with BF16-split defect steps (precision 2)")
-    ap.add_argument("--no-fp16", action="store_true",
-                    help="skip the sequences with FP16-split defect steps (precision 3)")
-    ap.add_argument("--train-steps", type=int, default=1500)
-    ap.add_argument("--variants", default="",
-                    help="comma list of the extra sequences to time (default all): "
-                         "mixed+learned, fp64+learned, mixed+seqcal, fp64+seqcal, mixed-bf16, "
-                         "mixed-bf16+seqcal, mixed-bf16+learned, mixed-fp16, mixed-fp16+seqcal, "
-                         "mixed-fp16+learned (fp64 and mixed always run)")
-    ap.add_argument("--no-lambda0", action="store_true",
-                    help="warm-start from the previous Ritz vectors only (one extra QR + "
-                         "Rayleigh-Ritz per problem) instead of vectors and values")
     args = ap.parse_args()
+    t_start = time.perf_counter()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the library solves "
                                    "each problem (or batch) on one device and has no multi-GPU "
@@ -301,175 +433,107 @@ def main():
     if args.filter_only:
         filter_only(conf, args.degree)
         return
-    total = args.warmup + args.steps
-    if total > conf.length:
-        log(f"warmup + steps = {total} exceeds the sequence length {conf.length}; "
-            f"the sequence is extended with the same perturbation schedule")
-        conf = gen.SequenceConfig(conf.name, conf.cfg, conf.n, conf.nev, conf.nex,
-                                  conf.generalized, total, conf.delta, conf.b_weight, conf.tol,
-                                  conf.deg0)
+    steps = max(1, min(args.steps, conf.length - 1))
+    if steps != args.steps:
+        log(f"timing {steps} problems: the sequence has {conf.length} problems and the first "
+            f"is the untimed cold start")
     dev = "cuda:0"
-    t0 = time.perf_counter()
-    # large problems draw their Gaussian matrices on the GPU (much faster)
-    draw = "device" if conf.n > 10000 else "host"
-    seq = gen.Sequence(conf, kind="torch", device=dev, draw=draw)
-    problems = []
-    for l, a in seq.problems():
-        problems.append(a)
-        if l >= total:
-            break
-    B = seq.B
-    torch.cuda.synchronize()
-    log(f"generated {len(problems)} problems (n={conf.n}) in {time.perf_counter() - t0:.1f}s")
-    a1_host = problems[0].cpu().numpy() if not args.no_cpu_baseline else None
-
     n, nev, nex, k = conf.n, conf.nev, conf.nex, conf.k
-    stream = torch.cuda.current_stream(dev)
-    opts0 = ch.chfsi_default_opts()
-    opts1 = ch.chfsi_default_opts()
-    opts1.precision = 1
-    opts2 = ch.chfsi_default_opts()
-    opts2.precision = 2
-    opts3 = ch.chfsi_default_opts()
-    opts3.precision = 3
-    wb = max(ch.chfsi_workspace_bytes(n, nev, nex, B is not None, o)
-             for o in (opts0, opts1, opts2, opts3))
-    work = torch.empty(wb, dtype=torch.uint8, device=dev)
-    X = ch.colmajor(torch.empty((n, k), dtype=torch.complex128, device=dev))
 
-    # Filter tile autotuner (untimed): both K-stage variants of the filter
-    # step on the full window and narrower ones; later launches take the
-    # choice of the nearest measured shape.
+    def elapsed():
+        return time.perf_counter() - t_start
+
+    # Filter tile autotuner (untimed): the tile variants of the FP64 step on
+    # the full window and narrower ones; later launches take the choice of
+    # the nearest measured shape.
     tune_shapes = [(n, k), (n, (3 * k) // 4), (n, k // 2), (n, k // 4), (n, max(k // 8, 16))]
     tv, ttf = ch.chfsi_autotune_filter([a for a, _ in tune_shapes], [b for _, b in tune_shapes])
-    autotune = [{"n": a, "N": b, "variant": int(v), "tflops_kb8": round(float(t[0]), 2),
-                 "tflops_kb16": round(float(t[1]), 2), "tflops_wide": round(float(t[2]), 2)}
-                for (a, b), v, t in zip(tune_shapes, tv, ttf)]
-    log(f"autotune: {autotune}")
+    log("autotune: " + ", ".join(f"N={b}: variant {int(v)} ({max(t):.1f} TFLOP/s)"
+                                 for (_, b), v, t in zip(tune_shapes, tv, ttf)))
 
-    # Degree network (untimed): convergence logs of a sequence with the same
-    # recipe under another seed, then training with the library's kernels.
-    blob, train_report = None, None
+    # Degree network (untimed), trained with the library's kernels.
+    blob, train = None, None
     if not args.no_learned:
         from paper_1404_4161_amd import learned
         t0 = time.perf_counter()
-        tconf = gen.variant(conf, conf.cfg + 100)
-        tseq = gen.Sequence(tconf, kind="torch", device=dev, draw=draw)
-        tprobs = [a.clone() for l, a in tseq.problems() if l <= min(tconf.length, total)]
-        buf = learned.LogBuffer(400_000)
-        tw = torch.empty(wb, dtype=torch.uint8, device=dev)
-        collect = []
-        for prec, jit in ((0, 0.0), (0, 0.3)):
-            o = ch.chfsi_default_opts()
-            o.precision, o.first_rule, o.degree_jitter, o.seed = prec, 1, jit, 7
-            its = [i["iters"] for i in learned.solve_sequence_logged(
-                tprobs, tseq.B, nev, nex, conf.tol, o, buf, work=tw)]
-            collect.append({"precision": prec, "jitter": jit, "iters": its})
-        del tprobs, tseq, tw
-        torch.cuda.empty_cache()
+        rec, sources = training_logs(dev, quick=args.quick_logs)
         tc = time.perf_counter()
-        blob, train_report = learned.fit(buf.records(), steps=args.train_steps)
-        train_report["train_seconds"] = round(time.perf_counter() - tc, 2)
-        train_report["collect_seconds"] = round(tc - t0, 2)
-        train_report["log_runs"] = collect
-        train_report["training_sequence"] = f"{conf.name} recipe, seed namespace {tconf.cfg}"
-        log(f"degree network: {train_report}")
+        blob, rep = learned.fit(rec, steps=args.train_steps)
+        train = {"records": rep["records"], "usable": rep["usable"],
+                 "holdout_mse": round(rep["holdout_mse"], 4),
+                 "target_var": round(rep["target_var"], 4), "margin": round(rep["margin"], 4),
+                 "train_s": round(time.perf_counter() - tc, 1), "logs_s": round(tc - t0, 1),
+                 "sources": ",".join(f"{s['recipe']}:{s['problems']}" for s in sources)}
+        log(f"degree network: {rep}")
 
+    t0 = time.perf_counter()
+    draw = "device" if n > 10000 else "host"
+    seq = gen.Sequence(conf, kind="torch", device=dev, draw=draw)
+    B = seq.B
+    torch.cuda.synchronize()
+    log(f"generated problem 1 (n={n}) in {time.perf_counter() - t0:.1f}s")
+
+    o3 = ch.chfsi_default_opts()
+    o3.precision = 3
+    wb = max(ch.chfsi_workspace_bytes(n, nev, nex, B is not None, ch.chfsi_default_opts()),
+             ch.chfsi_workspace_bytes(n, nev, nex, B is not None, o3))
+    work = torch.empty(wb, dtype=torch.uint8, device=dev)
+    X = ch.colmajor(torch.empty((n, k), dtype=torch.complex128, device=dev))
+    X1 = ch.colmajor(torch.empty((n, k), dtype=torch.complex128, device=dev))
+
+    # Problem 1, cold (random start block), untimed: solved with the rule and
+    # (when trained) with the network; the rule's solution starts every
+    # timed variant.
+    a1 = next(seq.problems(1))[1]
     cold = {}
-
-    def run_sequence(opts, label):
-        """Warm-up problem(s), then the timed steps; returns per-step infos,
-        wall times, eigenvalues and the elapsed time of the timed region."""
-        x_prev, lam_prev = None, None
-        rates = np.full(k, np.nan) if opts.degree_mode == 3 else None
-
-        def solve(a):
-            st, lam, x, info = ch.chfsi_solve(
-                a, B, nev, nex, conf.tol, X0=x_prev, opts=opts, X=X, work=work, stream=stream,
-                Lambda0=None if (args.no_lambda0 or x_prev is None) else lam_prev,
-                mlp=blob if opts.degree_mode == 2 else None, seq_rates=rates)
-            if st != 0:
-                raise RuntimeError(f"chfsi_solve status {st}")
-            return lam, info
-
-        for w in range(args.warmup):
-            lam_prev, info = solve(problems[w])
-            x_prev = X
-            log(f"[{label}] warmup problem {w + 1}: iters {info['iters']} total "
-                f"{info['total_seconds']:.3f}s")
-            if w == 0:
-                # the cold first problem (random start block), untimed
-                cold[label] = {"seconds": round(info["total_seconds"], 4),
-                               "iters": info["iters"],
-                               "filter_matvecs": info["filter_matvecs"]}
-        torch.cuda.synchronize()
-        infos, walls, lams = [], [], []
-        t_start = time.perf_counter()
-        for s_ in range(args.steps):
-            ts = time.perf_counter()
-            lam_prev, info = solve(problems[args.warmup + s_])
-            x_prev = X
-            walls.append(time.perf_counter() - ts)
-            infos.append(info)
-            lams.append(lam_prev[:nev].copy())
-            log(f"[{label}] problem {args.warmup + s_ + 1}: iters {info['iters']} "
-                f"(fp32 {info['filter_iters_fp32']}) filter {info['filter_seconds'] * 1e3:.1f} ms "
-                f"step {walls[-1] * 1e3:.1f} ms")
-        torch.cuda.synchronize()
-        return infos, walls, lams, time.perf_counter() - t_start
-
-    infos, walls, lams64, elapsed = run_sequence(opts0, "fp64")
-    minfos, mwalls, lams32, melapsed = run_sequence(opts1, "mixed")
-    # further variants: (label, precision, degree_mode, first_rule).  Mixed
-    # precision keeps deg0 in the first loop of a warm start (FP32 defect
-    # form); FP64 takes the first loop's degrees from X0's residuals.
-    # degree_mode 2: the learned network; 3: Multiple Optimization (each
-    # eigenvector's speed measured earlier in the sequence, no training).
-    plan = []
-    if blob is not None:
-        plan += [("mixed+learned", 1, 2, 0), ("fp64+learned", 0, 2, 1)]
-    plan += [("mixed+seqcal", 1, 3, 0), ("fp64+seqcal", 0, 3, 1)]
-    if not args.no_bf16:
-        plan += [("mixed-bf16", 2, 0, 0), ("mixed-bf16+seqcal", 2, 3, 0)]
-        if blob is not None:
-            plan.append(("mixed-bf16+learned", 2, 2, 0))
-    if not args.no_fp16:
-        plan += [("mixed-fp16", 3, 0, 0), ("mixed-fp16+seqcal", 3, 3, 0)]
-        if blob is not None:
-            plan.append(("mixed-fp16+learned", 3, 2, 0))
-    if args.variants:
-        keep = set(args.variants.split(","))
-        plan = [p for p in plan if p[0] in keep]
-    learned_runs = {}
-    variant_modes = {}
-    for label, prec, mode, fr in plan:
+    for label in ([HEADLINE] if blob is not None else []) + [RULE_TWIN]:
+        prec, mode, first = VARIANTS[label]
         o = ch.chfsi_default_opts()
-        o.precision, o.degree_mode, o.first_rule = prec, mode, fr
-        learned_runs[label] = run_sequence(o, label)
-        variant_modes[label] = (prec, mode)
+        o.precision, o.degree_mode = prec, mode
+        st, lam1, _, info = ch.chfsi_solve(a1, B, nev, nex, conf.tol, opts=o, X=X1, work=work,
+                                           mlp=blob if mode == 2 else None)
+        if st != 0:
+            raise RuntimeError(f"cold solve ({label}) status {st}")
+        cold[label] = {"s": round(info["total_seconds"], 2), "loops": info["iters"],
+                       "filter_matvecs": info["filter_matvecs"]}
+        log(f"cold problem 1 [{label}]: {cold[label]}")
+    x1 = X1
 
+    runs = {}
+    order = ["fp64"] + ([HEADLINE] if blob is not None else []) + [RULE_TWIN]
+    order += [v for v in args.variants.split(",") if v and v not in order
+              and (blob is not None or VARIANTS[v][1] != 2)]
+    skipped = []
+    for label in order:
+        if label not in ("fp64", HEADLINE) and runs:
+            # optional variants run only if they fit the wall-clock budget
+            est = 1.25 * min(sum(r["walls"]) for r in runs.values())
+            if elapsed() + est > args.budget_s:
+                skipped.append(label)
+                log(f"[{label}] skipped: {elapsed():.0f}s elapsed, about {est:.0f}s needed, "
+                    f"budget {args.budget_s:.0f}s")
+                continue
+        runs[label] = run_variant(label, seq, conf, B, x1, lam1, steps, work, X, blob, dev)
+        torch.cuda.synchronize()
+
+    r64 = runs["fp64"]
+    infos = r64["infos"]
     flops = sum(i["filter_flops"] for i in infos)
     fsec = sum(i["filter_seconds"] for i in infos)
     launches = sum(i["filter_launches"] for i in infos)
     tflops = flops / fsec / 1e12
-    avg_launch = fsec / launches
-    phases = np.sum([i["step_seconds"] for i in infos], axis=0) / args.steps
-    mphases = np.sum([i["step_seconds"] for i in minfos], axis=0) / args.steps
-    phase_names = ["reduction", "lanczos", "filter", "orthonormalize", "rayleigh_ritz",
-                   "residuals", "locking", "back_transform"]
-    mflops = sum(i["filter_flops"] for i in minfos)
-    msec = sum(i["filter_seconds"] for i in minfos)
-    f32_flops = sum(i["filter_flops_fp32"] for i in minfos)
-    f32_sec = sum(i["filter_seconds_fp32"] for i in minfos)
-    eig_diff = [float(np.max(np.abs(a - b) / np.abs(a))) for a, b in zip(lams64, lams32)]
+    wall64 = sum(r64["walls"])
+    phases = np.sum([i["step_seconds"] for i in infos], axis=0) / steps
+    summ = {lab: summarize(lab, r, None if lab == "fp64" else r64["lams"])
+            for lab, r in runs.items()}
     out = {
         "metric": "filter TFLOP/s + s/sequence-step at 1e-10 residual, FP64 vs mixed+learned",
         "value": round(tflops, 3),
         "unit": "TFLOP/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "steps": steps,
+        "warmup": 1,
+        "ms_per_step": round(1e3 * wall64 / steps, 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -477,119 +541,92 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (f"{conf.name}: {'generalized' if B is not None else 'standard'} complex "
-                         f"Hermitian sequence, n={n}, nev={nev}, nex={nex}, tol={conf.tol}, "
-                         f"FP64 filter (complex, 4M split on MFMA)"),
-            "n": n, "nev": nev, "nex": nex, "problems_timed": args.steps,
-            "warm_start": "X0 only" if args.no_lambda0 else "X0 and Lambda0",
+                         f"Hermitian sequence of {conf.length} problems, n={n}, nev={nev}, "
+                         f"nex={nex}, tol {conf.tol}; problem 1 cold (untimed), problems 2-"
+                         f"{steps + 1} timed, each warm-started from the previous solution; "
+                         f"value = FP64 filter (complex, 4M split on MFMA)"),
+            "n": n, "nev": nev, "nex": nex, "problems": conf.length, "problems_timed": steps,
         },
-        "s_per_sequence_step_median": round(statistics.median(walls), 4),
-        "filter_tflops_over_wall": round(flops / elapsed / 1e12, 3),
-        "filter_share_of_step": round(fsec / elapsed, 3),
-        "phase_seconds_per_step": {nm: round(float(v), 4) for nm, v in zip(phase_names, phases)},
-        "iters_per_step": [i["iters"] for i in infos],
-        "rr_eigensolves_refined_dense": [sum(i["rr_refined"] for i in infos),
-                                         sum(i["rr_dense"] for i in infos)],
-        "b_factor_reused_per_step": [i["b_factor_reused"] for i in infos],
         "roofline": {
-            "kernel": "zgemm_kernel<OP_N, OP_N, EPI_CHEB> (Chebyshev filter step)",
             "bound": "mfma",
             "achieved": round(tflops, 3),
             "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(tflops / PEAK_FP64_TFLOPS, 4),
-            "traffic": traffic_entry(tv[0]),
+            "traffic": traffic_entry(n, k, tv[0]),
+            "kernel": "FP64 filter step zgemm_kernel<OP_N,OP_N,EPI_CHEB> / cheb_wide_kernel",
             "tile_variant_full_width": int(tv[0]),
-            "traffic_unit": "GB per full-width step (n=8000, N=480), HBM, from FETCH_SIZE/WRITE_SIZE",
-            "algorithmic_bytes_full_width_gb": 1.208,
-            "avg_launch_us": round(avg_launch * 1e6, 2),
-            "launches": launches,
+            "traffic_note": f"HBM GB of one full-width launch (n={n}, N={k}); algorithmic "
+                            f"{(16 * n * n + 48 * n * k) / 1e9:.3f} GB",
+            "avg_launch_us": round(fsec / launches * 1e6, 1),
         },
-        "mixed": {
-            "precision": "FP32 defect filter where the residuals allow, FP64 QR/RR/residuals",
-            "ms_per_step": round(1e3 * melapsed / args.steps, 3),
-            "s_per_sequence_step_median": round(statistics.median(mwalls), 4),
-            "speedup_vs_fp64_per_step": round(elapsed / melapsed, 3),
-            "filter_effective_tflops": round(mflops / msec / 1e12, 3),
-            "fp32_gemm_tflops": round(f32_flops / f32_sec / 1e12, 3) if f32_sec > 0 else None,
-            "fp32_peak_tflops": 157.3,
-            "fp32_filter_loops_per_step": [i["filter_iters_fp32"] for i in minfos],
-            "iters_per_step": [i["iters"] for i in minfos],
-            "phase_seconds_per_step": {nm: round(float(v), 4) for nm, v in zip(phase_names, mphases)},
-            "max_rel_eig_diff_vs_fp64_per_step": eig_diff,
-        },
+        "s_per_sequence_step_median": round(statistics.median(r64["walls"]), 4),
+        "phase_s_per_step": {nm: round(float(v), 3) for nm, v in zip(PHASES, phases)
+                             if v > 0},
     }
-    precision_text = {
-        0: "FP64 filter",
-        1: "FP32 defect filter where the residuals allow",
-        2: ("FP32 defect filter where the residuals allow; its early steps with BF16-split "
-            "products (3 BF16 MFMA products, FP32 accumulate) where their rounding is damped "
-            "enough"),
-        3: ("FP32 defect filter where the residuals allow; its steps with FP16-split products "
-            "of power-of-two scaled operands (3 FP16 MFMA products, FP32 accumulate) where "
-            "their rounding is damped enough (nearly all)"),
-    }
-    degree_text = {
-        0: "analytic rule (Sec. 3.1.1)",
-        2: "learned (network trained on logs of another sequence; rule fallback)",
-        3: "sequence-calibrated (speeds measured earlier in the sequence; rule floor)",
-    }
-    for label, (linfos, lwalls, llams, lelapsed) in learned_runs.items():
-        lph = np.sum([i["step_seconds"] for i in linfos], axis=0) / args.steps
-        prec, mode = variant_modes[label]
-        out[label] = {
-            "precision": precision_text[prec],
-            "degrees": degree_text[mode],
-            "first_loop_degrees": ("deg0" if prec >= 1 else
-                                   "from the residuals of X0 (one extra product H X0)"),
-            "ms_per_step": round(1e3 * lelapsed / args.steps, 3),
-            "s_per_sequence_step_median": round(statistics.median(lwalls), 4),
-            "speedup_vs_fp64_per_step": round(elapsed / lelapsed, 3),
-            "iters_per_step": [i["iters"] for i in linfos],
-            "rr_eigensolves_refined_dense": [sum(i["rr_refined"] for i in linfos),
-                                             sum(i["rr_dense"] for i in linfos)],
-            "fp32_filter_loops_per_step": [i["filter_iters_fp32"] for i in linfos],
-            "filter_matvecs_per_step": [i["filter_matvecs"] for i in linfos],
-            "learned_cols": sum(i["learned_cols"] for i in linfos),
-            "fallback_cols": sum(i["fallback_cols"] for i in linfos),
-            "learned_raised_cols": sum(i["learned_raised"] for i in linfos),
-            "phase_seconds_per_step": {nm: round(float(v), 4) for nm, v in zip(phase_names, lph)},
-            "max_rel_eig_diff_vs_fp64_per_step": [
-                float(np.max(np.abs(a - b) / np.abs(a))) for a, b in zip(lams64, llams)],
-        }
-        if prec >= 2:
-            w = "bf16" if prec == 2 else "fp16"
-            f16 = sum(i[f"filter_flops_{w}"] for i in linfos)
-            f32 = sum(i["filter_flops_fp32"] for i in linfos)
-            out[label][f"{w}_steps_per_step"] = [i[f"filter_steps_{w}"] for i in linfos]
-            out[label][f"{w}_share_of_defect_flops"] = round(f16 / max(f16 + f32, 1.0), 3)
-            lsec = sum(i["filter_seconds"] for i in linfos)
-            out[label]["filter_effective_tflops"] = round(
-                sum(i["filter_flops"] for i in linfos) / lsec / 1e12, 3)
-    # the metric's comparison: FP64 against the fastest mixed-precision
-    # variant with learned degrees
-    ml = [lab for lab in learned_runs if lab.startswith("mixed") and lab.endswith("+learned")]
-    if ml:
-        best = min(ml, key=lambda lab: out[lab]["ms_per_step"])
-        out["fp64_vs_mixed_learned"] = {
-            "fp64_ms_per_step": out["ms_per_step"],
-            "variant": best,
-            "ms_per_step": out[best]["ms_per_step"],
-            "speedup": out[best]["speedup_vs_fp64_per_step"],
-            "max_rel_eig_diff_vs_fp64": max(out[best]["max_rel_eig_diff_vs_fp64_per_step"]),
-        }
-    out["fp64_filter_matvecs_per_step"] = [i["filter_matvecs"] for i in infos]
-    out["cold_first_problem_untimed"] = cold
-    out["filter_autotune"] = autotune
-    if train_report is not None:
-        out["degree_network"] = train_report
+    if HEADLINE in summ:
+        h = summ[HEADLINE]
+        cmp_ = {"fp64_ms_per_step": out["ms_per_step"],
+                "mixed_learned_ms_per_step": h["ms_per_step"],
+                "speedup": round(out["ms_per_step"] / h["ms_per_step"], 3),
+                "max_rel_eig_diff_vs_fp64": h["max_rel_eig_diff_vs_fp64"],
+                "variant": HEADLINE}
+        if RULE_TWIN in summ:
+            cmp_["rule_ms_per_step"] = summ[RULE_TWIN]["ms_per_step"]
+            cmp_["learned_vs_rule"] = round(summ[RULE_TWIN]["ms_per_step"] / h["ms_per_step"], 3)
+        out["fp64_vs_mixed_learned"] = cmp_
+    out["variants"] = {lab: {kk: v for kk, v in s.items() if kk in
+                             ("ms_per_step", "loops", "filter_matvecs", "filter_ms_per_step",
+                              "max_rel_eig_diff_vs_fp64")} for lab, s in summ.items()}
+    if skipped:
+        out["skipped_for_budget"] = skipped
+    out["cold_problem_1"] = cold
+    if train is not None:
+        out["degree_network"] = train
+    detail = {lab: {"walls_s": [round(w, 4) for w in r["walls"]],
+                    "loops": [i["iters"] for i in r["infos"]],
+                    "fp32_loops": [i["filter_iters_fp32"] for i in r["infos"]],
+                    "fp16_steps": [i["filter_steps_fp16"] for i in r["infos"]],
+                    "filter_matvecs": [i["filter_matvecs"] for i in r["infos"]],
+                    "filter_s": [round(i["filter_seconds"], 4) for i in r["infos"]],
+                    "learned_cols": [i["learned_cols"] for i in r["infos"]],
+                    "fallback_cols": [i["fallback_cols"] for i in r["infos"]],
+                    "rr_refined_dense": [[i["rr_refined"], i["rr_dense"]] for i in r["infos"]],
+                    "phase_s_per_step": {nm: round(float(v), 4) for nm, v in zip(
+                        PHASES, np.sum([i["step_seconds"] for i in r["infos"]], axis=0) / steps)},
+                    **summ[lab]}
+              for lab, r in runs.items()}
+    detail["autotune"] = [{"N": b, "variant": int(v), "tflops": [round(float(x), 2) for x in t]}
+                          for (_, b), v, t in zip(tune_shapes, tv, ttf)]
     if not args.no_cpu_baseline:
-        del problems
-        torch.cuda.empty_cache()
-        log("timing the CPU oracle's filter on a bounded sample")
-        # a bounded sample: about k (8000 / n)^2 columns (all of them at n = 8000)
-        cols = max(16, min(k, int(round(k * (8000.0 / n) ** 2))))
-        out["cpu_baseline"] = cpu_baseline(a1_host, cols, args.cpu_degree)
-    print(json.dumps(out), flush=True)
+        # about 1.2e13 flops of the oracle's filter (10-20 s on a few dozen
+        # host cores), on problem 1's matrix copied to the host
+        cols = int(max(16, min(k, round(1.2e13 / (8.0 * n * n * args.cpu_degree)))))
+        est = 1.2e13 / 0.5e12 + n * n * 16 / 2e9
+        if elapsed() + est > args.budget_s + 40:
+            out["cpu_baseline"] = None
+            del seq, a1, work, X, X1, runs
+            log(f"cpu baseline skipped: {elapsed():.0f}s elapsed")
+        else:
+            a_host = a1.cpu().numpy()
+            del seq, a1, work, X, X1, runs
+            torch.cuda.empty_cache()
+            log(f"timing the CPU oracle's filter on {cols} columns at degree {args.cpu_degree}")
+            cb = cpu_baseline(a_host, cols, args.cpu_degree)
+            # the oracle's filter alone at this rate, for the FP64 step's mat-vecs
+            cb["filter_s_per_step_at_this_rate"] = round(flops / steps / (cb["value"] * 1e12), 1)
+            out["cpu_baseline"] = cb
+    log("detail " + json.dumps(detail))
+    if args.detail_out:
+        with open(args.detail_out, "w") as fh:
+            json.dump({"line": out, "detail": detail}, fh, indent=1)
+    line = json.dumps(out)
+    if len(line) > 4000:
+        log(f"result line is {len(line)} bytes; dropping the per-variant table")
+        out.pop("variants", None)
+        line = json.dumps(out)
+    log(f"total {elapsed():.1f}s")
+    print(line, flush=True)
 
 
 if __name__ == "__main__":

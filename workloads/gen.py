@@ -250,9 +250,8 @@ class Sequence:
         z = self._gauss(ROLE_Q, n, n)
         q = self.be.qr_unitary(z)
         del z
-        self._a = self.be.from_spectrum(q, self.lam)
+        self._a1 = self.be.from_spectrum(q, self.lam)
         del q
-        self._l = 1
         self.B = None
         if conf.generalized:
             m = self._gauss(ROLE_B, n, n)
@@ -269,14 +268,20 @@ class Sequence:
         z = torch.randn((cols, rows), dtype=torch.complex128, device=self.be.device, generator=g)
         return z.transpose(0, 1)   # column-major view, E|z|^2 = 1
 
-    def problems(self):
-        """Yield (l, A^(l)) for l = 1..N; A^(l) is the backend's array."""
-        yield 1, self._a
-        for l in range(1, self.conf.length):
+    def problems(self, count: Optional[int] = None):
+        """Yield (l, A^(l)) for l = 1..min(N, count); A^(l) is the backend's
+        array.  Every call starts again from A^(1) (kept by the object) and
+        redraws the perturbations from their seeds, so the same sequence can
+        be replayed (e.g. once per solver variant) while only A^(1) and the
+        current problem are held."""
+        last = self.conf.length if count is None else min(count, self.conf.length)
+        a = self._a1
+        yield 1, a
+        for l in range(1, last):
             h = self.be.herm_unit(self._gauss(ROLE_PERTURB + l, self.conf.n, self.conf.n))
-            self._a = self.be.axpy(self._a, self.conf.delta(l), h)
+            a = self.be.axpy(a, self.conf.delta(l), h)
             del h
-            yield l + 1, self._a
+            yield l + 1, a
 
 
 def start_block(conf: SequenceConfig) -> np.ndarray:
