@@ -15,4 +15,12 @@ Modules
   chfsi       the ChFSI loop (Alg. 1): bounds, filter, QR, Rayleigh-Ritz,
               residuals, locking, degree optimisation, reduction to
               standard form
+  mlp         the degree network (forward, gradient, Adam), its features,
+              training target and margin, and the learned degree rule
+
+Not here, parity unpinned: the sequence-level degree optimisation the paper
+calls Multiple Optimization (Sec. 3.1.1; the library's degree_mode 3).  The
+paper defers that algorithm to another publication, so no definition exists
+to write an oracle from; the library's form is tested against its own
+definition and its eigenvalues against this oracle.
 """
