@@ -347,6 +347,28 @@ int chfsi_filter(int n, int k, const void* H, int ldh, void* Y, int ldy,
                  void* work, size_t work_bytes, void* stream,
                  double* flops_out, int* launches_out);
 
+/* chfsi_filter without a workspace argument and without any device
+ * allocation, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same operation, arguments, degree order and result as chfsi_filter; the
+ * library keeps the filter's ping-pong blocks, the degrees and the split-K
+ * partial sums in a static device array of CHFSI_NOALLOC_SCRATCH_BYTES per
+ * GPU (held by each GPU the library runs on until the process ends).
+ *   Limit: chfsi_filter_noalloc_need_bytes(n, k) = 2 n k 16 bytes plus the
+ *   degrees, rounded to 256-byte blocks, must not exceed
+ *   CHFSI_NOALLOC_SCRATCH_BYTES (n k up to about 2.09e6), else
+ *   CHFSI_INVALID_ARG before any device work.  The split-K partial sums use
+ *   what is left of the array (fewer splits than chfsi_filter when little is
+ *   left: the same result up to the order of the sums).
+ *   Every call on one GPU shares that GPU's array and leaves its contents
+ *   behind; calls that overlap on one GPU (several host threads or streams)
+ *   race and must be serialised by the caller. */
+#define CHFSI_NOALLOC_SCRATCH_BYTES (64u << 20)
+size_t chfsi_filter_noalloc_need_bytes(int n, int k);
+int chfsi_filter_noalloc(int n, int k, const void* H, int ldh, void* Y, int ldy,
+                         const int* degrees, double c, double e, double gamma, void* stream,
+                         double* flops_out, int* launches_out);
+
 /* Mixed-precision form of chfsi_filter (same result, FP32 GEMMs): filters
  * the Ritz vectors Q (n x k, ascending degrees as in chfsi_filter) given
  * Z = H Q and the Ritz values mu (HOST, k doubles), by running the

@@ -8,7 +8,7 @@ from .binding import (ChfsiError, ChfsiInfo, ChfsiOpts, chfsi_default_opts, chfs
                       chfsi_autotune_filter, chfsi_autotune_reset, chfsi_autotune_set,
                       chfsi_degree_features, chfsi_degrees_sequence, chfsi_degrees_learned, chfsi_mlp_adam,
                       chfsi_mlp_forward, chfsi_mlp_gradient, chfsi_mlp_train,
-                      chfsi_eigh_projected, chfsi_filter, chfsi_filter_defect, chfsi_filter_defect_split, chfsi_split_schedule, chfsi_lanczos_bounds, chfsi_orthonormalize,
+                      chfsi_eigh_projected, chfsi_filter, chfsi_filter_noalloc, chfsi_filter_noalloc_need_bytes, chfsi_filter_defect, chfsi_filter_defect_split, chfsi_split_schedule, chfsi_lanczos_bounds, chfsi_orthonormalize,
                       chfsi_rayleigh_ritz, chfsi_reduce_standard, chfsi_reduce_workspace_bytes,
                       chfsi_solve, chfsi_solve_batch, chfsi_batch_workspace_bytes,
                       chfsi_status_string, chfsi_step_workspace_bytes,

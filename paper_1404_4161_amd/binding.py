@@ -102,6 +102,10 @@ _SIGS = {
     "chfsi_lanczos_bounds": (c_int, [c_int, c_void_p, c_int, c_int, c_ulonglong, c_void_p,
                                      c_size_t, c_void_p, POINTER(c_double), POINTER(c_double),
                                      POINTER(c_double)]),
+    "chfsi_filter_noalloc_need_bytes": (c_size_t, [c_int, c_int]),
+    "chfsi_filter_noalloc": (c_int, [c_int, c_int, c_void_p, c_int, c_void_p, c_int,
+                                     POINTER(c_int), c_double, c_double, c_double, c_void_p,
+                                     POINTER(c_double), POINTER(c_int)]),
     "chfsi_reduce_workspace_bytes": (c_size_t, [c_int]),
     "chfsi_reduce_standard": (c_int, [c_int, c_void_p, c_int, c_void_p, c_int, c_void_p, c_int,
                                       c_void_p, c_int, c_void_p, c_size_t, c_void_p]),
@@ -297,6 +301,24 @@ def chfsi_filter(H, Y, degrees, c, e, gamma, work=None, stream=None):
     _check(lib().chfsi_filter(n, k, _ptr(H), _ld(H), _ptr(Y), _ld(Y), deg, c, e, gamma, _ptr(w),
                               wb, _stream(stream, Y.device), ctypes.byref(fl), ctypes.byref(ln)),
            "chfsi_filter")
+    return fl.value, ln.value
+
+
+def chfsi_filter_noalloc_need_bytes(n, k):
+    return int(lib().chfsi_filter_noalloc_need_bytes(n, k))
+
+
+def chfsi_filter_noalloc(H, Y, degrees, c, e, gamma, stream=None):
+    """chfsi_filter without a workspace (the library's static device
+    scratch); in place on Y; returns (flops, launches)."""
+    n, k = Y.shape
+    deg = (c_int * k)(*[int(x) for x in degrees])
+    fl = c_double(0.0)
+    ln = c_int(0)
+    _check(lib().chfsi_filter_noalloc(n, k, _ptr(H), _ld(H), _ptr(Y), _ld(Y), deg, c, e, gamma,
+                                      _stream(stream, Y.device), ctypes.byref(fl),
+                                      ctypes.byref(ln)),
+           "chfsi_filter_noalloc")
     return fl.value, ln.value
 
 

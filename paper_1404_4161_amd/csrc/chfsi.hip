@@ -2082,7 +2082,46 @@ int validate_solve(int n, int nev, int nex, const void* A, int lda, const void* 
 
 using namespace chfsi;
 
+// Device scratch of chfsi_filter_noalloc: one copy per GPU, held until the
+// process ends.  Host code never uses this name as an address (on the host
+// it is only a stand-in for the symbol): the device address of each GPU's
+// copy comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) char scratch[CHFSI_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of the current GPU's scratch (looked up on the first call
+// on that device, with the device current); status code.
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  CK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return CHFSI_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    CK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return CHFSI_DEVICE_ERROR;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return CHFSI_OK;
+}
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
 extern "C" {
+
+size_t chfsi_filter_noalloc_need_bytes(int n, int k) {
+  if (n < 1 || k < 1) return 0;
+  const size_t nk = (size_t)n * (size_t)k;
+  return 2 * round256(nk * sizeof(zc)) + round256(sizeof(int) * (size_t)k);
+}
 
 int chfsi_default_opts(chfsi_opts* o) {
   if (!o) return CHFSI_INVALID_ARG;
@@ -2289,6 +2328,56 @@ int chfsi_filter(int n, int k, const void* H, int ldh, void* Y, int ldy, const i
                    b.fpart_elems, &fl, &ln));
     CKS(upload_ints(s, b.deg, m));
     CK(gather_parity(s, n, k, b.T1, b.T2, n, (zc*)Y, ldy, b.deg));
+    CK(hipStreamSynchronize(s));
+    if (flops_out) *flops_out = fl;
+    if (launches_out) *launches_out = ln;
+    return CHFSI_OK;
+  } catch (const std::exception& ex) {
+    report_failure(ex.what(), __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
+  } catch (...) {
+    report_failure("unknown exception", __LINE__, -1);
+    return CHFSI_DEVICE_ERROR;
+  }
+}
+
+int chfsi_filter_noalloc(int n, int k, const void* H, int ldh, void* Y, int ldy,
+                         const int* degrees, double c, double e, double gamma, void* stream,
+                         double* flops_out, int* launches_out) {
+  try {
+    if (n < 1 || k < 1 || ldh < n || ldy < n || !degrees || !(e > 0.0) || gamma == c)
+      return CHFSI_INVALID_ARG;
+    if (check_ptr(H) || check_ptr(Y)) return CHFSI_INVALID_ARG;
+    for (int j = 0; j < k; ++j) {
+      if (degrees[j] < 1 || (j > 0 && degrees[j] < degrees[j - 1])) return CHFSI_INVALID_ARG;
+    }
+    const size_t need = chfsi_filter_noalloc_need_bytes(n, k);
+    if (need > (size_t)CHFSI_NOALLOC_SCRATCH_BYTES) return CHFSI_INVALID_ARG;
+    void* base = nullptr;
+    CKS(noalloc_scratch(&base));
+    hipStream_t s = as_stream(stream);
+    // scratch: ping-pong blocks P0, P1 (packed n x k), the degrees, and the
+    // rest for split-K partial sums (up to CHEB_MAX_SPLITS blocks; fewer
+    // splits when less room is left)
+    const size_t nk = (size_t)n * (size_t)k;
+    char* p = (char*)base;
+    zc* P0 = (zc*)p;
+    p += round256(nk * sizeof(zc));
+    zc* P1 = (zc*)p;
+    p += round256(nk * sizeof(zc));
+    int* deg = (int*)p;
+    p += round256(sizeof(int) * (size_t)k);
+    zc* part = (zc*)p;
+    const size_t left = (size_t)CHFSI_NOALLOC_SCRATCH_BYTES - need;
+    const size_t part_elems = std::min(left / sizeof(zc), (size_t)CHEB_MAX_SPLITS * nk);
+    std::vector<int> m(degrees, degrees + k);
+    CK(copy2d(s, n, k, (const zc*)Y, ldy, P0, n));
+    double fl = 0.0;
+    int ln = 0;
+    CKS(filter_dev(s, n, k, (const zc*)H, ldh, P0, P1, n, m, c, e, gamma,
+                   part_elems >= 2 * nk ? part : nullptr, part_elems, &fl, &ln));
+    CKS(upload_ints(s, deg, m));
+    CK(gather_parity(s, n, k, P0, P1, n, (zc*)Y, ldy, deg));
     CK(hipStreamSynchronize(s));
     if (flops_out) *flops_out = fl;
     if (launches_out) *launches_out = ln;
