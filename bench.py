@@ -153,8 +153,9 @@ def kpoints(args):
     (perturbations 1e-2 * 0.5^l).  Step 1 (random starts) is the warm-up;
     steps 2-5 are timed, every problem warm-started from its previous
     solution.  Variants: one chfsi_solve_batch call per step (grouped filter
-    launches; FP64, FP64 with graph capture, mixed precision) against 32
-    chfsi_solve calls per step (FP64).  Prints one JSON line."""
+    launches: FP64, FP64 with graph capture, mixed precision with the defect
+    filters grouped or each on its problem's stream) against 32 chfsi_solve
+    calls per step (FP64 and mixed).  Prints one JSON line."""
     import torch
     import paper_1404_4161_amd as ch
     from workloads import gen
@@ -169,7 +170,7 @@ def kpoints(args):
     log(f"autotune of {len(shapes)} shapes in {time.perf_counter() - t0:.1f}s: "
         f"variant 1 chosen for {int(tv.sum())}")
 
-    def run(label, precision, batched, graph, serial=False):
+    def run(label, precision, batched, graph, serial=False, own_defect=False):
         t0 = time.perf_counter()
         seqs = [gen.Sequence(c, kind="torch", device=dev, draw="device") for c in confs]
         gens = [s_.problems() for s_ in seqs]
@@ -193,7 +194,7 @@ def kpoints(args):
                     st, lams, _, infos, sts = ch.chfsi_solve_batch(
                         As, Bs, [c.nev for c in confs], [c.nex for c in confs], 1e-10,
                         X0s=x0s, Lambda0s=lam0s, opts=o, Xs=Xs, works=works, stream=stream,
-                        graph=graph, serial=serial)
+                        graph=graph, serial=serial, own_defect=own_defect)
                     if st != 0:
                         raise RuntimeError(f"chfsi_solve_batch status {st} {sts}")
                 else:
@@ -239,6 +240,9 @@ def kpoints(args):
                 "batched-mixed": ("batched mixed", 1, True, False),
                 "batched-mixed-bf16": ("batched mixed bf16", 2, True, False),
                 "batched-mixed-fp16": ("batched mixed fp16", 3, True, False),
+                "batched-mixed-fp16-own": ("batched mixed fp16 own", 3, True, False, False,
+                                           True),
+                "sequential-mixed-fp16": ("sequential mixed fp16", 3, False, False),
                 "batched-fp64-serial": ("batched fp64 serial", 0, True, False, True)}
     chosen = args.kp_variants.split(",")
     for key in chosen:
@@ -259,6 +263,10 @@ def kpoints(args):
         "speedup_batched_vs_sequential_fp64": (round(
             results["sequential fp64"]["s_per_step"] / results["batched fp64"]["s_per_step"], 3)
             if {"sequential fp64", "batched fp64"} <= set(results) else None),
+        "speedup_batched_vs_sequential_mixed_fp16": (round(
+            results["sequential mixed fp16"]["s_per_step"]
+            / results["batched mixed fp16"]["s_per_step"], 3)
+            if {"sequential mixed fp16", "batched mixed fp16"} <= set(results) else None),
         "variants": results,
     }
     print(json.dumps(out), flush=True)
@@ -410,9 +418,8 @@ def main():
     ap.add_argument("--degree", type=int, default=4)
     ap.add_argument("--kp-count", type=int, default=32,
                     help="k-point workload: number of problems (32 in the full workload)")
-    ap.add_argument("--kp-variants", default="batched-fp64,batched-fp64-graph,sequential-fp64,"
-                                             "batched-mixed,batched-mixed-bf16,"
-                                             "batched-mixed-fp16")
+    ap.add_argument("--kp-variants", default="batched-fp64,sequential-fp64,batched-mixed-fp16,"
+                                             "batched-mixed-fp16-own,sequential-mixed-fp16")
     args = ap.parse_args()
     t_start = time.perf_counter()
     if args.gpus != 1:

@@ -283,10 +283,13 @@ int chfsi_solve(int n, int nev, int nex,
  * sequence): `count` problems, each with the arguments of chfsi_solve given
  * by index q (arrays of count entries), run their outer loops in lockstep.
  * The problems form two groups that alternate on `stream`; every loop's
- * FP64 filters of a group share one launch per recurrence step (a grouped
- * MFMA kernel over all its problems' tiles) on `stream`; the
- * per-problem phases (reduction, Lanczos, QR, Rayleigh-Ritz, FP32 defect
- * filters) run on up to 8 internal streams, each driven by a host thread of
+ * filters of a group share grouped launches on `stream`: the FP64 filters
+ * one launch per recurrence step (a grouped MFMA kernel over all its
+ * problems' tiles), the mixed-precision defect filters one launch per
+ * recurrence step and step form (with one grouped column-split launch
+ * before a split step); the per-problem phases (reduction, Lanczos, QR,
+ * Rayleigh-Ritz, the defect filters' set-up and assembly) run on up to 8
+ * internal streams, each driven by a host thread of
  * the library with its own rocSOLVER handle, so that different problems'
  * phases overlap.  Event dependencies order everything after the work
  * already queued on `stream`, and the call returns when all is done.  Each
@@ -298,7 +301,7 @@ int chfsi_solve(int n, int nev, int nex,
  *   work[q], work_bytes[q]  per-problem workspaces (chfsi_workspace_bytes),
  *               pairwise distinct; B's factor is reused per workspace.
  *   batch_work  device, >= chfsi_batch_workspace_bytes(count, opts): the
- *               launch arguments of the grouped filter.
+ *               launch arguments of the grouped filters.
  *   opts        shared by all problems; log_capacity must be 0 and
  *               seq_rates NULL (degree_mode 3 is not available here).
  *   flags       bit 0: capture each loop's grouped filter launches as one
@@ -306,6 +309,10 @@ int chfsi_solve(int n, int nev, int nex,
  *               bit 1: serial -- one internal stream driven by the calling
  *               thread (no worker threads; the per-problem phases of
  *               different problems do not overlap).
+ *               bit 2: run each problem's mixed-precision defect filter on
+ *               its own stream, one problem at a time (by default the
+ *               defect filters of a group share, per recurrence step, one
+ *               launch per step form: FP16-split, BF16-split or FP32).
  *   info        NULL or count statistics records.
  *   status      HOST, count ints out: each problem's status.
  * Returns CHFSI_OK when every problem converged, else the first error

@@ -579,7 +579,8 @@ def chfsi_batch_workspace_bytes(count, opts=None):
 
 
 def chfsi_solve_batch(As, Bs, nevs, nexs, tol, X0s=None, opts=None, Lambda0s=None, Xs=None,
-                      works=None, stream=None, graph=False, raise_on_error=True, serial=False):
+                      works=None, stream=None, graph=False, raise_on_error=True, serial=False,
+                      own_defect=False):
     """Solve len(As) independent problems in lockstep (grouped filter
     launches).  Bs / X0s / Lambda0s: lists (entries may be None) or None.
     Returns (status, [Lambda numpy], [X tensors], [info dicts], [statuses])."""
@@ -629,7 +630,7 @@ def chfsi_solve_batch(As, Bs, nevs, nexs, tol, X0s=None, opts=None, Lambda0s=Non
         P(*[a.data_ptr() for a in As]), I(*[_ld(a) for a in As]), b_ptrs, b_lds, float(tol),
         x0_ptrs, x0_lds, lam0, lam_ptrs, P(*[x.data_ptr() for x in Xs]), I(*[_ld(x) for x in Xs]),
         P(*[w.data_ptr() for w in works]), (c_size_t * count)(*wbs), _ptr(bwork), bw,
-        ctypes.byref(o), (1 if graph else 0) | (2 if serial else 0), _stream(stream, dev), infos,
+        ctypes.byref(o), (1 if graph else 0) | (2 if serial else 0) | (4 if own_defect else 0), _stream(stream, dev), infos,
         sts)
     if raise_on_error and st not in (CHFSI_OK, CHFSI_NO_CONVERGENCE):
         raise ChfsiError(st, "chfsi_solve_batch")

@@ -41,6 +41,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstring>
 
 namespace chfsi {
 
@@ -165,13 +166,13 @@ struct SplitTile {
 };
 
 template <int WGM, int WGN, int TI, int TJ, bool H16>
-__device__ __forceinline__ void split_tile_body(const SplitArgs& g, char* lds) {
+__device__ __forceinline__ void split_tile_body(const SplitArgs& g, char* lds, int bid) {
   using W = Words<H16>;
   typedef typename W::V V;
   using T = SplitTile<WGM, WGN, TI, TJ>;
   constexpr int BM = T::BM, BN = T::BN, NTH = T::NTH, CH = T::CHUNKS;
   // virtual tile rows (split, tile row) interleaved over the XCDs
-  const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
+  const int xcd = bid % NXCD, slot = bid / NXCD;
   const int vrows = g.splits * g.tiles_m;
   const int rows_x = (vrows - xcd + NXCD - 1) / NXCD;
   const int ri = slot / g.tiles_n;
@@ -342,22 +343,53 @@ using TileWide = SplitTile<4, 2, 2, 4>;    // 128 x 128, 512 threads
 
 __global__ void __launch_bounds__(TileSmall::NTH, 2) defect_gemm_split(SplitArgs g) {
   __shared__ __attribute__((aligned(16))) char lds[2 * TileSmall::LDS_STAGE];
-  split_tile_body<2, 2, 2, 2, false>(g, lds);
+  split_tile_body<2, 2, 2, 2, false>(g, lds, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(TileWide::NTH, 1) defect_gemm_split_wide(SplitArgs g) {
   __shared__ __attribute__((aligned(16))) char lds[2 * TileWide::LDS_STAGE];
-  split_tile_body<4, 2, 2, 4, false>(g, lds);
+  split_tile_body<4, 2, 2, 4, false>(g, lds, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(TileSmall::NTH, 2) defect_gemm_h16(SplitArgs g) {
   __shared__ __attribute__((aligned(16))) char lds[2 * TileSmall::LDS_STAGE];
-  split_tile_body<2, 2, 2, 2, true>(g, lds);
+  split_tile_body<2, 2, 2, 2, true>(g, lds, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(TileWide::NTH, 1) defect_gemm_h16_wide(SplitArgs g) {
   __shared__ __attribute__((aligned(16))) char lds[2 * TileWide::LDS_STAGE];
-  split_tile_body<4, 2, 2, 4, true>(g, lds);
+  split_tile_body<4, 2, 2, 4, true>(g, lds, blockIdx.x);
+}
+
+// Grouped launches (batches of independent problems): problem p of the
+// list owns the workgroups [slot_begin[p], slot_begin[p+1]), a multiple of
+// 8, so that the XCD interleaving inside each range is that of a launch of
+// its own; a binary search over slot_begin maps a workgroup to its problem.
+__device__ __forceinline__ int group_of(const int* slot_begin, int count, int b) {
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (slot_begin[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <bool H16>
+__global__ void __launch_bounds__(TileSmall::NTH, 2) defect_group_small(const SplitArgs* list,
+                                                                      const int* slot_begin,
+                                                                      int count) {
+  __shared__ __attribute__((aligned(16))) char lds[2 * TileSmall::LDS_STAGE];
+  const int p = group_of(slot_begin, count, blockIdx.x);
+  split_tile_body<2, 2, 2, 2, H16>(list[p], lds, blockIdx.x - slot_begin[p]);
+}
+
+template <bool H16>
+__global__ void __launch_bounds__(TileWide::NTH, 1) defect_group_wide(const SplitArgs* list,
+                                                                    const int* slot_begin,
+                                                                    int count) {
+  __shared__ __attribute__((aligned(16))) char lds[2 * TileWide::LDS_STAGE];
+  const int p = group_of(slot_begin, count, blockIdx.x);
+  split_tile_body<4, 2, 2, 4, H16>(list[p], lds, blockIdx.x - slot_begin[p]);
 }
 
 // Power-of-two scale that brings the largest magnitude m into [2^14, 2^15)
@@ -369,10 +401,9 @@ __device__ __forceinline__ int h16_scale_exp(float m) {
 
 // FP16 split panel of FP32 columns, each scaled by its own power of two:
 // one workgroup (256 threads) per column; inv[j] receives 1 / scale.
-__global__ void __launch_bounds__(256) split_cols_h16(int K, int Kp, const cf* E, long lde,
-                                                      char* S, long srow, float* inv) {
-  __shared__ float red[256];
-  const int j = blockIdx.x, t = threadIdx.x;
+__device__ __forceinline__ void split_col_h16_body(int K, int Kp, const cf* E, long lde, char* S,
+                                                   long srow, float* inv, int j, float* red) {
+  const int t = threadIdx.x;
   const cf* col = E + (long)j * lde;
   float m = 0.f;
   for (int r = t; r < K; r += 256) {
@@ -402,6 +433,49 @@ __global__ void __launch_bounds__(256) split_cols_h16(int K, int Kp, const cf* E
     for (int q = 0; q < 4; ++q) dst[q] = pl[q];
   }
   if (t == 0) inv[j] = ldexpf(1.f, -ex);
+}
+
+__global__ void __launch_bounds__(256) split_cols_h16(int K, int Kp, const cf* E, long lde,
+                                                      char* S, long srow, float* inv) {
+  __shared__ float red[256];
+  split_col_h16_body(K, Kp, E, lde, S, srow, inv, blockIdx.x, red);
+}
+
+// Per-column split panels of several problems' windows in one launch: one
+// workgroup per column, problem p owning the columns [col_begin[p],
+// col_begin[p+1]).  FP16 words of scaled values (with inv) or BF16 words.
+struct ColSplitArgs {
+  int K, Kp;
+  const cf* E; long lde;
+  char* S; long srow;
+  float* inv;
+};
+
+template <bool H16>
+__global__ void __launch_bounds__(256) split_cols_group(const ColSplitArgs* list,
+                                                        const int* col_begin, int count) {
+  __shared__ float red[256];
+  const int p = group_of(col_begin, count, blockIdx.x);
+  const ColSplitArgs& a = list[p];
+  const int j = blockIdx.x - col_begin[p];
+  if constexpr (H16) {
+    split_col_h16_body(a.K, a.Kp, a.E, a.lde, a.S, a.srow, a.inv, j, red);
+  } else {
+    const cf* col = a.E + (long)j * a.lde;
+    for (int grp = threadIdx.x; grp < a.Kp / 8; grp += 256) {
+      cf v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = grp * 8 + i;
+        v[i] = k < a.K ? col[k] : cf{0.f, 0.f};
+      }
+      uint4 pl[4];
+      split8(v, pl);
+      uint4* dst = (uint4*)(a.S + j * a.srow + (long)grp * GROUP_B);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) dst[q] = pl[q];
+    }
+  }
 }
 
 // Largest |re|, |im| of count complex64 values: one partial per workgroup.
@@ -576,6 +650,76 @@ int defect_step_split(hipStream_t s, int n, int N, const void* Hs, const void* E
   g.tiles_n = (N + TileSmall::BN - 1) / TileSmall::BN;
   const int grid = ((g.tiles_m + NXCD - 1) / NXCD) * g.tiles_n * NXCD;
   hipLaunchKernelGGL(defect_gemm_split, dim3(grid), dim3(TileSmall::NTH), 0, s, g);
+  return (int)hipGetLastError();
+}
+
+int split_wide_min_cols() { return SPLIT_WIDE_MIN_N; }
+
+size_t split_group_arg_bytes() { return sizeof(SplitArgs); }
+size_t colsplit_group_arg_bytes() { return sizeof(ColSplitArgs); }
+
+int split_group_fill(bool h16, bool wide, int n, int N, const void* Hs, float inv_h,
+                     const void* Es, const float* inv_e, const void* Ecur, const void* Eold,
+                     void* Eout, const void* R32, const float* cr, float shift, float sa,
+                     float sb, void* Es_next, void* out) {
+  SplitArgs g = {};
+  g.M = n; g.N = N; g.Kp = split_kp(n);
+  g.As = (const char*)Hs; g.a_row = (long)g.Kp * 8;
+  g.Bs = (const char*)Es; g.b_row = (long)g.Kp * 8;
+  g.Ecur = (const cf*)Ecur; g.Eold = (const cf*)Eold; g.Eout = (cf*)Eout; g.lde = n;
+  g.R = (const cf*)R32; g.ldr = n; g.cr = cr;
+  g.shift = shift; g.sa = sa; g.sb = sb;
+  g.Bnext = h16 ? nullptr : (char*)Es_next;
+  g.inv_a = inv_h; g.inv_b = inv_e;
+  g.splits = 1;
+  g.kstages = g.Kp / SBK;
+  const int bm = wide ? TileWide::BM : TileSmall::BM, bn = wide ? TileWide::BN : TileSmall::BN;
+  g.tiles_m = (n + bm - 1) / bm;
+  g.tiles_n = (N + bn - 1) / bn;
+  std::memcpy(out, &g, sizeof(g));
+  return ((g.tiles_m + NXCD - 1) / NXCD) * g.tiles_n * NXCD;
+}
+
+int split_group_launch(hipStream_t s, bool h16, bool wide, const void* dargs, const int* dslots,
+                       int count, int total) {
+  if (count <= 0 || total <= 0) return 0;
+  const SplitArgs* l = (const SplitArgs*)dargs;
+  if (wide) {
+    if (h16)
+      hipLaunchKernelGGL(defect_group_wide<true>, dim3(total), dim3(TileWide::NTH), 0, s, l,
+                         dslots, count);
+    else
+      hipLaunchKernelGGL(defect_group_wide<false>, dim3(total), dim3(TileWide::NTH), 0, s, l,
+                         dslots, count);
+  } else {
+    if (h16)
+      hipLaunchKernelGGL(defect_group_small<true>, dim3(total), dim3(TileSmall::NTH), 0, s, l,
+                         dslots, count);
+    else
+      hipLaunchKernelGGL(defect_group_small<false>, dim3(total), dim3(TileSmall::NTH), 0, s, l,
+                         dslots, count);
+  }
+  return (int)hipGetLastError();
+}
+
+int colsplit_group_fill(int K, const void* E, long lde, void* S, float* inv, void* out) {
+  ColSplitArgs a = {};
+  a.K = K; a.Kp = split_kp(K);
+  a.E = (const cf*)E; a.lde = lde;
+  a.S = (char*)S; a.srow = (long)a.Kp * 8;
+  a.inv = inv;
+  std::memcpy(out, &a, sizeof(a));
+  return 0;
+}
+
+int colsplit_group_launch(hipStream_t s, bool h16, const void* dargs, const int* dcols, int count,
+                          int total_cols) {
+  if (count <= 0 || total_cols <= 0) return 0;
+  const ColSplitArgs* l = (const ColSplitArgs*)dargs;
+  if (h16)
+    hipLaunchKernelGGL(split_cols_group<true>, dim3(total_cols), dim3(256), 0, s, l, dcols, count);
+  else
+    hipLaunchKernelGGL(split_cols_group<false>, dim3(total_cols), dim3(256), 0, s, l, dcols, count);
   return (int)hipGetLastError();
 }
 

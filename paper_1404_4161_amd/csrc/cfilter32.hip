@@ -24,6 +24,7 @@
 #include <atomic>
 
 #include <algorithm>
+#include <cstring>
 
 namespace chfsi {
 
@@ -55,10 +56,10 @@ struct DefArgs {
 };
 
 template <int PARTIAL>
-__global__ void __launch_bounds__(NT, 4) defect_gemm(DefArgs g) {
+__device__ __forceinline__ void defect_gemm_body(const DefArgs& g, int bid) {
   __shared__ cf As[2][BK][PA];
   __shared__ cf Bs[2][BK][PB];
-  const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD;
+  const int xcd = bid % NXCD, slot = bid / NXCD;
   const int vrows = g.splits * g.tiles_m;
   const int rows_x = (vrows - xcd + NXCD - 1) / NXCD;
   const int ri = slot / g.tiles_n;
@@ -170,6 +171,26 @@ __global__ void __launch_bounds__(NT, 4) defect_gemm(DefArgs g) {
           g.Eout[row + (long)col * g.lde] = out;
         }
       }
+}
+
+template <int PARTIAL>
+__global__ void __launch_bounds__(NT, 4) defect_gemm(DefArgs g) {
+  defect_gemm_body<PARTIAL>(g, blockIdx.x);
+}
+
+// Grouped form (batches of independent problems): problem p of the list
+// owns the workgroups [slot_begin[p], slot_begin[p+1]), a multiple of 8,
+// so that the XCD interleaving inside each range is that of a launch of its
+// own; no split-K.
+__global__ void __launch_bounds__(NT, 4) defect_gemm_group(const DefArgs* list,
+                                                          const int* slot_begin, int count) {
+  int lo = 0, hi = count;
+  const int b = blockIdx.x;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (slot_begin[mid] <= b) lo = mid; else hi = mid;
+  }
+  defect_gemm_body<0>(list[lo], b - slot_begin[lo]);
 }
 
 // Wide defect step for unsplit launches of wide windows: 128 x 128 output
@@ -403,6 +424,33 @@ int defect_reduce_launch(hipStream_t s, int M, int N, int splits, const void* pa
   hipLaunchKernelGGL(defect_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, M, N,
                      splits, (const cf*)part, (const cf*)Ecur, (const cf*)Eold, (cf*)Eout, lde,
                      (const cf*)R, ldr, cr, shift, sa, sb);
+  return (int)hipGetLastError();
+}
+
+size_t defect_group_arg_bytes() { return sizeof(DefArgs); }
+
+int defect_group_fill(int n, int N, const void* H32, const void* Ecur, const void* Eold,
+                      void* Eout, const void* R32, const float* cr, float shift, float sa,
+                      float sb, void* out) {
+  DefArgs g = {};
+  g.M = n; g.N = N; g.K = n;
+  g.A = (const cf*)H32; g.lda = n;
+  g.Ecur = (const cf*)Ecur; g.Eold = (const cf*)Eold; g.Eout = (cf*)Eout; g.lde = n;
+  g.R = (const cf*)R32; g.ldr = n; g.cr = cr;
+  g.shift = shift; g.sa = sa; g.sb = sb;
+  g.tiles_m = (n + BM - 1) / BM;
+  g.tiles_n = (N + BN - 1) / BN;
+  g.splits = 1;
+  g.kchunk = ((n + BK - 1) / BK) * BK;
+  std::memcpy(out, &g, sizeof(g));
+  return ((g.tiles_m + NXCD - 1) / NXCD) * g.tiles_n * NXCD;
+}
+
+int defect_group_launch(hipStream_t s, const void* dargs, const int* dslots, int count,
+                        int total) {
+  if (count <= 0 || total <= 0) return 0;
+  hipLaunchKernelGGL(defect_gemm_group, dim3(total), dim3(NT), 0, s, (const DefArgs*)dargs,
+                     dslots, count);
   return (int)hipGetLastError();
 }
 

@@ -602,12 +602,28 @@ struct SplitSteps {
   int steps_bf16 = 0, steps_fp16 = 0;
 };
 
-// flops32 receives the algorithmic flops of the FP32 steps; sp (or null)
-// selects split forms for some steps and counts them.
-int defect_filter_dev(hipStream_t s, int n, int k, const void* H32, const zc* Q, const zc* Z,
-                      long ld, const std::vector<double>& mu, const std::vector<int>& order,
-                      const std::vector<int>& m, double c, double e, double gamma, zc* Qs, zc* Y,
-                      StepBufs& b, double* flops32, int* launches, SplitSteps* sp = nullptr) {
+// Host plan of one defect filter: the sigmas of the recurrence, and for
+// every step i = 1 .. mmax - 1 (E_i -> E_{i+1}) the first column of its
+// window and its form (0 FP32, 1 BF16 split, 2 FP16 split).
+struct DefectPlan {
+  int n = 0, k = 0, mmax = 0;
+  double c = 0.0, e = 0.0;
+  std::vector<double> sig;
+  std::vector<int> first;
+  std::vector<char> kind;
+};
+
+// The part of the defect filter before its steps: the coefficient tables
+// (uploaded), R32 / E0 / E1 / Qs (defect_setup) and the plan.
+int defect_prepare(hipStream_t s, int n, int k, const zc* Q, const zc* Z, long ld,
+                   const std::vector<double>& mu, const std::vector<int>& order,
+                   const std::vector<int>& m, double c, double e, double gamma, zc* Qs,
+                   StepBufs& b, const SplitSteps* sp, DefectPlan& plan) {
+  plan = DefectPlan();
+  plan.n = n;
+  plan.k = k;
+  plan.c = c;
+  plan.e = e;
   if (k <= 0) return CHFSI_OK;
   const int mmax = m[k - 1];
   if (mmax > CR_ROWS) return CHFSI_INVALID_ARG;
@@ -637,32 +653,62 @@ int defect_filter_dev(hipStream_t s, int n, int k, const void* H32, const zc* Q,
   CKS(upload(s, b.pm, pm));
   CK(defect_setup_launch(s, n, k, Q, Z, ld, b.mu, b.perm, Qs, b.R32, b.E0, b.E1,
                          (float)(sig1 / e)));
+  plan.mmax = mmax;
+  plan.sig = sig;
+  plan.first.assign(mmax + 1, 0);
+  plan.kind.assign(mmax + 1, 0);
   int first = 0;
   while (first < k && m[first] <= 1) ++first;
+  for (int i = 1; i < mmax; ++i) {
+    plan.first[i] = first;
+    int kd = 0;
+    if (sp && sp->sched && i < (int)sp->sched->size()) {
+      const int v = (*sp->sched)[i];
+      if (v == 1 && sp->Hs) kd = 1;
+      if (v == 2 && sp->Hh) kd = 2;
+    }
+    plan.kind[i] = (char)kd;
+    while (first < k && m[first] <= i + 1) ++first;
+  }
+  return CHFSI_OK;
+}
+
+// Scalars of step i of a planned defect filter.
+struct DefectStepScalars {
+  float shift, sa, sb;
+};
+DefectStepScalars defect_scalars(const DefectPlan& p, int i) {
+  return {(float)p.c, (float)(2.0 * p.sig[i + 1] / p.e), (float)(p.sig[i + 1] * p.sig[i])};
+}
+
+// flops32 receives the algorithmic flops of the FP32 steps; sp (or null)
+// selects split forms for some steps and counts them.
+int defect_filter_dev(hipStream_t s, int n, int k, const void* H32, const zc* Q, const zc* Z,
+                      long ld, const std::vector<double>& mu, const std::vector<int>& order,
+                      const std::vector<int>& m, double c, double e, double gamma, zc* Qs, zc* Y,
+                      StepBufs& b, double* flops32, int* launches, SplitSteps* sp = nullptr) {
+  if (k <= 0) return CHFSI_OK;
+  DefectPlan plan;
+  CKS(defect_prepare(s, n, k, Q, Z, ld, mu, order, m, c, e, gamma, Qs, b, sp, plan));
+  const int mmax = plan.mmax;
   const size_t c64 = 8;   // bytes per complex64
   const size_t srow = (size_t)split_kp(n) * 8;   // bytes per split-panel row
-  auto kind = [&](int i) -> int {
-    if (!sp || !sp->sched || i >= (int)sp->sched->size()) return 0;
-    const int v = (*sp->sched)[i];
-    if (v == 1 && sp->Hs) return 1;
-    if (v == 2 && sp->Hh) return 2;
-    return 0;
-  };
   bool split_ready = false;   // the split panel of E_i holds the window
   for (int i = 1; i < mmax; ++i) {
+    const int first = plan.first[i];
     const char* cur = (const char*)((i & 1) ? b.E1 : b.E0);
     char* old = (char*)((i & 1) ? b.E0 : b.E1);
     const size_t off = (size_t)first * n * c64;
     const int cols = k - first;
-    const float shift = (float)c, sa = (float)(2.0 * sig[i + 1] / e);
-    const float sbeta = (float)(sig[i + 1] * sig[i]);
+    const DefectStepScalars sc = defect_scalars(plan, i);
+    const float shift = sc.shift, sa = sc.sa, sbeta = sc.sb;
     const float* cri = b.crtab + (size_t)i * k + first;
-    const int kd = kind(i);
+    const int kd = plan.kind[i];
     if (kd == 1) {
       char* scur = (char*)((i & 1) ? b.S1 : b.S0) + first * srow;
       char* snext = (char*)((i & 1) ? b.S0 : b.S1) + first * srow;
       if (!split_ready) CK(cols_to_split(s, n, cols, cur + off, n, scur));
-      const bool next16 = kind(i + 1) == 1 && i + 1 < mmax;
+      const bool next16 = i + 1 < mmax && plan.kind[i + 1] == 1;
       CK(defect_step_split(s, n, cols, sp->Hs, scur, cur + off, old + off, old + off,
                            (const char*)b.R32 + off, cri, shift, sa, sbeta,
                            next16 ? snext : nullptr));
@@ -685,7 +731,6 @@ int defect_filter_dev(hipStream_t s, int n, int k, const void* H32, const zc* Q,
       *flops32 += 8.0 * (double)n * n * cols;
     }
     *launches += 1;
-    while (first < k && m[first] <= i + 1) ++first;
   }
   CK(defect_assemble_launch(s, n, k, Qs, ld, b.E0, b.E1, b.deg, b.pm, Y, ld));
   return CHFSI_OK;
@@ -1132,6 +1177,10 @@ struct Solve {
   bool have_res = false;   // residuals of the current block known
   hipEvent_t fe0 = nullptr, fe1 = nullptr;
   bool done = false;
+  // batch: this loop's defect filter runs in its group's launches (prepared
+  // on this problem's stream; end_loop assembles the filtered block)
+  DefectPlan dplan;
+  bool grouped_defect = false;
 
   // the current loop
   int ka = 0, nw_loop = 0;
@@ -1485,10 +1534,44 @@ struct Solve {
     return CHFSI_OK;
   }
 
+  // Batch: the defect filter's preparation on this problem's stream (tables,
+  // residual block, E_0, E_1); its steps run in the group's launches.
+  int defect_prepare_own() {
+    StepBufs& sb = b.st;
+    tm.begin(2);
+    std::vector<char> sched;
+    SplitSteps sp;
+    if (o.precision >= 2) {
+      const bool h16 = o.precision == 3;
+      sched = split_step_schedule(nev - nl, mu, res,
+                                  std::vector<int>(deg.begin(), deg.begin() + ka), c, e, tol,
+                                  norm_h, h16 ? FP16_SPLIT_EPS : BF16_SPLIT_EPS, h16 ? 2 : 1);
+      sp.Hs = b.Hs;
+      sp.Hh = b.Hh;
+      sp.inv_h = b.inv_hh;
+      sp.sched = &sched;
+    }
+    CKS(defect_prepare(s, n, ka, b.QA, b.ZA, ld,
+                       std::vector<double>(mu.begin(), mu.begin() + ka), order, msort, c, e,
+                       gamma, b.P0, sb, &sp, dplan));
+    tm.end();
+    grouped_defect = true;
+    iters32 += 1;
+    for (int j = 0; j < ka; ++j) filter_flops += 8.0 * (double)n * n * msort[j];
+    return CHFSI_OK;
+  }
+
   // End of an outer loop: QR, Rayleigh-Ritz, residuals, log, locking and
   // the next loop's degrees.  Sets done on convergence.
   int end_loop() {
     StepBufs& sb = b.st;
+    if (grouped_defect) {
+      // Y = Qs diag(p_m(mu)) + E_m of the grouped defect filter
+      tm.begin(2);
+      CK(defect_assemble_launch(s, n, ka, b.P0, ld, sb.E0, sb.E1, sb.deg, sb.pm, b.TMP, ld));
+      tm.end();
+      grouped_defect = false;
+    }
     for (int j = 0; j < ka; ++j) filter_mv += msort[j];
     matvecs += std::accumulate(msort.begin(), msort.end(), 0LL);
     if (!use32) {
@@ -1832,21 +1915,226 @@ struct FilterGroup {
   }
 };
 
+// The mixed-precision defect filters of a group's problems in grouped
+// launches: per recurrence step one launch per form present at that step
+// (FP16-split, BF16-split, FP32) over all those problems' windows, each
+// split form preceded by one launch that splits the problems' E_i columns
+// (where the previous step did not leave the split).  The problems'
+// preparation (tables, residual blocks) and assembly run on their own
+// streams; every launch argument of a loop is built on the host and
+// uploaded once.  No split-K (the problems together fill the GPU).
+struct DefectGroup {
+  char* dargs = nullptr;   // device argument arrays (batch workspace)
+  int* dslots = nullptr;
+  char* hargs = nullptr;   // pinned staging
+  int* hslots = nullptr;
+  size_t cap_bytes = 0, cap_slots = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::vector<Solve*> jobs;
+  std::vector<double> fl;
+  bool pending = false;
+  // one launch: form (0 FP32 step, 1 BF16 step, 2 FP16 step, 3 BF16 column
+  // split, 4 FP16 column split), tile, argument and slot offsets, size
+  struct Launch {
+    int form;
+    bool wide;
+    size_t arg_off, slot_off;
+    int count, total;
+  };
+  std::vector<Launch> plan;
+
+  ~DefectGroup() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (hargs) (void)hipHostFree(hargs);
+    if (hslots) (void)hipHostFree(hslots);
+  }
+
+  int init(char* da, int* ds, size_t cb, size_t cs) {
+    dargs = da;
+    dslots = ds;
+    cap_bytes = cb;
+    cap_slots = cs;
+    CK(hipHostMalloc((void**)&hargs, std::max<size_t>(cb, 1)));
+    CK(hipHostMalloc((void**)&hslots, sizeof(int) * std::max<size_t>(cs, 1)));
+    CK(hipEventCreate(&e0));
+    CK(hipEventCreate(&e1));
+    return CHFSI_OK;
+  }
+
+  int launch(hipStream_t s, const std::vector<Solve*>& js) {
+    jobs = js;
+    plan.clear();
+    const int count = (int)jobs.size();
+    fl.assign(count, 0.0);
+    int steps = 0;
+    for (Solve* j : jobs) steps = std::max(steps, j->dplan.mmax);
+    const size_t arg_sz[5] = {defect_group_arg_bytes(), split_group_arg_bytes(),
+                              split_group_arg_bytes(), colsplit_group_arg_bytes(),
+                              colsplit_group_arg_bytes()};
+    size_t ab = 0, ns = 0;
+    std::vector<char> ready(count, 0);   // split panel of E_i holds the window (BF16)
+    const int wide_min = split_wide_min_cols();
+    for (int i = 1; i < steps; ++i) {
+      // the step's entries per form, in the order they are launched
+      struct Ent {
+        int q, cols, first;
+        bool next;
+      };
+      std::vector<Ent> by[5];
+      for (int q = 0; q < count; ++q) {
+        const DefectPlan& p = jobs[q]->dplan;
+        if (i >= p.mmax) continue;
+        const int first = p.first[i], cols = p.k - first;
+        const int kd = p.kind[i];
+        if (kd == 2) {
+          by[4].push_back({q, cols, first, false});
+          by[2].push_back({q, cols, first, false});
+          ready[q] = 0;
+        } else if (kd == 1) {
+          const bool next = i + 1 < p.mmax && p.kind[i + 1] == 1;
+          if (!ready[q]) by[3].push_back({q, cols, first, false});
+          by[1].push_back({q, cols, first, next});
+          ready[q] = next;
+        } else {
+          by[0].push_back({q, cols, first, false});
+          ready[q] = 0;
+        }
+      }
+      const int order[5] = {4, 3, 2, 1, 0};
+      for (int f : order) {
+        if (by[f].empty()) continue;
+        Launch L = {};
+        L.form = f;
+        ab = (ab + 255) / 256 * 256;
+        L.arg_off = ab;
+        L.slot_off = ns;
+        L.count = (int)by[f].size();
+        if (ab + arg_sz[f] * L.count > cap_bytes || ns + L.count + 1 > cap_slots)
+          return CHFSI_INVALID_ARG;
+        if (f == 1 || f == 2) {   // tile: the one carrying more of the flops
+          double w = 0.0, tot = 0.0;
+          for (const Ent& x : by[f]) {
+            const double fx = (double)jobs[x.q]->n * jobs[x.q]->n * x.cols;
+            tot += fx;
+            if (x.cols >= wide_min) w += fx;
+          }
+          L.wide = 2.0 * w > tot;
+        }
+        int total = 0;
+        hslots[ns] = 0;
+        for (int e = 0; e < L.count; ++e) {
+          const Ent& x = by[f][e];
+          Solve& S = *jobs[x.q];
+          StepBufs& sb = S.b.st;
+          const int n = S.n, k = S.dplan.k;
+          const size_t off = (size_t)x.first * n * 8;   // complex64 window offset
+          const size_t srow = (size_t)split_kp(n) * 8;
+          const char* cur = (const char*)((i & 1) ? sb.E1 : sb.E0);
+          char* old = (char*)((i & 1) ? sb.E0 : sb.E1);
+          const float* cri = sb.crtab + (size_t)i * k + x.first;
+          const DefectStepScalars sc = defect_scalars(S.dplan, i);
+          void* out = hargs + L.arg_off + arg_sz[f] * e;
+          int wg = 0;
+          if (f == 0) {
+            wg = defect_group_fill(n, x.cols, S.b.H32, cur + off, old + off, old + off,
+                                   (const char*)sb.R32 + off, cri, sc.shift, sc.sa, sc.sb, out);
+            S.flops32 += 8.0 * (double)n * n * x.cols;
+          } else if (f == 1 || f == 2) {
+            const bool h16 = f == 2;
+            char* scur = (char*)((h16 || !(i & 1)) ? sb.S0 : sb.S1) + x.first * srow;
+            char* snext = (char*)((i & 1) ? sb.S0 : sb.S1) + x.first * srow;
+            wg = split_group_fill(h16, L.wide, n, x.cols, h16 ? S.b.Hh : S.b.Hs, S.b.inv_hh,
+                                  scur, sb.colscale + x.first, cur + off, old + off, old + off,
+                                  (const char*)sb.R32 + off, cri, sc.shift, sc.sa, sc.sb,
+                                  x.next ? snext : nullptr, out);
+            if (h16) {
+              S.flopsh += 8.0 * (double)n * n * x.cols;
+              S.stepsh += 1;
+            } else {
+              S.flops16 += 8.0 * (double)n * n * x.cols;
+              S.steps16 += 1;
+            }
+          } else {
+            const bool h16 = f == 4;
+            char* scur = (char*)((h16 || !(i & 1)) ? sb.S0 : sb.S1) + x.first * srow;
+            colsplit_group_fill(n, cur + off, n, scur, sb.colscale + x.first, out);
+            wg = x.cols;
+          }
+          if (f <= 2) {
+            fl[x.q] += 8.0 * (double)n * n * x.cols;
+            S.launches += 1;
+          }
+          total += wg;
+          hslots[ns + e + 1] = total;
+        }
+        L.total = total;
+        ns += L.count + 1;
+        ab += arg_sz[f] * L.count;
+        plan.push_back(L);
+      }
+    }
+    if (ab) CK(hipMemcpyAsync(dargs, hargs, ab, hipMemcpyHostToDevice, s));
+    if (ns) CK(hipMemcpyAsync(dslots, hslots, sizeof(int) * ns, hipMemcpyHostToDevice, s));
+    CK(hipEventRecord(e0, s));
+    for (const Launch& L : plan) {
+      const char* a = dargs + L.arg_off;
+      const int* sl = dslots + L.slot_off;
+      if (L.form == 0) CK(defect_group_launch(s, a, sl, L.count, L.total));
+      else if (L.form <= 2) CK(split_group_launch(s, L.form == 2, L.wide, a, sl, L.count, L.total));
+      else CK(colsplit_group_launch(s, L.form == 4, a, sl, L.count, L.total));
+    }
+    CK(hipEventRecord(e1, s));
+    pending = true;
+    return CHFSI_OK;
+  }
+
+  int finish() {
+    if (!pending) return CHFSI_OK;
+    pending = false;
+    CK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    CK(hipEventElapsedTime(&ms, e0, e1));
+    double ftot = 0.0;
+    for (double f : fl) ftot += f;
+    for (size_t q = 0; q < jobs.size(); ++q) {
+      if (ftot <= 0.0) break;
+      const double t = 1e-3 * ms * fl[q] / ftot;
+      jobs[q]->filter_sec += t;
+      jobs[q]->sec32 += t;
+    }
+    return CHFSI_OK;
+  }
+};
+
 // Launch-argument capacity of the batch workspace for `count` solves (two
-// groups).
+// groups): the grouped FP64 filter (one entry per problem and step) and the
+// grouped defect filter (per step, at most two launches per problem: its
+// column split and its step).
 void batch_caps(int count, const chfsi_opts& o, size_t* entries, size_t* slots) {
   const size_t steps = (size_t)std::max(std::max(o.deg0, o.deg_max), 1);
   *entries = steps * (size_t)count;
   *slots = steps * ((size_t)count + 1);
 }
 
+void batch_defect_caps(int count, const chfsi_opts& o, size_t* bytes, size_t* slots) {
+  const size_t steps = (size_t)std::max(std::max(o.deg0, o.deg_max), 1);
+  const size_t a = std::max(defect_group_arg_bytes(),
+                            std::max(split_group_arg_bytes(), colsplit_group_arg_bytes()));
+  *bytes = steps * (2 * (size_t)count * a + 5 * 256);
+  *slots = steps * 5 * ((size_t)count + 1);
+}
+
 size_t batch_bytes(int count, const chfsi_opts& o) {
-  size_t entries = 0, slots = 0;
+  size_t entries = 0, slots = 0, dbytes = 0, dslots = 0;
   batch_caps(count, o, &entries, &slots);
+  batch_defect_caps(count, o, &dbytes, &dslots);
   Carver c(nullptr);
   for (int g = 0; g < 2; ++g) {
     c.take<GemmArgs>(entries);
     c.take<int>(slots);
+    c.take<char>(dbytes);
+    c.take<int>(dslots);
   }
   return c.off + ALIGN;
 }
@@ -1865,10 +2153,12 @@ size_t batch_bytes(int count, const chfsi_opts& o) {
 constexpr int BATCH_WORKERS = 8;
 
 int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void* bwork,
-                     size_t bbytes, bool graph, bool serial, std::vector<int>& status) {
+                     size_t bbytes, bool graph, bool serial, bool own_defect,
+                     std::vector<int>& status) {
   const int count = (int)S.size();
-  size_t cap_entries = 0, cap_slots = 0;
+  size_t cap_entries = 0, cap_slots = 0, cap_dbytes = 0, cap_dslots = 0;
   batch_caps(count, S[0]->o, &cap_entries, &cap_slots);
+  batch_defect_caps(count, S[0]->o, &cap_dbytes, &cap_dslots);
   if (bbytes < batch_bytes(count, S[0]->o)) return CHFSI_INVALID_ARG;
   int dev = 0;
   CK(hipGetDevice(&dev));
@@ -1910,11 +2200,15 @@ int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void
   for (auto& e : r.ev) CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   hipEvent_t ev_main = r.ev[T];
   std::vector<FilterGroup> fg(ngroups);
+  std::vector<DefectGroup> dg(ngroups);
   Carver cv(bwork);
   for (int g = 0; g < ngroups; ++g) {
     GemmArgs* dl = cv.take<GemmArgs>(cap_entries);
     int* ds = cv.take<int>(cap_slots);
     CKS(fg[g].init(dl, ds, cap_entries, cap_slots));
+    char* da = cv.take<char>(cap_dbytes);
+    int* dd = cv.take<int>(cap_dslots);
+    CKS(dg[g].init(da, dd, cap_dbytes, cap_dslots));
   }
   // inputs written on the caller's stream are visible to the workers
   CK(hipEventRecord(ev_main, s));
@@ -1971,28 +2265,32 @@ int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void
       active[q] = 0;
       if (failed[q] || S[q]->done) return;
       status[q] = S[q]->begin_loop();
-      if (status[q] == CHFSI_OK && !S[q]->done && S[q]->use32) status[q] = S[q]->filter_own();
+      if (status[q] == CHFSI_OK && !S[q]->done && S[q]->use32 && S[q]->ka > 0)
+        status[q] = own_defect ? S[q]->filter_own() : S[q]->defect_prepare_own();
       if (status[q] != CHFSI_OK) {
         failed[q] = 1;
         return;
       }
       if (!S[q]->done) active[q] = 1;
     });
-    std::vector<Solve*> fp64;
+    std::vector<Solve*> fp64, mixed;
     live = false;
     for (int q : members[g]) {
       if (!active[q]) continue;
       live = true;
       if (!S[q]->use32 && S[q]->ka > 0) fp64.push_back(S[q].get());
+      if (S[q]->grouped_defect) mixed.push_back(S[q].get());
     }
-    if (fp64.empty()) return CHFSI_OK;
+    if (fp64.empty() && mixed.empty()) return CHFSI_OK;
     for (int t = t0[g]; t < t0[g] + tn[g]; ++t) {
       CK(hipEventRecord(r.ev[t], r.st[t]));
       CK(hipStreamWaitEvent(s, r.ev[t], 0));
     }
-    CKS(fg[g].launch(s, fp64, graph));
-    // the group's workers continue after its filter
-    for (int t = t0[g]; t < t0[g] + tn[g]; ++t) CK(hipStreamWaitEvent(r.st[t], fg[g].e1, 0));
+    if (!fp64.empty()) CKS(fg[g].launch(s, fp64, graph));
+    if (!mixed.empty()) CKS(dg[g].launch(s, mixed));
+    // the group's workers continue after its filters
+    hipEvent_t done_ev = !mixed.empty() ? dg[g].e1 : fg[g].e1;
+    for (int t = t0[g]; t < t0[g] + tn[g]; ++t) CK(hipStreamWaitEvent(r.st[t], done_ev, 0));
     return CHFSI_OK;
   };
 
@@ -2012,6 +2310,7 @@ int solve_batch_impl(std::vector<std::unique_ptr<Solve>>& S, hipStream_t s, void
     for (int g = 0; g < ngroups; ++g) {
       if (!live[g]) continue;
       CKS(fg[g].finish());
+      CKS(dg[g].finish());
       parallel(g, [&](int q) {
         if (!active[q]) return;
         status[q] = S[q]->end_loop();
@@ -2162,7 +2461,7 @@ int chfsi_solve_batch(int count, const int* n, const int* nev, const int* nex,
                       void* stream, chfsi_info* info, int* status) {
   try {
     if (count < 1 || !n || !nev || !nex || !A || !lda || !Lambda || !X || !ldx || !work ||
-        !work_bytes || !status || check_ptr(batch_work) || (flags & ~3))
+        !work_bytes || !status || check_ptr(batch_work) || (flags & ~7))
       return CHFSI_INVALID_ARG;
     if ((B && !ldb) || (X0 && !ldx0)) return CHFSI_INVALID_ARG;
     if ((flags & 1) && !stream) return CHFSI_INVALID_ARG;   // no capture on the null stream
@@ -2199,7 +2498,7 @@ int chfsi_solve_batch(int count, const int* n, const int* nev, const int* nex,
     }
     std::vector<int> st;
     CKS(solve_batch_impl(S, as_stream(stream), batch_work, batch_work_bytes, (flags & 1) != 0,
-                         (flags & 2) != 0, st));
+                         (flags & 2) != 0, (flags & 4) != 0, st));
     int worst = CHFSI_OK;
     for (int q = 0; q < count; ++q) {
       status[q] = st[q];

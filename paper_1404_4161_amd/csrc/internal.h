@@ -173,6 +173,19 @@ int defect_step(hipStream_t s, int n, int N, const void* H32, const void* Ecur, 
 int defect_assemble_launch(hipStream_t s, int n, int k, const zc* Qs, long ld, const void* E0,
                            const void* E1, const int* deg, const double* pm, zc* Y, long ldy);
 
+// Grouped defect steps of several independent problems in one launch (k-point
+// batches).  *_fill writes one problem's kernel arguments (arg_bytes of them)
+// to host memory `out` and returns its workgroup count (a multiple of 8);
+// the caller lays the problems' ranges out in slots (prefix sums, slots[0]
+// = 0, slots[count] = total), uploads both, and launches once per step.
+// FP32 form (64 x 64 tiles, no split-K):
+size_t defect_group_arg_bytes();
+int defect_group_fill(int n, int N, const void* H32, const void* Ecur, const void* Eold,
+                      void* Eout, const void* R32, const float* cr, float shift, float sa,
+                      float sb, void* out);
+int defect_group_launch(hipStream_t s, const void* dargs, const int* dslots, int count,
+                        int total);
+
 // Sum of split-K partials part[p * M * N + i + j * M] (p < splits) followed
 // by the defect step's epilogue (the form of defect_step), into Eout.
 int defect_reduce_launch(hipStream_t s, int M, int N, int splits, const void* part,
@@ -195,6 +208,25 @@ int cols_to_split(hipStream_t s, int K, int cols, const void* E, long lde, void*
 int defect_step_split(hipStream_t s, int n, int N, const void* Hs, const void* Es,
                       const void* Ecur, const void* Eold, void* Eout, const void* R32,
                       const float* cr, float shift, float sa, float sb, void* Es_next);
+// Grouped BF16- (h16 false) or FP16-split (h16 true) defect steps, 64 x 64
+// or (wide) 128 x 128 tiles, no split-K; arguments as defect_step_split /
+// defect_step_h16 (Es_next: BF16 only).
+// windows of at least this many columns take the 128 x 128 tile
+int split_wide_min_cols();
+size_t split_group_arg_bytes();
+int split_group_fill(bool h16, bool wide, int n, int N, const void* Hs, float inv_h,
+                     const void* Es, const float* inv_e, const void* Ecur, const void* Eold,
+                     void* Eout, const void* R32, const float* cr, float shift, float sa,
+                     float sb, void* Es_next, void* out);
+int split_group_launch(hipStream_t s, bool h16, bool wide, const void* dargs, const int* dslots,
+                       int count, int total);
+// Grouped column splits (cols_to_split / cols_to_split_h16 of several
+// problems): one workgroup per column, problem p owning the columns
+// [cols[p], cols[p+1]); colsplit_group_fill returns 0.
+size_t colsplit_group_arg_bytes();
+int colsplit_group_fill(int K, const void* E, long lde, void* S, float* inv, void* out);
+int colsplit_group_launch(hipStream_t s, bool h16, const void* dargs, const int* dcols, int count,
+                          int total_cols);
 // FP16 form (same panel geometry, FP16 words of scaled values).  Hs row m =
 // split(2^s fp32(H[m, :])) with one power of two s from the largest
 // magnitude of H32 (= fp32(H), n x n contiguous; part: 1024 floats of

@@ -1,8 +1,10 @@
 """Batched solves (chfsi_solve_batch): problems of uneven size run their
 outer loops in lockstep and share one grouped filter launch per recurrence
-step.  Every problem must match the oracle's eigenvalues to 1e-10 and the
-single-problem solver's to rounding; graph capture must not change the
-result; errors stay per problem."""
+step (FP64), or per recurrence step and step form (the mixed-precision
+defect filters: FP16-split, BF16-split, FP32).  Every problem must match the
+oracle's eigenvalues to 1e-10 and the single-problem solver's to rounding;
+graph capture and per-problem defect filters must not change the result;
+errors stay per problem."""
 import numpy as np
 import pytest
 
@@ -41,7 +43,7 @@ def _opts(**kw):
     return o
 
 
-@pytest.mark.parametrize("precision", [0, 1, 3])
+@pytest.mark.parametrize("precision", [0, 1, 2, 3])
 def test_batch_sequence_matches_oracle_and_single_solves(precision):
     import torch
     seqs, probs = _batch(length=3)
@@ -154,3 +156,73 @@ def test_batch_with_the_second_tile_variant():
         ref = _ref(probs[q][0], seqs[q].B, nev)
         assert np.abs(r1[1][q][:nev] - ref).max() <= RTOL * np.abs(ref).min()
         assert np.abs(r1[1][q][:nev] - r0[1][q][:nev]).max() <= 1e-12 * np.abs(ref).min()
+
+
+@pytest.mark.parametrize("precision", [2, 3])
+def test_grouped_defect_filters_match_per_problem_ones(precision):
+    """The grouped defect filter (default) against the same batch with each
+    problem's defect filter on its own stream (flag bit 2), and both against
+    the oracle, along a 3-problem sequence; the split steps did run."""
+    seqs, probs = _batch(length=3, cfg0=800)
+    nevs = [p[1] for p in SIZES]
+    nexs = [p[2] for p in SIZES]
+    Bs = [dev(s.B) if s.B is not None else None for s in seqs]
+    o = _opts(precision=precision)
+    state = {False: (None, None), True: (None, None)}
+    for l in range(3):
+        As = [dev(p[l]) for p in probs]
+        out = {}
+        for own in (False, True):
+            x0s, lam0s = state[own]
+            out[own] = ch.chfsi_solve_batch(As, Bs, nevs, nexs, 1e-10, X0s=x0s, Lambda0s=lam0s,
+                                            opts=o, own_defect=own)
+            assert out[own][0] == 0
+            state[own] = (out[own][2], out[own][1])
+        key = "filter_steps_bf16" if precision == 2 else "filter_steps_fp16"
+        if l > 0:
+            assert sum(i[key] for i in out[False][3]) > 0
+        for q, (n, nev, nex, g) in enumerate(SIZES):
+            ref = _ref(probs[q][l], seqs[q].B, nev)
+            for own in (False, True):
+                assert np.abs(out[own][1][q][:nev] - ref).max() <= RTOL * np.abs(ref).min()
+            assert (np.abs(out[False][1][q][:nev] - out[True][1][q][:nev]).max()
+                    <= 1e-12 * np.abs(ref).min())
+
+
+def test_grouped_defect_filter_with_wide_windows():
+    """Two problems with k = 300 (windows of at least 257 columns take the
+    128 x 128 tile in the grouped FP16-split launch) and a small one, three
+    warm-started problems each, against the oracle and the single solver."""
+    import torch
+    sizes = [(1200, 280, 20, False), (1100, 270, 30, True), (300, 16, 4, False)]
+    seqs, probs = [], []
+    for q, (n, nev, nex, g) in enumerate(sizes):
+        conf = gen.small_config("w", n, nev, nex, g, length=3, cfg=820 + q, delta=1e-2)
+        seq = gen.Sequence(conf)
+        seqs.append(seq)
+        probs.append([a.copy() for _, a in seq.problems()])
+    nevs = [p[1] for p in sizes]
+    nexs = [p[2] for p in sizes]
+    Bs = [dev(s.B) if s.B is not None else None for s in seqs]
+    o = _opts(precision=3)
+    x0s = lam0s = None
+    sx = [None] * len(sizes)
+    slam = [None] * len(sizes)
+    for l in range(3):
+        print(f"wide grouped defect filter: problem {l + 1}", flush=True)
+        As = [dev(p[l]) for p in probs]
+        st, lams, xs, infos, sts = ch.chfsi_solve_batch(As, Bs, nevs, nexs, 1e-10, X0s=x0s,
+                                                        Lambda0s=lam0s, opts=o)
+        assert st == 0
+        if l > 0:
+            assert sum(i["filter_steps_fp16"] for i in infos) > 0
+        for q, (n, nev, nex, g) in enumerate(sizes):
+            ref = _ref(probs[q][l], seqs[q].B, nev)
+            assert np.abs(lams[q][:nev] - ref).max() <= RTOL * np.abs(ref).min(), (l, q)
+            st1, lam1, x1, _ = ch.chfsi_solve(As[q], Bs[q], nev, nex, 1e-10, X0=sx[q],
+                                              Lambda0=slam[q], opts=o)
+            assert st1 == 0
+            assert np.abs(lam1[:nev] - lams[q][:nev]).max() <= 1e-12 * np.abs(ref).min()
+            sx[q], slam[q] = x1, lam1
+        x0s, lam0s = xs, lams
+        torch.cuda.synchronize()
