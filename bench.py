@@ -44,15 +44,16 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 
-# HBM bytes of one full-width launch of the FP64 filter step kernel, from
-# the two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE) of
-# `bench.py --filter-only`, calibrated on a 1 GiB device copy; keyed by
-# (n, N, tile variant).  Valid only for the kernel source they were
+# Bytes beyond the L2 (HBM and Infinity Cache) of one full-width launch of
+# the FP64 filter step kernel, from the two rocprofv3 --pmc passes
+# (FETCH_SIZE, WRITE_SIZE) of `bench.py --filter-only`, calibrated on a
+# 1 GiB device copy; keyed by (n, N, tile variant).  Valid only for the kernel source they were
 # measured on (the hash); otherwise the roofline reports traffic null.
 TRAFFIC_MEASURED = {
     "zgemm_sha256": "8df37dde5efc6e7bda01d1ea51ab5cea363e65cd6970b6f321f9b3caf55a364e",
     "bytes_per_full_width_launch": {(8000, 480, 0): 4.571e9, (8000, 480, 1): 2.370e9,
-                                    (8000, 480, 2): 1.697e9},
+                                    (8000, 480, 2): 1.697e9, (30000, 1800, 0): 517.01e9,
+                                    (30000, 1800, 1): 445.44e9, (30000, 1800, 2): 192.18e9},
 }
 
 
@@ -122,7 +123,7 @@ def filter_only(conf, degree):
     dt = time.perf_counter() - t
     # then the defect filter at the same shape with every step in BF16-split
     # form (the Ritz-pair inputs do not change its cost)
-    q = ch.colmajor(torch.linalg.qr(y)[0])
+    q = ch.colmajor(y / torch.linalg.vector_norm(y, dim=0, keepdim=True))
     z = ch.colmajor(h @ q)
     mu = np.linspace(-1.2 * nrm, -1.1 * nrm, k)
     torch.cuda.synchronize()
@@ -563,9 +564,11 @@ def main():
             "traffic": traffic_entry(n, k, tv[0]),
             "kernel": "FP64 filter step zgemm_kernel<OP_N,OP_N,EPI_CHEB> / cheb_wide_kernel",
             "tile_variant_full_width": int(tv[0]),
-            "traffic_note": f"HBM GB of one full-width launch (n={n}, N={k}); algorithmic "
+            "traffic_note": f"GB beyond the L2 (FETCH_SIZE + WRITE_SIZE, calibrated) of one "
+                            f"full-width launch (n={n}, N={k}); algorithmic "
                             f"{(16 * n * n + 48 * n * k) / 1e9:.3f} GB",
             "avg_launch_us": round(fsec / launches * 1e6, 1),
+            "launches": launches,
         },
         "s_per_sequence_step_median": round(statistics.median(r64["walls"]), 4),
         "phase_s_per_step": {nm: round(float(v), 3) for nm, v in zip(PHASES, phases)

@@ -55,7 +55,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 constexpr int SBK = 32;                        // K per LDS stage
 constexpr int SPLIT_WIDE_MIN_N = 257;          // windows that take the 128 x 128 tile
 constexpr int GROUP_B = 64;                    // bytes per (row, 8 k) group
-constexpr int ROWB = (SBK / 8) * GROUP_B + 16; // LDS bytes per tile row (+16 B pad)
+constexpr int ROWB = (SBK / 8) * GROUP_B;      // LDS bytes per tile row and stage
 constexpr int NXCD = 8;
 
 __device__ __forceinline__ unsigned bf16_rne(float x) {
@@ -152,25 +152,34 @@ struct SplitArgs {
 
 // One defect step on tiles of BM x BN complex outputs: WGM x WGN waves, each
 // owning TI x TJ sub-tiles of 16 x 16 (BM = 16 WGM TI, BN = 16 WGN TJ), K
-// staged 32 deep through two LDS stages of (BM + BN) rows x 272 B; tile rows
-// interleaved over the 8 XCDs.  Instances: 64 x 64 with 4 waves of 32 x 32
-// (68 KB of LDS, two workgroups per CU) and 128 x 128 with 8 waves of 32 x
-// 64 (136 KB, one per CU: half the operand traffic per output and a third
+// staged 32 deep through two LDS stages of (BM + BN) rows x 256 B; tile rows
+// interleaved over the 8 XCDs.  The operand rows go from global memory
+// straight to LDS (global_load_lds_dwordx4: one instruction of a wave fills
+// 1 KB, 4 tile rows, lane L taking 16 B of row L / 16), so no registers hold
+// staged data and the next stage's loads run under the current stage's
+// MFMAs.  The 16-byte chunks of LDS row r sit at position chunk ^ (r & 15):
+// the fragment reads of 16 consecutive rows then touch 16 distinct chunk
+// positions, all 64 banks once.  Instances: 64 x 64 with 4 waves of 32 x 32
+// (64 KB of LDS, two workgroups per CU) and 128 x 128 with 8 waves of 32 x
+// 64 (128 KB, one per CU: half the operand traffic per output and a third
 // fewer LDS reads per MFMA).
 template <int WGM, int WGN, int TI, int TJ>
 struct SplitTile {
   static constexpr int BM = 16 * WGM * TI, BN = 16 * WGN * TJ;
   static constexpr int NTH = 64 * WGM * WGN;
   static constexpr int LDS_STAGE = (BM + BN) * ROWB;
-  static constexpr int CHUNKS = (BM + BN) * 16 / NTH;   // 16-byte staging loads per thread
+  static constexpr int BLOCKS = (BM + BN) / 4;       // 1 KB blocks per stage
+  static constexpr int PER_WAVE = BLOCKS / (NTH / 64);
+  static_assert(BLOCKS % (NTH / 64) == 0, "whole blocks per wave");
 };
 
 template <int WGM, int WGN, int TI, int TJ, bool H16>
-__device__ __forceinline__ void split_tile_body(const SplitArgs& g, char* lds, int bid) {
+__device__ __forceinline__ void split_tile_body(const SplitArgs& g, char* lds0, char* lds1,
+                                                int bid) {
   using W = Words<H16>;
   typedef typename W::V V;
   using T = SplitTile<WGM, WGN, TI, TJ>;
-  constexpr int BM = T::BM, BN = T::BN, NTH = T::NTH, CH = T::CHUNKS;
+  constexpr int BM = T::BM, NW = T::NTH / 64, PW = T::PER_WAVE;
   // virtual tile rows (split, tile row) interleaved over the XCDs
   const int xcd = bid % NXCD, slot = bid / NXCD;
   const int vrows = g.splits * g.tiles_m;
@@ -180,7 +189,7 @@ __device__ __forceinline__ void split_tile_body(const SplitArgs& g, char* lds, i
   if (ri >= rows_x) return;
   const int v = xcd + NXCD * ri;
   const int split = v / g.tiles_m, tm = v - split * g.tiles_m;
-  const int m0 = tm * BM, n0 = tn * BN;
+  const int m0 = tm * BM, n0 = tn * T::BN;
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int wm = wave % WGM, wn = wave / WGM;
@@ -194,57 +203,44 @@ __device__ __forceinline__ void split_tile_body(const SplitArgs& g, char* lds, i
       accR[i][j] = f4{0.f, 0.f, 0.f, 0.f};
       accI[i][j] = f4{0.f, 0.f, 0.f, 0.f};
     }
-  // staging: 16 chunks of 16 B per tile row and stage; chunk c < BM * 16 is
-  // an A row, the rest B rows
-  uint4 rs[CH];
-  auto load = [&](int k0) {
+  // this lane's source in each of the wave's 1 KB blocks: tile row
+  // 4 b + lane / 16 (A rows first, then B rows), the chunk that belongs at
+  // position lane % 16; rows beyond M or N read a valid row instead (their
+  // products only reach outputs that are not stored)
+  const char* src[PW];
 #pragma unroll
-    for (int i = 0; i < CH; ++i) {
-      const int c = t + NTH * i;
-      const int row = c >> 4, ch = c & 15;
-      const long koff = (long)k0 * 8 + ch * 16;
-      if (row < BM) {
-        const int gm = m0 + row;
-        rs[i] = gm < g.M ? *(const uint4*)(g.As + gm * g.a_row + koff) : uint4{0u, 0u, 0u, 0u};
-      } else {
-        const int gn = n0 + row - BM;
-        rs[i] = gn < g.N ? *(const uint4*)(g.Bs + gn * g.b_row + koff) : uint4{0u, 0u, 0u, 0u};
-      }
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < CH; ++i) {
-      const int c = t + NTH * i;
-      const int row = c >> 4, ch = c & 15;
-      *(uint4*)(lds + buf * T::LDS_STAGE + row * ROWB + ch * 16) = rs[i];
-    }
-  };
-  const int kt0 = split * g.kstages;
-  const int nk = min(g.Kp / SBK, kt0 + g.kstages) - kt0;
-  if (nk > 0) {
-    load(kt0 * SBK);
-    store(0);
+  for (int i = 0; i < PW; ++i) {
+    const int b = i * NW + wave;
+    const int row = 4 * b + (lane >> 4);
+    const int chunk = (lane & 15) ^ (row & 15);
+    if (row < BM)
+      src[i] = g.As + (long)min(m0 + row, g.M - 1) * g.a_row + chunk * 16;
+    else
+      src[i] = g.Bs + (long)min(n0 + row - BM, g.N - 1) * g.b_row + chunk * 16;
   }
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    const bool more = kt + 1 < nk;
-    if (more) load((kt0 + kt + 1) * SBK);
-    const char* la = lds + cur * T::LDS_STAGE;
+  auto load = [&](int k0, char* buf) {
+#pragma unroll
+    for (int i = 0; i < PW; ++i)
+      __builtin_amdgcn_global_load_lds(
+          (const void*)(src[i] + (long)k0 * 8),
+          (__attribute__((address_space(3))) void*)(buf + (i * NW + wave) * 1024), 16, 0, 0);
+  };
+  auto compute = [&](const char* la) {
     const char* lb = la + BM * ROWB;
     uint4 a[TI][4], b[TJ][4];
 #pragma unroll
     for (int i = 0; i < TI; ++i) {
-      const char* p = la + (wm * 16 * TI + i * 16 + lr) * ROWB + lg * GROUP_B;
+      const int r = wm * 16 * TI + i * 16 + lr;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) a[i][q] = *(const uint4*)(p + 16 * q);
+      for (int q = 0; q < 4; ++q)
+        a[i][q] = *(const uint4*)(la + r * ROWB + (((lg * 4 + q) ^ (r & 15)) * 16));
     }
 #pragma unroll
     for (int j = 0; j < TJ; ++j) {
-      const char* p = lb + (wn * 16 * TJ + j * 16 + lr) * ROWB + lg * GROUP_B;
+      const int r = wn * 16 * TJ + j * 16 + lr;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) b[j][q] = *(const uint4*)(p + 16 * q);
+      for (int q = 0; q < 4; ++q)
+        b[j][q] = *(const uint4*)(lb + r * ROWB + (((lg * 4 + q) ^ (r & 15)) * 16));
     }
     // planes: 0 re_hi, 1 im_hi, 2 re_lo, 3 im_lo
     // real part: Ar Br - Ai Bi (the A imaginary planes negated)
@@ -272,7 +268,26 @@ __device__ __forceinline__ void split_tile_body(const SplitArgs& g, char* lds, i
         accI[i][j] = W::mma(ail, brh, accI[i][j]);
       }
     }
-    if (more) store(cur ^ 1);
+  };
+  // two LDS stages used alternately (the loop is unrolled by two so that
+  // each stage's buffer is fixed); every stage ends with this wave's loads
+  // landed and a barrier, so the other buffer is free for the next loads
+  const int kt0 = split * g.kstages;
+  const int nk = min(g.Kp / SBK, kt0 + g.kstages) - kt0;
+  if (nk > 0) load(kt0 * SBK, lds0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  for (int kt = 0; kt < nk; kt += 2) {
+    if (kt + 1 < nk) load((kt0 + kt + 1) * SBK, lds1);
+    compute(lds0);
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (kt + 1 >= nk) break;
+    if (kt + 2 < nk) load((kt0 + kt + 2) * SBK, lds0);
+    compute(lds1);
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
   }
   // MFMA output: lane l, register r holds row 4 (l / 16) + r, column l % 16
@@ -342,23 +357,27 @@ using TileSmall = SplitTile<2, 2, 2, 2>;   // 64 x 64, 256 threads
 using TileWide = SplitTile<4, 2, 2, 4>;    // 128 x 128, 512 threads
 
 __global__ void __launch_bounds__(TileSmall::NTH, 2) defect_gemm_split(SplitArgs g) {
-  __shared__ __attribute__((aligned(16))) char lds[2 * TileSmall::LDS_STAGE];
-  split_tile_body<2, 2, 2, 2, false>(g, lds, blockIdx.x);
+  __shared__ __attribute__((aligned(1024))) char lds0[TileSmall::LDS_STAGE];
+  __shared__ __attribute__((aligned(1024))) char lds1[TileSmall::LDS_STAGE];
+  split_tile_body<2, 2, 2, 2, false>(g, lds0, lds1, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(TileWide::NTH, 1) defect_gemm_split_wide(SplitArgs g) {
-  __shared__ __attribute__((aligned(16))) char lds[2 * TileWide::LDS_STAGE];
-  split_tile_body<4, 2, 2, 4, false>(g, lds, blockIdx.x);
+  __shared__ __attribute__((aligned(1024))) char lds0[TileWide::LDS_STAGE];
+  __shared__ __attribute__((aligned(1024))) char lds1[TileWide::LDS_STAGE];
+  split_tile_body<4, 2, 2, 4, false>(g, lds0, lds1, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(TileSmall::NTH, 2) defect_gemm_h16(SplitArgs g) {
-  __shared__ __attribute__((aligned(16))) char lds[2 * TileSmall::LDS_STAGE];
-  split_tile_body<2, 2, 2, 2, true>(g, lds, blockIdx.x);
+  __shared__ __attribute__((aligned(1024))) char lds0[TileSmall::LDS_STAGE];
+  __shared__ __attribute__((aligned(1024))) char lds1[TileSmall::LDS_STAGE];
+  split_tile_body<2, 2, 2, 2, true>(g, lds0, lds1, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(TileWide::NTH, 1) defect_gemm_h16_wide(SplitArgs g) {
-  __shared__ __attribute__((aligned(16))) char lds[2 * TileWide::LDS_STAGE];
-  split_tile_body<4, 2, 2, 4, true>(g, lds, blockIdx.x);
+  __shared__ __attribute__((aligned(1024))) char lds0[TileWide::LDS_STAGE];
+  __shared__ __attribute__((aligned(1024))) char lds1[TileWide::LDS_STAGE];
+  split_tile_body<4, 2, 2, 4, true>(g, lds0, lds1, blockIdx.x);
 }
 
 // Grouped launches (batches of independent problems): problem p of the
@@ -378,18 +397,20 @@ template <bool H16>
 __global__ void __launch_bounds__(TileSmall::NTH, 2) defect_group_small(const SplitArgs* list,
                                                                       const int* slot_begin,
                                                                       int count) {
-  __shared__ __attribute__((aligned(16))) char lds[2 * TileSmall::LDS_STAGE];
+  __shared__ __attribute__((aligned(1024))) char lds0[TileSmall::LDS_STAGE];
+  __shared__ __attribute__((aligned(1024))) char lds1[TileSmall::LDS_STAGE];
   const int p = group_of(slot_begin, count, blockIdx.x);
-  split_tile_body<2, 2, 2, 2, H16>(list[p], lds, blockIdx.x - slot_begin[p]);
+  split_tile_body<2, 2, 2, 2, H16>(list[p], lds0, lds1, blockIdx.x - slot_begin[p]);
 }
 
 template <bool H16>
 __global__ void __launch_bounds__(TileWide::NTH, 1) defect_group_wide(const SplitArgs* list,
                                                                     const int* slot_begin,
                                                                     int count) {
-  __shared__ __attribute__((aligned(16))) char lds[2 * TileWide::LDS_STAGE];
+  __shared__ __attribute__((aligned(1024))) char lds0[TileWide::LDS_STAGE];
+  __shared__ __attribute__((aligned(1024))) char lds1[TileWide::LDS_STAGE];
   const int p = group_of(slot_begin, count, blockIdx.x);
-  split_tile_body<4, 2, 2, 4, H16>(list[p], lds, blockIdx.x - slot_begin[p]);
+  split_tile_body<4, 2, 2, 4, H16>(list[p], lds0, lds1, blockIdx.x - slot_begin[p]);
 }
 
 // Power-of-two scale that brings the largest magnitude m into [2^14, 2^15)

@@ -87,3 +87,42 @@ def test_gen_n8000_filter_sampled_columns(sequence):
     for j, m in enumerate(deg):
         ref = chebyshev.chebyshev_filter(a_host, y0[:, j:j + 1], [m], c, e, gamma)
         assert rel_col_err(got[:, j:j + 1], ref).max() < 1e-12, (j, m)
+
+
+@pytest.mark.timeout(900)
+def test_gen_n8000_sequence_with_the_tuned_wide_tile(sequence):
+    """The FP64 sequence again with the tile variants the benchmark's
+    autotuner picks at this size (the 128 x 128 tile `cheb_wide_kernel` for
+    the full 480-column window, the 64 x 64 tiles with the 16-deep K stage
+    for narrow windows), set explicitly so that the wide tile runs whatever
+    the timing on this device; then a full-width filter of 480 columns with
+    the wide tile, sampled columns against the oracle."""
+    import torch
+    conf, seq, probs = sequence
+    ref = _golden()
+    try:
+        for N, v in ((480, 2), (360, 2), (240, 1), (120, 1), (60, 1)):
+            ch.chfsi_autotune_set(conf.n, N, v)
+        x, lam = None, None
+        for l, a in enumerate(probs, start=1):
+            st, lam, xd, info = ch.chfsi_solve(a, seq.B, conf.nev, conf.nex, conf.tol, X0=x,
+                                               Lambda0=lam if x is not None else None)
+            assert st == 0, (l, st)
+            err = np.abs(lam[:conf.nev] - ref[l]) / np.abs(ref[l])
+            assert err.max() <= 1e-10, (l, err.max())
+            x = xd
+        a = probs[0]
+        y0 = gen.random_block(conf.n, conf.k, 78)
+        deg = [6] * conf.k
+        c, e, gamma = 12.5, 27.5, -20.0
+        yd = dev(y0)
+        _, launches = ch.chfsi_filter(a, yd, deg, c, e, gamma)
+        assert launches == 6
+        got = host(yd)
+        a_host = host(a)
+        for j in (0, conf.k // 2, conf.k - 1):
+            r = chebyshev.chebyshev_filter(a_host, y0[:, j:j + 1], [6], c, e, gamma)
+            assert rel_col_err(got[:, j:j + 1], r).max() < 1e-12, j
+        torch.cuda.synchronize()
+    finally:
+        ch.chfsi_autotune_reset()

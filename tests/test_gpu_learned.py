@@ -111,3 +111,41 @@ def test_sequence_calibrated_degrees_need_fewer_loops():
     print("rule (loops, matvecs):", totals[0], "sequence-calibrated:", totals[3])
     assert totals[3][0] < totals[0][0], totals
     assert totals[3][1] <= 1.2 * totals[0][1], totals
+
+
+@pytest.mark.timeout(600)
+def test_learned_degrees_in_fp32_capped_mixed_loops(network):
+    """The mixed-precision regime of the benchmark (precision 3, FP16-split
+    defect filters whose loops are capped at one FP32 loop's reach, first
+    loop of each warm start at deg0): a standard sequence with constant
+    perturbations 1e-3 H_l, solved with the rule and with the network.  Over
+    the warm-started problems the network needs no more loops than the rule
+    (it raises degrees where that lets a capped loop finish), both match the
+    oracle's eigenvalues to 1e-10."""
+    import torch
+    blob, _ = network
+    conf = gen.small_config("lgm", 800, 40, 8, False, length=6, cfg=514, delta=1e-3)
+    seq = gen.Sequence(conf, kind="torch", device="cuda:0")
+    probs = [a.clone() for _, a in seq.problems()]
+    torch.cuda.synchronize()
+    totals = {}
+    for mode in (0, 2):
+        o = ch.chfsi_default_opts()
+        o.precision, o.degree_mode = 3, mode
+        x = lam = None
+        loops = mv = fp32 = 0
+        for l, a in enumerate(probs):
+            st, lam, x, info = ch.chfsi_solve(a, None, conf.nev, conf.nex, 1e-10, X0=x,
+                                              Lambda0=lam if x is not None else None, opts=o,
+                                              mlp=blob if mode == 2 else None)
+            assert st == 0, (mode, l, st)
+            if l > 0:
+                loops += info["iters"]
+                mv += info["matvecs"]
+                fp32 += info["filter_iters_fp32"]
+            ref = eigh.eigvalsh(a.cpu().numpy())[:conf.nev]
+            assert np.abs(lam[:conf.nev] - ref).max() <= 1e-10 * np.abs(ref).min(), (mode, l)
+        totals[mode] = (loops, mv, fp32)
+    print("warm problems, rule (loops, matvecs, fp32 loops):", totals[0], "learned:", totals[2])
+    assert totals[0][2] > 0 and totals[2][2] > 0          # the FP32 defect loops did run
+    assert totals[2][0] <= totals[0][0], totals
