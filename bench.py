@@ -50,15 +50,17 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 # 1 GiB device copy; keyed by (n, N, tile variant).  Valid only for the kernel source they were
 # measured on (the hash); otherwise the roofline reports traffic null.
 TRAFFIC_MEASURED = {
-    "zgemm_sha256": "8df37dde5efc6e7bda01d1ea51ab5cea363e65cd6970b6f321f9b3caf55a364e",
-    "bytes_per_full_width_launch": {(8000, 480, 0): 4.571e9, (8000, 480, 1): 2.370e9,
-                                    (8000, 480, 2): 1.697e9, (30000, 1800, 0): 517.01e9,
-                                    (30000, 1800, 1): 445.44e9, (30000, 1800, 2): 192.18e9},
+    "zgemm_sha256": "8b1f370d4a80c3281bdd1045d0fdc443bcfa4f2a1cac424c34ac4b794de9ed2d",
+    # a full-width step at n = 30000 runs as two K splits (partial sums and
+    # cheb_reduce, both counted) whatever the tile variant
+    "bytes_per_full_width_launch": {(8000, 480, 0): 4.566e9, (8000, 480, 1): 2.357e9,
+                                    (8000, 480, 2): 1.698e9, (30000, 1800, 0): 495.07e9,
+                                    (30000, 1800, 1): 495.07e9, (30000, 1800, 2): 495.07e9},
 }
 
 
 def traffic_entry(n, N, variant):
-    """Measured HBM GB of one full-width step launch at (n, N), or None."""
+    """Measured GB beyond the L2 of one full-width filter step at (n, N), or None."""
     import hashlib
     src = os.path.join(ROOT, "paper_1404_4161_amd", "csrc", "zgemm.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
@@ -562,7 +564,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(tflops / PEAK_FP64_TFLOPS, 4),
             "traffic": traffic_entry(n, k, tv[0]),
-            "kernel": "FP64 filter step zgemm_kernel<OP_N,OP_N,EPI_CHEB> / cheb_wide_kernel",
+            "kernel": "FP64 filter step zgemm_kernel<OP_N,OP_N,EPI_CHEB> / cheb_wide_kernel "
+                      "(split-K steps: partial sums + cheb_reduce)",
             "tile_variant_full_width": int(tv[0]),
             "traffic_note": f"GB beyond the L2 (FETCH_SIZE + WRITE_SIZE, calibrated) of one "
                             f"full-width launch (n={n}, N={k}); algorithmic "

@@ -255,9 +255,25 @@ def test_defect_filter_matches_oracle_with_error_scaling_like_the_residual(delta
     # eq. (resl): rounding grows like (|rho_1| / |rho_j|)^m relative to column j
     growth = (chebyshev.rho(np.array([(gamma - c) / e]))[0]
               / chebyshev.rho((mu - c) / e)) ** np.array(deg)
-    bound = 1e3 * 2.0 ** -24 * (res / norm_h) * growth + 1e-13
+    bound = _defect_bound(err, deg, n, 2.0 ** -24, res, norm_h, growth, "FP32 defect filter")
     assert np.all(err <= bound), (err / bound).max()
     assert f32 == pytest.approx(8.0 * n * n * sum(m - 1 for m in deg))
+
+
+def _defect_bound(err, deg, n, eps, res, norm_h, growth, label):
+    """Error bound of a defect filter run column by column: each of the m_j
+    steps adds at most about eps times |H| |E_i| to the defect, i.e. about
+    sqrt(n) eps (r_j / ||H||) relative to the column (eq. resl: E_i scales
+    with the residual r_j; the sqrt(n) takes |H| |E_i| to ||H|| ||E_i||
+    for rounding errors of random sign over the n-term sums), and the
+    later steps grow an error by at most the filter's growth factor; so
+    err_j <= m_j sqrt(n) eps (r_j / ||H||) growth_j (plus 1e-13 for the
+    FP64 parts).  Prints the largest ratio to the model without the
+    m_j sqrt(n) factor."""
+    model = eps * (res / norm_h) * growth
+    print(f"{label}: max err / (eps r/||H|| growth) = {np.max(err / (model + 1e-300)):.1f} "
+          f"(bound factor m sqrt(n) up to {np.max(deg) * np.sqrt(n):.0f})")
+    return np.array(deg) * np.sqrt(n) * model + 1e-13
 
 
 def _ritz_block(n, k, delta, seed):
@@ -322,7 +338,8 @@ def test_bf16_split_filter_matches_oracle_with_error_scaling_like_the_residual(d
     norm_h = np.abs(lam).max()
     growth = (chebyshev.rho(np.array([(gamma - c) / e]))[0]
               / chebyshev.rho((mu - c) / e)) ** np.array(deg)
-    bound = 1e3 * 3.0 * 2.0 ** -16 * (res / norm_h) * growth + 1e-13
+    bound = _defect_bound(err, deg, n, 3.0 * 2.0 ** -16, res, norm_h, growth,
+                          "BF16-split defect filter")
     assert np.all(err <= bound), (err / bound).max()
     d = np.array(deg)
     want16 = sum(int(np.sum(d > i)) for i in range(1, min(steps, d.max() - 1) + 1))
@@ -438,7 +455,8 @@ def test_fp16_split_filter_matches_oracle_with_error_scaling_like_the_residual(d
     norm_h = np.abs(lam).max()
     growth = (chebyshev.rho(np.array([(gamma - c) / e]))[0]
               / chebyshev.rho((mu - c) / e)) ** np.array(deg)
-    bound = 1e3 * 3.0 * 2.0 ** -22 * (res / norm_h) * growth + 1e-13
+    bound = _defect_bound(err, deg, n, 3.0 * 2.0 ** -22, res, norm_h, growth,
+                          "FP16-split defect filter")
     assert np.all(err <= bound), (err / bound).max()
     d = np.array(deg)
     wanth = sum(int(np.sum(d > i)) for i in range(1, min(steps, d.max() - 1) + 1))
