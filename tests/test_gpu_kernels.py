@@ -276,6 +276,17 @@ def _defect_bound(err, deg, n, eps, res, norm_h, growth, label):
     return np.array(deg) * np.sqrt(n) * model + 1e-13
 
 
+def _split_word_check(err, eps, res, norm_h, growth):
+    """A split form that kept both words of every operand stays within a
+    few times eps (r / ||H||) growth of the oracle (measured on these inputs:
+    at most 0.2 times for BF16 words, 1.2 times for FP16 words); one that
+    dropped an operand's second word errs by about 2^-8 (BF16) or 2^-11
+    (FP16) per product, 85 or 680 times eps.  8 times the model separates
+    the two."""
+    assert np.all(err <= 8.0 * eps * (res / norm_h) * growth + 1e-13), \
+        np.max(err / (eps * (res / norm_h) * growth + 1e-300))
+
+
 def _ritz_block(n, k, delta, seed):
     lam, h = _herm_problem(n, seed)
     q0 = np.linalg.eigh(h)[1][:, :k]
@@ -341,6 +352,7 @@ def test_bf16_split_filter_matches_oracle_with_error_scaling_like_the_residual(d
     bound = _defect_bound(err, deg, n, 3.0 * 2.0 ** -16, res, norm_h, growth,
                           "BF16-split defect filter")
     assert np.all(err <= bound), (err / bound).max()
+    _split_word_check(err, 3.0 * 2.0 ** -16, res, norm_h, growth)
     d = np.array(deg)
     want16 = sum(int(np.sum(d > i)) for i in range(1, min(steps, d.max() - 1) + 1))
     assert f16 == pytest.approx(8.0 * n * n * want16)
@@ -458,6 +470,7 @@ def test_fp16_split_filter_matches_oracle_with_error_scaling_like_the_residual(d
     bound = _defect_bound(err, deg, n, 3.0 * 2.0 ** -22, res, norm_h, growth,
                           "FP16-split defect filter")
     assert np.all(err <= bound), (err / bound).max()
+    _split_word_check(err, 3.0 * 2.0 ** -22, res, norm_h, growth)
     d = np.array(deg)
     wanth = sum(int(np.sum(d > i)) for i in range(1, min(steps, d.max() - 1) + 1))
     assert fh == pytest.approx(8.0 * n * n * wanth)
