@@ -479,7 +479,9 @@ int eigh_projected(hipStream_t s, int k, StepBufs& b, int refine, int* refined) 
 int rayleigh_ritz_dev(hipStream_t s, int n, int k, const zc* H, long ldh, const zc* Q, long ldq,
                       zc* Z, long ldz, zc* Qout, long ldqo, zc* Zout, long ldzo, StepBufs& b,
                       double* mu_h, double* res_h, int refine = 1, int* refined_out = nullptr) {
-  CK(zgemm(s, OP_N, OP_N, n, k, n, ONE, H, ldh, Q, ldq, ZERO, Z, ldz, false, nullptr, 0));
+  // (the filter's partial-sum buffer is free here: split K for long H Q)
+  CK(zgemm(s, OP_N, OP_N, n, k, n, ONE, H, ldh, Q, ldq, ZERO, Z, ldz, false, b.fpart,
+           b.fpart_elems));
   CK(zgemm(s, OP_C, OP_N, k, k, n, ONE, Q, ldq, Z, ldz, ZERO, b.G, k, true, b.scratch,
            b.scratch_elems));
   CK(herm_from_lower(s, k, b.G, k));
@@ -1414,7 +1416,8 @@ struct Solve {
     if (!have_res && (o.precision >= 1 || warm_rule)) {
       // one product gives Z = H Q and the residuals of the warm start block
       tm.begin(4);
-      CK(zgemm(s, OP_N, OP_N, n, ka, n, ONE, H, ldh, b.QA, ld, ZERO, b.ZA, ld, false, nullptr, 0));
+      CK(zgemm(s, OP_N, OP_N, n, ka, n, ONE, H, ldh, b.QA, ld, ZERO, b.ZA, ld, false, sb.fpart,
+               sb.fpart_elems));
       CKS(upload(s, sb.mu, std::vector<double>(mu.begin(), mu.begin() + ka)));
       CK(resid_norms(s, n, ka, b.QA, ld, b.ZA, ld, sb.mu, sb.res));
       CK(hipMemcpyAsync(res.data(), sb.res, sizeof(double) * ka, hipMemcpyDeviceToHost, s));

@@ -551,6 +551,17 @@ Plan make_plan(int M, int N, int K, bool lower_only, bool allow_split) {
       p.kchunk = chunk;
       p.splits = (K + chunk - 1) / chunk;
     }
+  } else if (allow_split && !lower_only && K >= 4096) {
+    // long products (H Q of Rayleigh-Ritz): split K, as the filter step
+    // does, when the last round of resident workgroups would be far from
+    // full
+    const int s = wave_splits(p.total, K, 4, 0.97);
+    if (s > 1) {
+      int chunk = (K + s - 1) / s;
+      chunk = ((chunk + BK - 1) / BK) * BK;
+      p.kchunk = chunk;
+      p.splits = (K + chunk - 1) / chunk;
+    }
   }
   return p;
 }
