@@ -190,6 +190,10 @@ typedef struct chfsi_info {
   int rr_dense;            /* ... and by the dense eigensolver (zheevd)          */
   int filter_steps_fp16;   /* defect-filter steps run with FP16-split products   */
   double filter_flops_fp16;/* 8 n^2 per column of those steps                    */
+  double filter_flops_fp64_mfma; /* real flops the MFMAs of the FP64 filter steps
+                            executed: 8 n^2 per column mat-vec with the 4M
+                            complex split, 6 n^2 with 3M (filter_flops counts
+                            8 n^2 for both)                                   */
 } chfsi_info;
 
 /* Convergence log record (CHFSI_LOG_FIELDS doubles), one per wanted vector
@@ -572,23 +576,29 @@ int chfsi_mlp_adam(float* params, const float* grad, float* m, float* v, float l
 int chfsi_mlp_train(int n, const float* X, const float* T, float* params, int steps, float lr,
                     void* work, size_t work_bytes, void* stream, float* loss_out);
 
-/* Filter tile autotuner.  The Chebyshev-step kernel exists in three
- * variants: 0 (64 x 64 tiles) stages K 8 deep through LDS with four
- * workgroups per CU, 1 stages it 16 deep with two per CU, 2 uses 128 x 128
- * tiles of 16 waves (one workgroup per CU; windows of N >= 256 columns, and
- * not in the grouped launches of chfsi_solve_batch, which take 0 instead).
- * Another variant than 0 is kept only when it is 2 % faster.
- * chfsi_autotune_filter times them on each given
+/* Filter tile autotuner.  The FP64 Chebyshev-step kernel exists in
+ * CHFSI_FILTER_VARIANTS variants: 0 (64 x 64 tiles, the 4M complex split:
+ * four real products per complex multiply-add) stages K 8 deep through LDS
+ * with four workgroups per CU, 1 stages it 16 deep with two per CU, 2 uses
+ * 128 x 128 tiles of 16 waves (one workgroup per CU; windows of N >= 256
+ * columns, and not in the grouped launches of chfsi_solve_batch, which take
+ * 0 instead); 3 and 4 are 0 and 1 with the 3M split (three real products
+ * Ar Br, Ai Bi, (Ar + Ai)(Br + Bi) per complex multiply-add; three and two
+ * workgroups per CU).  Another variant than 0 is kept only when it is 2 %
+ * faster.  chfsi_autotune_filter times them on each given
  * launch shape (an n x n Hermitian-sized operand times an n x N block, the
- * width N of a filter window; synthetic data in `work`), records the faster
+ * width N of a filter window; synthetic data in `work`), records the fastest
  * one per device, and every later filter step (single or batched) takes
  * the choice of the nearest recorded shape (log distance in n and N; with
  * none recorded, variant 0).
- *   variant  HOST, count ints out.   tflops  HOST, 3 * count doubles out
- *   (variants 0, 1, 2 per shape; 0.0 where not timed) or NULL.
+ *   variant  HOST, count ints out.   tflops  HOST,
+ *   CHFSI_FILTER_VARIANTS * count doubles out (complex-equivalent TFLOP/s,
+ *   8 n^2 N flops per step for every variant, per shape in variant order;
+ *   0.0 where not timed) or NULL.
  *   work     device, >= chfsi_autotune_workspace_bytes(max n, max N).
  * chfsi_autotune_set records a choice directly; chfsi_autotune_reset
  * clears the current device's table. */
+#define CHFSI_FILTER_VARIANTS 5
 size_t chfsi_autotune_workspace_bytes(int n_max, int N_max);
 int chfsi_autotune_filter(int count, const int* n, const int* N, void* work, size_t work_bytes,
                           void* stream, int* variant, double* tflops);

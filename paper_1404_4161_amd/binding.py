@@ -48,7 +48,8 @@ class ChfsiInfo(Structure):
                 ("learned_cols", c_int), ("fallback_cols", c_int), ("learned_raised", c_int),
                 ("filter_steps_bf16", c_int), ("filter_flops_bf16", c_double),
                 ("rr_refined", c_int), ("rr_dense", c_int),
-                ("filter_steps_fp16", c_int), ("filter_flops_fp16", c_double)]
+                ("filter_steps_fp16", c_int), ("filter_flops_fp16", c_double),
+                ("filter_flops_fp64_mfma", c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "step_seconds"}
@@ -638,19 +639,25 @@ def chfsi_solve_batch(As, Bs, nevs, nexs, tol, X0s=None, opts=None, Lambda0s=Non
             [int(v) for v in sts])
 
 
+# filter-step variants (CHFSI_FILTER_VARIANTS): 0 / 1 64 x 64 tiles, 4M
+# split, K 8 / 16 deep; 2 128 x 128 tiles; 3 / 4 as 0 / 1 with the 3M split
+FILTER_VARIANTS = 5
+
+
 def chfsi_autotune_filter(ns, Ns, device="cuda", stream=None):
-    """Time both filter-step variants on each (n, N) launch shape and record
-    the fastest; returns (variants, tflops (count x 3)) numpy arrays."""
+    """Time the filter-step variants on each (n, N) launch shape and record
+    the fastest; returns (variants, tflops (count x FILTER_VARIANTS,
+    complex-equivalent)) numpy arrays."""
     torch = _torch()
     count = len(ns)
     dev = torch.device(device)
     wb = int(lib().chfsi_autotune_workspace_bytes(max(ns), max(Ns)))
     w = _work(wb, dev)
     v = (c_int * count)()
-    tf = (c_double * (3 * count))()
+    tf = (c_double * (FILTER_VARIANTS * count))()
     _check(lib().chfsi_autotune_filter(count, (c_int * count)(*ns), (c_int * count)(*Ns), _ptr(w),
                                        wb, _stream(stream, dev), v, tf), "chfsi_autotune_filter")
-    return np.array(v[:]), np.array(tf[:]).reshape(count, 3)
+    return np.array(v[:]), np.array(tf[:]).reshape(count, FILTER_VARIANTS)
 
 
 def chfsi_autotune_set(n, N, variant):

@@ -547,16 +547,19 @@ int lanczos_dev(hipStream_t s, int n, const zc* H, long ldh, int steps, unsigned
 }
 
 // Alg. 2 on device.  P0 holds Y_0 (n x k, columns sorted by ascending
-// degree m); on return column j of P[m_j mod 2] holds Y_{m_j}.
+// degree m); on return column j of P[m_j mod 2] holds Y_{m_j}.  flops gets
+// the algorithmic count (8 n^2 per column mat-vec), mfma_flops (if given)
+// the real flops the MFMAs execute (6 n^2 per column with the 3M split).
 int filter_dev(hipStream_t s, int n, int k, const zc* H, long ldh, zc* P0, zc* P1, long ld,
                const std::vector<int>& m, double c, double e, double gamma, zc* part,
-               size_t part_elems, double* flops, int* launches) {
+               size_t part_elems, double* flops, int* launches, double* mfma_flops = nullptr) {
   if (k <= 0) return CHFSI_OK;
   const double sig1 = e / (gamma - c);
   const double nn = (double)n * (double)n;
   // Y_1 = (sigma_1 / e)(H Y_0 - c Y_0)
   CK(cheb_step(s, n, k, H, ldh, P0, ld, nullptr, ld, P1, ld, c, sig1 / e, 0.0, part, part_elems));
   *flops += 8.0 * nn * k;
+  if (mfma_flops) *mfma_flops += 2.0 * filter_step_cm(n, k) * nn * k;
   *launches += 1;
   double sig = sig1;
   int first = 0;
@@ -570,6 +573,7 @@ int filter_dev(hipStream_t s, int n, int k, const zc* H, long ldh, zc* P0, zc* P
     CK(cheb_step(s, n, cols, H, ldh, cur + (size_t)first * ld, ld, old + (size_t)first * ld, ld,
                  old + (size_t)first * ld, ld, c, 2.0 * sn / e, sn * sig, part, part_elems));
     *flops += 8.0 * nn * cols;
+    if (mfma_flops) *mfma_flops += 2.0 * filter_step_cm(n, cols) * nn * cols;
     *launches += 1;
     sig = sn;
     while (first < k && m[first] <= i + 1) ++first;
@@ -1174,7 +1178,7 @@ struct Solve {
   int it = 0;
   int status = CHFSI_NO_CONVERGENCE;
   double filter_flops = 0.0, filter_sec = 0.0, flops32 = 0.0, sec32 = 0.0, flops16 = 0.0;
-  double flopsh = 0.0;
+  double flopsh = 0.0, flops64_mfma = 0.0;
   int iters32 = 0, launches = 0, steps16 = 0, stepsh = 0, rr_refined = 0, rr_dense = 0;
   bool have_res = false;   // residuals of the current block known
   hipEvent_t fe0 = nullptr, fe1 = nullptr;
@@ -1529,7 +1533,7 @@ struct Solve {
       // Chebyshev filter (Alg. 2)
       tm.begin(2);
       CKS(filter_dev(s, n, ka, H, ldh, b.P0, b.P1, ld, msort, c, e, gamma, sb.fpart,
-                     sb.fpart_elems, &filter_flops, &launches));
+                     sb.fpart_elems, &filter_flops, &launches, &flops64_mfma));
       tm.end();
     }
     CK(hipEventRecord(fe1, s));
@@ -1734,6 +1738,7 @@ struct Solve {
       info->filter_flops_bf16 = flops16;
       info->filter_steps_bf16 = steps16;
       info->filter_flops_fp16 = flopsh;
+      info->filter_flops_fp64_mfma = flops64_mfma;
       info->filter_steps_fp16 = stepsh;
       info->filter_seconds_fp32 = sec32;
       info->beta = beta;
@@ -1788,6 +1793,7 @@ struct FilterGroup {
   hipGraphExec_t gexec = nullptr;
   std::vector<Solve*> jobs;
   std::vector<double> fl;
+  int cm = 4;                  // real products per complex multiply-add of the launches
   bool pending = false;
 
   ~FilterGroup() {
@@ -1869,10 +1875,15 @@ struct FilterGroup {
     CK(hipMemcpyAsync(dslots, hslots, sizeof(int) * ns, hipMemcpyHostToDevice, s));
     // one tile variant per grouped launch: the tuned choice carrying the
     // most flops among the problems
-    double w[2] = {0.0, 0.0};
-    for (int q = 0; q < count; ++q)
-      w[filter_variant(jobs[q]->n, jobs[q]->ka) == 1 ? 1 : 0] += fl[q];
-    const int variant = w[1] > w[0] ? 1 : 0;
+    double w[FILTER_VARIANTS] = {};
+    for (int q = 0; q < count; ++q) {
+      const int v = filter_variant(jobs[q]->n, jobs[q]->ka);
+      w[v == 2 ? 0 : v] += fl[q];
+    }
+    int variant = 0;
+    for (int v = 1; v < FILTER_VARIANTS; ++v)
+      if (w[v] > w[variant]) variant = v;
+    cm = variant_cm(variant);
     CK(hipEventRecord(e0, s));
     if (use_graph) {
       CK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -1912,6 +1923,7 @@ struct FilterGroup {
     for (double f : fl) ftot += f;
     for (size_t q = 0; q < jobs.size(); ++q) {
       jobs[q]->filter_flops += fl[q];
+      jobs[q]->flops64_mfma += fl[q] * cm / 4.0;
       if (ftot > 0.0) jobs[q]->filter_sec += 1e-3 * ms * fl[q] / ftot;
     }
     return CHFSI_OK;
@@ -3147,10 +3159,10 @@ int chfsi_autotune_filter(int count, const int* n, const int* N, void* work, siz
     for (int i = 0; i < count; ++i) {
       CK(fill_counter_random(s, n[i], N[i], Y0, n[i], 2, 1));
       CK(fill_counter_random(s, n[i], N[i], Y1, n[i], 3, 1));
-      double tf[3] = {0.0, 0.0, 0.0};
+      double tf[FILTER_VARIANTS] = {};
       CK(tune_filter_shape(s, n[i], N[i], H, Y0, Y1, &variant[i], tf));
       if (tflops)
-        for (int v = 0; v < 3; ++v) tflops[3 * i + v] = tf[v];
+        for (int v = 0; v < FILTER_VARIANTS; ++v) tflops[FILTER_VARIANTS * i + v] = tf[v];
     }
     CK(hipStreamSynchronize(s));
     return CHFSI_OK;
@@ -3164,7 +3176,7 @@ int chfsi_autotune_filter(int count, const int* n, const int* N, void* work, siz
 }
 
 int chfsi_autotune_set(int n, int N, int variant) {
-  if (n < 1 || N < 1 || variant < 0 || variant > 2) return CHFSI_INVALID_ARG;
+  if (n < 1 || N < 1 || variant < 0 || variant >= FILTER_VARIANTS) return CHFSI_INVALID_ARG;
   tune_set(n, N, variant);
   return CHFSI_OK;
 }

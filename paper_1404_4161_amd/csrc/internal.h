@@ -85,21 +85,30 @@ GemmArgs cheb_group_args(int n, int N, const zc* H, long ldh, const zc* Ycur, lo
                          double sb, int* slots);
 // One launch running `count` steps; list (device) holds their arguments and
 // slot_begin (device, count + 1 ints, multiples of 8) their workgroup ranges.
-// variant: K-stage depth of the tile (0: 8, four workgroups per CU; 1: 16,
-// two per CU); the wide variant 2 of single steps runs as 0 here.
+// variant: the filter variant (below); the wide variant 2 of single steps
+// runs as 0 here.
 int cheb_step_group(hipStream_t s, const GemmArgs* list, const int* slot_begin, int count,
                     int total_slots, int variant);
 
-// Filter tile autotuner (zgemm.hip).  filter_variant: the variant for an
-// n x n by n x N step (nearest measured shape; 0 when none).
-// tune_filter_shape: times both variants of a step on the given buffers
-// (H n x n, Y0 and Y1 n x N, ld n; Y1 is overwritten), records the faster
-// and returns it with the TFLOP/s of each (variant 2, 128 x 128 tiles, only
-// for N >= 256; tf[2] = 0 otherwise).  tune_set / tune_reset edit the
-// table directly.
+// Filter tile autotuner (zgemm.hip).  Variants of the FP64 filter step:
+// 0 / 1: 64 x 64 tiles with the 4M complex split, K staged 8 / 16 deep
+// (four / two workgroups per CU); 2: 128 x 128 tiles (4M, one workgroup
+// per CU, windows of N >= 256); 3 / 4: as 0 / 1 with the 3M split (three
+// real products per complex multiply-add; three / two workgroups per CU).
+// filter_variant: the variant for an n x n by n x N step (nearest measured
+// shape; 0 when none).  tune_filter_shape: times the variants of a step on
+// the given buffers (H n x n, Y0 and Y1 n x N, ld n; Y1 is overwritten),
+// records the fastest (another than 0 only when 2 % faster) and returns it
+// with the complex-equivalent TFLOP/s of each (tf[2] = 0 for N < 256).
+// tune_set / tune_reset edit the table directly.
+constexpr int FILTER_VARIANTS = 5;
+constexpr int variant_cm(int variant) { return variant == 3 || variant == 4 ? 3 : 4; }
 int filter_variant(int n, int N);
+// real products per complex multiply-add (3 or 4) of a filter step of n x n
+// by n x N
+inline int filter_step_cm(int n, int N) { return variant_cm(filter_variant(n, N)); }
 int tune_filter_shape(hipStream_t s, int n, int N, const zc* H, zc* Y0, zc* Y1, int* variant,
-                      double tf[3]);
+                      double tf[FILTER_VARIANTS]);
 void tune_set(int n, int N, int variant);
 void tune_reset();
 

@@ -34,6 +34,7 @@ namespace chfsi {
 namespace {
 
 constexpr int BM = 64, BN = 64, BK = 8, NT = 256;
+constexpr int GENERAL_3M_MIN_K = 512;   // general products of K >= this use 3M
 constexpr int PA = BM + 1, PB = BN + 1;   // LDS pitches in complex elements
 constexpr int NXCD = 8;
 
@@ -126,8 +127,9 @@ __device__ __forceinline__ void lower_tile(int t, int& tm, int& tn) {
 }
 
 // One 64x64 output tile (tile row tm, tile column tn, K chunk `split`) of
-// the launch described by g, with its epilogue; K staged KB deep in LDS.
-template <int OPA, int OPB, int EPI, int KB>
+// the launch described by g, with its epilogue; K staged KB deep in LDS;
+// CM real products per complex multiply-add (4: the 4M split, 3: 3M).
+template <int OPA, int OPB, int EPI, int KB, int CM>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, int tn,
                                           zc (*As)[KB][PA], zc (*Bs)[KB][PB]);
 
@@ -181,11 +183,15 @@ __device__ __forceinline__ bool rect_tile(const GemmArgs& g, int local, int& spl
   return true;
 }
 
-// KB = 8: four resident workgroups per CU (16 waves); the kernel fits in
-// 128 registers per lane without spills, with accumulators in VGPRs.
-// KB = 16 (twice the LDS per workgroup): two per CU.
-template <int OPA, int OPB, int EPI, int KB>
-__global__ void __launch_bounds__(NT, KB == 8 ? 4 : 2) zgemm_kernel(GemmArgs g) {
+// Resident workgroups per CU: KB = 8 with the 4M split: four (16 waves);
+// the kernel fits in 128 registers per lane without spills, with
+// accumulators in VGPRs.  The 3M form holds three accumulator sets instead
+// of two (32 more registers per lane): three per CU.  KB = 16 (twice the
+// LDS per workgroup): two per CU.
+constexpr int tile_occupancy(int KB, int CM) { return KB == 8 ? (CM == 4 ? 4 : 3) : 2; }
+
+template <int OPA, int OPB, int EPI, int KB, int CM>
+__global__ void __launch_bounds__(NT, tile_occupancy(KB, CM)) zgemm_kernel(GemmArgs g) {
   __shared__ zc As[2][KB][PA];
   __shared__ zc Bs[2][KB][PB];
 
@@ -207,15 +213,15 @@ __global__ void __launch_bounds__(NT, KB == 8 ? 4 : 2) zgemm_kernel(GemmArgs g) 
   } else {
     if (!rect_tile(g, blockIdx.x, split, tm, tn)) return;
   }
-  gemm_tile<OPA, OPB, EPI, KB>(g, split, tm, tn, As, Bs);
+  gemm_tile<OPA, OPB, EPI, KB, CM>(g, split, tm, tn, As, Bs);
 }
 
 // Several independent Chebyshev steps (one per problem of a batch) in one
 // launch: problem p owns workgroups [slot_begin[p], slot_begin[p + 1]), a
 // multiple of the XCD count, scheduled inside its range exactly as a launch
 // of its own.
-template <int KB>
-__global__ void __launch_bounds__(NT, KB == 8 ? 4 : 2)
+template <int KB, int CM>
+__global__ void __launch_bounds__(NT, tile_occupancy(KB, CM))
     zgemm_group_cheb(const GemmArgs* __restrict__ list, const int* __restrict__ slot_begin,
                      int count) {
   __shared__ zc As[2][KB][PA];
@@ -230,7 +236,7 @@ __global__ void __launch_bounds__(NT, KB == 8 ? 4 : 2)
   const GemmArgs g = list[lo];
   int split, tm, tn;
   if (!rect_tile(g, b - slot_begin[lo], split, tm, tn)) return;
-  gemm_tile<OP_N, OP_N, EPI_CHEB, KB>(g, split, tm, tn, As, Bs);
+  gemm_tile<OP_N, OP_N, EPI_CHEB, KB, CM>(g, split, tm, tn, As, Bs);
 }
 
 // Wide filter step (tile variant 2): 128 x 128 output tiles, 16 waves in a
@@ -332,9 +338,10 @@ __global__ void __launch_bounds__(WNT, 1) cheb_wide_kernel(GemmArgs g) {
       }
 }
 
-template <int OPA, int OPB, int EPI, int KB>
+template <int OPA, int OPB, int EPI, int KB, int CM>
 __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, int tn,
                                           zc (*As)[KB][PA], zc (*Bs)[KB][PB]) {
+  static_assert(CM == 3 || CM == 4, "4M or 3M split");
   const int m0 = tm * BM, n0 = tn * BN;
   int kbeg = split * g.kchunk;
   int kend = min(g.K, kbeg + g.kchunk);
@@ -353,13 +360,16 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, 
   const int wm = wave & 1, wn = wave >> 1;
   const int lr = lane & 15, lk = lane >> 4;
 
-  d4 accR[2][2], accI[2][2];
+  // 4M: acc0 = Re, acc1 = Im.  3M: acc0 = Ar Br, acc1 = Ai Bi,
+  // acc2 = (Ar + Ai)(Br + Bi); Re = acc0 - acc1, Im = acc2 - acc0 - acc1.
+  d4 acc0[2][2], acc1[2][2], acc2[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      accR[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      accI[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      acc0[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      acc1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      acc2[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     }
 
   const int nk = (kend - kbeg + KB - 1) / KB;
@@ -387,22 +397,42 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, 
       for (int i = 0; i < 2; ++i) a[i] = As[cur][kk * 4 + lk][wm * 32 + i * 16 + lr];
 #pragma unroll
       for (int j = 0; j < 2; ++j) b[j] = Bs[cur][kk * 4 + lk][wn * 32 + j * 16 + lr];
+      if constexpr (CM == 4) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) accR[i][j] = mfma(a[i].x, b[j].x, accR[i][j]);
+          for (int j = 0; j < 2; ++j) acc0[i][j] = mfma(a[i].x, b[j].x, acc0[i][j]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) accI[i][j] = mfma(a[i].x, b[j].y, accI[i][j]);
+          for (int j = 0; j < 2; ++j) acc1[i][j] = mfma(a[i].x, b[j].y, acc1[i][j]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) accR[i][j] = mfma(-a[i].y, b[j].y, accR[i][j]);
+          for (int j = 0; j < 2; ++j) acc0[i][j] = mfma(-a[i].y, b[j].y, acc0[i][j]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) accI[i][j] = mfma(a[i].y, b[j].x, accI[i][j]);
+          for (int j = 0; j < 2; ++j) acc1[i][j] = mfma(a[i].y, b[j].x, acc1[i][j]);
+      } else {
+        double as[2], bs[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) as[i] = a[i].x + a[i].y;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bs[j] = b[j].x + b[j].y;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc0[i][j] = mfma(a[i].x, b[j].x, acc0[i][j]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc1[i][j] = mfma(a[i].y, b[j].y, acc1[i][j]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc2[i][j] = mfma(as[i], bs[j], acc2[i][j]);
+      }
     }
     if (more) {
       store_a<OPA, KB>(As[cur ^ 1], ra);
@@ -422,7 +452,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, 
         const int row = m0 + wm * 32 + i * 16 + lk + 4 * r;
         const int col = n0 + wn * 32 + j * 16 + lr;
         if (row >= g.M || col >= g.N) continue;
-        const zc acc = zc{accR[i][j][r], accI[i][j][r]};
+        const zc acc = CM == 4 ? zc{acc0[i][j][r], acc1[i][j][r]}
+                               : zc{acc0[i][j][r] - acc1[i][j][r],
+                                    (acc2[i][j][r] - acc0[i][j][r]) - acc1[i][j][r]};
         if (EPI == EPI_STORE) {
           zc out = cmul(g.alpha, acc);
           zc* cp = g.C + row + (long)col * g.ldc;
@@ -566,7 +598,7 @@ Plan make_plan(int M, int N, int K, bool lower_only, bool allow_split) {
   return p;
 }
 
-template <int OPA, int OPB, int EPI, int KB = BK>
+template <int OPA, int OPB, int EPI, int KB = BK, int CM = 4>
 int launch(hipStream_t s, GemmArgs& g) {
   int grid;
   if (g.lower_only && g.splits == 1) {
@@ -580,16 +612,27 @@ int launch(hipStream_t s, GemmArgs& g) {
   // rows whose K range is longest first (triangular A with the long rows at
   // the bottom), so the tail of the launch is made of short tiles
   g.rows_desc = (g.ktri == KTRI_A_LOWER || g.ktri == KTRI_A_LOWER_B_UPPER) ? 1 : 0;
-  hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, EPI, KB>), dim3(grid), dim3(NT), 0, s, g);
+  hipLaunchKernelGGL((zgemm_kernel<OPA, OPB, EPI, KB, CM>), dim3(grid), dim3(NT), 0, s, g);
   return (int)hipGetLastError();
 }
 
+template <int EPI, int CM>
+int dispatch_cm(hipStream_t s, Op opa, Op opb, GemmArgs& g) {
+  if (opa == OP_N && opb == OP_N) return launch<OP_N, OP_N, EPI, BK, CM>(s, g);
+  if (opa == OP_N && opb == OP_C) return launch<OP_N, OP_C, EPI, BK, CM>(s, g);
+  if (opa == OP_C && opb == OP_N) return launch<OP_C, OP_N, EPI, BK, CM>(s, g);
+  return launch<OP_C, OP_C, EPI, BK, CM>(s, g);
+}
+
+// General products: the 3M split for rectangular products with a long inner
+// dimension (25 % fewer MFMAs; measured 1.2x faster on filter-sized
+// products).  Gram products (lower triangle) keep the 4M split: a small
+// share of the time, and CholeskyQR's accuracy rests on them (3M's error
+// bound on the imaginary part is the larger one).
 template <int EPI>
 int dispatch(hipStream_t s, Op opa, Op opb, GemmArgs& g) {
-  if (opa == OP_N && opb == OP_N) return launch<OP_N, OP_N, EPI>(s, g);
-  if (opa == OP_N && opb == OP_C) return launch<OP_N, OP_C, EPI>(s, g);
-  if (opa == OP_C && opb == OP_N) return launch<OP_C, OP_N, EPI>(s, g);
-  return launch<OP_C, OP_C, EPI>(s, g);
+  if (!g.lower_only && g.K >= GENERAL_3M_MIN_K) return dispatch_cm<EPI, 3>(s, opa, opb, g);
+  return dispatch_cm<EPI, 4>(s, opa, opb, g);
 }
 
 // Filter tile autotuner: measured (n, N) launch shapes and the faster
@@ -617,11 +660,16 @@ int launch_cheb_wide(hipStream_t s, const GemmArgs& g0) {
   return (int)hipGetLastError();
 }
 
+// Variants of the filter step: 0 / 1 the 64 x 64 tile with the 4M split,
+// K staged 8 / 16 deep; 2 the wide tile (4M); 3 / 4 as 0 / 1 with the 3M
+// split.  A split-K step has no wide form and takes 0 for 2.
 template <int EPI>
 int launch_cheb_variant(hipStream_t s, GemmArgs& g, int variant) {
   if (variant == 2 && EPI == EPI_CHEB && g.splits == 1) return launch_cheb_wide(s, g);
-  if (variant == 1) return launch<OP_N, OP_N, EPI, 16>(s, g);
-  return launch<OP_N, OP_N, EPI, 8>(s, g);
+  if (variant == 1) return launch<OP_N, OP_N, EPI, 16, 4>(s, g);
+  if (variant == 3) return launch<OP_N, OP_N, EPI, 8, 3>(s, g);
+  if (variant == 4) return launch<OP_N, OP_N, EPI, 16, 3>(s, g);
+  return launch<OP_N, OP_N, EPI, 8, 4>(s, g);
 }
 
 // Variant 2 needs a window of at least this many columns.
@@ -669,7 +717,7 @@ void tune_reset() {
 }
 
 int tune_filter_shape(hipStream_t s, int n, int N, const zc* H, zc* Y0, zc* Y1, int* variant,
-                      double tf[3]) {
+                      double tf[FILTER_VARIANTS]) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess) return (int)hipErrorUnknown;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -687,12 +735,15 @@ int tune_filter_shape(hipStream_t s, int n, int N, const zc* H, zc* Y0, zc* Y1, 
   // rounds alternate the variants (two launches each); the best round of
   // each counts
   const int rounds = 4, reps = 2;
-  const int nv = N >= WIDE_MIN_N ? 3 : 2;
-  float best[3] = {1e30f, 1e30f, 1e30f};
+  const bool wide_ok = N >= WIDE_MIN_N;
+  float best[FILTER_VARIANTS];
+  for (int v = 0; v < FILTER_VARIANTS; ++v) best[v] = 1e30f;
   int err = 0;
-  for (int v = 0; v < nv && !err; ++v) err = launch_cheb_variant<EPI_CHEB>(s, g, v);
+  for (int v = 0; v < FILTER_VARIANTS && !err; ++v)
+    if (v != 2 || wide_ok) err = launch_cheb_variant<EPI_CHEB>(s, g, v);
   for (int r = 0; r < rounds && !err; ++r) {
-    for (int v = 0; v < nv && !err; ++v) {
+    for (int v = 0; v < FILTER_VARIANTS && !err; ++v) {
+      if (v == 2 && !wide_ok) continue;
       err = (int)hipEventRecord(e0, s);
       for (int i = 0; i < reps && !err; ++i) err = launch_cheb_variant<EPI_CHEB>(s, g, v);
       if (!err) err = (int)hipEventRecord(e1, s);
@@ -705,11 +756,13 @@ int tune_filter_shape(hipStream_t s, int n, int N, const zc* H, zc* Y0, zc* Y1, 
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (err) return err;
-  for (int v = 0; v < 3; ++v)
-    tf[v] = v < nv ? 8.0 * (double)n * n * N * reps / (1e-3 * best[v]) / 1e12 : 0.0;
+  // complex-equivalent rate (8 real flops per complex multiply-add, also
+  // for the 3M variants, which execute 6)
+  for (int v = 0; v < FILTER_VARIANTS; ++v)
+    tf[v] = best[v] < 1e29f ? 8.0 * (double)n * n * N * reps / (1e-3 * best[v]) / 1e12 : 0.0;
   // another variant than the default only when clearly (2 %) faster
   int pick = 0;
-  for (int v = 1; v < nv; ++v)
+  for (int v = 1; v < FILTER_VARIANTS; ++v)
     if (tf[v] > 1.02 * tf[0] && tf[v] > tf[pick]) pick = v;
   *variant = pick;
   tune_set(n, N, *variant);
@@ -773,12 +826,19 @@ GemmArgs cheb_group_args(int n, int N, const zc* H, long ldh, const zc* Ycur, lo
 int cheb_step_group(hipStream_t s, const GemmArgs* list, const int* slot_begin, int count,
                     int total_slots, int variant) {
   if (count <= 0 || total_slots <= 0) return 0;
-  if (variant == 1)   // (the wide variant has no grouped form: 8-deep tiles)
-    hipLaunchKernelGGL(zgemm_group_cheb<16>, dim3(total_slots), dim3(NT), 0, s, list, slot_begin,
-                       count);
+  // (the wide variant has no grouped form: 8-deep tiles)
+  if (variant == 1)
+    hipLaunchKernelGGL((zgemm_group_cheb<16, 4>), dim3(total_slots), dim3(NT), 0, s, list,
+                       slot_begin, count);
+  else if (variant == 3)
+    hipLaunchKernelGGL((zgemm_group_cheb<8, 3>), dim3(total_slots), dim3(NT), 0, s, list,
+                       slot_begin, count);
+  else if (variant == 4)
+    hipLaunchKernelGGL((zgemm_group_cheb<16, 3>), dim3(total_slots), dim3(NT), 0, s, list,
+                       slot_begin, count);
   else
-    hipLaunchKernelGGL(zgemm_group_cheb<8>, dim3(total_slots), dim3(NT), 0, s, list, slot_begin,
-                       count);
+    hipLaunchKernelGGL((zgemm_group_cheb<8, 4>), dim3(total_slots), dim3(NT), 0, s, list,
+                       slot_begin, count);
   return (int)hipGetLastError();
 }
 
@@ -812,7 +872,7 @@ int cheb_step(hipStream_t s, int n, int N, const zc* H, long ldh, const zc* Ycur
   g.kchunk = chunk;
   g.splits = (n + chunk - 1) / chunk;
   g.part = part;
-  int err = launch<OP_N, OP_N, EPI_PARTIAL_CHEB>(s, g);
+  int err = launch_cheb_variant<EPI_PARTIAL_CHEB>(s, g, filter_variant(n, N));
   if (err) return err;
   const long total = (long)n * N;
   hipLaunchKernelGGL(cheb_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, n, N,

@@ -17,6 +17,46 @@ def test_library_exports_every_declared_function():
     assert missing == []
 
 
+def _header_struct(name):
+    """(C type, field name) pairs of `typedef struct name {...} name;` in the
+    public header, comments removed."""
+    import os
+    import re
+    path = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "chfsi.h")
+    src = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), src, re.S).group(1)
+    out = []
+    for decl in body.split(";"):
+        decl = " ".join(decl.split())
+        if not decl:
+            continue
+        m = re.match(r"(.*?)\s*\b(\w+)(\[\d+\])?$", decl)
+        out.append((m.group(1).replace(" *", "*").strip(), m.group(2) + (m.group(3) or "")))
+    return out
+
+
+@pytest.mark.parametrize("cname,pystruct", [("chfsi_opts", ch.binding.ChfsiOpts),
+                                            ("chfsi_info", ch.binding.ChfsiInfo)])
+def test_binding_structs_follow_the_header(cname, pystruct):
+    """The ctypes mirrors of the option and statistics structs have the
+    header's fields in the header's order, with matching C types."""
+    import ctypes as C
+    ctype_of = {"double": C.c_double, "int": C.c_int, "long long": C.c_longlong,
+                "unsigned long long": C.c_ulonglong, "double*": C.c_void_p,
+                "const float*": C.c_void_p}
+    fields = _header_struct(cname)
+    py = pystruct._fields_
+    assert [f for _, f in fields] == [f + ("[8]" if f == "step_seconds" else "") for f, _ in py]
+    for (ct, f), (pf, pt) in zip(fields, py):
+        if f.endswith("]"):
+            assert pt == C.c_double * 8, f
+        elif ct in ("double*", "const float*"):
+            assert C.sizeof(pt) == C.sizeof(C.c_void_p), f
+        else:
+            assert C.sizeof(pt) == C.sizeof(ctype_of[ct]) and \
+                (pt in (C.c_double,)) == (ct == "double"), f
+
+
 def test_default_options_and_status_strings():
     o = ch.chfsi_default_opts()
     assert (o.tol, o.deg0, o.deg_max, o.max_iter, o.lanczos_steps, o.alpha_rule,
@@ -186,7 +226,8 @@ def test_degree_features_match_oracle():
 def test_autotuner_and_batch_argument_checks():
     lib = ch.lib()
     assert lib.chfsi_autotune_set(0, 5, 0) == ch.binding.CHFSI_INVALID_ARG
-    assert lib.chfsi_autotune_set(10, 5, 3) == ch.binding.CHFSI_INVALID_ARG
+    assert lib.chfsi_autotune_set(10, 5, ch.binding.FILTER_VARIANTS) == \
+        ch.binding.CHFSI_INVALID_ARG
     assert lib.chfsi_autotune_set(10, 5, -1) == ch.binding.CHFSI_INVALID_ARG
     assert lib.chfsi_autotune_workspace_bytes(100, 10) >= 16 * (100 * 100 + 2 * 100 * 10)
     n = (ctypes.c_int * 1)(10)

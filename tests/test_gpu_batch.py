@@ -137,9 +137,11 @@ def test_batch_rejects_bad_arguments():
                              stream=torch.cuda.default_stream())
 
 
-def test_batch_with_the_second_tile_variant():
-    """The grouped launch with the 16-deep K stage (forced through the
-    autotuner's table) gives the same eigenvalues as the default."""
+@pytest.mark.parametrize("variant", [1, 3, 4])
+def test_batch_with_another_tile_variant(variant):
+    """The grouped launch with the 16-deep K stage or the 3M split (forced
+    through the autotuner's table) gives the same eigenvalues as the
+    default."""
     seqs, probs = _batch(length=1, cfg0=780)
     nevs = [p[1] for p in SIZES]
     nexs = [p[2] for p in SIZES]
@@ -148,7 +150,7 @@ def test_batch_with_the_second_tile_variant():
     r0 = ch.chfsi_solve_batch(As, Bs, nevs, nexs, 1e-10)
     try:
         for (n, nev, nex, g) in SIZES:
-            ch.chfsi_autotune_set(n, nev + nex, 1)
+            ch.chfsi_autotune_set(n, nev + nex, variant)
         r1 = ch.chfsi_solve_batch(As, Bs, nevs, nexs, 1e-10)
     finally:
         ch.chfsi_autotune_reset()

@@ -89,19 +89,25 @@ def test_gen_n8000_filter_sampled_columns(sequence):
         assert rel_col_err(got[:, j:j + 1], ref).max() < 1e-12, (j, m)
 
 
+# tile variants per window width: the 4M tiles (the 128 x 128 tile
+# `cheb_wide_kernel` for wide windows, the 16-deep K stage for narrow ones)
+# and the 3M tiles (16-deep for wide windows, 8-deep for narrow ones)
+TABLES = {"4m-wide": ((480, 2), (360, 2), (240, 1), (120, 1), (60, 1)),
+          "3m": ((480, 4), (360, 4), (240, 3), (120, 3), (60, 3))}
+
+
 @pytest.mark.timeout(900)
-def test_gen_n8000_sequence_with_the_tuned_wide_tile(sequence):
-    """The FP64 sequence again with the tile variants the benchmark's
-    autotuner picks at this size (the 128 x 128 tile `cheb_wide_kernel` for
-    the full 480-column window, the 64 x 64 tiles with the 16-deep K stage
-    for narrow windows), set explicitly so that the wide tile runs whatever
-    the timing on this device; then a full-width filter of 480 columns with
-    the wide tile, sampled columns against the oracle."""
+@pytest.mark.parametrize("table", sorted(TABLES))
+def test_gen_n8000_sequence_with_the_tuned_wide_tile(sequence, table):
+    """The FP64 sequence again with tile variants the benchmark's autotuner
+    picks at this size, set explicitly so that they run whatever the timing
+    on this device; then a full-width filter of 480 columns with the
+    full-width variant, sampled columns against the oracle."""
     import torch
     conf, seq, probs = sequence
     ref = _golden()
     try:
-        for N, v in ((480, 2), (360, 2), (240, 1), (120, 1), (60, 1)):
+        for N, v in TABLES[table]:
             ch.chfsi_autotune_set(conf.n, N, v)
         x, lam = None, None
         for l, a in enumerate(probs, start=1):

@@ -477,11 +477,12 @@ def test_fp16_split_filter_matches_oracle_with_error_scaling_like_the_residual(d
     assert fh + f32 == pytest.approx(8.0 * n * n * sum(m - 1 for m in deg))
 
 
-@pytest.mark.parametrize("variant,k", [(0, 70), (1, 70), (2, 300)])
+@pytest.mark.parametrize("variant,k", [(0, 70), (1, 70), (2, 300), (3, 70), (4, 70), (3, 300)])
 def test_filter_tile_variants_match_oracle(variant, k):
     """Every tile variant of the filter step gives the oracle's filter (the
     autotuner only chooses between them); the wide variant runs while the
-    window is at least 256 columns wide, then the default takes over."""
+    window is at least 256 columns wide, then the default takes over;
+    variants 3 and 4 are the 3M complex split."""
     n = 333
     lam, h = _herm_problem(n, 31)
     degrees = np.sort(np.random.default_rng(5).integers(1, 12, k)).tolist()
@@ -500,8 +501,9 @@ def test_autotuner_records_a_choice_per_shape():
     ch.chfsi_autotune_reset()
     try:
         v, tf = ch.chfsi_autotune_filter([700, 1300, 1300], [64, 130, 300])
-        assert v.shape == (3,) and set(v.tolist()) <= {0, 1, 2}
-        assert np.all(tf[:, :2] > 0) and np.all(tf[:2, 2] == 0) and tf[2, 2] > 0
+        assert v.shape == (3,) and set(v.tolist()) <= set(range(ch.binding.FILTER_VARIANTS))
+        assert tf.shape == (3, ch.binding.FILTER_VARIANTS)
+        assert np.all(tf[:, [0, 1, 3, 4]] > 0) and np.all(tf[:2, 2] == 0) and tf[2, 2] > 0
         # another variant only when it is clearly (2 %) faster than the default
         for q in range(3):
             if v[q] == 0:
