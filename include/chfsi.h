@@ -582,15 +582,17 @@ int chfsi_mlp_train(int n, const float* X, const float* T, float* params, int st
  * with four workgroups per CU, 1 stages it 16 deep with two per CU, 2 uses
  * 128 x 128 tiles of 16 waves (one workgroup per CU; windows of N >= 256
  * columns, and not in the grouped launches of chfsi_solve_batch, which take
- * 0 instead); 3 and 4 are 0 and 1 with the 3M split (three real products
+ * the default instead); 3 and 4 are 0 and 1 with the 3M split (three real products
  * Ar Br, Ai Bi, (Ar + Ai)(Br + Bi) per complex multiply-add; three and two
- * workgroups per CU).  Another variant than 0 is kept only when it is 2 %
- * faster.  chfsi_autotune_filter times them on each given
+ * workgroups per CU); 5 and 6 load both operands straight into LDS (no
+ * register staging), 5 with the 3M split and three stages in flight, 6
+ * with 4M and two.  Variant 5 is the default; another is kept only when it
+ * is 2 % faster.  chfsi_autotune_filter times them on each given
  * launch shape (an n x n Hermitian-sized operand times an n x N block, the
  * width N of a filter window; synthetic data in `work`), records the fastest
  * one per device, and every later filter step (single or batched) takes
  * the choice of the nearest recorded shape (log distance in n and N; with
- * none recorded, variant 0).
+ * none recorded, variant 5).
  *   variant  HOST, count ints out.   tflops  HOST,
  *   CHFSI_FILTER_VARIANTS * count doubles out (complex-equivalent TFLOP/s,
  *   8 n^2 N flops per step for every variant, per shape in variant order;
@@ -598,7 +600,7 @@ int chfsi_mlp_train(int n, const float* X, const float* T, float* params, int st
  *   work     device, >= chfsi_autotune_workspace_bytes(max n, max N).
  * chfsi_autotune_set records a choice directly; chfsi_autotune_reset
  * clears the current device's table. */
-#define CHFSI_FILTER_VARIANTS 5
+#define CHFSI_FILTER_VARIANTS 7
 size_t chfsi_autotune_workspace_bytes(int n_max, int N_max);
 int chfsi_autotune_filter(int count, const int* n, const int* N, void* work, size_t work_bytes,
                           void* stream, int* variant, double* tflops);

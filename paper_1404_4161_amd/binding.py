@@ -640,8 +640,10 @@ def chfsi_solve_batch(As, Bs, nevs, nexs, tol, X0s=None, opts=None, Lambda0s=Non
 
 
 # filter-step variants (CHFSI_FILTER_VARIANTS): 0 / 1 64 x 64 tiles, 4M
-# split, K 8 / 16 deep; 2 128 x 128 tiles; 3 / 4 as 0 / 1 with the 3M split
-FILTER_VARIANTS = 5
+# split, K 8 / 16 deep; 2 128 x 128 tiles; 3 / 4 as 0 / 1 with the 3M split;
+# 5 / 6 operands loaded straight into LDS, 3M / 4M
+FILTER_VARIANTS = 7
+DEFAULT_FILTER_VARIANT = 5   # taken where no shape was measured
 
 
 def chfsi_autotune_filter(ns, Ns, device="cuda", stream=None):

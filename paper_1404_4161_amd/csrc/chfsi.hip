@@ -1878,9 +1878,9 @@ struct FilterGroup {
     double w[FILTER_VARIANTS] = {};
     for (int q = 0; q < count; ++q) {
       const int v = filter_variant(jobs[q]->n, jobs[q]->ka);
-      w[v == 2 ? 0 : v] += fl[q];
+      w[v == 2 ? DEFAULT_FILTER_VARIANT : v] += fl[q];
     }
-    int variant = 0;
+    int variant = DEFAULT_FILTER_VARIANT;
     for (int v = 1; v < FILTER_VARIANTS; ++v)
       if (w[v] > w[variant]) variant = v;
     cm = variant_cm(variant);

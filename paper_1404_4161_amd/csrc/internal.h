@@ -86,7 +86,7 @@ GemmArgs cheb_group_args(int n, int N, const zc* H, long ldh, const zc* Ycur, lo
 // One launch running `count` steps; list (device) holds their arguments and
 // slot_begin (device, count + 1 ints, multiples of 8) their workgroup ranges.
 // variant: the filter variant (below); the wide variant 2 of single steps
-// runs as 0 here.
+// runs as the default here.
 int cheb_step_group(hipStream_t s, const GemmArgs* list, const int* slot_begin, int count,
                     int total_slots, int variant);
 
@@ -94,15 +94,21 @@ int cheb_step_group(hipStream_t s, const GemmArgs* list, const int* slot_begin, 
 // 0 / 1: 64 x 64 tiles with the 4M complex split, K staged 8 / 16 deep
 // (four / two workgroups per CU); 2: 128 x 128 tiles (4M, one workgroup
 // per CU, windows of N >= 256); 3 / 4: as 0 / 1 with the 3M split (three
-// real products per complex multiply-add; three / two workgroups per CU).
+// real products per complex multiply-add; three / two workgroups per CU);
+// 5 / 6: operands loaded straight into LDS, 3M with a three-stage ring
+// (three workgroups per CU) / 4M with two stages (four per CU).
 // filter_variant: the variant for an n x n by n x N step (nearest measured
-// shape; 0 when none).  tune_filter_shape: times the variants of a step on
-// the given buffers (H n x n, Y0 and Y1 n x N, ld n; Y1 is overwritten),
-// records the fastest (another than 0 only when 2 % faster) and returns it
+// shape; DEFAULT_FILTER_VARIANT when none).  tune_filter_shape: times the
+// variants of a step on the given buffers (H n x n, Y0 and Y1 n x N, ld n;
+// Y1 is overwritten), records the fastest (another than the default only
+// when 2 % faster) and returns it
 // with the complex-equivalent TFLOP/s of each (tf[2] = 0 for N < 256).
 // tune_set / tune_reset edit the table directly.
-constexpr int FILTER_VARIANTS = 5;
-constexpr int variant_cm(int variant) { return variant == 3 || variant == 4 ? 3 : 4; }
+constexpr int FILTER_VARIANTS = 7;
+constexpr int DEFAULT_FILTER_VARIANT = 5;   // with no measurement for a shape
+constexpr int variant_cm(int variant) {
+  return variant == 3 || variant == 4 || variant == 5 ? 3 : 4;
+}
 int filter_variant(int n, int N);
 // real products per complex multiply-add (3 or 4) of a filter step of n x n
 // by n x N

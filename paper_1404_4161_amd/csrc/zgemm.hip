@@ -338,13 +338,57 @@ __global__ void __launch_bounds__(WNT, 1) cheb_wide_kernel(GemmArgs g) {
       }
 }
 
-template <int OPA, int OPB, int EPI, int KB, int CM>
-__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, int tn,
-                                          zc (*As)[KB][PA], zc (*Bs)[KB][PB]) {
-  static_assert(CM == 3 || CM == 4, "4M or 3M split");
-  const int m0 = tm * BM, n0 = tn * BN;
-  int kbeg = split * g.kchunk;
-  int kend = min(g.K, kbeg + g.kchunk);
+// Epilogue of a wave's 32 x 32 sub-tile at (r0, c0).  MFMA output layout:
+// lane l, register r holds row (l / 16) + 4 r and column l % 16 of the
+// 16x16 tile.  The accumulators are combined per the complex split (4M:
+// acc0 = Re, acc1 = Im; 3M: Re = acc0 - acc1, Im = acc2 - acc0 - acc1).
+template <int EPI, int CM>
+__device__ __forceinline__ void tile_store(const GemmArgs& g, int split, int r0, int c0, int lr,
+                                           int lk, const d4 (&acc0)[2][2],
+                                           const d4 (&acc1)[2][2], const d4 (&acc2)[2][2]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + i * 16 + lk + 4 * r;
+        const int col = c0 + j * 16 + lr;
+        if (row >= g.M || col >= g.N) continue;
+        const zc acc = CM == 4 ? zc{acc0[i][j][r], acc1[i][j][r]}
+                               : zc{acc0[i][j][r] - acc1[i][j][r],
+                                    (acc2[i][j][r] - acc0[i][j][r]) - acc1[i][j][r]};
+        if (EPI == EPI_STORE) {
+          zc out = cmul(g.alpha, acc);
+          zc* cp = g.C + row + (long)col * g.ldc;
+          if (g.beta.x != 0.0 || g.beta.y != 0.0) {
+            const zc cv = *cp;
+            const zc bc = cmul(g.beta, cv);
+            out.x += bc.x;
+            out.y += bc.y;
+          }
+          *cp = out;
+        } else if (EPI == EPI_CHEB) {
+          const zc yc = g.Ycur[row + (long)col * g.ldyc];
+          zc out = zc{g.sa * (acc.x - g.shift * yc.x), g.sa * (acc.y - g.shift * yc.y)};
+          if (g.sb != 0.0) {
+            const zc yo = g.Yold[row + (long)col * g.ldyo];
+            out.x -= g.sb * yo.x;
+            out.y -= g.sb * yo.y;
+          }
+          g.C[row + (long)col * g.ldc] = out;
+        } else {
+          g.part[(long)split * g.M * g.N + row + (long)col * g.M] = acc;
+        }
+      }
+}
+
+// K range [kbeg, kend) of tile (tm, tn) in K chunk `split`, after the
+// triangular-operand limits.
+__device__ __forceinline__ void tile_k_range(const GemmArgs& g, int split, int m0, int n0,
+                                             int& kbeg, int& kend) {
+  kbeg = split * g.kchunk;
+  kend = min(g.K, kbeg + g.kchunk);
   if (g.ktri == KTRI_A_LOWER) kend = min(kend, m0 + BM);
   else if (g.ktri == KTRI_B_UPPER) kend = min(kend, n0 + BN);
   else if (g.ktri == KTRI_A_UPPER) kbeg = max(kbeg, m0);
@@ -354,6 +398,15 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, 
   } else if (g.ktri == KTRI_A_LOWER_B_UPPER) {
     kend = min(kend, min(m0 + BM, n0 + BN));
   }
+}
+
+template <int OPA, int OPB, int EPI, int KB, int CM>
+__device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, int tn,
+                                          zc (*As)[KB][PA], zc (*Bs)[KB][PB]) {
+  static_assert(CM == 3 || CM == 4, "4M or 3M split");
+  const int m0 = tm * BM, n0 = tn * BN;
+  int kbeg, kend;
+  tile_k_range(g, split, m0, n0, kbeg, kend);
 
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
@@ -441,43 +494,203 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, 
     __syncthreads();
   }
 
-  // Epilogue.  MFMA output layout: lane l, register r holds row
-  // (l / 16) + 4 r and column l % 16 of the 16x16 tile.
+  tile_store<EPI, CM>(g, split, m0 + wm * 32, n0 + wn * 32, lr, lk, acc0, acc1, acc2);
+}
+
+// Direct-to-LDS form of the tile for op(A) = A, op(B) = B (the filter step
+// and the plain products): both operands go from global memory straight
+// into LDS with global_load_lds_dwordx4 (lane L of an instruction writes
+// the 16 bytes at LDS offset 16 L from the wave's pointer), so no registers
+// hold staged data and loads run DMA_STAGES(CM) - 1 stages ahead of the
+// MFMAs.  Stage layout: the A rows k = 0..7 of 64 complex elements, m
+// contiguous, pitch PA elements (one instruction per row: the column
+// segment A[m0 .. m0 + 63, k] is 1 KB contiguous); then the B rows n =
+// 0..63 of 8 complex elements (128 B, k contiguous as in memory), the
+// 16-byte chunk of k stored at position k ^ ((n >> 1) & 7) so that the
+// MFMA operand reads of 16 consecutive rows fall on 16 distinct 16-byte
+// bank groups (one instruction fills 8 rows).  Out-of-range operands: rows
+// m >= M and columns n >= N read the last valid row or column (their
+// products only reach outputs that are not stored); A rows k >= K read row
+// K - 1, and B elements with k >= kend read a zero page, so the K tail adds
+// exact zeros.
+constexpr int DKB = 8;                               // K per stage
+constexpr int DA_BYTES = DKB * PA * 16;              // 8320
+constexpr int DB_BYTES = BN * DKB * 16;              // 8192
+constexpr int DSTAGE = DA_BYTES + DB_BYTES;          // 16512
+constexpr int dma_stages(int CM) { return CM == 3 ? 3 : 2; }
+
+__device__ __align__(16) double dma_zero_page[2];    // zero-initialised
+
+// One LDS-DMA load: lane L's 16 bytes at gsrc go to LDS byte lds + 16 L
+// (lds wave-uniform).  Issued in asm so that the compiler, which does not
+// see the LDS write, inserts no wait for it before the LDS reads of the
+// other stages; the caller waits with vmcnt before reading this stage (and
+// a barrier for the other waves' loads).  No output register.
+__device__ __forceinline__ void lds_dma16(const void* gsrc, unsigned lds) {
+  asm volatile(
+      "s_mov_b32 m0, %0\n\t"
+      "s_nop 0\n\t"
+      "global_load_lds_dwordx4 %1, off" ::"s"(lds),
+      "v"(gsrc)
+      : "memory", "m0");
+}
+
+template <int EPI, int CM>
+__device__ __forceinline__ void gemm_tile_dma(const GemmArgs& g, int split, int tm, int tn,
+                                              char* lds) {
+  static_assert(CM == 3 || CM == 4, "4M or 3M split");
+  constexpr int NS = dma_stages(CM);
+  const int m0 = tm * BM, n0 = tn * BN;
+  int kbeg, kend;
+  tile_k_range(g, split, m0, n0, kbeg, kend);
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int lr = lane & 15, lk = lane >> 4;
+
+  d4 acc0[2][2], acc1[2][2], acc2[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 2; ++j) {
+      acc0[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      acc1[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      acc2[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+
+  // this wave's instructions per stage: A rows k = 4 i + wave (i = 0, 1);
+  // B rows n = 8 (4 j + wave) + lane / 8 (j = 0, 1), the chunk that belongs
+  // at position lane % 8
+  const zc* a_src = g.A + min(m0 + lane, g.M - 1);
+  const int bn_row0 = 8 * wave + (lane >> 3), bn_row1 = 8 * (4 + wave) + (lane >> 3);
+  const int bc0 = (lane & 7) ^ ((bn_row0 >> 1) & 7), bc1 = (lane & 7) ^ ((bn_row1 >> 1) & 7);
+  const zc* b_col0 = g.B + (long)min(n0 + bn_row0, g.N - 1) * g.ldb;
+  const zc* b_col1 = g.B + (long)min(n0 + bn_row1, g.N - 1) * g.ldb;
+  const zc* zero = (const zc*)dma_zero_page;
+  // LDS byte address of the workgroup's ring, uniform
+  const unsigned lds_base = (unsigned)(size_t)(__attribute__((address_space(3))) char*)lds;
+  const unsigned wave_u = (unsigned)__builtin_amdgcn_readfirstlane(wave);
+  auto load = [&](int k0, unsigned st) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 32 + i * 16 + lk + 4 * r;
-        const int col = n0 + wn * 32 + j * 16 + lr;
-        if (row >= g.M || col >= g.N) continue;
-        const zc acc = CM == 4 ? zc{acc0[i][j][r], acc1[i][j][r]}
-                               : zc{acc0[i][j][r] - acc1[i][j][r],
-                                    (acc2[i][j][r] - acc0[i][j][r]) - acc1[i][j][r]};
-        if (EPI == EPI_STORE) {
-          zc out = cmul(g.alpha, acc);
-          zc* cp = g.C + row + (long)col * g.ldc;
-          if (g.beta.x != 0.0 || g.beta.y != 0.0) {
-            const zc cv = *cp;
-            const zc bc = cmul(g.beta, cv);
-            out.x += bc.x;
-            out.y += bc.y;
-          }
-          *cp = out;
-        } else if (EPI == EPI_CHEB) {
-          const zc yc = g.Ycur[row + (long)col * g.ldyc];
-          zc out = zc{g.sa * (acc.x - g.shift * yc.x), g.sa * (acc.y - g.shift * yc.y)};
-          if (g.sb != 0.0) {
-            const zc yo = g.Yold[row + (long)col * g.ldyo];
-            out.x -= g.sb * yo.x;
-            out.y -= g.sb * yo.y;
-          }
-          g.C[row + (long)col * g.ldc] = out;
-        } else {
-          g.part[(long)split * g.M * g.N + row + (long)col * g.M] = acc;
-        }
+    for (int i = 0; i < 2; ++i) {
+      const int k = min(k0 + 4 * i + wave, g.K - 1);
+      lds_dma16(a_src + (long)k * g.lda, st + (4 * i + wave_u) * PA * 16);
+    }
+    const int k0c = k0 + bc0, k1c = k0 + bc1;
+    lds_dma16(k0c < kend ? b_col0 + k0c : zero, st + DA_BYTES + wave_u * 1024);
+    lds_dma16(k1c < kend ? b_col1 + k1c : zero, st + DA_BYTES + (4 + wave_u) * 1024);
+  };
+  auto compute = [&](const char* st) {
+    const char* sb = st + DA_BYTES;
+#pragma unroll
+    for (int kk = 0; kk < DKB / 4; ++kk) {
+      const int k = kk * 4 + lk;
+      zc a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        a[i] = *(const zc*)(st + (k * PA + wm * 32 + i * 16 + lr) * 16);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = wn * 32 + j * 16 + lr;
+        b[j] = *(const zc*)(sb + n * (DKB * 16) + ((k ^ ((n >> 1) & 7)) * 16));
       }
+      if constexpr (CM == 4) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc0[i][j] = mfma(a[i].x, b[j].x, acc0[i][j]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc1[i][j] = mfma(a[i].x, b[j].y, acc1[i][j]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc0[i][j] = mfma(-a[i].y, b[j].y, acc0[i][j]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc1[i][j] = mfma(a[i].y, b[j].x, acc1[i][j]);
+      } else {
+        double as[2], bs[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) as[i] = a[i].x + a[i].y;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bs[j] = b[j].x + b[j].y;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc0[i][j] = mfma(a[i].x, b[j].x, acc0[i][j]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc1[i][j] = mfma(a[i].y, b[j].y, acc1[i][j]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) acc2[i][j] = mfma(as[i], bs[j], acc2[i][j]);
+      }
+    }
+  };
+
+  // NS stages in a ring: stage kt is computed while the loads of stages
+  // up to kt + NS - 1 are in flight; each stage ends with this wave's loads
+  // of the next stage landed (vmcnt counts the 4 loads per stage in order,
+  // and no other vector memory operation is issued in the loop) and a
+  // barrier, after which the stage just computed is free
+  const int nk = (kend - kbeg + DKB - 1) / DKB;
+  if (nk > 0) {
+    load(kbeg, lds_base);
+    if (NS == 3 && nk > 1) {
+      load(kbeg + DKB, lds_base + DSTAGE);
+      asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+    } else {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int kt = 0; kt < nk; ++kt) {
+    const bool issue = kt + NS - 1 < nk;
+    if (issue) {
+      int st = cur + NS - 1;
+      if (st >= NS) st -= NS;
+      load(kbeg + (kt + NS - 1) * DKB, lds_base + st * DSTAGE);
+    }
+    compute(lds + cur * DSTAGE);
+    __builtin_amdgcn_sched_barrier(0);
+    if (NS == 3 && issue) asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    cur = cur + 1 == NS ? 0 : cur + 1;
+  }
+  tile_store<EPI, CM>(g, split, m0 + wm * 32, n0 + wn * 32, lr, lk, acc0, acc1, acc2);
+}
+
+template <int EPI, int CM>
+__global__ void __launch_bounds__(NT, CM == 3 ? 3 : 4) zgemm_dma_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(1024))) char lds[dma_stages(CM) * DSTAGE];
+  int split, tm, tn;
+  if (!rect_tile(g, blockIdx.x, split, tm, tn)) return;
+  gemm_tile_dma<EPI, CM>(g, split, tm, tn, lds);
+}
+
+template <int CM>
+__global__ void __launch_bounds__(NT, CM == 3 ? 3 : 4)
+    zgemm_group_cheb_dma(const GemmArgs* __restrict__ list, const int* __restrict__ slot_begin,
+                         int count) {
+  __shared__ __attribute__((aligned(1024))) char lds[dma_stages(CM) * DSTAGE];
+  const int b = blockIdx.x;
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (slot_begin[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  const GemmArgs g = list[lo];
+  int split, tm, tn;
+  if (!rect_tile(g, b - slot_begin[lo], split, tm, tn)) return;
+  gemm_tile_dma<EPI_CHEB, CM>(g, split, tm, tn, lds);
 }
 
 // Sum the split-K partials in a fixed order: C = alpha sum_s P_s + beta C.
@@ -617,6 +830,9 @@ int launch(hipStream_t s, GemmArgs& g) {
 }
 
 template <int EPI, int CM>
+int launch_dma(hipStream_t s, GemmArgs& g);
+
+template <int EPI, int CM>
 int dispatch_cm(hipStream_t s, Op opa, Op opb, GemmArgs& g) {
   if (opa == OP_N && opb == OP_N) return launch<OP_N, OP_N, EPI, BK, CM>(s, g);
   if (opa == OP_N && opb == OP_C) return launch<OP_N, OP_C, EPI, BK, CM>(s, g);
@@ -626,12 +842,16 @@ int dispatch_cm(hipStream_t s, Op opa, Op opb, GemmArgs& g) {
 
 // General products: the 3M split for rectangular products with a long inner
 // dimension (25 % fewer MFMAs; measured 1.2x faster on filter-sized
-// products).  Gram products (lower triangle) keep the 4M split: a small
-// share of the time, and CholeskyQR's accuracy rests on them (3M's error
-// bound on the imaginary part is the larger one).
+// products), on the direct-to-LDS tile when neither operand is transposed.
+// Gram products (lower triangle) keep the 4M split: a small share of the
+// time, and CholeskyQR's accuracy rests on them (3M's error bound on the
+// imaginary part is the larger one).
 template <int EPI>
 int dispatch(hipStream_t s, Op opa, Op opb, GemmArgs& g) {
-  if (!g.lower_only && g.K >= GENERAL_3M_MIN_K) return dispatch_cm<EPI, 3>(s, opa, opb, g);
+  if (!g.lower_only && g.K >= GENERAL_3M_MIN_K) {
+    if (opa == OP_N && opb == OP_N) return launch_dma<EPI, 3>(s, g);
+    return dispatch_cm<EPI, 3>(s, opa, opb, g);
+  }
   return dispatch_cm<EPI, 4>(s, opa, opb, g);
 }
 
@@ -660,8 +880,19 @@ int launch_cheb_wide(hipStream_t s, const GemmArgs& g0) {
   return (int)hipGetLastError();
 }
 
+// Direct-to-LDS tiles (op N, N only): rectangular tile sets.
+template <int EPI, int CM>
+int launch_dma(hipStream_t s, GemmArgs& g) {
+  const int vrows = g.splits * g.tiles_m;
+  const int grid = ((vrows + NXCD - 1) / NXCD) * g.tiles_n * NXCD;
+  g.rows_desc = (g.ktri == KTRI_A_LOWER || g.ktri == KTRI_A_LOWER_B_UPPER) ? 1 : 0;
+  hipLaunchKernelGGL((zgemm_dma_kernel<EPI, CM>), dim3(grid), dim3(NT), 0, s, g);
+  return (int)hipGetLastError();
+}
+
 // Variants of the filter step: 0 / 1 the 64 x 64 tile with the 4M split,
-// K staged 8 / 16 deep; 2 the wide tile (4M); 3 / 4 as 0 / 1 with the 3M
+// K staged 8 / 16 deep through registers; 2 the wide tile (4M); 3 / 4 as
+// 0 / 1 with the 3M split; 5 / 6 the direct-to-LDS tile with the 3M / 4M
 // split.  A split-K step has no wide form and takes 0 for 2.
 template <int EPI>
 int launch_cheb_variant(hipStream_t s, GemmArgs& g, int variant) {
@@ -669,6 +900,8 @@ int launch_cheb_variant(hipStream_t s, GemmArgs& g, int variant) {
   if (variant == 1) return launch<OP_N, OP_N, EPI, 16, 4>(s, g);
   if (variant == 3) return launch<OP_N, OP_N, EPI, 8, 3>(s, g);
   if (variant == 4) return launch<OP_N, OP_N, EPI, 16, 3>(s, g);
+  if (variant == 5) return launch_dma<EPI, 3>(s, g);
+  if (variant == 6) return launch_dma<EPI, 4>(s, g);
   return launch<OP_N, OP_N, EPI, 8, 4>(s, g);
 }
 
@@ -679,10 +912,10 @@ constexpr int WIDE_MIN_N = 256;
 
 int filter_variant(int n, int N) {
   const int dev = current_device();
-  if (dev < 0) return 0;
+  if (dev < 0) return DEFAULT_FILTER_VARIANT;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   const auto& t = g_tune[dev];
-  int best = 0;
+  int best = DEFAULT_FILTER_VARIANT;
   double bd = 1e300;
   for (const auto& e : t) {
     const double a = std::log((double)n / e.n), b = std::log((double)N / e.N);
@@ -692,7 +925,7 @@ int filter_variant(int n, int N) {
       best = e.variant;
     }
   }
-  if (best == 2 && N < WIDE_MIN_N) best = 0;
+  if (best == 2 && N < WIDE_MIN_N) best = DEFAULT_FILTER_VARIANT;
   return best;
 }
 
@@ -761,9 +994,10 @@ int tune_filter_shape(hipStream_t s, int n, int N, const zc* H, zc* Y0, zc* Y1, 
   for (int v = 0; v < FILTER_VARIANTS; ++v)
     tf[v] = best[v] < 1e29f ? 8.0 * (double)n * n * N * reps / (1e-3 * best[v]) / 1e12 : 0.0;
   // another variant than the default only when clearly (2 %) faster
-  int pick = 0;
-  for (int v = 1; v < FILTER_VARIANTS; ++v)
-    if (tf[v] > 1.02 * tf[0] && tf[v] > tf[pick]) pick = v;
+  constexpr int d = DEFAULT_FILTER_VARIANT;
+  int pick = d;
+  for (int v = 0; v < FILTER_VARIANTS; ++v)
+    if (v != d && tf[v] > 1.02 * tf[d] && tf[v] > tf[pick]) pick = v;
   *variant = pick;
   tune_set(n, N, *variant);
   return 0;
@@ -826,7 +1060,8 @@ GemmArgs cheb_group_args(int n, int N, const zc* H, long ldh, const zc* Ycur, lo
 int cheb_step_group(hipStream_t s, const GemmArgs* list, const int* slot_begin, int count,
                     int total_slots, int variant) {
   if (count <= 0 || total_slots <= 0) return 0;
-  // (the wide variant has no grouped form: 8-deep tiles)
+  // (the wide variant has no grouped form: the default instead)
+  if (variant == 2) variant = DEFAULT_FILTER_VARIANT;
   if (variant == 1)
     hipLaunchKernelGGL((zgemm_group_cheb<16, 4>), dim3(total_slots), dim3(NT), 0, s, list,
                        slot_begin, count);
@@ -835,6 +1070,12 @@ int cheb_step_group(hipStream_t s, const GemmArgs* list, const int* slot_begin, 
                        slot_begin, count);
   else if (variant == 4)
     hipLaunchKernelGGL((zgemm_group_cheb<16, 3>), dim3(total_slots), dim3(NT), 0, s, list,
+                       slot_begin, count);
+  else if (variant == 5)
+    hipLaunchKernelGGL((zgemm_group_cheb_dma<3>), dim3(total_slots), dim3(NT), 0, s, list,
+                       slot_begin, count);
+  else if (variant == 6)
+    hipLaunchKernelGGL((zgemm_group_cheb_dma<4>), dim3(total_slots), dim3(NT), 0, s, list,
                        slot_begin, count);
   else
     hipLaunchKernelGGL((zgemm_group_cheb<8, 4>), dim3(total_slots), dim3(NT), 0, s, list,

@@ -137,7 +137,7 @@ def test_batch_rejects_bad_arguments():
                              stream=torch.cuda.default_stream())
 
 
-@pytest.mark.parametrize("variant", [1, 3, 4])
+@pytest.mark.parametrize("variant", [1, 3, 4, 5, 6])
 def test_batch_with_another_tile_variant(variant):
     """The grouped launch with the 16-deep K stage or the 3M split (forced
     through the autotuner's table) gives the same eigenvalues as the
