@@ -570,15 +570,31 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs& g, int split, int 
   // LDS byte address of the workgroup's ring, uniform
   const unsigned lds_base = (unsigned)(size_t)(__attribute__((address_space(3))) char*)lds;
   const unsigned wave_u = (unsigned)__builtin_amdgcn_readfirstlane(wave);
+  // stages that lie wholly inside [kbeg, kend) (all but possibly the last)
+  // advance four fixed per-lane pointers by a uniform offset; the last one
+  // clamps A's rows and reads B's tail from the zero page
+  const zc* pa0 = a_src + (long)(kbeg + wave) * g.lda;
+  const zc* pa1 = pa0 + 4 * g.lda;
+  const zc* pb0 = b_col0 + kbeg + bc0;
+  const zc* pb1 = b_col1 + kbeg + bc1;
   auto load = [&](int k0, unsigned st) {
+    if (k0 + DKB <= kend) {
+      const long ao = (long)(k0 - kbeg) * g.lda;
+      const int bo = k0 - kbeg;
+      lds_dma16(pa0 + ao, st + wave_u * PA * 16);
+      lds_dma16(pa1 + ao, st + (4 + wave_u) * PA * 16);
+      lds_dma16(pb0 + bo, st + DA_BYTES + wave_u * 1024);
+      lds_dma16(pb1 + bo, st + DA_BYTES + (4 + wave_u) * 1024);
+    } else {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int k = min(k0 + 4 * i + wave, g.K - 1);
-      lds_dma16(a_src + (long)k * g.lda, st + (4 * i + wave_u) * PA * 16);
+      for (int i = 0; i < 2; ++i) {
+        const int k = min(k0 + 4 * i + wave, g.K - 1);
+        lds_dma16(a_src + (long)k * g.lda, st + (4 * i + wave_u) * PA * 16);
+      }
+      const int k0c = k0 + bc0, k1c = k0 + bc1;
+      lds_dma16(k0c < kend ? b_col0 + k0c : zero, st + DA_BYTES + wave_u * 1024);
+      lds_dma16(k1c < kend ? b_col1 + k1c : zero, st + DA_BYTES + (4 + wave_u) * 1024);
     }
-    const int k0c = k0 + bc0, k1c = k0 + bc1;
-    lds_dma16(k0c < kend ? b_col0 + k0c : zero, st + DA_BYTES + wave_u * 1024);
-    lds_dma16(k1c < kend ? b_col1 + k1c : zero, st + DA_BYTES + (4 + wave_u) * 1024);
   };
   auto compute = [&](const char* st) {
     const char* sb = st + DA_BYTES;
@@ -740,7 +756,7 @@ __global__ void cheb_reduce(int M, int N, int splits, const zc* part, const zc* 
 }
 
 // Resident workgroup slots of the device (CUs x 4), cached per device.
-int device_slots() {
+int device_slots(int per_cu = 4) {
   static std::atomic<int> cache[64] = {};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 1024;
@@ -749,16 +765,17 @@ int device_slots() {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         cus <= 0)
       cus = 256;
-    cache[dev] = 4 * cus;
+    cache[dev] = cus;
   }
-  return cache[dev];
+  return per_cu * cache[dev];
 }
 
-// Split count for a launch of `tiles` output tiles with inner size K: the
-// smallest split (<= max_splits, chunks >= 1024) whose workgroup count fills
-// the resident slots to at least 90%, else the best one.
-int wave_splits(int tiles, int K, int max_splits, double enough = 0.9) {
-  const int slots = device_slots();
+// Split count for a launch of `tiles` output tiles with inner size K, run by
+// a kernel with per_cu resident workgroups per CU: the smallest split
+// (<= max_splits, chunks >= 1024) whose workgroup count fills the resident
+// slots to at least `enough`, else the best one.
+int wave_splits(int tiles, int K, int max_splits, double enough, int per_cu) {
+  const int slots = device_slots(per_cu);
   int best = 1;
   double best_u = 0.0;
   for (int s = 1; s <= max_splits; ++s) {
@@ -800,7 +817,7 @@ Plan make_plan(int M, int N, int K, bool lower_only, bool allow_split) {
     // long products (H Q of Rayleigh-Ritz): split K, as the filter step
     // does, when the last round of resident workgroups would be far from
     // full
-    const int s = wave_splits(p.total, K, 4, 0.97);
+    const int s = wave_splits(p.total, K, 4, 0.97, 4);
     if (s > 1) {
       int chunk = (K + s - 1) / s;
       chunk = ((chunk + BK - 1) / BK) * BK;
@@ -907,6 +924,7 @@ int launch_cheb_variant(hipStream_t s, GemmArgs& g, int variant) {
 
 // Variant 2 needs a window of at least this many columns.
 constexpr int WIDE_MIN_N = 256;
+
 
 }  // namespace
 
@@ -1094,26 +1112,31 @@ int cheb_step(hipStream_t s, int n, int N, const zc* H, long ldh, const zc* Ycur
   g.Ycur = Ycur; g.ldyc = ldyc; g.Yold = Yold; g.ldyo = ldyo;
   g.shift = shift; g.sa = sa; g.sb = sb;
   g.tiles_m = p.tiles_m; g.tiles_n = p.tiles_n; g.total_tiles = p.total;
+  const int variant = filter_variant(n, N);
   int splits = 1;
   if (part != nullptr) {
     const int max_s = (int)std::min<size_t>(CHEB_MAX_SPLITS, part_elems / ((size_t)n * N));
     // a filter step is long (up to 0.2 s at n = 30 000): split K until the
-    // last round of resident workgroups is nearly full (at n = 30 000 and
-    // 1800 columns one launch without split-K leaves 5 % of the slot time
-    // idle in its last round; two splits: 1.6 %, measured 1.3 % faster)
-    if (max_s > 1) splits = wave_splits(p.total, n, max_s, 0.97);
+    // last round of four workgroups per CU is nearly full.  At n = 30 000
+    // and 1800 columns (13 601 tiles) one launch of the 4M tile leaves 5 %
+    // of the slot time idle in its last round and two splits 1.6 %
+    // (measured 1.3 % faster); the 3M tiles, three per CU, would fill 98 %
+    // of their last round unsplit, yet run 1.8 % faster with the two splits
+    // as well (85.8 against 84.3 TFLOP/s): counting four slots per CU for
+    // every variant matched the measurements best.
+    if (max_s > 1) splits = wave_splits(p.total, n, max_s, 0.97, 4);
   }
   if (splits == 1) {
     g.splits = 1;
     g.kchunk = p.kchunk;
-    return launch_cheb_variant<EPI_CHEB>(s, g, filter_variant(n, N));
+    return launch_cheb_variant<EPI_CHEB>(s, g, variant);
   }
   int chunk = (n + splits - 1) / splits;
   chunk = ((chunk + BK - 1) / BK) * BK;
   g.kchunk = chunk;
   g.splits = (n + chunk - 1) / chunk;
   g.part = part;
-  int err = launch_cheb_variant<EPI_PARTIAL_CHEB>(s, g, filter_variant(n, N));
+  int err = launch_cheb_variant<EPI_PARTIAL_CHEB>(s, g, variant);
   if (err) return err;
   const long total = (long)n * N;
   hipLaunchKernelGGL(cheb_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, n, N,
