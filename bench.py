@@ -50,12 +50,11 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 # 1 GiB device copy; keyed by (n, N, tile variant).  Valid only for the kernel source they were
 # measured on (the hash); otherwise the roofline reports traffic null.
 TRAFFIC_MEASURED = {
-    "zgemm_sha256": "8b1f370d4a80c3281bdd1045d0fdc443bcfa4f2a1cac424c34ac4b794de9ed2d",
-    # a full-width step at n = 30000 runs as two K splits (partial sums and
-    # cheb_reduce, both counted) whatever the tile variant
-    "bytes_per_full_width_launch": {(8000, 480, 0): 4.566e9, (8000, 480, 1): 2.357e9,
-                                    (8000, 480, 2): 1.698e9, (30000, 1800, 0): 495.07e9,
-                                    (30000, 1800, 1): 495.07e9, (30000, 1800, 2): 495.07e9},
+    "zgemm_sha256": "61db8f0f463ddd681377a9bffd37913efcd0ad6799724845edd8f74fd14c069c",
+    # the default tile (variant 5, 3M, operands loaded straight into LDS); a
+    # full-width step at n = 30000 runs as two K splits (partial sums and
+    # cheb_reduce, both counted)
+    "bytes_per_full_width_launch": {(8000, 480, 5): 3.232e9, (30000, 1800, 5): 428.32e9},
 }
 
 
@@ -573,8 +572,9 @@ def main():
             "unit": "TFLOP/s",
             "frac": round(mtflops / PEAK_FP64_TFLOPS, 4),
             "traffic": traffic_entry(n, k, tv[0]),
-            "kernel": "FP64 filter step zgemm_kernel<OP_N,OP_N,EPI_CHEB,KB,CM> / "
-                      "cheb_wide_kernel (split-K steps: partial sums + cheb_reduce)",
+            "kernel": "FP64 filter step zgemm_dma_kernel<EPI_CHEB,3> (3M split, operands "
+                      "loaded straight into LDS; split-K steps: partial sums + cheb_reduce; "
+                      "other tile variants where the autotuner picks them)",
             "flops_note": "achieved = real flops executed on MFMA (6 n^2 per column mat-vec "
                           "with the 3M split, 8 with 4M) / filter device time",
             "tile_variant_full_width": int(tv[0]),
