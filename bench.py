@@ -50,11 +50,11 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 # 1 GiB device copy; keyed by (n, N, tile variant).  Valid only for the kernel source they were
 # measured on (the hash); otherwise the roofline reports traffic null.
 TRAFFIC_MEASURED = {
-    "zgemm_sha256": "61db8f0f463ddd681377a9bffd37913efcd0ad6799724845edd8f74fd14c069c",
+    "zgemm_sha256": "78d66e516777c6b1c8ee1507f3212f0b18b27bb6184419597d125aeff0ec3e46",
     # the default tile (variant 5, 3M, operands loaded straight into LDS); a
     # full-width step at n = 30000 runs as two K splits (partial sums and
     # cheb_reduce, both counted)
-    "bytes_per_full_width_launch": {(8000, 480, 5): 3.232e9, (30000, 1800, 5): 428.32e9},
+    "bytes_per_full_width_launch": {(8000, 480, 5): 3.237e9, (30000, 1800, 5): 428.22e9},
 }
 
 

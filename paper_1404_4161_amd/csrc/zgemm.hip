@@ -857,16 +857,20 @@ int dispatch_cm(hipStream_t s, Op opa, Op opb, GemmArgs& g) {
   return launch<OP_C, OP_C, EPI, BK, CM>(s, g);
 }
 
-// General products: the 3M split for rectangular products with a long inner
-// dimension (25 % fewer MFMAs; measured 1.2x faster on filter-sized
-// products), on the direct-to-LDS tile when neither operand is transposed.
-// Gram products (lower triangle) keep the 4M split: a small share of the
-// time, and CholeskyQR's accuracy rests on them (3M's error bound on the
-// imaginary part is the larger one).
+// General products: the 3M split for products with a long inner dimension
+// (25 % fewer MFMAs; measured 1.2x faster on filter-sized products), on the
+// direct-to-LDS tile for rectangular products whose operands are not
+// transposed.  Lower-triangle products with a transposed operand are the
+// Gram and Cholesky-update products (X^H X, Q^H Z, A21 A21^H): they keep
+// the 4M split, a small share of the time on which the accuracy of
+// CholeskyQR and of the B factor rests (3M's error bound on the imaginary
+// part is the larger one).  The lower-triangle product of the reduction
+// (Linv T, both operands plain) takes 3M.
 template <int EPI>
 int dispatch(hipStream_t s, Op opa, Op opb, GemmArgs& g) {
-  if (!g.lower_only && g.K >= GENERAL_3M_MIN_K) {
-    if (opa == OP_N && opb == OP_N) return launch_dma<EPI, 3>(s, g);
+  const bool gram = g.lower_only && (opa != OP_N || opb != OP_N);
+  if (!gram && g.K >= GENERAL_3M_MIN_K) {
+    if (!g.lower_only && opa == OP_N && opb == OP_N) return launch_dma<EPI, 3>(s, g);
     return dispatch_cm<EPI, 3>(s, opa, opb, g);
   }
   return dispatch_cm<EPI, 4>(s, opa, opb, g);
