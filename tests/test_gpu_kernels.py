@@ -21,8 +21,13 @@ def _rand(m, n, seed):
 
 @pytest.mark.parametrize("opa,opb", [("N", "N"), ("N", "C"), ("C", "N"), ("C", "C")])
 @pytest.mark.parametrize("M,N,K", [(1, 1, 1), (17, 5, 9), (64, 64, 64), (130, 67, 71),
-                                   (200, 129, 300), (40, 36, 5000), (8, 3, 0)])
+                                   (200, 129, 300), (40, 36, 5000), (8, 3, 0), (130, 67, 1001),
+                                   (2048, 1030, 777)])
 def test_zgemm_matches_numpy(opa, opb, M, N, K):
+    """K >= 512 runs the 3M split (for N, N the direct-to-LDS tile, whose K
+    tail reads a zero page: 1001 and 777 leave 1 of 8); (130, 67, 1001)
+    splits K, (2048, 1030, 777) is a launch of 544 tiles without split-K
+    and with ragged edges."""
     a = _rand(M, K, 1) if opa == "N" else _rand(K, M, 1)
     b = _rand(K, N, 2) if opb == "N" else _rand(N, K, 2)
     c = _rand(M, N, 3)
