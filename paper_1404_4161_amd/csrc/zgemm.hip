@@ -525,14 +525,17 @@ __device__ __align__(16) double dma_zero_page[2];    // zero-initialised
 // (lds wave-uniform).  Issued in asm so that the compiler, which does not
 // see the LDS write, inserts no wait for it before the LDS reads of the
 // other stages; the caller waits with vmcnt before reading this stage (and
-// a barrier for the other waves' loads).  No output register.
+// a barrier for the other waves' loads).  No output register.  M0 is a
+// register the compiler reserves and does not otherwise use in these
+// kernels (no clobber can be declared for it): the block sets it right
+// before the load.
 __device__ __forceinline__ void lds_dma16(const void* gsrc, unsigned lds) {
   asm volatile(
       "s_mov_b32 m0, %0\n\t"
       "s_nop 0\n\t"
       "global_load_lds_dwordx4 %1, off" ::"s"(lds),
       "v"(gsrc)
-      : "memory", "m0");
+      : "memory");
 }
 
 template <int EPI, int CM>
@@ -976,7 +979,7 @@ int tune_filter_shape(hipStream_t s, int n, int N, const zc* H, zc* Y0, zc* Y1, 
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess) return (int)hipErrorUnknown;
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return (int)hipErrorUnknown;
   }
   Plan p = make_plan(n, N, n, false, false);
@@ -1008,8 +1011,8 @@ int tune_filter_shape(hipStream_t s, int n, int N, const zc* H, zc* Y0, zc* Y1, 
       if (!err) best[v] = std::min(best[v], ms);
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (err) return err;
   // complex-equivalent rate (8 real flops per complex multiply-add, also
   // for the 3M variants, which execute 6)
