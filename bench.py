@@ -50,11 +50,11 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 # 1 GiB device copy; keyed by (n, N, tile variant).  Valid only for the kernel source they were
 # measured on (the hash); otherwise the roofline reports traffic null.
 TRAFFIC_MEASURED = {
-    "zgemm_sha256": "78d66e516777c6b1c8ee1507f3212f0b18b27bb6184419597d125aeff0ec3e46",
+    "zgemm_sha256": "2217364bfc13f498b995a827f5d788d9718b8fd517cf4ba5e1c5c3d872045dbd",
     # the default tile (variant 5, 3M, operands loaded straight into LDS); a
     # full-width step at n = 30000 runs as two K splits (partial sums and
     # cheb_reduce, both counted)
-    "bytes_per_full_width_launch": {(8000, 480, 5): 3.237e9, (30000, 1800, 5): 428.22e9},
+    "bytes_per_full_width_launch": {(8000, 480, 5): 3.233e9, (30000, 1800, 5): 428.7e9},
 }
 
 
