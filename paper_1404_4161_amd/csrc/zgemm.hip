@@ -512,12 +512,19 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs& g, int split, int tm, 
 // m >= M and columns n >= N read the last valid row or column (their
 // products only reach outputs that are not stored); A rows k >= K read row
 // K - 1, and B elements with k >= kend read a zero page, so the K tail adds
-// exact zeros.
+// exact zeros.  With op(B) = B^H (OPB = OP_C: element (k, n) is the
+// conjugate of B[n + k ldb]) the rows k of op(B)'s panel are 1 KB contiguous
+// segments as well: they are staged like A's (pitch PB, one instruction
+// per row, the conjugation applied to the operand registers), and their K
+// tail (k >= kend) comes from the zero page.
 constexpr int DKB = 8;                               // K per stage
 constexpr int DA_BYTES = DKB * PA * 16;              // 8320
 constexpr int DB_BYTES = BN * DKB * 16;              // 8192
 constexpr int DSTAGE = DA_BYTES + DB_BYTES;          // 16512
 constexpr int dma_stages(int CM) { return CM == 3 ? 3 : 2; }
+constexpr int dma_stage_bytes(int OPB) {
+  return DA_BYTES + (OPB == OP_N ? DB_BYTES : DKB * PB * 16);
+}
 
 __device__ __align__(16) double dma_zero_page[2];    // zero-initialised
 
@@ -538,11 +545,12 @@ __device__ __forceinline__ void lds_dma16(const void* gsrc, unsigned lds) {
       : "memory");
 }
 
-template <int EPI, int CM>
+template <int EPI, int CM, int OPB = OP_N>
 __device__ __forceinline__ void gemm_tile_dma(const GemmArgs& g, int split, int tm, int tn,
                                               char* lds) {
   static_assert(CM == 3 || CM == 4, "4M or 3M split");
   constexpr int NS = dma_stages(CM);
+  constexpr int DSTAGE = dma_stage_bytes(OPB);
   const int m0 = tm * BM, n0 = tn * BN;
   int kbeg, kend;
   tile_k_range(g, split, m0, n0, kbeg, kend);
@@ -580,23 +588,43 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs& g, int split, int 
   const zc* pa1 = pa0 + 4 * g.lda;
   const zc* pb0 = b_col0 + kbeg + bc0;
   const zc* pb1 = b_col1 + kbeg + bc1;
+  // op(B) = B^H: rows k = 4 j + wave of the k-major panel, lane L taking
+  // column n0 + L
+  const zc* bh_src = g.B + min(n0 + lane, g.N - 1);
+  const zc* ph0 = bh_src + (long)(kbeg + wave) * g.ldb;
+  const zc* ph1 = ph0 + 4 * g.ldb;
   auto load = [&](int k0, unsigned st) {
     if (k0 + DKB <= kend) {
       const long ao = (long)(k0 - kbeg) * g.lda;
-      const int bo = k0 - kbeg;
       lds_dma16(pa0 + ao, st + wave_u * PA * 16);
       lds_dma16(pa1 + ao, st + (4 + wave_u) * PA * 16);
-      lds_dma16(pb0 + bo, st + DA_BYTES + wave_u * 1024);
-      lds_dma16(pb1 + bo, st + DA_BYTES + (4 + wave_u) * 1024);
+      if constexpr (OPB == OP_N) {
+        const int bo = k0 - kbeg;
+        lds_dma16(pb0 + bo, st + DA_BYTES + wave_u * 1024);
+        lds_dma16(pb1 + bo, st + DA_BYTES + (4 + wave_u) * 1024);
+      } else {
+        const long bo = (long)(k0 - kbeg) * g.ldb;
+        lds_dma16(ph0 + bo, st + DA_BYTES + wave_u * PB * 16);
+        lds_dma16(ph1 + bo, st + DA_BYTES + (4 + wave_u) * PB * 16);
+      }
     } else {
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int k = min(k0 + 4 * i + wave, g.K - 1);
         lds_dma16(a_src + (long)k * g.lda, st + (4 * i + wave_u) * PA * 16);
       }
-      const int k0c = k0 + bc0, k1c = k0 + bc1;
-      lds_dma16(k0c < kend ? b_col0 + k0c : zero, st + DA_BYTES + wave_u * 1024);
-      lds_dma16(k1c < kend ? b_col1 + k1c : zero, st + DA_BYTES + (4 + wave_u) * 1024);
+      if constexpr (OPB == OP_N) {
+        const int k0c = k0 + bc0, k1c = k0 + bc1;
+        lds_dma16(k0c < kend ? b_col0 + k0c : zero, st + DA_BYTES + wave_u * 1024);
+        lds_dma16(k1c < kend ? b_col1 + k1c : zero, st + DA_BYTES + (4 + wave_u) * 1024);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int k = k0 + 4 * j + wave;
+          lds_dma16(k < kend ? bh_src + (long)k * g.ldb : zero,
+                    st + DA_BYTES + (4 * j + wave_u) * PB * 16);
+        }
+      }
     }
   };
   auto compute = [&](const char* st) {
@@ -610,8 +638,13 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs& g, int split, int 
         a[i] = *(const zc*)(st + (k * PA + wm * 32 + i * 16 + lr) * 16);
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const int n = wn * 32 + j * 16 + lr;
-        b[j] = *(const zc*)(sb + n * (DKB * 16) + ((k ^ ((n >> 1) & 7)) * 16));
+        if constexpr (OPB == OP_N) {
+          const int n = wn * 32 + j * 16 + lr;
+          b[j] = *(const zc*)(sb + n * (DKB * 16) + ((k ^ ((n >> 1) & 7)) * 16));
+        } else {
+          const zc v = *(const zc*)(sb + (k * PB + wn * 32 + j * 16 + lr) * 16);
+          b[j] = zc{v.x, -v.y};
+        }
       }
       if constexpr (CM == 4) {
 #pragma unroll
@@ -686,12 +719,22 @@ __device__ __forceinline__ void gemm_tile_dma(const GemmArgs& g, int split, int 
   tile_store<EPI, CM>(g, split, m0 + wm * 32, n0 + wn * 32, lr, lk, acc0, acc1, acc2);
 }
 
-template <int EPI, int CM>
+template <int EPI, int CM, int OPB>
 __global__ void __launch_bounds__(NT, CM == 3 ? 3 : 4) zgemm_dma_kernel(GemmArgs g) {
-  __shared__ __attribute__((aligned(1024))) char lds[dma_stages(CM) * DSTAGE];
+  __shared__ __attribute__((aligned(1024))) char lds[dma_stages(CM) * dma_stage_bytes(OPB)];
   int split, tm, tn;
   if (!rect_tile(g, blockIdx.x, split, tm, tn)) return;
-  gemm_tile_dma<EPI, CM>(g, split, tm, tn, lds);
+  gemm_tile_dma<EPI, CM, OPB>(g, split, tm, tn, lds);
+}
+
+// Lower-triangle tile sets without split-K (the reduction's Linv T), in
+// the per-XCD order of lower_tile_xcd.
+template <int EPI, int CM>
+__global__ void __launch_bounds__(NT, CM == 3 ? 3 : 4) zgemm_dma_lower_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(1024))) char lds[dma_stages(CM) * DSTAGE];
+  int tm, tn;
+  if (!lower_tile_xcd(g, blockIdx.x, tm, tn)) return;
+  gemm_tile_dma<EPI, CM, OP_N>(g, 0, tm, tn, lds);
 }
 
 template <int CM>
@@ -849,8 +892,15 @@ int launch(hipStream_t s, GemmArgs& g) {
   return (int)hipGetLastError();
 }
 
-template <int EPI, int CM>
+template <int EPI, int CM, int OPB = OP_N>
 int launch_dma(hipStream_t s, GemmArgs& g);
+
+template <int EPI, int CM>
+int launch_dma_lower(hipStream_t s, GemmArgs& g) {
+  hipLaunchKernelGGL((zgemm_dma_lower_kernel<EPI, CM>), dim3(lower_xcd_grid(g.tiles_m)), dim3(NT),
+                     0, s, g);
+  return (int)hipGetLastError();
+}
 
 template <int EPI, int CM>
 int dispatch_cm(hipStream_t s, Op opa, Op opb, GemmArgs& g) {
@@ -862,18 +912,20 @@ int dispatch_cm(hipStream_t s, Op opa, Op opb, GemmArgs& g) {
 
 // General products: the 3M split for products with a long inner dimension
 // (25 % fewer MFMAs; measured 1.2x faster on filter-sized products), on the
-// direct-to-LDS tile for rectangular products whose operands are not
-// transposed.  Lower-triangle products with a transposed operand are the
-// Gram and Cholesky-update products (X^H X, Q^H Z, A21 A21^H): they keep
-// the 4M split, a small share of the time on which the accuracy of
-// CholeskyQR and of the B factor rests (3M's error bound on the imaginary
-// part is the larger one).  The lower-triangle product of the reduction
-// (Linv T, both operands plain) takes 3M.
+// direct-to-LDS tile where op(A) = A (rectangular products with op(B) = B
+// or B^H, and unsplit lower-triangle ones).  Lower-triangle products with
+// a transposed operand are the Gram and Cholesky-update products (X^H X,
+// Q^H Z, A21 A21^H): they keep the 4M split, a small share of the time on
+// which the accuracy of CholeskyQR and of the B factor rests (3M's error
+// bound on the imaginary part is the larger one).  The reduction's
+// products (Linv T, lower triangle, and M Linv^H) take 3M.
 template <int EPI>
 int dispatch(hipStream_t s, Op opa, Op opb, GemmArgs& g) {
   const bool gram = g.lower_only && (opa != OP_N || opb != OP_N);
   if (!gram && g.K >= GENERAL_3M_MIN_K) {
-    if (!g.lower_only && opa == OP_N && opb == OP_N) return launch_dma<EPI, 3>(s, g);
+    if (opa == OP_N && !g.lower_only)
+      return opb == OP_N ? launch_dma<EPI, 3, OP_N>(s, g) : launch_dma<EPI, 3, OP_C>(s, g);
+    if (opa == OP_N && opb == OP_N && g.splits == 1) return launch_dma_lower<EPI, 3>(s, g);
     return dispatch_cm<EPI, 3>(s, opa, opb, g);
   }
   return dispatch_cm<EPI, 4>(s, opa, opb, g);
@@ -904,13 +956,13 @@ int launch_cheb_wide(hipStream_t s, const GemmArgs& g0) {
   return (int)hipGetLastError();
 }
 
-// Direct-to-LDS tiles (op N, N only): rectangular tile sets.
-template <int EPI, int CM>
+// Direct-to-LDS tiles (op(A) = A; op(B) = B or B^H): rectangular tile sets.
+template <int EPI, int CM, int OPB>
 int launch_dma(hipStream_t s, GemmArgs& g) {
   const int vrows = g.splits * g.tiles_m;
   const int grid = ((vrows + NXCD - 1) / NXCD) * g.tiles_n * NXCD;
   g.rows_desc = (g.ktri == KTRI_A_LOWER || g.ktri == KTRI_A_LOWER_B_UPPER) ? 1 : 0;
-  hipLaunchKernelGGL((zgemm_dma_kernel<EPI, CM>), dim3(grid), dim3(NT), 0, s, g);
+  hipLaunchKernelGGL((zgemm_dma_kernel<EPI, CM, OPB>), dim3(grid), dim3(NT), 0, s, g);
   return (int)hipGetLastError();
 }
 
