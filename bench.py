@@ -50,11 +50,11 @@ PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 (matrix and vector)
 # 1 GiB device copy; keyed by (n, N, tile variant).  Valid only for the kernel source they were
 # measured on (the hash); otherwise the roofline reports traffic null.
 TRAFFIC_MEASURED = {
-    "zgemm_sha256": "2217364bfc13f498b995a827f5d788d9718b8fd517cf4ba5e1c5c3d872045dbd",
+    "zgemm_sha256": "fc73129498a79014fc6f164424c783167f77c67ee9b9e9de9c0922857e7525cd",
     # the default tile (variant 5, 3M, operands loaded straight into LDS); a
     # full-width step at n = 30000 runs as two K splits (partial sums and
     # cheb_reduce, both counted)
-    "bytes_per_full_width_launch": {(8000, 480, 5): 3.233e9, (30000, 1800, 5): 428.7e9},
+    "bytes_per_full_width_launch": {(8000, 480, 5): 3.234e9, (30000, 1800, 5): 428.1e9},
 }
 
 
