@@ -611,7 +611,12 @@ int chfsi_autotune_reset(void);
  * C <- alpha op(A) op(B) + beta C with op in {'N', 'C'} (no-op or conjugate
  * transpose); C is M x N, the inner dimension K.  alpha, beta are complex
  * (HOST, two doubles each).  Uses split-K (and `work`) when M*N is small
- * compared with K.  C must not overlap A or B. */
+ * compared with K, or when K >= 4096 and the last round of workgroups would
+ * be far from full.  For K >= 512 the product runs the 3M split (three real
+ * products per complex multiply-add): its error stays within a small
+ * multiple of eps K max|A| |B| per element, as 4M's does, though the
+ * imaginary part's bound is (|Ar| + |Ai|)(|Br| + |Bi|) instead of |A| |B|.
+ * C must not overlap A or B. */
 int chfsi_zgemm(char opa, char opb, int M, int N, int K,
                 const double* alpha, const void* A, int lda, const void* B, int ldb,
                 const double* beta, void* C, int ldc,
